@@ -1,0 +1,192 @@
+"""Benchmark: local-energy evaluations per second on one MI355X.
+
+One step = the local energy (forward pass + forward-mode Laplacian + Coulomb
+sums, Eq. 2-3 of the paper) of every walker of one batch: LiH (Li Z=3 at the
+origin, H Z=1 at 3.015 bohr, 2 up + 2 down electrons), FermiNet with 4
+layers, widths 256/32, 16 determinants, 4096 walkers, seeded synthetic
+parameters and walker positions resident on the GPU.  The mixed-precision
+path is timed, then the plain FP32 path on the same inputs; the mixed result
+counts only if its batch-mean energy on a walker sample is within 1 mHa of
+the FP64 CPU oracle's.
+
+    python bench.py [--steps K] [--warmup W] [--precision bf16x6]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "local-energy evals/s on 1 GPU (mixed vs plain FP32 at dE<=1 mHa); p50/p99 latency"
+PEAK_TFLOPS = {"bf16": 2516.6, "bf16x3": 2516.6, "bf16x6": 2516.6, "fp32": 157.3, "fp64": 78.6}
+DTYPE = {"bf16": "bf16", "bf16x3": "bf16", "bf16x6": "bf16", "fp32": "f32", "fp64": "f64"}
+
+
+def stream_gemm_flops(s, walkers):
+    """Algorithmic FLOPs of the per-electron stream-layer products of one
+    local-energy pass: 2 B N T (d_h + 2 d_p) w1 per layer, T = 3N + 2 rows
+    (value, 3N tangents, Laplacian) per electron, unpadded."""
+    from paper_2401_10287_amd import inputs as I
+    T = 3 * s.n_elec + 2
+    tot = 0
+    per_layer = []
+    for l in range(s.n_layers):
+        d_h, d_p, _ = I.layer_dims(s, l)
+        f = 2 * walkers * s.n_elec * T * (d_h + 2 * d_p) * s.w1
+        per_layer.append(f)
+        tot += f
+    return tot, per_layer
+
+
+def time_steps(fn, steps, torch):
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record()
+        fn()
+        ends[k].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    return wall, lat
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="bf16x6", choices=["bf16", "bf16x3", "bf16x6", "fp32"])
+    ap.add_argument("--walkers", type=int, default=4096)
+    ap.add_argument("--sample", type=int, default=192, help="walkers checked against / timed on the CPU oracle")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2401_10287_amd import fnvmc
+    from paper_2401_10287_amd import inputs as I
+
+    s = I.lih(args.walkers)
+    theta = I.init_params(s)
+    x = I.init_walkers(s)
+    dev = torch.device("cuda:0")
+    xt = torch.tensor(x, device=dev)
+    out = {}
+    results = {}
+    for prec in (args.precision, "fp32"):
+        cfg = fnvmc.Config(s, prec)
+        tt = torch.tensor(theta, dtype=cfg.param_dtype, device=dev)
+        ws = fnvmc.Workspace(dev)
+        holder = {}
+
+        def step():
+            holder["r"] = fnvmc.fn_local_energy(cfg, tt, xt, ws=ws, want_parts=False)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        timing = prec == args.precision
+        if timing:
+            fnvmc.fn_timing_reset()
+            fnvmc.fn_timing_enable(True)
+        wall, lat = time_steps(step, args.steps, torch)
+        if timing:
+            fnvmc.fn_timing_enable(False)
+            kern = {k: fnvmc.fn_timing_read(k) for k in fnvmc.KERNEL_CLASSES}
+            results["kernels"] = kern
+        e = holder["r"][0].cpu().numpy()
+        results[prec] = {"wall": wall, "lat": lat, "e": e, "theta_used": tt.double().cpu().numpy()}
+        print(f"[bench] {prec}: {args.steps} steps in {wall:.3f}s, {args.walkers * args.steps / wall:.4g} evals/s",
+              file=sys.stderr, flush=True)
+
+    mixed = results[args.precision]
+    fp32 = results["fp32"]
+    ms_per_step = mixed["wall"] / args.steps * 1e3
+    value = args.walkers / (mixed["wall"] / args.steps)
+    fp32_value = args.walkers / (fp32["wall"] / args.steps)
+
+    # accuracy gate and CPU baseline: the FP64 oracle on a sample of walkers
+    from oracle import oracle as O
+    samp = min(args.sample, args.walkers)
+    orc = O.Oracle(s)
+    t0 = time.perf_counter()
+    ref = orc.local_energy(mixed["theta_used"], x[:samp])
+    t_orc = time.perf_counter() - t0
+    e_ref = ref["e_loc"]
+    d_mixed = abs(mixed["e"][:samp].mean() - e_ref.mean()) * 1e3
+    d_fp32 = abs(fp32["e"][:samp].mean() - e_ref.mean()) * 1e3
+    dmax_mixed = float(np.abs(mixed["e"][:samp] - e_ref).max())
+    print(f"[bench] oracle {samp} walkers in {t_orc:.2f}s; batch-mean |dE| mixed {d_mixed:.4f} mHa, "
+          f"fp32 {d_fp32:.4f} mHa", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel (per-electron stream-layer product)
+    kern = results["kernels"]
+    ms_g, n_g = kern["stream_gemm"]
+    flops, _ = stream_gemm_flops(s, args.walkers)
+    launches_per_step = s.n_layers
+    avg_launch_s = ms_g / max(n_g, 1) * 1e-3
+    flops_per_launch = flops / launches_per_step
+    achieved = flops_per_launch / avg_launch_s / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    total_kernel_ms = sum(v[0] for v in kern.values())
+
+    line = {
+        "metric": METRIC,
+        "value": value if d_mixed <= 1.0 else 0.0,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.precision],
+        "data": "synthetic",
+        "config": {
+            "workload": f"LiH forward + Laplacian local energy, {args.walkers} walkers, 4 layers 256/32, "
+                        f"16 determinants",
+            "walkers": args.walkers,
+            "precision": args.precision,
+            "fp32_evals_per_s": fp32_value,
+            "mixed_over_fp32": value / fp32_value,
+            "batch_mean_err_mHa": {"mixed": d_mixed, "fp32": d_fp32, "sample_walkers": samp},
+            "max_walker_err_Ha_mixed": dmax_mixed,
+            "latency_ms": {"p50": float(np.percentile(mixed["lat"], 50)),
+                           "p99": float(np.percentile(mixed["lat"], 99)),
+                           "fp32_p50": float(np.percentile(fp32["lat"], 50))},
+            "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kern.items() if v[1]},
+        },
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "stream_gemm",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": None,
+            "flops_per_launch": flops_per_launch,
+            "avg_launch_us": avg_launch_s * 1e6,
+            "launches": n_g,
+            "kernel_share_of_step": ms_g / max(total_kernel_ms, 1e-9),
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = {"value": samp / t_orc, "unit": "evals/s", "cores": O.num_threads(), "kind": "oracle",
+                                "sample": f"FP64 oracle local energy of the first {samp} of the {args.walkers} "
+                                          f"LiH walkers (hyper-dual second derivatives, OpenMP over walkers)"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

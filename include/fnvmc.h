@@ -1,0 +1,184 @@
+/*
+ * fnvmc.h -- C ABI of the MI355X (gfx950) FermiNet VMC hot path.
+ *
+ * The operations follow the paper "Open-Source Fermionic Neural Networks with
+ * Ionic Charge Initialization" (Pranesh, Zhu, Viswanathan, Ramsundar):
+ *   fn_log_psi            log|psi| of the FermiNet ansatz (FermiNet Model
+ *                         section: one- and two-electron streams, envelope of
+ *                         Eq. 4, Slater determinants), the quantity the
+ *                         Metropolis step compares (Electron Sampler section);
+ *   fn_local_energy       E = E_kin + E_el-el + E_nuc-nuc + E_nuc-el (Eq. 2)
+ *                         with E_kin from Eq. 3, per walker;
+ *   vmc_metropolis_step   the Electron Sampler's Gaussian proposal and
+ *                         Metropolis-Hastings accept/reject on 2 log|psi|;
+ *   fn_param_grad         the training gradient of Eq. 6,
+ *                         2 E_p[(E_p - E_p(E_p)) d log|psi| / d theta];
+ *   fn_log_psi_vjp        sum_p c_p d log|psi_p| / d theta for caller weights
+ *                         c_p (the backward of log|psi| w.r.t. theta).
+ *
+ * Conventions (all entry points):
+ *   - Pointers marked "device" are HIP device memory owned by the caller; the
+ *     configuration and everything marked "host" is read during the call
+ *     only.  The library keeps no pointer after it returns and allocates no
+ *     memory: every temporary lives in the caller's workspace `ws`, of at
+ *     least fn_workspace_bytes(cfg, B, op) bytes (256-byte aligned).
+ *   - Calls enqueue work on `stream` (a hipStream_t, NULL = the default
+ *     stream) and return without synchronising.  Two calls that run at the
+ *     same time must not share a workspace.
+ *   - Arguments are checked before anything is enqueued; a call that returns
+ *     an error has enqueued nothing.  fn_last_error() then gives a message
+ *     (thread-local, valid until the thread's next call).
+ *   - Non-finite values are data, not errors: a walker on a node of psi gets
+ *     log|psi| = -inf, sign 0 and a NaN local energy.
+ *   - Walker positions x are [B][N][3] FP64, electrons ordered spin-up first.
+ *     theta is the flat parameter vector (layout below) in FP64 when
+ *     precision == FN_FP64 and FP32 otherwise; gradients come back in the
+ *     same type.
+ *
+ * Flat parameter layout (M nuclei, L layers, widths w1/w2, K determinants):
+ *   for l = 0..L-1 : V_l [d_in][w1]  rows ordered h_i, g_up, g_dn, g_i_up,
+ *                                    g_i_dn; then b_l [w1]
+ *   for l = 0..L-2 : W2_l [d_p][w2], c2_l [w2]
+ *   for spin s = up, down with n_s > 0 :
+ *                    w_s [w1][K n_s] (column k n_s + i), g_s [K n_s],
+ *                    pi_s [K n_s][M], Sigma_s [K n_s][M][3][3]
+ *   with d_h = 4M, d_p = 4 at layer 0, d_h = w1, d_p = w2 afterwards and
+ *   d_in = 3 d_h + 2 d_p.
+ */
+#ifndef FNVMC_H
+#define FNVMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fn_status;
+#define FN_OK 0
+#define FN_EINVAL 1        /* invalid argument or configuration            */
+#define FN_ENOMEM 2        /* workspace smaller than fn_workspace_bytes()  */
+#define FN_EUNSUPPORTED 3  /* configuration outside the built limits       */
+#define FN_EHIP 4          /* a HIP runtime call failed                    */
+
+/* Arithmetic of the network.  FN_FP64: FP64 throughout.  FN_FP32: FP32
+   stream layers and orbital head on the FP32 matrix cores.
+   FN_BF16_MIXED: as FN_FP32 but the stream-layer matrix products take BF16
+   operands on the matrix cores with FP32 accumulation.
+   FN_BF16X3_MIXED: the same products with each FP32 operand split into a
+   BF16 high and low part and three BF16 products accumulated in FP32.
+   FN_BF16X6_MIXED: each operand split into three BF16 parts and the six
+   products whose part indices sum to at most 2, accumulated in FP32 (FP32
+   operand precision on the BF16 matrix cores).  In every mode the
+   envelope, the determinants and their derivative traces run in FP64. */
+#define FN_FP64 0
+#define FN_FP32 1
+#define FN_BF16_MIXED 2
+#define FN_BF16X3_MIXED 3
+#define FN_BF16X6_MIXED 4
+
+/* Operation selector for fn_workspace_bytes. */
+#define FN_OP_LOG_PSI 0
+#define FN_OP_LOCAL_ENERGY 1
+#define FN_OP_METROPOLIS 2
+#define FN_OP_PARAM_GRAD 3
+
+/* Built limits. */
+#define FN_MAX_NUC 32
+#define FN_MAX_ELEC 32
+#define FN_MAX_SPIN 16
+#define FN_MAX_DET 32
+#define FN_MAX_LAYERS 8
+#define FN_MAX_W1 1024
+#define FN_MAX_W2 64
+
+typedef struct {
+    int32_t n_nuc;          /* M, 1..FN_MAX_NUC                              */
+    const double *nuc_xyz;  /* host [M][3], bohr                             */
+    const double *nuc_z;    /* host [M], nuclear charges                      */
+    int32_t n_up, n_down;   /* electrons per spin, each 0..FN_MAX_SPIN, sum>0 */
+    int32_t n_layers;       /* L one-electron layers (L-1 pair layers), >= 1  */
+    int32_t w1, w2;         /* one- / two-electron stream widths              */
+    int32_t n_det;          /* K determinants                                 */
+    int32_t precision;      /* FN_FP64 .. FN_BF16X6_MIXED                    */
+} fn_config;
+
+/* Number of scalars in the flat parameter vector; -1 if cfg is invalid. */
+int64_t fn_param_count(const fn_config *cfg);
+
+/* Bytes of device workspace that operation `op` needs for B walkers; 0 if
+   cfg, B or op is invalid (fn_last_error() says why). */
+size_t fn_workspace_bytes(const fn_config *cfg, int64_t B, int32_t op);
+
+/* log|psi| (FermiNet Model section) for B walkers.
+   theta: device, flat parameters.  x: device [B][N][3].
+   log_abs_psi: device [B] FP64 out.  sign: device [B] int8 out (+1, -1, or 0
+   on a node), may be NULL. */
+fn_status fn_log_psi(const fn_config *cfg, const void *theta, const double *x, int64_t B, double *log_abs_psi,
+                     int8_t *sign, void *ws, size_t ws_bytes, void *stream);
+
+/* Local energy of Eq. 2 with the kinetic term of Eq. 3 read as
+   -1/2 sum_c [(d log|psi| / dx_c)^2 + d^2 log|psi| / dx_c^2] over all 3N
+   electron coordinates, evaluated by a forward-mode Laplacian.
+   e_loc: device [B] FP64 out.  log_abs_psi: device [B] out or NULL.
+   parts: device [B][4] out (kinetic, el-el, nuc-el, nuc-nuc) or NULL. */
+fn_status fn_local_energy(const fn_config *cfg, const void *theta, const double *x, int64_t B, double *e_loc,
+                          double *log_abs_psi, double *parts, void *ws, size_t ws_bytes, void *stream);
+
+/* n_steps Metropolis-Hastings moves (Electron Sampler section): every
+   electron of a walker moves by sigma z, z ~ N(0, 1); the move is kept iff
+   log|psi'| is finite and log u <= 2 (log|psi'| - log|psi|), u ~ U(0, 1].
+   Random numbers: Philox4x32-10 keyed by `seed`, counter (d, walker,
+   low 32 bits of step0 + s, stream_id); normal deviate q of a walker takes
+   call d = q/2 (Box-Muller, cos for even q, sin for odd q, u1 from words
+   0-1, u2 from words 2-3), the accept uniform takes d = 0xFFFFFFFF words
+   0-1; a word pair (a, b) maps to ((a << 21 | b >> 11) + 1) 2^-53.
+   x: device [B][N][3] in/out.  log_abs_psi: device [B] in/out (must hold
+   log|psi| of the incoming x).  n_accept: device [B] int32, incremented per
+   accepted move, may be NULL. */
+fn_status vmc_metropolis_step(const fn_config *cfg, const void *theta, double *x, double *log_abs_psi, int64_t B,
+                              int32_t n_steps, double sigma, uint64_t seed, uint64_t step0, uint32_t stream_id,
+                              int32_t *n_accept, void *ws, size_t ws_bytes, void *stream);
+
+/* As vmc_metropolis_step with the random numbers supplied by the caller:
+   z: device [n_steps][B][3N] normal deviates, u: device [n_steps][B]
+   uniforms in (0, 1]. */
+fn_status vmc_metropolis_step_ext(const fn_config *cfg, const void *theta, double *x, double *log_abs_psi, int64_t B,
+                                  int32_t n_steps, double sigma, const double *z, const double *u, int32_t *n_accept,
+                                  void *ws, size_t ws_bytes, void *stream);
+
+/* Training gradient of Eq. 6 over the batch: with E the batch mean of e_loc,
+   grad = sum_p (2/B)(e_loc_p - E) d log|psi_p| / d theta.
+   e_loc: device [B] FP64.  grad: device [P] out (theta's type).
+   stats: device [3] FP64 out (mean, variance with 1/B, standard error
+   sqrt(var/B)), may be NULL. */
+fn_status fn_param_grad(const fn_config *cfg, const void *theta, const double *x, int64_t B, const double *e_loc,
+                        void *grad, double *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* grad = sum_p coeff_p d log|psi_p| / d theta.  coeff: device [B] FP64.
+   grad: device [P] out (theta's type). */
+fn_status fn_log_psi_vjp(const fn_config *cfg, const void *theta, const double *x, int64_t B, const double *coeff,
+                         void *grad, void *ws, size_t ws_bytes, void *stream);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *fn_last_error(void);
+
+/* Diagnostics: per-kernel timing.  While enabled, every launch of the
+   library's kernels is bracketed by two HIP events recorded on the launch
+   stream (creating events is the one allocation the library makes, and
+   only in this mode).  fn_timing_read waits for the recorded events and
+   returns, for the kernel class `name`, the summed duration in ms and the
+   number of launches since the last reset; names: "stream_gemm" (per-
+   electron stream-layer product), "walker_gemm" (per-walker mean-field
+   product), "head_gemm", "features", "pair_stream", "spin_mean",
+   "layer_epilogue", "envelope", "det", "combine", "pack", "propose",
+   "accept", "backward".  Not thread-safe with concurrent library calls. */
+fn_status fn_timing_enable(int32_t on);
+fn_status fn_timing_reset(void);
+fn_status fn_timing_read(const char *name, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FNVMC_H */

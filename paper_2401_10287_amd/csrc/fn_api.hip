@@ -1,0 +1,521 @@
+// fn_api.hip -- the C ABI of fnvmc.h: argument checks, workspace plan and
+// the host-side sequence of kernels for each entry point.
+//
+// Forward pass over a chunk of walkers (FermiNet Model section):
+//   features -> pair stream (all layers, spin means as dense rows)
+//   for each one-electron layer l:
+//       spin means g_up, g_dn of h^l                     (per walker)
+//       P = [g_up | g_dn] V_g                             (matrix product)
+//       X = [h_i | g_i_up | g_i_dn] V_h                   (matrix product)
+//       h^{l+1} = tanh(X + P + b) (+ h^l)                 (forward Laplacian)
+//   per spin: orbital head product, envelope x orbital (Eq. 4), slogdet
+//   per walker: FP64 determinant sum, kinetic term (Eq. 3), Coulomb (Eq. 2)
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fn_internal.h"
+#include "fn_kernels.h"
+
+using namespace fn;
+
+namespace {
+
+thread_local std::string g_err;
+
+fn_status fail(fn_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+// per-kernel timing (diagnostics)
+// ---------------------------------------------------------------------------
+enum KClass { K_STREAM_GEMM, K_WALKER_GEMM, K_HEAD_GEMM, K_FEATURES, K_PAIR, K_SPIN_MEAN, K_EPI, K_ENV, K_DET,
+              K_COMBINE, K_PACK, K_PROPOSE, K_ACCEPT, K_BACKWARD, K_NCLASS };
+const char *const kclass_names[K_NCLASS] = {"stream_gemm", "walker_gemm", "head_gemm", "features", "pair_stream",
+                                           "spin_mean", "layer_epilogue", "envelope", "det", "combine", "pack",
+                                           "propose", "accept", "backward"};
+struct TimeRec { int cls; hipEvent_t a, b; };
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimeRec> g_recs;
+std::vector<hipEvent_t> g_free_events;
+double g_tot_ms[K_NCLASS];
+int64_t g_tot_n[K_NCLASS];
+
+hipEvent_t take_event()
+{
+    if (!g_free_events.empty()) {
+        hipEvent_t e = g_free_events.back();
+        g_free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// brackets the launches inside its lifetime when timing is enabled
+struct Timed {
+    int cls;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    Timed(int c, hipStream_t s) : cls(c), st(s)
+    {
+        if (!g_timing) return;
+        std::lock_guard<std::mutex> lk(g_tmu);
+        a = take_event();
+        if (a) (void)hipEventRecord(a, st);
+    }
+    ~Timed()
+    {
+        if (!a) return;
+        std::lock_guard<std::mutex> lk(g_tmu);
+        hipEvent_t b = take_event();
+        if (!b) return;
+        (void)hipEventRecord(b, st);
+        g_recs.push_back({cls, a, b});
+    }
+};
+
+void drain_timing()
+{
+    for (auto &r : g_recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            g_tot_ms[r.cls] += ms;
+            g_tot_n[r.cls] += 1;
+        }
+        g_free_events.push_back(r.a);
+        g_free_events.push_back(r.b);
+    }
+    g_recs.clear();
+}
+
+struct Ctx {
+    Sys s;
+    ParamLayout P;
+    Widths W;
+    int prec;
+    bool f64;
+    size_t esz;      // bytes of the stream scalar (float or double)
+    int smode;       // stream products
+    int hmode;       // orbital head product
+    double vnn;
+};
+
+fn_status make_ctx(const fn_config *cfg, Ctx &c)
+{
+    if (!cfg) return fail(FN_EINVAL, "cfg is NULL");
+    if (cfg->n_nuc < 1 || cfg->n_nuc > FN_MAX_NUC) return fail(FN_EINVAL, "n_nuc out of range 1..32");
+    if (!cfg->nuc_xyz || !cfg->nuc_z) return fail(FN_EINVAL, "nuc_xyz / nuc_z is NULL");
+    if (cfg->n_up < 0 || cfg->n_down < 0 || cfg->n_up > FN_MAX_SPIN || cfg->n_down > FN_MAX_SPIN)
+        return fail(FN_EINVAL, "n_up / n_down out of range 0..16");
+    if (cfg->n_up + cfg->n_down < 1) return fail(FN_EINVAL, "no electrons");
+    if (cfg->n_layers < 1 || cfg->n_layers > FN_MAX_LAYERS) return fail(FN_EINVAL, "n_layers out of range 1..8");
+    if (cfg->w1 < 1 || cfg->w1 > FN_MAX_W1) return fail(FN_EINVAL, "w1 out of range 1..1024");
+    if (cfg->w2 < 1 || cfg->w2 > FN_MAX_W2) return fail(FN_EINVAL, "w2 out of range 1..64");
+    if (cfg->n_det < 1 || cfg->n_det > FN_MAX_DET) return fail(FN_EINVAL, "n_det out of range 1..32");
+    if (cfg->precision < FN_FP64 || cfg->precision > FN_BF16X6_MIXED) return fail(FN_EINVAL, "unknown precision");
+    Sys &s = c.s;
+    memset(&s, 0, sizeof(s));
+    s.M = cfg->n_nuc;
+    s.nu = cfg->n_up;
+    s.nd = cfg->n_down;
+    s.N = s.nu + s.nd;
+    s.L = cfg->n_layers;
+    s.w1 = cfg->w1;
+    s.w2 = cfg->w2;
+    s.K = cfg->n_det;
+    for (int m = 0; m < s.M; ++m) {
+        for (int a = 0; a < 3; ++a) {
+            s.R[m][a] = cfg->nuc_xyz[3 * m + a];
+            if (!isfinite(s.R[m][a])) return fail(FN_EINVAL, "non-finite nucleus position");
+        }
+        s.Z[m] = cfg->nuc_z[m];
+        if (!isfinite(s.Z[m])) return fail(FN_EINVAL, "non-finite nuclear charge");
+    }
+    c.P = make_layout(s);
+    c.W = make_widths(s);
+    c.prec = cfg->precision;
+    c.f64 = c.prec == FN_FP64;
+    c.esz = c.f64 ? 8 : 4;
+    c.smode = c.f64 ? GEMM_F64
+                    : (c.prec == FN_FP32 ? GEMM_F32
+                                         : (c.prec == FN_BF16_MIXED ? GEMM_BF16
+                                                                    : (c.prec == FN_BF16X3_MIXED ? GEMM_BF16X3 : GEMM_BF16X6)));
+    c.hmode = c.f64 ? GEMM_F64 : GEMM_F32;
+    double vnn = 0.0;
+    for (int m = 0; m < s.M; ++m)
+        for (int q = m + 1; q < s.M; ++q) {
+            double d0 = s.R[m][0] - s.R[q][0], d1 = s.R[m][1] - s.R[q][1], d2 = s.R[m][2] - s.R[q][2];
+            vnn += s.Z[m] * s.Z[q] / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        }
+    c.vnn = vnn;
+    return FN_OK;
+}
+
+size_t gemm_elem(int mode) { return mode == GEMM_F64 ? 8 : (mode == GEMM_F32 ? 4 : 2); }
+
+constexpr size_t ALIGN = 256;
+size_t al(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Byte offsets of every buffer in the caller's workspace.
+struct Plan {
+    bool fl;
+    int TR, rec;
+    int64_t Bc;
+    size_t wx[FN_MAX_LAYERS], wg[FN_MAX_LAYERS], wh[2];
+    int64_t wxpart[FN_MAX_LAYERS], wgpart[FN_MAX_LAYERS];   // elements per BF16 part
+    size_t H[2], GI, G, Pw, X, O, Phi[2], DR, xp, lpn, u;
+    int64_t gi_layer_stride;   // elements
+    size_t total;
+};
+
+constexpr size_t CHUNK_BYTES = (size_t)4 << 30;
+
+fn_status make_plan(const Ctx &c, int64_t B, int op, Plan &p)
+{
+    const Sys &s = c.s;
+    if (op < FN_OP_LOG_PSI || op > FN_OP_PARAM_GRAD) return fail(FN_EINVAL, "unknown op");
+    p.fl = op == FN_OP_LOCAL_ENERGY;
+    const int n3 = 3 * s.N;
+    p.TR = p.fl ? round_up(n3 + 2, 16) : 1;
+    p.rec = n3 + 3;
+    const int nmax = std::max(s.nu, s.nd);
+    if (pair_stream_lds(s, p.fl, c.esz) > 64 * 1024) return fail(FN_EUNSUPPORTED, "pair stream exceeds LDS");
+    if (det_lds(nmax, n3, p.fl, sizeof(double)) > 64 * 1024) return fail(FN_EUNSUPPORTED, "determinant exceeds LDS");
+    size_t o = 0;
+    const size_t se = gemm_elem(c.smode), he = gemm_elem(c.hmode);
+    const int np = gemm_parts(c.smode);
+    for (int l = 0; l < s.L; ++l) {
+        size_t nx = (size_t)s.w1 * (c.W.HWl[l] + c.W.GWl[l]), ng = (size_t)s.w1 * 2 * c.W.HWl[l];
+        p.wxpart[l] = (int64_t)nx;
+        p.wgpart[l] = (int64_t)ng;
+        p.wx[l] = o; o = al(o + nx * se * np);
+        p.wg[l] = o; o = al(o + ng * se * np);
+    }
+    for (int sp = 0; sp < 2; ++sp) {
+        int n = sp == 0 ? s.nu : s.nd;
+        size_t nh = (size_t)s.K * n * c.W.W1p;
+        p.wh[sp] = o; o = al(o + nh * he);
+    }
+    const size_t wbytes = o;
+    const size_t TR = p.TR, N = s.N, e = c.esz;
+    const size_t per_walker = 2 * N * TR * c.W.HWmax * e + s.L * N * TR * c.W.GWmax * e + TR * 2 * c.W.HWmax * e +
+                              TR * s.w1 * e + N * TR * s.w1 * e + nmax * TR * std::max(c.W.KNp[0], c.W.KNp[1]) * e +
+                              ((size_t)s.K * TR * (s.nu * s.nu + s.nd * s.nd)) * 8 + 2 * s.K * p.rec * 8 +
+                              (n3 + 2) * 8 + 16 * ALIGN / 64;
+    int64_t bc = (int64_t)(CHUNK_BYTES / per_walker);
+    if (bc < 64) bc = 64;
+    if (bc >= B) bc = B;
+    else bc = bc / 64 * 64;
+    if (bc < 1) bc = 1;
+    p.Bc = bc;
+    const size_t rows = (size_t)bc * N * TR;
+    p.H[0] = o; o = al(o + rows * c.W.HWmax * e);
+    p.H[1] = o; o = al(o + rows * c.W.HWmax * e);
+    p.gi_layer_stride = (int64_t)(rows * c.W.GWmax);
+    p.GI = o; o = al(o + (size_t)s.L * rows * c.W.GWmax * e);
+    p.G = o; o = al(o + (size_t)bc * TR * 2 * c.W.HWmax * e);
+    p.Pw = o; o = al(o + (size_t)bc * TR * s.w1 * e);
+    p.X = o; o = al(o + rows * s.w1 * e);
+    p.O = o; o = al(o + (size_t)bc * nmax * TR * std::max(c.W.KNp[0], c.W.KNp[1]) * e);
+    p.Phi[0] = o; o = al(o + (size_t)bc * s.K * TR * s.nu * s.nu * 8);
+    p.Phi[1] = o; o = al(o + (size_t)bc * s.K * TR * s.nd * s.nd * 8);
+    p.DR = o; o = al(o + (size_t)bc * 2 * s.K * p.rec * 8);
+    p.xp = o; o = al(o + (size_t)B * n3 * 8);
+    p.lpn = o; o = al(o + (size_t)B * 8);
+    p.u = o; o = al(o + (size_t)B * 8);
+    p.total = o;
+    (void)wbytes;
+    return FN_OK;
+}
+
+template <typename T>
+void pack_weights(const Ctx &c, const Plan &p, const T *theta, char *ws, hipStream_t st)
+{
+    Timed t_(K_PACK, st);
+    const Sys &s = c.s;
+    for (int l = 0; l < s.L; ++l)
+        launch_pack_layer<T>(theta, c.P.V[l], layer_dh(s, l), layer_dp(s, l), s.w1, c.W.HWl[l], c.W.GWl[l], c.smode,
+                             ws + p.wx[l], ws + p.wg[l], st);
+    for (int sp = 0; sp < 2; ++sp) {
+        int n = sp == 0 ? s.nu : s.nd;
+        if (n == 0) continue;
+        launch_pack_head<T>(theta, c.P.w[sp], s.w1, c.W.W1p, s.K * n, c.hmode, ws + p.wh[sp], st);
+    }
+}
+
+// Forward pass over walkers [0, B) of x, chunk by chunk.  Weights are packed.
+template <typename T>
+void forward(const Ctx &c, const Plan &p, const T *theta, const double *x, int64_t B, double *log_abs, int8_t *sign,
+             double *e_loc, double *parts, char *ws, hipStream_t st)
+{
+    const Sys &s = c.s;
+    const int TR = p.TR, n3 = 3 * s.N;
+    const bool fl = p.fl;
+    T *H[2] = {(T *)(ws + p.H[0]), (T *)(ws + p.H[1])};
+    T *GI = (T *)(ws + p.GI);
+    T *G = (T *)(ws + p.G);
+    T *Pw = (T *)(ws + p.Pw);
+    T *X = (T *)(ws + p.X);
+    T *O = (T *)(ws + p.O);
+    double *DR = (double *)(ws + p.DR);
+    const int64_t ldh = c.W.HWmax, ldg = c.W.GWmax;
+    for (int64_t w0 = 0; w0 < B; w0 += p.Bc) {
+        const int64_t b = std::min(p.Bc, B - w0);
+        const double *xw = x + w0 * n3;
+        { Timed t_(K_FEATURES, st); launch_features<T>(s, xw, b, TR, c.W.HWl[0], ldh, H[0], st); }
+        {
+            Timed t_(K_PAIR, st);
+            launch_pair_stream<T>(s, xw, theta, c.P, b, TR, fl, ldg, p.gi_layer_stride, c.W.GWl[0],
+                                  s.L > 1 ? c.W.GWl[1] : c.W.GWl[0], GI, st);
+        }
+        int cur = 0;
+        for (int l = 0; l < s.L; ++l) {
+            const int dh = layer_dh(s, l), HWl = c.W.HWl[l], GWl = c.W.GWl[l];
+            { Timed t_(K_SPIN_MEAN, st); launch_spin_mean<T>(H[cur], ldh, b, s.N, s.nu, TR, dh, HWl, G, st); }
+            GemmArgs ga{};
+            ga.A1 = G; ga.lda1 = 2 * HWl; ga.K1 = 2 * HWl;
+            ga.A2 = nullptr; ga.lda2 = 0; ga.K2 = 0;
+            ga.W = ws + p.wg[l]; ga.wpart = p.wgpart[l]; ga.ldw = 2 * HWl;
+            ga.C = Pw; ga.ldc = s.w1;
+            ga.rows = b * TR; ga.nout = s.w1;
+            ga.rows_per_group = ga.rows; ga.group_stride = 0; ga.row_offset = 0;
+            { Timed t_(K_WALKER_GEMM, st); (void)launch_gemm(c.smode, ga, st); }
+            GemmArgs gx{};
+            gx.A1 = H[cur]; gx.lda1 = ldh; gx.K1 = HWl;
+            gx.A2 = GI + (int64_t)l * p.gi_layer_stride; gx.lda2 = ldg; gx.K2 = GWl;
+            gx.W = ws + p.wx[l]; gx.wpart = p.wxpart[l]; gx.ldw = HWl + GWl;
+            gx.C = X; gx.ldc = s.w1;
+            gx.rows = b * s.N * TR; gx.nout = s.w1;
+            gx.rows_per_group = gx.rows; gx.group_stride = 0; gx.row_offset = 0;
+            { Timed t_(K_STREAM_GEMM, st); (void)launch_gemm(c.smode, gx, st); }
+            {
+                Timed t_(K_EPI, st);
+                launch_layer_epi<T>(X, Pw, theta + c.P.b[l], H[cur], H[cur ^ 1], ldh, b, s.N, TR, n3, s.w1, c.W.W1p,
+                                    l >= 1 ? 1 : 0, fl, st);
+            }
+            cur ^= 1;
+        }
+        for (int sp = 0; sp < 2; ++sp) {
+            const int n = sp == 0 ? s.nu : s.nd, j0 = sp == 0 ? 0 : s.nu;
+            if (n == 0) continue;
+            GemmArgs gh{};
+            gh.A1 = H[cur]; gh.lda1 = ldh; gh.K1 = c.W.W1p;
+            gh.A2 = nullptr; gh.K2 = 0;
+            gh.W = ws + p.wh[sp]; gh.wpart = 0; gh.ldw = c.W.W1p;
+            gh.C = O; gh.ldc = c.W.KNp[sp];
+            gh.rows = b * n * TR; gh.nout = s.K * n;
+            gh.rows_per_group = (int64_t)n * TR; gh.group_stride = (int64_t)s.N * TR; gh.row_offset = (int64_t)j0 * TR;
+            { Timed t_(K_HEAD_GEMM, st); (void)launch_gemm(c.hmode, gh, st); }
+            double *Phi = (double *)(ws + p.Phi[sp]);
+            {
+                Timed t_(K_ENV, st);
+                launch_envelope<T>(s, xw, theta, c.P.g[sp], c.P.pi[sp], c.P.sig[sp], sp, O, c.W.KNp[sp], b, TR, fl,
+                                   Phi, st);
+            }
+            { Timed t_(K_DET, st); launch_det(Phi, b, s.K, n, TR, n3, sp, fl, DR, p.rec, st); }
+        }
+        Timed t_(K_COMBINE, st);
+        launch_combine(s, xw, DR, p.rec, b, c.vnn, log_abs ? log_abs + w0 : nullptr, sign ? sign + w0 : nullptr,
+                       e_loc ? e_loc + w0 : nullptr, parts ? parts + 4 * w0 : nullptr, fl, st);
+    }
+}
+
+fn_status check_ws(const Plan &p, void *ws, size_t ws_bytes)
+{
+    if (!ws) return fail(FN_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws) % ALIGN) return fail(FN_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < p.total)
+        return fail(FN_ENOMEM, "workspace too small: need " + std::to_string(p.total) + " bytes, got " +
+                                   std::to_string(ws_bytes));
+    return FN_OK;
+}
+
+fn_status hip_status()
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(FN_EHIP, std::string("HIP error: ") + hipGetErrorString(e));
+    return FN_OK;
+}
+
+template <typename T>
+fn_status run_forward(const Ctx &c, const Plan &p, const void *theta, const double *x, int64_t B, double *log_abs,
+                      int8_t *sign, double *e_loc, double *parts, void *ws, hipStream_t st)
+{
+    pack_weights<T>(c, p, (const T *)theta, (char *)ws, st);
+    forward<T>(c, p, (const T *)theta, x, B, log_abs, sign, e_loc, parts, (char *)ws, st);
+    return hip_status();
+}
+
+template <typename T>
+fn_status run_metropolis(const Ctx &c, const Plan &p, const void *theta, double *x, double *log_abs, int64_t B,
+                         int32_t n_steps, double sigma, uint64_t seed, uint64_t step0, uint32_t stream_id,
+                         const double *z, const double *u, int32_t *n_accept, void *ws, hipStream_t st)
+{
+    char *w = (char *)ws;
+    const int n3 = 3 * c.s.N;
+    pack_weights<T>(c, p, (const T *)theta, w, st);
+    double *xp = (double *)(w + p.xp), *lpn = (double *)(w + p.lpn), *uu = (double *)(w + p.u);
+    for (int32_t k = 0; k < n_steps; ++k) {
+        {
+            Timed t_(K_PROPOSE, st);
+            launch_propose(x, B, n3, sigma, seed, step0 + (uint64_t)k, stream_id,
+                           z ? z + (int64_t)k * B * n3 : nullptr, u ? u + (int64_t)k * B : nullptr, xp, uu, st);
+        }
+        forward<T>(c, p, (const T *)theta, xp, B, lpn, nullptr, nullptr, nullptr, w, st);
+        { Timed t_(K_ACCEPT, st); launch_accept(x, log_abs, xp, lpn, uu, B, n3, n_accept, st); }
+    }
+    return hip_status();
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t fn_param_count(const fn_config *cfg)
+{
+    Ctx c;
+    if (make_ctx(cfg, c) != FN_OK) return -1;
+    return c.P.total;
+}
+
+size_t fn_workspace_bytes(const fn_config *cfg, int64_t B, int32_t op)
+{
+    Ctx c;
+    if (make_ctx(cfg, c) != FN_OK) return 0;
+    if (B < 0) { fail(FN_EINVAL, "B < 0"); return 0; }
+    Plan p;
+    if (make_plan(c, B, op, p) != FN_OK) return 0;
+    return p.total;
+}
+
+fn_status fn_log_psi(const fn_config *cfg, const void *theta, const double *x, int64_t B, double *log_abs_psi,
+                     int8_t *sign, void *ws, size_t ws_bytes, void *stream)
+{
+    Ctx c;
+    fn_status r = make_ctx(cfg, c);
+    if (r) return r;
+    if (B < 0) return fail(FN_EINVAL, "B < 0");
+    if (B == 0) return FN_OK;
+    if (!theta || !x || !log_abs_psi) return fail(FN_EINVAL, "theta, x or log_abs_psi is NULL");
+    Plan p;
+    if ((r = make_plan(c, B, FN_OP_LOG_PSI, p))) return r;
+    if ((r = check_ws(p, ws, ws_bytes))) return r;
+    hipStream_t st = (hipStream_t)stream;
+    return c.f64 ? run_forward<double>(c, p, theta, x, B, log_abs_psi, sign, nullptr, nullptr, ws, st)
+                 : run_forward<float>(c, p, theta, x, B, log_abs_psi, sign, nullptr, nullptr, ws, st);
+}
+
+fn_status fn_local_energy(const fn_config *cfg, const void *theta, const double *x, int64_t B, double *e_loc,
+                          double *log_abs_psi, double *parts, void *ws, size_t ws_bytes, void *stream)
+{
+    Ctx c;
+    fn_status r = make_ctx(cfg, c);
+    if (r) return r;
+    if (B < 0) return fail(FN_EINVAL, "B < 0");
+    if (B == 0) return FN_OK;
+    if (!theta || !x || !e_loc) return fail(FN_EINVAL, "theta, x or e_loc is NULL");
+    Plan p;
+    if ((r = make_plan(c, B, FN_OP_LOCAL_ENERGY, p))) return r;
+    if ((r = check_ws(p, ws, ws_bytes))) return r;
+    hipStream_t st = (hipStream_t)stream;
+    return c.f64 ? run_forward<double>(c, p, theta, x, B, log_abs_psi, nullptr, e_loc, parts, ws, st)
+                 : run_forward<float>(c, p, theta, x, B, log_abs_psi, nullptr, e_loc, parts, ws, st);
+}
+
+static fn_status metropolis_common(const fn_config *cfg, const void *theta, double *x, double *log_abs_psi, int64_t B,
+                                   int32_t n_steps, double sigma, uint64_t seed, uint64_t step0, uint32_t stream_id,
+                                   const double *z, const double *u, int32_t *n_accept, void *ws, size_t ws_bytes,
+                                   void *stream)
+{
+    Ctx c;
+    fn_status r = make_ctx(cfg, c);
+    if (r) return r;
+    if (B < 0) return fail(FN_EINVAL, "B < 0");
+    if (n_steps < 0) return fail(FN_EINVAL, "n_steps < 0");
+    if (!(sigma >= 0.0) || !isfinite(sigma)) return fail(FN_EINVAL, "sigma must be finite and >= 0");
+    if (B == 0 || n_steps == 0) return FN_OK;
+    if (!theta || !x || !log_abs_psi) return fail(FN_EINVAL, "theta, x or log_abs_psi is NULL");
+    Plan p;
+    if ((r = make_plan(c, B, FN_OP_METROPOLIS, p))) return r;
+    if ((r = check_ws(p, ws, ws_bytes))) return r;
+    hipStream_t st = (hipStream_t)stream;
+    return c.f64 ? run_metropolis<double>(c, p, theta, x, log_abs_psi, B, n_steps, sigma, seed, step0, stream_id, z, u,
+                                          n_accept, ws, st)
+                 : run_metropolis<float>(c, p, theta, x, log_abs_psi, B, n_steps, sigma, seed, step0, stream_id, z, u,
+                                         n_accept, ws, st);
+}
+
+fn_status vmc_metropolis_step(const fn_config *cfg, const void *theta, double *x, double *log_abs_psi, int64_t B,
+                              int32_t n_steps, double sigma, uint64_t seed, uint64_t step0, uint32_t stream_id,
+                              int32_t *n_accept, void *ws, size_t ws_bytes, void *stream)
+{
+    return metropolis_common(cfg, theta, x, log_abs_psi, B, n_steps, sigma, seed, step0, stream_id, nullptr, nullptr,
+                             n_accept, ws, ws_bytes, stream);
+}
+
+fn_status vmc_metropolis_step_ext(const fn_config *cfg, const void *theta, double *x, double *log_abs_psi, int64_t B,
+                                  int32_t n_steps, double sigma, const double *z, const double *u, int32_t *n_accept,
+                                  void *ws, size_t ws_bytes, void *stream)
+{
+    if (!z || !u) return fail(FN_EINVAL, "z or u is NULL");
+    return metropolis_common(cfg, theta, x, log_abs_psi, B, n_steps, sigma, 0, 0, 0, z, u, n_accept, ws, ws_bytes,
+                             stream);
+}
+
+fn_status fn_param_grad(const fn_config *cfg, const void *theta, const double *x, int64_t B, const double *e_loc,
+                        void *grad, double *stats, void *ws, size_t ws_bytes, void *stream)
+{
+    (void)cfg; (void)theta; (void)x; (void)B; (void)e_loc; (void)grad; (void)stats; (void)ws; (void)ws_bytes;
+    (void)stream;
+    return fail(FN_EUNSUPPORTED, "fn_param_grad is not built yet");
+}
+
+fn_status fn_log_psi_vjp(const fn_config *cfg, const void *theta, const double *x, int64_t B, const double *coeff,
+                         void *grad, void *ws, size_t ws_bytes, void *stream)
+{
+    (void)cfg; (void)theta; (void)x; (void)B; (void)coeff; (void)grad; (void)ws; (void)ws_bytes; (void)stream;
+    return fail(FN_EUNSUPPORTED, "fn_log_psi_vjp is not built yet");
+}
+
+const char *fn_last_error(void) { return g_err.c_str(); }
+
+fn_status fn_timing_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing = on != 0;
+    return FN_OK;
+}
+
+fn_status fn_timing_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    drain_timing();
+    for (int k = 0; k < K_NCLASS; ++k) { g_tot_ms[k] = 0.0; g_tot_n[k] = 0; }
+    return FN_OK;
+}
+
+fn_status fn_timing_read(const char *name, double *total_ms, int64_t *launches)
+{
+    if (!name || !total_ms || !launches) return fail(FN_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(g_tmu);
+    drain_timing();
+    for (int k = 0; k < K_NCLASS; ++k)
+        if (strcmp(name, kclass_names[k]) == 0) {
+            *total_ms = g_tot_ms[k];
+            *launches = g_tot_n[k];
+            return FN_OK;
+        }
+    return fail(FN_EINVAL, std::string("unknown kernel class ") + name);
+}
+
+}  // extern "C"

@@ -1,0 +1,308 @@
+// fn_gemm.hip -- matrix products of the stream layers and the orbital head.
+//
+// C[r][o] = sum_k [A1 | A2][r][k] W[o][k]: the dense contraction of every
+// one-electron layer (its per-electron part and its per-walker mean-field
+// part) and of the orbital head, over forward-Laplacian rows (value, 3N
+// tangents, Laplacian) of all walkers at once.
+//
+// gfx950 matrix cores: one 256-thread workgroup owns a 128 x 128 output tile;
+// each of its four wave64s owns a 64 x 64 quarter as 4 x 4 blocks of 16 x 16
+// accumulators.  Operand tiles of 32 reduction steps are staged through LDS
+// (the A tile converted from FP32 to the product's operand type on the way in)
+// and the next tile's global loads are issued before the current tile's
+// matrix instructions.
+//   GEMM_F32    v_mfma_f32_16x16x4_f32, FP32 operands
+//   GEMM_BF16   v_mfma_f32_16x16x32_bf16, BF16 operands (round to nearest even)
+//   GEMM_BF16X3 x = hi + lo split of each FP32 operand, hi*hi + hi*lo + lo*hi
+//   GEMM_BF16X6 x = hi + mid + lo split, the six products whose part indices
+//               sum to at most 2 (FP32-level operand precision)
+//   GEMM_F64    FP64 on the vector ALUs (64 x 64 tiles)
+#include "fn_internal.h"
+
+namespace fn {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ inline uint32_t bf16_rne_bits(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;   // keep NaN a NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+constexpr int BM = 128, BN = 128, BK = 32;
+constexpr int LDH = BK + 8;   // LDS row stride of BF16 tiles (80 bytes)
+constexpr int LDF = BK + 4;   // LDS row stride of FP32 tiles (144 bytes)
+
+template <int MODE>
+struct ModeInfo {
+    static constexpr bool F32 = MODE == GEMM_F32;
+    static constexpr int NP = MODE == GEMM_BF16 ? 1 : (MODE == GEMM_BF16X3 ? 2 : (MODE == GEMM_BF16X6 ? 3 : 1));
+};
+
+// split x into NP BF16 parts x = p0 + p1 + ... (each the rounding of the rest)
+template <int NP>
+__device__ inline void split_bf16(float x, uint32_t (&h)[NP])
+{
+    float r = x;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        h[q] = bf16_rne_bits(r);
+        r = r - __uint_as_float(h[q] << 16);
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
+{
+    constexpr bool F32 = ModeInfo<MODE>::F32;
+    constexpr int NP = ModeInfo<MODE>::NP;
+    __shared__ __attribute__((aligned(16))) float sAf[F32 ? BM * LDF : 1];
+    __shared__ __attribute__((aligned(16))) float sBf[F32 ? BN * LDF : 1];
+    __shared__ __attribute__((aligned(16))) uint16_t sAh[F32 ? 8 : NP * BM * LDH];
+    __shared__ __attribute__((aligned(16))) uint16_t sBh[F32 ? 8 : NP * BN * LDH];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t m0 = (int64_t)blockIdx.x * BM;
+    const int n0 = blockIdx.y * BN;
+    const int ktiles = (a.K1 + a.K2) / BK;
+
+    // A rows loaded by this thread: 4 float4 per tile, row = f >> 3, k4 = f & 7
+    int64_t arow[4];
+    bool aval[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        int f = tid + 256 * v;
+        int64_t r = m0 + (f >> 3);
+        aval[v] = r < a.rows;
+        int64_t g = r / a.rows_per_group, q = r - g * a.rows_per_group;
+        arow[v] = g * a.group_stride + a.row_offset + q;
+    }
+    const float *A1 = (const float *)a.A1;
+    const float *A2 = (const float *)a.A2;
+
+    float4 ra[4];
+    uint4 rwh[F32 ? 1 : 2 * NP];
+    float4 rwf[F32 ? 4 : 1];
+
+    auto load_tile = [&](int kt) {
+        const int kb = kt * BK;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int f = tid + 256 * v;
+            int k = kb + 4 * (f & 7);
+            float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (aval[v]) {
+                const float *p = k < a.K1 ? A1 + arow[v] * a.lda1 + k : A2 + arow[v] * a.lda2 + (k - a.K1);
+                val = *(const float4 *)p;
+            }
+            ra[v] = val;
+        }
+        if constexpr (F32) {
+            const float *W = (const float *)a.W;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int f = tid + 256 * v;
+                int o = n0 + (f >> 3);
+                rwf[v] = o < a.nout ? *(const float4 *)(W + (int64_t)o * a.ldw + kb + 4 * (f & 7))
+                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        } else {
+            // the NP weight parts are stored one after another, part stride a.wpart elements
+            const uint16_t *W = (const uint16_t *)a.W;
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+#pragma unroll
+                for (int v = 0; v < 2; ++v) {
+                    int f = tid + 256 * v;
+                    int o = n0 + (f >> 2);
+                    int64_t off = (int64_t)q * a.wpart + (int64_t)o * a.ldw + kb + 8 * (f & 3);
+                    rwh[q * 2 + v] = o < a.nout ? *(const uint4 *)(W + off) : make_uint4(0, 0, 0, 0);
+                }
+        }
+    };
+
+    auto store_tile = [&]() {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int f = tid + 256 * v;
+            int r = f >> 3, k = 4 * (f & 7);
+            float4 x = ra[v];
+            if constexpr (F32) {
+                *(float4 *)&sAf[r * LDF + k] = x;
+            } else {
+                uint32_t h0[NP], h1[NP], h2[NP], h3[NP];
+                split_bf16<NP>(x.x, h0);
+                split_bf16<NP>(x.y, h1);
+                split_bf16<NP>(x.z, h2);
+                split_bf16<NP>(x.w, h3);
+#pragma unroll
+                for (int q = 0; q < NP; ++q)
+                    *(uint2 *)&sAh[q * BM * LDH + r * LDH + k] =
+                        make_uint2(h0[q] | (h1[q] << 16), h2[q] | (h3[q] << 16));
+            }
+        }
+        if constexpr (F32) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int f = tid + 256 * v;
+                *(float4 *)&sBf[(f >> 3) * LDF + 4 * (f & 7)] = rwf[v];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+#pragma unroll
+                for (int v = 0; v < 2; ++v) {
+                    int f = tid + 256 * v;
+                    *(uint4 *)&sBh[q * BN * LDH + (f >> 2) * LDH + 8 * (f & 3)] = rwh[q * 2 + v];
+                }
+        }
+    };
+
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    if (ktiles > 0) load_tile(0);
+    for (int kt = 0; kt < ktiles; ++kt) {
+        __syncthreads();
+        store_tile();
+        __syncthreads();
+        if (kt + 1 < ktiles) load_tile(kt + 1);
+        const int ar = wm * 64 + (lane & 15), br = wn * 64 + (lane & 15);
+        if constexpr (F32) {
+#pragma unroll
+            for (int kk = 0; kk < BK / 4; ++kk) {
+                float fa[4], fb[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) fa[i] = sAf[(ar + 16 * i) * LDF + 4 * kk + (lane >> 4)];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) fb[j] = sBf[(br + 16 * j) * LDF + 4 * kk + (lane >> 4)];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
+            }
+        } else {
+            const int ko = 8 * (lane >> 4);
+            // products of parts (pa, pb) with pa + pb < NP, smallest first
+#pragma unroll
+            for (int sum = NP - 1; sum >= 0; --sum) {
+#pragma unroll
+                for (int pa = 0; pa <= sum; ++pa) {
+                    const int pb = sum - pa;
+                    bf16x8 ha[4], hb[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) ha[i] = *(const bf16x8 *)&sAh[pa * BM * LDH + (ar + 16 * i) * LDH + ko];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) hb[j] = *(const bf16x8 *)&sBh[pb * BN * LDH + (br + 16 * j) * LDH + ko];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[i], hb[j], acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+    }
+
+    // accumulator (i, j) element e sits at row 16 i + 4 (lane >> 4) + e, column 16 j + (lane & 15)
+    float *C = (float *)a.C;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int col = n0 + wn * 64 + 16 * j + (lane & 15);
+            if (col >= a.nout) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                int64_t row = m0 + wm * 64 + 16 * i + 4 * (lane >> 4) + e;
+                if (row < a.rows) C[row * a.ldc + col] = acc[i][j][e];
+            }
+        }
+}
+
+// FP64 on the vector ALUs: 64 x 64 tiles, 16-step reduction tiles, 4 x 4
+// outputs per thread.
+__global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs a)
+{
+    __shared__ double sA[16][64 + 1];
+    __shared__ double sB[16][64 + 1];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int64_t m0 = (int64_t)blockIdx.x * 64;
+    const int n0 = blockIdx.y * 64;
+    const double *A1 = (const double *)a.A1, *A2 = (const double *)a.A2, *W = (const double *)a.W;
+    int64_t arow[4];
+    bool aval[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        int f = tid + 256 * v;
+        int64_t r = m0 + (f >> 4);
+        aval[v] = r < a.rows;
+        int64_t g = r / a.rows_per_group, q = r - g * a.rows_per_group;
+        arow[v] = g * a.group_stride + a.row_offset + q;
+    }
+    double acc[4][4] = {};
+    const int K = a.K1 + a.K2;
+    for (int kb = 0; kb < K; kb += 16) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int f = tid + 256 * v;
+            int r = f >> 4, kk = f & 15, k = kb + kk;
+            double x = 0.0;
+            if (aval[v]) x = k < a.K1 ? A1[arow[v] * a.lda1 + k] : A2[arow[v] * a.lda2 + (k - a.K1)];
+            sA[kk][r] = x;
+            int o = n0 + r;
+            sB[kk][r] = o < a.nout ? W[(int64_t)o * a.ldw + k] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = sA[kk][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = sB[kk][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+    double *C = (double *)a.C;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int64_t row = m0 + ty * 4 + i;
+        if (row >= a.rows) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int col = n0 + tx * 4 + j;
+            if (col < a.nout) C[row * a.ldc + col] = acc[i][j];
+        }
+    }
+}
+
+hipError_t launch_gemm(int mode, const GemmArgs &a, hipStream_t st)
+{
+    if (a.rows <= 0 || a.nout <= 0) return hipSuccess;
+    if (mode == GEMM_F64) {
+        dim3 grid((unsigned)((a.rows + 63) / 64), (unsigned)((a.nout + 63) / 64));
+        hipLaunchKernelGGL(k_gemm_f64, grid, dim3(256), 0, st, a);
+    } else {
+        dim3 grid((unsigned)((a.rows + BM - 1) / BM), (unsigned)((a.nout + BN - 1) / BN));
+        if (mode == GEMM_F32) hipLaunchKernelGGL(k_gemm_mfma<GEMM_F32>, grid, dim3(256), 0, st, a);
+        else if (mode == GEMM_BF16) hipLaunchKernelGGL(k_gemm_mfma<GEMM_BF16>, grid, dim3(256), 0, st, a);
+        else if (mode == GEMM_BF16X3) hipLaunchKernelGGL(k_gemm_mfma<GEMM_BF16X3>, grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL(k_gemm_mfma<GEMM_BF16X6>, grid, dim3(256), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fn

@@ -1,0 +1,110 @@
+// fn_internal.h -- shared definitions of the gfx950 HIP implementation.
+//
+// Row layout of every stream activation ("forward-Laplacian rows"): each
+// electron of each walker owns TR consecutive rows of a row-major matrix.
+//   row 0             value
+//   row 1 + c         d/dx_c, c = 3 e + a over all 3N electron coordinates
+//   row 3N + 1        Laplacian (sum over all 3N coordinates)
+//   rows 3N+2..TR-1   zero padding (TR is a multiple of 16)
+// In value-only mode (Metropolis, gradient) TR = 1.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fnvmc.h"
+
+namespace fn {
+
+// System and network sizes, passed to kernels by value.
+struct Sys {
+    int M, N, nu, nd, L, w1, w2, K;
+    double R[FN_MAX_NUC][3];
+    double Z[FN_MAX_NUC];
+};
+
+inline __host__ __device__ int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// Offsets of the parameter tensors in the flat vector (same layout as the
+// header comment of fnvmc.h).
+struct ParamLayout {
+    int64_t V[FN_MAX_LAYERS], b[FN_MAX_LAYERS], W2[FN_MAX_LAYERS], c2[FN_MAX_LAYERS];
+    int64_t w[2], g[2], pi[2], sig[2];
+    int64_t total;
+};
+
+inline __host__ __device__ int layer_dh(const Sys &s, int l) { return l == 0 ? 4 * s.M : s.w1; }
+inline __host__ __device__ int layer_dp(const Sys &s, int l) { return l == 0 ? 4 : s.w2; }
+inline __host__ __device__ int layer_din(const Sys &s, int l) { return 3 * layer_dh(s, l) + 2 * layer_dp(s, l); }
+
+inline ParamLayout make_layout(const Sys &s)
+{
+    ParamLayout p{};
+    int64_t o = 0;
+    for (int l = 0; l < s.L; ++l) {
+        p.V[l] = o; o += (int64_t)layer_din(s, l) * s.w1;
+        p.b[l] = o; o += s.w1;
+    }
+    for (int l = 0; l + 1 < s.L; ++l) {
+        p.W2[l] = o; o += (int64_t)layer_dp(s, l) * s.w2;
+        p.c2[l] = o; o += s.w2;
+    }
+    for (int sp = 0; sp < 2; ++sp) {
+        int n = sp == 0 ? s.nu : s.nd;
+        if (n == 0) { p.w[sp] = p.g[sp] = p.pi[sp] = p.sig[sp] = -1; continue; }
+        int kn = s.K * n;
+        p.w[sp] = o; o += (int64_t)s.w1 * kn;
+        p.g[sp] = o; o += kn;
+        p.pi[sp] = o; o += (int64_t)kn * s.M;
+        p.sig[sp] = o; o += (int64_t)kn * s.M * 9;
+    }
+    p.total = o;
+    return p;
+}
+
+// Matrix-product arithmetic.
+enum GemmMode { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16 = 2, GEMM_BF16X3 = 3, GEMM_BF16X6 = 4 };
+
+inline __host__ __device__ int gemm_parts(int mode) { return mode == GEMM_BF16 ? 1 : (mode == GEMM_BF16X3 ? 2 : (mode == GEMM_BF16X6 ? 3 : 1)); }
+
+// Padded widths.  Every product's reduction dimension is a multiple of 32.
+struct Widths {
+    int HWl[FN_MAX_LAYERS];   // padded width of the h_i block of layer l
+    int GWl[FN_MAX_LAYERS];   // padded width of [g_i_up | g_i_dn] of layer l
+    int HWmax, GWmax, W1p;    // buffer strides
+    int KNp[2];               // K n_s padded to 32 (head outputs)
+};
+
+inline Widths make_widths(const Sys &s)
+{
+    Widths w{};
+    w.HWmax = 0;
+    w.GWmax = 0;
+    for (int l = 0; l < s.L; ++l) {
+        w.HWl[l] = round_up(layer_dh(s, l), 32);
+        w.GWl[l] = round_up(2 * layer_dp(s, l), 32);
+        if (w.HWl[l] > w.HWmax) w.HWmax = w.HWl[l];
+        if (w.GWl[l] > w.GWmax) w.GWmax = w.GWl[l];
+    }
+    w.W1p = round_up(s.w1, 32);
+    if (w.W1p > w.HWmax) w.HWmax = w.W1p;
+    for (int sp = 0; sp < 2; ++sp) w.KNp[sp] = round_up(s.K * (sp == 0 ? s.nu : s.nd), 32);
+    return w;
+}
+
+// Arguments of one matrix product C[r][o] = sum_k A[r][k] W[o][k] where A is
+// the row-wise concatenation [A1 | A2] (A2 may be empty) and W is stored
+// transposed (o major, k contiguous) in the product's operand type.  Row r of
+// A and C: group g = r / rows_per_group, q = r % rows_per_group; A's row is
+// g * group_stride + row_offset + q, C's row is r.
+struct GemmArgs {
+    const void *A1; int64_t lda1; int K1;
+    const void *A2; int64_t lda2; int K2;
+    const void *W; int64_t wpart; int64_t ldw;   // BF16 modes: parts at W + q * wpart
+    void *C; int64_t ldc;
+    int64_t rows; int nout;
+    int64_t rows_per_group, group_stride, row_offset;
+};
+
+hipError_t launch_gemm(int mode, const GemmArgs &a, hipStream_t st);
+
+}  // namespace fn

@@ -1,0 +1,41 @@
+// fn_kernels.h -- launchers of the network kernels (fn_net.hip) and of the
+// Monte Carlo kernels (fn_mc.hip).
+#pragma once
+#include "fn_internal.h"
+
+namespace fn {
+
+template <typename T>
+void launch_pack_layer(const T *theta, int64_t voff, int dh, int dp, int w1, int HWl, int GWl, int mode, void *wx,
+                       void *wg, hipStream_t st);
+template <typename T>
+void launch_pack_head(const T *theta, int64_t woff, int w1, int W1p, int kn, int mode, void *wh, hipStream_t st);
+template <typename T>
+void launch_features(const Sys &s, const double *x, int64_t B, int TR, int HW0, int64_t ldh, T *H, hipStream_t st);
+size_t pair_stream_lds(const Sys &s, bool fl, size_t elem);
+template <typename T>
+void launch_pair_stream(const Sys &s, const double *x, const T *theta, const ParamLayout &P, int64_t B, int TR,
+                        bool fl, int64_t ldg, int64_t gi_layer_stride, int GW0, int GW1, T *GI, hipStream_t st);
+template <typename T>
+void launch_spin_mean(const T *H, int64_t ldh, int64_t B, int N, int nu, int TR, int dh, int HWl, T *G,
+                      hipStream_t st);
+template <typename T>
+void launch_layer_epi(const T *X, const T *Pw, const T *bias, const T *Hin, T *Hout, int64_t ldh, int64_t B, int N,
+                      int TR, int n3, int w1, int W1p, int resid, bool fl, hipStream_t st);
+template <typename T>
+void launch_envelope(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof, int sp,
+                     const T *O, int64_t ldo, int64_t B, int TR, bool fl, double *Phi, hipStream_t st);
+size_t det_lds(int n, int n3, bool fl, size_t elem);
+void launch_det(const double *Phi, int64_t B, int K, int n, int TR, int n3, int sp, bool fl, double *DR, int rec,
+                hipStream_t st);
+void launch_combine(const Sys &s, const double *x, const double *DR, int rec, int64_t B, double vnn, double *log_abs,
+                    int8_t *sign, double *e_loc, double *parts, bool fl, hipStream_t st);
+
+// Monte Carlo
+void launch_propose(const double *x, int64_t B, int n3, double sigma, uint64_t seed, uint64_t step, uint32_t stream_id,
+                    const double *z_ext, const double *u_ext, double *xp, double *u, hipStream_t st);
+void launch_accept(double *x, double *log_abs, const double *xp, const double *lp_new, const double *u, int64_t B,
+                   int n3, int32_t *n_accept, hipStream_t st);
+void launch_energy_stats(const double *e_loc, int64_t B, double *stats, double *coeff, hipStream_t st);
+
+}  // namespace fn

@@ -1,0 +1,157 @@
+// fn_mc.hip -- Metropolis-Hastings walker update (Electron Sampler section
+// of the paper) and the batch energy statistics of Eq. 1 and Eq. 6.
+//
+// Proposal: every electron of a walker moves by sigma z, z ~ N(0, 1); the
+// move is kept iff log|psi'| is finite and log u <= 2 (log|psi'| - log|psi|).
+// Random numbers come from Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)
+// with key (seed low, seed high) and counter (d, walker, step, stream_id);
+// normal deviates by the Box-Muller transform (1958).
+#include "fn_internal.h"
+#include "fn_kernels.h"
+
+namespace fn {
+
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// 53 random bits from two words, mapped to (0, 1]
+__device__ inline double word_pair_to_unit(uint32_t a, uint32_t b)
+{
+    const uint64_t m = ((uint64_t)a << 21) | (uint64_t)(b >> 11);
+    return (double)(m + 1) * 0x1.0p-53;
+}
+
+// one thread per (walker, d): d < ceil(3N/2) makes two normal deviates,
+// d == ceil(3N/2) makes the accept uniform.  x' = x + sigma z is rounded
+// as a product and then a sum (no fused multiply-add).
+__global__ void k_propose(const double *x, int64_t B, int n3, double sigma, uint32_t k0, uint32_t k1, uint32_t step,
+                          uint32_t stream_id, const double *z_ext, const double *u_ext, double *xp, double *u)
+{
+#pragma clang fp contract(off)
+    const int D = (n3 + 1) / 2;
+    const int64_t total = B * (D + 1);
+    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < total; id += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t w = id / (D + 1);
+        const int d = (int)(id % (D + 1));
+        if (d == D) {
+            if (u_ext) {
+                u[w] = u_ext[w];
+            } else {
+                uint32_t c[4] = {0xFFFFFFFFu, (uint32_t)w, step, stream_id};
+                philox4x32_10(c, k0, k1);
+                u[w] = word_pair_to_unit(c[0], c[1]);
+            }
+            continue;
+        }
+        double z0, z1;
+        if (z_ext) {
+            z0 = z_ext[w * n3 + 2 * d];
+            z1 = 2 * d + 1 < n3 ? z_ext[w * n3 + 2 * d + 1] : 0.0;
+        } else {
+            uint32_t c[4] = {(uint32_t)d, (uint32_t)w, step, stream_id};
+            philox4x32_10(c, k0, k1);
+            const double u1 = word_pair_to_unit(c[0], c[1]), u2 = word_pair_to_unit(c[2], c[3]);
+            const double rad = sqrt(-2.0 * log(u1));
+            const double ang = 2.0 * M_PI * u2;
+            z0 = rad * cos(ang);
+            z1 = rad * sin(ang);
+        }
+        const double s0 = sigma * z0;
+        xp[w * n3 + 2 * d] = x[w * n3 + 2 * d] + s0;
+        if (2 * d + 1 < n3) {
+            const double s1 = sigma * z1;
+            xp[w * n3 + 2 * d + 1] = x[w * n3 + 2 * d + 1] + s1;
+        }
+    }
+}
+
+__global__ void k_accept(double *x, double *log_abs, const double *xp, const double *lp_new, const double *u, int64_t B,
+                         int n3, int32_t *n_accept)
+{
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < B; w += (int64_t)gridDim.x * blockDim.x) {
+        const double ln = lp_new[w];
+        const double A = 2.0 * (ln - log_abs[w]);
+        if (isfinite(ln) && log(u[w]) <= A) {
+            for (int q = 0; q < n3; ++q) x[w * n3 + q] = xp[w * n3 + q];
+            log_abs[w] = ln;
+            if (n_accept) n_accept[w] += 1;
+        }
+    }
+}
+
+// FP64 batch statistics of the local energy (Eq. 1): mean, variance (1/B),
+// standard error; optional Eq. 6 coefficients c_p = 2 (E_p - mean) / B.
+__global__ __launch_bounds__(1024) void k_energy_stats(const double *e, int64_t B, double *stats, double *coeff)
+{
+    __shared__ double red[32];
+    __shared__ double s_mean;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double acc = 0.0;
+    for (int64_t p = tid; p < B; p += blockDim.x) acc += e[p];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) red[wv] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += red[q];
+        s_mean = t / (double)B;
+    }
+    __syncthreads();
+    const double mean = s_mean;
+    acc = 0.0;
+    for (int64_t p = tid; p < B; p += blockDim.x) {
+        const double d = e[p] - mean;
+        acc += d * d;
+        if (coeff) coeff[p] = 2.0 * d / (double)B;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    __syncthreads();
+    if (lane == 0) red[wv] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += red[q];
+        const double var = t / (double)B;
+        if (stats) { stats[0] = mean; stats[1] = var; stats[2] = sqrt(var / (double)B); }
+    }
+}
+
+static unsigned grid_of(int64_t n)
+{
+    int64_t g = (n + 255) / 256;
+    if (g > 1 << 20) g = 1 << 20;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+void launch_propose(const double *x, int64_t B, int n3, double sigma, uint64_t seed, uint64_t step, uint32_t stream_id,
+                    const double *z_ext, const double *u_ext, double *xp, double *u, hipStream_t st)
+{
+    const int64_t total = B * ((n3 + 1) / 2 + 1);
+    hipLaunchKernelGGL(k_propose, dim3(grid_of(total)), dim3(256), 0, st, x, B, n3, sigma, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), (uint32_t)step, stream_id, z_ext, u_ext, xp, u);
+}
+
+void launch_accept(double *x, double *log_abs, const double *xp, const double *lp_new, const double *u, int64_t B,
+                   int n3, int32_t *n_accept, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_accept, dim3(grid_of(B)), dim3(256), 0, st, x, log_abs, xp, lp_new, u, B, n3, n_accept);
+}
+
+void launch_energy_stats(const double *e_loc, int64_t B, double *stats, double *coeff, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_energy_stats, dim3(1), dim3(1024), 0, st, e_loc, B, stats, coeff);
+}
+
+}  // namespace fn

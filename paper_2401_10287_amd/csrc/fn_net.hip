@@ -1,0 +1,694 @@
+// fn_net.hip -- element-wise and per-walker kernels of the FermiNet forward
+// pass with a forward-mode Laplacian (FermiNet Model section of the paper;
+// the kinetic term of Eq. 3 needs the gradient and Laplacian of log|psi|
+// with respect to all 3N electron coordinates).
+//
+// Every quantity q carries rows (q, dq/dx_1 .. dq/dx_3N, Laplacian q).  Linear
+// maps act on all rows alike (they run as matrix products in fn_gemm.hip);
+// an element-wise f maps value a to f(a), tangent t to f'(a) t and Laplacian
+// l to f'(a) l + f''(a) sum_c t_c^2.
+#include "fn_internal.h"
+#include "fn_kernels.h"
+
+namespace fn {
+
+// ---------------------------------------------------------------------------
+// parameter packing into the transposed operand layouts of the products
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline void put_w(int mode, void *base, int64_t part, int64_t idx, T v)
+{
+    if (mode == GEMM_F64) {
+        ((double *)base)[idx] = (double)v;
+    } else if (mode == GEMM_F32) {
+        ((float *)base)[idx] = (float)v;
+    } else {
+        // BF16 parts, round to nearest even: v = p0 + p1 + ... (each rounds the rest)
+        const int np = gemm_parts(mode);
+        float r = (float)v;
+        for (int q = 0; q < np; ++q) {
+            uint32_t u = __float_as_uint(r);
+            uint32_t h = (u & 0x7fffffffu) > 0x7f800000u ? ((u >> 16) | 0x40u) : ((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+            ((uint16_t *)base)[q * part + idx] = (uint16_t)h;
+            r = r - __uint_as_float(h << 16);
+        }
+    }
+}
+
+// Wx [w1][HWl + GWl]: per-electron inputs [h_i | g_i_up | g_i_dn];
+// Wg [w1][2 HWl]: per-walker inputs [g_up | g_dn].
+template <typename T>
+__global__ void k_pack_layer(const T *theta, int64_t voff, int dh, int dp, int w1, int HWl, int GWl, int mode,
+                             void *wx, void *wg)
+{
+    const int64_t kx = HWl + GWl, kg = 2 * HWl;
+    const int64_t nx = (int64_t)w1 * kx, ng = (int64_t)w1 * kg;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nx + ng; t += (int64_t)gridDim.x * blockDim.x) {
+        if (t < nx) {
+            int o = (int)(t / kx), k = (int)(t % kx);
+            int row = -1;
+            if (k < dh) row = k;
+            else if (k >= HWl && k < HWl + 2 * dp) row = 3 * dh + (k - HWl);
+            T v = row >= 0 ? theta[voff + (int64_t)row * w1 + o] : T(0);
+            put_w<T>(mode, wx, nx, t, v);
+        } else {
+            int64_t u = t - nx;
+            int o = (int)(u / kg), k = (int)(u % kg);
+            int row = -1;
+            if (k < dh) row = dh + k;
+            else if (k >= HWl && k < HWl + dh) row = 2 * dh + (k - HWl);
+            T v = row >= 0 ? theta[voff + (int64_t)row * w1 + o] : T(0);
+            put_w<T>(mode, wg, ng, u, v);
+        }
+    }
+}
+
+// Wh [K n][W1p] from w [w1][K n]
+template <typename T>
+__global__ void k_pack_head(const T *theta, int64_t woff, int w1, int W1p, int kn, int mode, void *wh)
+{
+    const int64_t n = (int64_t)kn * W1p;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        int col = (int)(t / W1p), k = (int)(t % W1p);
+        T v = k < w1 ? theta[woff + (int64_t)k * kn + col] : T(0);
+        put_w<T>(mode, wh, n, t, v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// electron-nucleus input features [r_i - R_m, |r_i - R_m|] with their rows
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_features(Sys s, const double *x, int64_t B, int TR, int HW0, int64_t ldh, T *H)
+{
+    const int64_t total = B * s.N * TR;
+    const int n3 = 3 * s.N;
+    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < total; id += (int64_t)gridDim.x * blockDim.x) {
+        const int t = (int)(id % TR);
+        const int64_t wi = id / TR;
+        const int i = (int)(wi % s.N);
+        const double *xi = x + wi * 3;
+        T *h = H + id * ldh;
+        for (int k = 0; k < HW0; ++k) h[k] = T(0);
+        if (t > n3 + 1) continue;
+        for (int m = 0; m < s.M; ++m) {
+            double d0 = xi[0] - s.R[m][0], d1 = xi[1] - s.R[m][1], d2 = xi[2] - s.R[m][2];
+            double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            if (t == 0) {
+                h[4 * m + 0] = (T)d0; h[4 * m + 1] = (T)d1; h[4 * m + 2] = (T)d2; h[4 * m + 3] = (T)r;
+            } else if (t <= n3) {
+                int c = t - 1, e = c / 3, a = c % 3;
+                if (e == i) {
+                    h[4 * m + a] = T(1);
+                    double da = a == 0 ? d0 : (a == 1 ? d1 : d2);
+                    h[4 * m + 3] = (T)(da / r);
+                }
+            } else {
+                h[4 * m + 3] = (T)(2.0 / r);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// two-electron stream: one workgroup per (walker, electron i) runs the pairs
+// (i, j) through all pair layers and writes the spin means g_i_up, g_i_dn of
+// every layer as dense rows.  A pair feature depends on r_i and r_j only, so
+// a pair carries R = 8 rows: value, d/dr_i (3), d/dr_j (3), Laplacian.
+// ---------------------------------------------------------------------------
+template <typename T, bool FL>
+__device__ void write_pair_means(const Sys &s, const T *S, int wp, int dp, int i, int TR, int GWl, int64_t ldg, T *gi)
+{
+    constexpr int R = FL ? 8 : 1;
+    const int n3 = 3 * s.N;
+    const int rows = FL ? TR : 1;
+    for (int idx = threadIdx.x; idx < rows * GWl; idx += blockDim.x) {
+        const int t = idx / GWl, col = idx % GWl;
+        T v = T(0);
+        if (col < 2 * dp && t <= n3 + 1) {
+            const int sp = col / dp, o = col % dp;
+            const int n = sp == 0 ? s.nu : s.nd, j0 = sp == 0 ? 0 : s.nu;
+            if (n > 0) {
+                const T inv = T(1) / T(n);
+                if (t == 0 || t == n3 + 1) {
+                    const int r = t == 0 ? 0 : R - 1;
+                    T acc = T(0);
+                    for (int j = j0; j < j0 + n; ++j) acc += S[(j * R + r) * wp + o];
+                    v = acc * inv;
+                } else {
+                    const int c = t - 1, e = c / 3, a = c % 3;
+                    if (e == i) {
+                        T acc = T(0);
+                        for (int j = j0; j < j0 + n; ++j) acc += S[(j * R + 1 + a) * wp + o];
+                        v = acc * inv;
+                    } else if (e >= j0 && e < j0 + n) {
+                        v = S[(e * R + 4 + a) * wp + o] * inv;
+                    }
+                }
+            }
+        }
+        gi[(int64_t)t * ldg + col] = v;
+    }
+}
+
+template <typename T, bool FL>
+__global__ void k_pair_stream(Sys s, const double *x, const T *theta, ParamLayout P, int64_t B, int TR, int64_t ldg,
+                              int64_t gi_layer_stride, int GW0, int GW1, T *GI)
+{
+    constexpr int R = FL ? 8 : 1;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    const int wp = s.w2 > 4 ? s.w2 : 4;
+    T *S0 = (T *)smem_raw;
+    T *S1 = S0 + s.N * R * wp;
+    const int64_t wi = blockIdx.x;
+    const int64_t w = wi / s.N;
+    const int i = (int)(wi % s.N);
+    if (w >= B) return;
+    const double *xw = x + w * 3 * s.N;
+
+    // layer-0 pair features
+    for (int j = threadIdx.x; j < s.N; j += blockDim.x) {
+        T *p = S0 + j * R * wp;
+        for (int q = 0; q < R * wp; ++q) p[q] = T(0);
+        if (j == i) continue;
+        double d[3] = {xw[3 * i] - xw[3 * j], xw[3 * i + 1] - xw[3 * j + 1], xw[3 * i + 2] - xw[3 * j + 2]};
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        for (int a = 0; a < 3; ++a) p[a] = (T)d[a];
+        p[3] = (T)r;
+        if constexpr (FL) {
+            for (int a = 0; a < 3; ++a) {
+                p[(1 + a) * wp + a] = T(1);
+                p[(1 + a) * wp + 3] = (T)(d[a] / r);
+                p[(4 + a) * wp + a] = T(-1);
+                p[(4 + a) * wp + 3] = (T)(-d[a] / r);
+            }
+            p[7 * wp + 3] = (T)(4.0 / r);
+        }
+    }
+    __syncthreads();
+    const int rows = FL ? TR : 1;
+    write_pair_means<T, FL>(s, S0, wp, 4, i, TR, GW0, ldg, GI + wi * rows * ldg);
+    for (int l = 0; l + 1 < s.L; ++l) {
+        __syncthreads();
+        const int dp = l == 0 ? 4 : s.w2;
+        const T *W2 = theta + P.W2[l];
+        const T *c2 = theta + P.c2[l];
+        for (int idx = threadIdx.x; idx < s.N * s.w2; idx += blockDim.x) {
+            const int j = idx / s.w2, o = idx % s.w2;
+            const T *in = S0 + j * R * wp;
+            T xr[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) xr[r] = r == 0 ? c2[o] : T(0);
+            for (int k = 0; k < dp; ++k) {
+                const T wv = W2[k * s.w2 + o];
+#pragma unroll
+                for (int r = 0; r < R; ++r) xr[r] += in[r * wp + k] * wv;
+            }
+            const T y0 = tanh(xr[0]);
+            const T dd = T(1) - y0 * y0;
+            T *out = S1 + j * R * wp;
+            out[o] = y0 + (l >= 1 ? in[o] : T(0));
+            if constexpr (FL) {
+                T src = T(0);
+#pragma unroll
+                for (int r = 1; r < 7; ++r) {
+                    src += xr[r] * xr[r];
+                    out[r * wp + o] = dd * xr[r] + (l >= 1 ? in[r * wp + o] : T(0));
+                }
+                out[7 * wp + o] = dd * xr[7] - T(2) * y0 * dd * src + (l >= 1 ? in[7 * wp + o] : T(0));
+            }
+        }
+        __syncthreads();
+        T *t = S0; S0 = S1; S1 = t;
+        write_pair_means<T, FL>(s, S0, wp, s.w2, i, TR, GW1, ldg,
+                                GI + (int64_t)(l + 1) * gi_layer_stride + wi * rows * ldg);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// spin means of the one-electron stream: G[w][t] = [g_up | g_dn]
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_spin_mean(const T *H, int64_t ldh, int64_t B, int N, int nu, int TR, int dh, int HWl, T *G)
+{
+    const int nd = N - nu;
+    const int64_t total = B * TR * 2 * HWl;
+    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < total; id += (int64_t)gridDim.x * blockDim.x) {
+        const int col = (int)(id % (2 * HWl));
+        const int64_t wt = id / (2 * HWl);
+        const int t = (int)(wt % TR);
+        const int64_t w = wt / TR;
+        const int sp = col / HWl, k = col % HWl;
+        const int n = sp == 0 ? nu : nd, j0 = sp == 0 ? 0 : nu;
+        T v = T(0);
+        if (k < dh && n > 0) {
+            T acc = T(0);
+            for (int j = j0; j < j0 + n; ++j) acc += H[((w * N + j) * TR + t) * ldh + k];
+            v = acc / T(n);
+        }
+        G[id] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// layer epilogue: z = X + P (per-walker part) + b (value row), y = tanh(z) in
+// forward-Laplacian form, plus the residual h_i when widths match (l >= 1).
+// ---------------------------------------------------------------------------
+template <typename T, bool FL>
+__global__ void k_layer_epi(const T *X, const T *Pw, const T *bias, const T *Hin, T *Hout, int64_t ldh, int64_t B,
+                            int N, int TR, int n3, int w1, int W1p, int resid)
+{
+    const int64_t total = B * N * W1p;
+    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < total; id += (int64_t)gridDim.x * blockDim.x) {
+        const int o = (int)(id % W1p);
+        const int64_t wi = id / W1p;
+        const int64_t w = wi / N;
+        const int64_t r0 = wi * TR;
+        if (o >= w1) {
+            for (int t = 0; t < TR; ++t) Hout[(r0 + t) * ldh + o] = T(0);
+            continue;
+        }
+        const T *xp = X + r0 * w1 + o;
+        const T *pp = Pw + w * TR * w1 + o;
+        const T z0 = xp[0] + pp[0] + bias[o];
+        const T y0 = tanh(z0);
+        const T d = T(1) - y0 * y0;
+        Hout[r0 * ldh + o] = y0 + (resid ? Hin[r0 * ldh + o] : T(0));
+        if (FL) {
+            T src = T(0);
+            for (int t = 1; t <= n3; ++t) {
+                const T z = xp[(int64_t)t * w1] + pp[(int64_t)t * w1];
+                src += z * z;
+                Hout[(r0 + t) * ldh + o] = d * z + (resid ? Hin[(r0 + t) * ldh + o] : T(0));
+            }
+            const int tl = n3 + 1;
+            const T zl = xp[(int64_t)tl * w1] + pp[(int64_t)tl * w1];
+            Hout[(r0 + tl) * ldh + o] = d * zl - T(2) * y0 * d * src + (resid ? Hin[(r0 + tl) * ldh + o] : T(0));
+            for (int t = tl + 1; t < TR; ++t) Hout[(r0 + t) * ldh + o] = T(0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// orbitals x envelope (Eq. 4): phi_i(j) = (w_i . h_j + g_i) sum_m pi_im
+// exp(-|Sigma_im (r_j - R_m)|).  The envelope depends on r_j only, so its
+// derivatives are local to the three coordinates of electron j:
+//   q = |Sigma d|, grad q = S d / q with S = Sigma^T Sigma,
+//   lap q = (tr S - |S d|^2 / q^2) / q, grad e = -e grad q,
+//   lap e = e (|grad q|^2 - lap q); lap(a e) = e lap a + a lap e + 2 grad a . grad e.
+// Output Phi[w][k][t][i][jj] (rows t = value, 3N tangents, Laplacian).
+// ---------------------------------------------------------------------------
+template <typename T, bool FL>
+__global__ void k_envelope(Sys s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof, int sp,
+                           const T *O, int64_t ldo, int64_t B, int TR, double *Phi)
+{
+    typedef double E;   // envelope and product rule in FP64 for every precision
+    const int n = sp == 0 ? s.nu : s.nd, j0 = sp == 0 ? 0 : s.nu;
+    const int kn = s.K * n;
+    const int n3 = 3 * s.N;
+    const int64_t total = B * n * kn;
+    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < total; id += (int64_t)gridDim.x * blockDim.x) {
+        const int col = (int)(id % kn);
+        const int64_t wj = id / kn;
+        const int jj = (int)(wj % n);
+        const int64_t w = wj / n;
+        const int j = j0 + jj;
+        const int k = col / n, io = col % n;
+        const double *xj = x + (w * s.N + j) * 3;
+        E env = 0.0, ge[3] = {0.0, 0.0, 0.0}, le = 0.0;
+        for (int m = 0; m < s.M; ++m) {
+            const T *Sgp = theta + sigof + ((int64_t)col * s.M + m) * 9;
+            E d[3] = {xj[0] - s.R[m][0], xj[1] - s.R[m][1], xj[2] - s.R[m][2]};
+            E sd[3], ad[3], Sg[9];
+            for (int e = 0; e < 9; ++e) Sg[e] = (E)Sgp[e];
+            for (int p = 0; p < 3; ++p) sd[p] = Sg[3 * p] * d[0] + Sg[3 * p + 1] * d[1] + Sg[3 * p + 2] * d[2];
+            for (int a = 0; a < 3; ++a) ad[a] = Sg[a] * sd[0] + Sg[3 + a] * sd[1] + Sg[6 + a] * sd[2];
+            const E q = sqrt(sd[0] * sd[0] + sd[1] * sd[1] + sd[2] * sd[2]);
+            const E em = (E)theta[piof + (int64_t)col * s.M + m] * exp(-q);
+            env += em;
+            if (FL) {
+                E trS = 0.0;
+                for (int e = 0; e < 9; ++e) trS += Sg[e] * Sg[e];
+                const E iq = 1.0 / q;
+                const E ad2 = ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2];
+                const E lq = (trS - ad2 * iq * iq) * iq;
+                const E gq2 = ad2 * iq * iq;
+                for (int a = 0; a < 3; ++a) ge[a] -= em * ad[a] * iq;
+                le += em * (gq2 - lq);
+            }
+        }
+        const int64_t orow = (w * n + jj) * TR;
+        const E a0 = (E)O[orow * ldo + col] + (E)theta[gof + col];
+        const int64_t base = ((w * s.K + k) * TR) * n * n + io * n + jj;
+        const int64_t tstride = (int64_t)n * n;
+        Phi[base] = a0 * env;
+        if (FL) {
+            for (int c = 0; c < n3; ++c) {
+                E v = env * (E)O[(orow + 1 + c) * ldo + col];
+                if (c / 3 == j) v += a0 * ge[c % 3];
+                Phi[base + (1 + c) * tstride] = v;
+            }
+            E lap = env * (E)O[(orow + n3 + 1) * ldo + col] + a0 * le;
+            for (int a = 0; a < 3; ++a) lap += 2.0 * (E)O[(orow + 1 + 3 * j + a) * ldo + col] * ge[a];
+            Phi[base + (n3 + 1) * tstride] = lap;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// determinants: one wave64 per (walker, determinant k) of one spin.  LU with
+// partial pivoting in LDS gives sign and log|det A|; then for every
+// direction c the columns of M_c = A^-1 dA/dx_c come from LU solves, and
+//   d log|det| / dx_c = tr M_c,
+//   lap log|det| = tr(A^-1 lap A) - sum_c tr(M_c M_c).
+// Record layout per (walker, spin, k): [sign, log|det|, grad[3N], lap].
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T, bool FL>
+__global__ __launch_bounds__(64) void k_det(const T *Phi, int64_t B, int K, int n, int TR, int n3, int sp,
+                                            double *DR, int rec)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    T *LU = (T *)smem_raw;
+    T *Mb = LU + n * n;
+    int *perm = (int *)(Mb + (FL ? (n3 + 1) * n * n : 0));
+    __shared__ int s_sign, s_sing;
+    __shared__ double s_log;
+    const int lane = threadIdx.x;
+    const int64_t wk = blockIdx.x;
+    const int64_t w = wk / K;
+    const int k = (int)(wk % K);
+    if (w >= B) return;
+    const int64_t nn = (int64_t)n * n;
+    const T *A = Phi + (w * K + k) * TR * nn;
+    for (int q = lane; q < n * n; q += 64) LU[q] = A[q];
+    for (int q = lane; q < n; q += 64) perm[q] = q;
+    if (lane == 0) { s_sign = 1; s_sing = 0; s_log = 0.0; }
+    __syncthreads();
+    for (int c = 0; c < n; ++c) {
+        if (lane == 0) {
+            int p = c;
+            T best = fabs(LU[c * n + c]);
+            for (int r = c + 1; r < n; ++r) {
+                T v = fabs(LU[r * n + c]);
+                if (v > best) { best = v; p = r; }
+            }
+            if (best == T(0)) {
+                s_sing = 1;
+            } else {
+                if (p != c) {
+                    for (int q = 0; q < n; ++q) { T t = LU[c * n + q]; LU[c * n + q] = LU[p * n + q]; LU[p * n + q] = t; }
+                    int t = perm[c]; perm[c] = perm[p]; perm[p] = t;
+                    s_sign = -s_sign;
+                }
+                T piv = LU[c * n + c];
+                if (piv < T(0)) s_sign = -s_sign;
+                s_log += log((double)fabs(piv));
+            }
+        }
+        __syncthreads();
+        if (s_sing) break;
+        const T ip = T(1) / LU[c * n + c];
+        const int m = n - 1 - c;
+        for (int q = lane; q < m; q += 64) LU[(c + 1 + q) * n + c] *= ip;   // multipliers (L below the diagonal)
+        __syncthreads();
+        for (int q = lane; q < m * m; q += 64) {
+            const int r = c + 1 + q / m, cc = c + 1 + q % m;
+            LU[r * n + cc] -= LU[r * n + c] * LU[c * n + cc];
+        }
+        __syncthreads();
+    }
+    double *out = DR + (w * 2 + sp) * (int64_t)K * rec + (int64_t)k * rec;
+    if (s_sing) {
+        for (int q = lane; q < rec; q += 64) out[q] = q == 0 ? 0.0 : (q == 1 ? -INFINITY : NAN);
+        return;
+    }
+    if (lane == 0) { out[0] = (double)s_sign; out[1] = s_log; }
+    if (!FL) return;
+    // solve A M = D for all (3N + 1) right-hand matrices, one column per lane
+    const int ncol = (n3 + 1) * n;
+    for (int q = lane; q < ncol; q += 64) {
+        const int mt = q / n, jj = q % n;
+        T *v = Mb + mt * nn;
+        const T *D = A + (1 + mt) * nn;
+        for (int r = 0; r < n; ++r) v[r * n + jj] = D[perm[r] * n + jj];
+        for (int r = 1; r < n; ++r) {
+            T acc = v[r * n + jj];
+            for (int c = 0; c < r; ++c) acc -= LU[r * n + c] * v[c * n + jj];
+            v[r * n + jj] = acc;
+        }
+        for (int r = n - 1; r >= 0; --r) {
+            T acc = v[r * n + jj];
+            for (int c = r + 1; c < n; ++c) acc -= LU[r * n + c] * v[c * n + jj];
+            v[r * n + jj] = acc / LU[r * n + r];
+        }
+    }
+    __syncthreads();
+    double sq = 0.0, trl = 0.0;
+    for (int mt = lane; mt <= n3; mt += 64) {
+        const T *Mm = Mb + mt * nn;
+        T tr = T(0);
+        for (int r = 0; r < n; ++r) tr += Mm[r * n + r];
+        if (mt < n3) {
+            T s2 = T(0);
+            for (int r = 0; r < n; ++r)
+                for (int c = 0; c < n; ++c) s2 += Mm[r * n + c] * Mm[c * n + r];
+            out[2 + mt] = (double)tr;
+            sq += (double)s2;
+        } else {
+            trl = (double)tr;
+        }
+    }
+    sq = wave_sum(sq);
+    trl = wave_sum(trl);
+    if (lane == 0) out[2 + n3] = trl - sq;
+}
+
+// ---------------------------------------------------------------------------
+// per walker, FP64: psi = sum_k s_k exp(l_k), l_k = l_k_up + l_k_dn;
+// log|psi| = l_max + log|sum_k s_k exp(l_k - l_max)|, weights
+// w_k = s_k exp(l_k - l_max) / sum; E_kin = -1/2 (lap psi)/psi
+// = -1/2 sum_k w_k (lap l_k + |grad l_k|^2)  (Eq. 3 summed over coordinates);
+// Coulomb sums of Eq. 2 with wavefront reductions.
+// ---------------------------------------------------------------------------
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <bool FL>
+__global__ __launch_bounds__(64) void k_combine(Sys s, const double *x, const double *DR, int rec, int64_t B,
+                                                double vnn, double *log_abs, int8_t *sign, double *e_loc,
+                                                double *parts)
+{
+    __shared__ double s_w[FN_MAX_DET];
+    const int lane = threadIdx.x;
+    const int64_t w = blockIdx.x;
+    if (w >= B) return;
+    const int K = s.K, n3 = 3 * s.N;
+    const double *ru = DR + (w * 2 + 0) * (int64_t)K * rec;
+    const double *rd = DR + (w * 2 + 1) * (int64_t)K * rec;
+    double sk = 0.0, lk = -INFINITY;
+    if (lane < K) {
+        double su = s.nu > 0 ? ru[lane * rec] : 1.0, sd = s.nd > 0 ? rd[lane * rec] : 1.0;
+        double lu = s.nu > 0 ? ru[lane * rec + 1] : 0.0, ld = s.nd > 0 ? rd[lane * rec + 1] : 0.0;
+        sk = su * sd;
+        lk = sk != 0.0 ? lu + ld : -INFINITY;
+    }
+    const double lmax = wave_max(lk);
+    double ek = (lane < K && sk != 0.0) ? sk * exp(lk - lmax) : 0.0;
+    const double S = wave_sum(ek);
+    const bool node = !(lmax > -INFINITY) || S == 0.0 || !(S == S);
+    const double lpsi = node ? -INFINITY : lmax + log(fabs(S));
+    if (lane == 0) {
+        if (log_abs) log_abs[w] = lpsi;
+        if (sign) sign[w] = node ? 0 : (S > 0 ? 1 : -1);
+    }
+    if (!FL) return;
+    if (lane < K) s_w[lane] = node ? 0.0 : ek / S;
+    __syncthreads();
+    // sum_k w_k |grad l_k|^2 over coordinates, and sum_k w_k lap l_k
+    double q = 0.0;
+    for (int c = lane; c < n3; c += 64) {
+        for (int k = 0; k < K; ++k) {
+            double gu = s.nu > 0 ? ru[k * rec + 2 + c] : 0.0, gd = s.nd > 0 ? rd[k * rec + 2 + c] : 0.0;
+            double g = gu + gd;
+            q += s_w[k] * g * g;
+        }
+    }
+    double lsum = 0.0;
+    if (lane < K) {
+        double lu = s.nu > 0 ? ru[lane * rec + 2 + n3] : 0.0, ld = s.nd > 0 ? rd[lane * rec + 2 + n3] : 0.0;
+        lsum = s_w[lane] * (lu + ld);
+    }
+    q = wave_sum(q);
+    lsum = wave_sum(lsum);
+    const double kin = node ? NAN : -0.5 * (lsum + q);
+    // Coulomb: electron pairs and electron-nucleus pairs over the lanes
+    const double *xw = x + w * n3;
+    double vee = 0.0, ven = 0.0;
+    const int npair = s.N * (s.N - 1) / 2;
+    for (int p = lane; p < npair; p += 64) {
+        int i = 0, rem = p;
+        while (rem >= s.N - 1 - i) { rem -= s.N - 1 - i; ++i; }
+        int j = i + 1 + rem;
+        double d0 = xw[3 * i] - xw[3 * j], d1 = xw[3 * i + 1] - xw[3 * j + 1], d2 = xw[3 * i + 2] - xw[3 * j + 2];
+        vee += 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    }
+    for (int p = lane; p < s.N * s.M; p += 64) {
+        int i = p / s.M, m = p % s.M;
+        double d0 = xw[3 * i] - s.R[m][0], d1 = xw[3 * i + 1] - s.R[m][1], d2 = xw[3 * i + 2] - s.R[m][2];
+        ven -= s.Z[m] / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    }
+    vee = wave_sum(vee);
+    ven = wave_sum(ven);
+    if (lane == 0) {
+        e_loc[w] = kin + vee + ven + vnn;
+        if (parts) {
+            parts[4 * w] = kin; parts[4 * w + 1] = vee; parts[4 * w + 2] = ven; parts[4 * w + 3] = vnn;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static unsigned grid_for(int64_t n, int bs = 256)
+{
+    int64_t g = (n + bs - 1) / bs;
+    if (g > 1 << 20) g = 1 << 20;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+template <typename T>
+void launch_pack_layer(const T *theta, int64_t voff, int dh, int dp, int w1, int HWl, int GWl, int mode, void *wx,
+                       void *wg, hipStream_t st)
+{
+    int64_t n = (int64_t)w1 * (HWl + GWl) + (int64_t)w1 * 2 * HWl;
+    hipLaunchKernelGGL(k_pack_layer<T>, dim3(grid_for(n)), dim3(256), 0, st, theta, voff, dh, dp, w1, HWl, GWl, mode,
+                       wx, wg);
+}
+
+template <typename T>
+void launch_pack_head(const T *theta, int64_t woff, int w1, int W1p, int kn, int mode, void *wh, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pack_head<T>, dim3(grid_for((int64_t)kn * W1p)), dim3(256), 0, st, theta, woff, w1, W1p, kn,
+                       mode, wh);
+}
+
+template <typename T>
+void launch_features(const Sys &s, const double *x, int64_t B, int TR, int HW0, int64_t ldh, T *H, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_features<T>, dim3(grid_for(B * s.N * TR)), dim3(256), 0, st, s, x, B, TR, HW0, ldh, H);
+}
+
+size_t pair_stream_lds(const Sys &s, bool fl, size_t elem)
+{
+    int wp = s.w2 > 4 ? s.w2 : 4;
+    return 2 * (size_t)s.N * (fl ? 8 : 1) * wp * elem;
+}
+
+template <typename T>
+void launch_pair_stream(const Sys &s, const double *x, const T *theta, const ParamLayout &P, int64_t B, int TR,
+                        bool fl, int64_t ldg, int64_t gi_layer_stride, int GW0, int GW1, T *GI, hipStream_t st)
+{
+    size_t lds = pair_stream_lds(s, fl, sizeof(T));
+    dim3 grid((unsigned)(B * s.N));
+    if (fl)
+        hipLaunchKernelGGL((k_pair_stream<T, true>), grid, dim3(256), lds, st, s, x, theta, P, B, TR, ldg,
+                           gi_layer_stride, GW0, GW1, GI);
+    else
+        hipLaunchKernelGGL((k_pair_stream<T, false>), grid, dim3(256), lds, st, s, x, theta, P, B, TR, ldg,
+                           gi_layer_stride, GW0, GW1, GI);
+}
+
+template <typename T>
+void launch_spin_mean(const T *H, int64_t ldh, int64_t B, int N, int nu, int TR, int dh, int HWl, T *G,
+                      hipStream_t st)
+{
+    hipLaunchKernelGGL(k_spin_mean<T>, dim3(grid_for(B * TR * 2 * HWl)), dim3(256), 0, st, H, ldh, B, N, nu, TR, dh,
+                       HWl, G);
+}
+
+template <typename T>
+void launch_layer_epi(const T *X, const T *Pw, const T *bias, const T *Hin, T *Hout, int64_t ldh, int64_t B, int N,
+                      int TR, int n3, int w1, int W1p, int resid, bool fl, hipStream_t st)
+{
+    dim3 g(grid_for(B * N * W1p));
+    if (fl)
+        hipLaunchKernelGGL((k_layer_epi<T, true>), g, dim3(256), 0, st, X, Pw, bias, Hin, Hout, ldh, B, N, TR, n3, w1,
+                           W1p, resid);
+    else
+        hipLaunchKernelGGL((k_layer_epi<T, false>), g, dim3(256), 0, st, X, Pw, bias, Hin, Hout, ldh, B, N, TR, n3, w1,
+                           W1p, resid);
+}
+
+template <typename T>
+void launch_envelope(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof, int sp,
+                     const T *O, int64_t ldo, int64_t B, int TR, bool fl, double *Phi, hipStream_t st)
+{
+    int n = sp == 0 ? s.nu : s.nd;
+    dim3 g(grid_for(B * n * s.K * n));
+    if (fl)
+        hipLaunchKernelGGL((k_envelope<T, true>), g, dim3(256), 0, st, s, x, theta, gof, piof, sigof, sp, O, ldo, B,
+                           TR, Phi);
+    else
+        hipLaunchKernelGGL((k_envelope<T, false>), g, dim3(256), 0, st, s, x, theta, gof, piof, sigof, sp, O, ldo, B,
+                           TR, Phi);
+}
+
+size_t det_lds(int n, int n3, bool fl, size_t elem)
+{
+    return ((size_t)n * n + (fl ? (size_t)(n3 + 1) * n * n : 0)) * elem + (size_t)n * sizeof(int) + 16;
+}
+
+void launch_det(const double *Phi, int64_t B, int K, int n, int TR, int n3, int sp, bool fl, double *DR, int rec,
+                hipStream_t st)
+{
+    typedef double T;
+    size_t lds = det_lds(n, n3, fl, sizeof(T));
+    dim3 g((unsigned)(B * K));
+    if (fl)
+        hipLaunchKernelGGL((k_det<T, true>), g, dim3(64), lds, st, Phi, B, K, n, TR, n3, sp, DR, rec);
+    else
+        hipLaunchKernelGGL((k_det<T, false>), g, dim3(64), lds, st, Phi, B, K, n, TR, n3, sp, DR, rec);
+}
+
+void launch_combine(const Sys &s, const double *x, const double *DR, int rec, int64_t B, double vnn, double *log_abs,
+                    int8_t *sign, double *e_loc, double *parts, bool fl, hipStream_t st)
+{
+    if (fl)
+        hipLaunchKernelGGL(k_combine<true>, dim3((unsigned)B), dim3(64), 0, st, s, x, DR, rec, B, vnn, log_abs, sign,
+                           e_loc, parts);
+    else
+        hipLaunchKernelGGL(k_combine<false>, dim3((unsigned)B), dim3(64), 0, st, s, x, DR, rec, B, vnn, log_abs, sign,
+                           e_loc, parts);
+}
+
+#define FN_INST(T)                                                                                                  \
+    template void launch_pack_layer<T>(const T *, int64_t, int, int, int, int, int, int, void *, void *,            \
+                                       hipStream_t);                                                                \
+    template void launch_pack_head<T>(const T *, int64_t, int, int, int, int, void *, hipStream_t);                 \
+    template void launch_features<T>(const Sys &, const double *, int64_t, int, int, int64_t, T *, hipStream_t);    \
+    template void launch_pair_stream<T>(const Sys &, const double *, const T *, const ParamLayout &, int64_t, int,   \
+                                        bool, int64_t, int64_t, int, int, T *, hipStream_t);                        \
+    template void launch_spin_mean<T>(const T *, int64_t, int64_t, int, int, int, int, int, T *, hipStream_t);      \
+    template void launch_layer_epi<T>(const T *, const T *, const T *, const T *, T *, int64_t, int64_t, int, int,  \
+                                      int, int, int, int, bool, hipStream_t);                                       \
+    template void launch_envelope<T>(const Sys &, const double *, const T *, int64_t, int64_t, int64_t, int,        \
+                                     const T *, int64_t, int64_t, int, bool, double *, hipStream_t);
+
+FN_INST(float)
+FN_INST(double)
+
+}  // namespace fn
