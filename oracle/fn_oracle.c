@@ -198,7 +198,8 @@ void orc_slogdet(int32_t n, int64_t count, const double *A /*[count][n][n]*/, do
 /* ------------------------------------------------------------------ */
 typedef struct {
     hd *h1, *h1n, *h2, *h2n, *f, *gu, *gd, *giu, *gid, *A;
-    hd *hL_out; /* optional copy of the final one-electron stream */
+    hd *hL_out;     /* optional copy of the final one-electron stream          */
+    double *mats;   /* optional copy of the orbital matrices [2][K][nmax][nmax] */
 } scratch;
 
 static scratch scratch_alloc(const orc_cfg *c)
@@ -220,6 +221,7 @@ static scratch scratch_alloc(const orc_cfg *c)
     s.gid = (hd *)calloc((size_t)pmax, sizeof(hd));
     s.A = (hd *)calloc((size_t)(nmax * nmax > 0 ? nmax * nmax : 1), sizeof(hd));
     s.hL_out = NULL;
+    s.mats = NULL;
     return s;
 }
 
@@ -354,6 +356,12 @@ static void eval_walker(const orc_cfg *c, const orc_layout *Ly, const double *th
                     }
                     S->A[io * ns + jj] = hmul(a, env);
                 }
+            }
+            if (S->mats) {
+                const int nmax = nu > nd ? nu : nd;
+                double *dst = S->mats + ((size_t)(s * K + k) * nmax * nmax);
+                for (int r = 0; r < ns; ++r)
+                    for (int q = 0; q < ns; ++q) dst[r * nmax + q] = S->A[r * ns + q].a;
             }
             int sg; hd la;
             lu_slogdet(ns, S->A, &sg, &la);
@@ -495,6 +503,32 @@ void orc_local_energy(const orc_cfg *c, const double *theta, const double *x, in
             if (log_abs) log_abs[w] = sg == 0 ? -INFINITY : lp0;
             if (parts) { parts[4 * w] = kin; parts[4 * w + 1] = ee; parts[4 * w + 2] = en; parts[4 * w + 3] = nn; }
             if (lap) lap[w] = sum_d2;
+        }
+        free(xh);
+        scratch_free(&S);
+    }
+}
+
+/* orbital matrices A[i][j] = phi_i(r_j) of every (spin, determinant):
+   out [B][2][K][nmax][nmax], nmax = max(n_up, n_dn), unused entries 0 */
+void orc_orbital_matrices(const orc_cfg *c, const double *theta, const double *x, int64_t B, double *out)
+{
+    orc_layout Ly;
+    make_layout(c, &Ly);
+    const int N = c->n_up + c->n_dn;
+    const int nmax = c->n_up > c->n_dn ? c->n_up : c->n_dn;
+    const size_t per = (size_t)2 * c->n_det * nmax * nmax;
+    memset(out, 0, sizeof(double) * per * (size_t)B);
+#pragma omp parallel
+    {
+        scratch S = scratch_alloc(c);
+        hd *xh = (hd *)malloc(sizeof(hd) * 3 * N);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t w = 0; w < B; ++w) {
+            load_real(xh, x + w * 3 * N, 3 * N);
+            S.mats = out + per * (size_t)w;
+            hd lp; int sg;
+            eval_walker(c, &Ly, theta, NULL, xh, &S, &lp, &sg, NULL);
         }
         free(xh);
         scratch_free(&S);

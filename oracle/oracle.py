@@ -55,6 +55,7 @@ def lib():
         _lib.orc_draws.argtypes = [ctypes.c_uint64, ctypes.c_uint32, i64, ctypes.c_int32, ctypes.c_uint64, vp, vp]
         _lib.orc_slogdet.argtypes = [ctypes.c_int32, i64, vp, vp, vp]
         _lib.orc_coulomb.argtypes = [vp, vp, i64, vp]
+        _lib.orc_orbital_matrices.argtypes = [vp, vp, vp, i64, vp]
         _lib.orc_num_threads.restype = ctypes.c_int32
     return _lib
 
@@ -116,6 +117,15 @@ class Oracle:
         idx = np.ascontiguousarray(idx, dtype=np.int64)
         out = np.empty((x.shape[0], idx.size))
         lib().orc_dlogpsi_dtheta_index(self._cp, _p(theta), _p(idx), idx.size, _p(x), x.shape[0], _p(out))
+        return out
+
+    def orbital_matrices(self, theta, x):
+        """[B][2][K][nmax][nmax] values phi_i(r_j) of each spin's orbital matrix."""
+        x = _f64(x)
+        theta = _f64(theta)
+        nmax = max(self.s.n_up, self.s.n_dn)
+        out = np.empty((x.shape[0], 2, self.s.n_det, nmax, nmax))
+        lib().orc_orbital_matrices(self._cp, _p(theta), _p(x), x.shape[0], _p(out))
         return out
 
     def coulomb(self, x):

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "fn_internal.h"
@@ -186,7 +187,7 @@ fn_status make_plan(const Ctx &c, int64_t B, int op, Plan &p)
     if (op < FN_OP_LOG_PSI || op > FN_OP_PARAM_GRAD) return fail(FN_EINVAL, "unknown op");
     p.fl = op == FN_OP_LOCAL_ENERGY;
     const int n3 = 3 * s.N;
-    p.TR = p.fl ? round_up(n3 + 2, 16) : 1;
+    p.TR = p.fl ? fl_rows(s.N) : 1;
     p.rec = n3 + 3;
     const int nmax = std::max(s.nu, s.nd);
     if (pair_stream_lds(s, p.fl, c.esz) > 64 * 1024) return fail(FN_EUNSUPPORTED, "pair stream exceeds LDS");
@@ -290,15 +291,29 @@ void forward(const Ctx &c, const Plan &p, const T *theta, const double *x, int64
             ga.rows = b * TR; ga.nout = s.w1;
             ga.rows_per_group = ga.rows; ga.group_stride = 0; ga.row_offset = 0;
             { Timed t_(K_WALKER_GEMM, st); (void)launch_gemm(c.smode, ga, st); }
-            GemmArgs gx{};
-            gx.A1 = H[cur]; gx.lda1 = ldh; gx.K1 = HWl;
-            gx.A2 = GI + (int64_t)l * p.gi_layer_stride; gx.lda2 = ldg; gx.K2 = GWl;
-            gx.W = ws + p.wx[l]; gx.wpart = p.wxpart[l]; gx.ldw = HWl + GWl;
-            gx.C = X; gx.ldc = s.w1;
-            gx.rows = b * s.N * TR; gx.nout = s.w1;
-            gx.rows_per_group = gx.rows; gx.group_stride = 0; gx.row_offset = 0;
-            { Timed t_(K_STREAM_GEMM, st); (void)launch_gemm(c.smode, gx, st); }
-            {
+            bool fused = false;
+            if constexpr (std::is_same<T, float>::value) fused = stream_layer_supported(c.smode, TR, c.W.W1p);
+            if constexpr (std::is_same<T, float>::value) if (fused) {
+                LayerArgs la{};
+                la.A1 = H[cur]; la.lda1 = ldh; la.K1 = HWl;
+                la.A2 = GI + (int64_t)l * p.gi_layer_stride; la.lda2 = ldg; la.K2 = GWl;
+                la.W = ws + p.wx[l]; la.wpart = p.wxpart[l]; la.ldw = HWl + GWl; la.nout = s.w1;
+                la.Pw = Pw; la.bias = theta + c.P.b[l];
+                la.Hout = H[cur ^ 1]; la.ldh_out = ldh;
+                la.rows = b * s.N * TR; la.N = s.N; la.n3 = n3; la.w1 = s.w1; la.W1p = c.W.W1p;
+                la.resid = l >= 1 ? 1 : 0;
+                Timed t_(K_STREAM_GEMM, st);
+                launch_stream_layer(c.smode, la, TR, st);
+            }
+            if (!fused) {
+                GemmArgs gx{};
+                gx.A1 = H[cur]; gx.lda1 = ldh; gx.K1 = HWl;
+                gx.A2 = GI + (int64_t)l * p.gi_layer_stride; gx.lda2 = ldg; gx.K2 = GWl;
+                gx.W = ws + p.wx[l]; gx.wpart = p.wxpart[l]; gx.ldw = HWl + GWl;
+                gx.C = X; gx.ldc = s.w1;
+                gx.rows = b * s.N * TR; gx.nout = s.w1;
+                gx.rows_per_group = gx.rows; gx.group_stride = 0; gx.row_offset = 0;
+                { Timed t_(K_STREAM_GEMM, st); (void)launch_gemm(c.smode, gx, st); }
                 Timed t_(K_EPI, st);
                 launch_layer_epi<T>(X, Pw, theta + c.P.b[l], H[cur], H[cur ^ 1], ldh, b, s.N, TR, n3, s.w1, c.W.W1p,
                                     l >= 1 ? 1 : 0, fl, st);

@@ -107,4 +107,32 @@ struct GemmArgs {
 
 hipError_t launch_gemm(int mode, const GemmArgs &a, hipStream_t st);
 
+// One fused one-electron stream layer (product + forward-Laplacian tanh
+// epilogue + residual).  A1 = h^l (rows of TR per electron, also the residual
+// source), A2 = pair means of layer l, W = packed V_h (nout = w1 columns),
+// Pw = per-walker part [walker * TR + t][w1], bias = b_l.
+struct LayerArgs {
+    const float *A1; int64_t lda1; int K1;
+    const float *A2; int64_t lda2; int K2;
+    const void *W; int64_t wpart; int64_t ldw; int nout;
+    const float *Pw; const float *bias;
+    float *Hout; int64_t ldh_out;
+    int64_t rows; int N; int n3; int w1; int W1p; int resid;
+};
+
+bool stream_layer_supported(int mode, int TR, int W1p);
+void launch_stream_layer(int mode, const LayerArgs &a, int TR, hipStream_t st);
+
+// Rows per electron in forward-Laplacian form: 3N + 2 rounded up to 16, or
+// to the next power of two (which the fused layer kernel handles) when that
+// pads by at most a quarter more.
+inline int fl_rows(int N)
+{
+    const int t = 3 * N + 2;
+    const int r16 = round_up(t, 16);
+    int p2 = 16;
+    while (p2 < t) p2 *= 2;
+    return (p2 <= 64 && 4 * p2 <= 5 * r16) ? p2 : r16;
+}
+
 }  // namespace fn

@@ -79,34 +79,32 @@ __global__ void k_pack_head(const T *theta, int64_t woff, int w1, int W1p, int k
 // electron-nucleus input features [r_i - R_m, |r_i - R_m|] with their rows
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_features(Sys s, const double *x, int64_t B, int TR, int HW0, int64_t ldh, T *H)
+__global__ __launch_bounds__(256) void k_features(Sys s, const double *x, int TR, int HW0, int64_t ldh, T *H)
 {
-    const int64_t total = B * s.N * TR;
+    const int wi = blockIdx.x;              // walker * N + electron
+    const int i = wi % s.N;
     const int n3 = 3 * s.N;
-    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < total; id += (int64_t)gridDim.x * blockDim.x) {
-        const int t = (int)(id % TR);
-        const int64_t wi = id / TR;
-        const int i = (int)(wi % s.N);
-        const double *xi = x + wi * 3;
-        T *h = H + id * ldh;
-        for (int k = 0; k < HW0; ++k) h[k] = T(0);
-        if (t > n3 + 1) continue;
-        for (int m = 0; m < s.M; ++m) {
-            double d0 = xi[0] - s.R[m][0], d1 = xi[1] - s.R[m][1], d2 = xi[2] - s.R[m][2];
-            double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    const double *xi = x + (int64_t)wi * 3;
+    for (int q = threadIdx.x; q < TR * HW0; q += blockDim.x) {
+        const int t = q / HW0, k = q - t * HW0;
+        T v = T(0);
+        if (k < 4 * s.M && t <= n3 + 1) {
+            const int m = k >> 2, f = k & 3;
+            const double d0 = xi[0] - s.R[m][0], d1 = xi[1] - s.R[m][1], d2 = xi[2] - s.R[m][2];
+            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
             if (t == 0) {
-                h[4 * m + 0] = (T)d0; h[4 * m + 1] = (T)d1; h[4 * m + 2] = (T)d2; h[4 * m + 3] = (T)r;
+                v = (T)(f == 0 ? d0 : (f == 1 ? d1 : (f == 2 ? d2 : r)));
             } else if (t <= n3) {
-                int c = t - 1, e = c / 3, a = c % 3;
+                const int c = t - 1, e = c / 3, a = c - 3 * e;
                 if (e == i) {
-                    h[4 * m + a] = T(1);
-                    double da = a == 0 ? d0 : (a == 1 ? d1 : d2);
-                    h[4 * m + 3] = (T)(da / r);
+                    const double da = a == 0 ? d0 : (a == 1 ? d1 : d2);
+                    v = f == 3 ? (T)(da / r) : (f == a ? T(1) : T(0));
                 }
-            } else {
-                h[4 * m + 3] = (T)(2.0 / r);
+            } else if (f == 3) {
+                v = (T)(2.0 / r);
             }
         }
+        H[((int64_t)wi * TR + t) * ldh + k] = v;
     }
 }
 
@@ -229,24 +227,25 @@ __global__ void k_pair_stream(Sys s, const double *x, const T *theta, ParamLayou
 // spin means of the one-electron stream: G[w][t] = [g_up | g_dn]
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_spin_mean(const T *H, int64_t ldh, int64_t B, int N, int nu, int TR, int dh, int HWl, T *G)
+__global__ __launch_bounds__(256) void k_spin_mean(const T *__restrict__ H, int64_t ldh, int N, int nu, int TR,
+                                                   int dh, int HWl, T *__restrict__ G)
 {
     const int nd = N - nu;
-    const int64_t total = B * TR * 2 * HWl;
-    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < total; id += (int64_t)gridDim.x * blockDim.x) {
-        const int col = (int)(id % (2 * HWl));
-        const int64_t wt = id / (2 * HWl);
-        const int t = (int)(wt % TR);
-        const int64_t w = wt / TR;
-        const int sp = col / HWl, k = col % HWl;
-        const int n = sp == 0 ? nu : nd, j0 = sp == 0 ? 0 : nu;
+    const int wt = blockIdx.x;              // walker * TR + t
+    const int w = wt / TR, t = wt - w * TR;
+    const T *h0 = H + ((int64_t)w * N * TR + t) * ldh;
+    const int64_t jstride = (int64_t)TR * ldh;
+    T *g = G + (int64_t)wt * 2 * HWl;
+    const T iu = nu > 0 ? T(1) / T(nu) : T(0), id = nd > 0 ? T(1) / T(nd) : T(0);
+    for (int col = threadIdx.x; col < 2 * HWl; col += blockDim.x) {
+        const int sp = col >= HWl, k = col - sp * HWl;
         T v = T(0);
-        if (k < dh && n > 0) {
-            T acc = T(0);
-            for (int j = j0; j < j0 + n; ++j) acc += H[((w * N + j) * TR + t) * ldh + k];
-            v = acc / T(n);
+        if (k < dh) {
+            const int j0 = sp ? nu : 0, j1 = sp ? N : nu;
+            for (int j = j0; j < j1; ++j) v += h0[j * jstride + k];
+            v *= sp ? id : iu;
         }
-        G[id] = v;
+        g[col] = v;
     }
 }
 
@@ -255,21 +254,21 @@ __global__ void k_spin_mean(const T *H, int64_t ldh, int64_t B, int N, int nu, i
 // forward-Laplacian form, plus the residual h_i when widths match (l >= 1).
 // ---------------------------------------------------------------------------
 template <typename T, bool FL>
-__global__ void k_layer_epi(const T *X, const T *Pw, const T *bias, const T *Hin, T *Hout, int64_t ldh, int64_t B,
-                            int N, int TR, int n3, int w1, int W1p, int resid)
+__global__ __launch_bounds__(256) void k_layer_epi(const T *__restrict__ X, const T *__restrict__ Pw,
+                                                   const T *__restrict__ bias, const T *__restrict__ Hin,
+                                                   T *__restrict__ Hout, int64_t ldh, int N, int TR, int n3, int w1,
+                                                   int W1p, int resid)
 {
-    const int64_t total = B * N * W1p;
-    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < total; id += (int64_t)gridDim.x * blockDim.x) {
-        const int o = (int)(id % W1p);
-        const int64_t wi = id / W1p;
-        const int64_t w = wi / N;
-        const int64_t r0 = wi * TR;
+    const int wi = blockIdx.x;              // walker * N + electron
+    const int w = wi / N;
+    const int64_t r0 = (int64_t)wi * TR;
+    for (int o = threadIdx.x; o < W1p; o += blockDim.x) {
         if (o >= w1) {
             for (int t = 0; t < TR; ++t) Hout[(r0 + t) * ldh + o] = T(0);
             continue;
         }
         const T *xp = X + r0 * w1 + o;
-        const T *pp = Pw + w * TR * w1 + o;
+        const T *pp = Pw + (int64_t)w * TR * w1 + o;
         const T z0 = xp[0] + pp[0] + bias[o];
         const T y0 = tanh(z0);
         const T d = T(1) - y0 * y0;
@@ -589,7 +588,7 @@ void launch_pack_head(const T *theta, int64_t woff, int w1, int W1p, int kn, int
 template <typename T>
 void launch_features(const Sys &s, const double *x, int64_t B, int TR, int HW0, int64_t ldh, T *H, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_features<T>, dim3(grid_for(B * s.N * TR)), dim3(256), 0, st, s, x, B, TR, HW0, ldh, H);
+    hipLaunchKernelGGL(k_features<T>, dim3((unsigned)(B * s.N)), dim3(256), 0, st, s, x, TR, HW0, ldh, H);
 }
 
 size_t pair_stream_lds(const Sys &s, bool fl, size_t elem)
@@ -616,20 +615,19 @@ template <typename T>
 void launch_spin_mean(const T *H, int64_t ldh, int64_t B, int N, int nu, int TR, int dh, int HWl, T *G,
                       hipStream_t st)
 {
-    hipLaunchKernelGGL(k_spin_mean<T>, dim3(grid_for(B * TR * 2 * HWl)), dim3(256), 0, st, H, ldh, B, N, nu, TR, dh,
-                       HWl, G);
+    hipLaunchKernelGGL(k_spin_mean<T>, dim3((unsigned)(B * TR)), dim3(256), 0, st, H, ldh, N, nu, TR, dh, HWl, G);
 }
 
 template <typename T>
 void launch_layer_epi(const T *X, const T *Pw, const T *bias, const T *Hin, T *Hout, int64_t ldh, int64_t B, int N,
                       int TR, int n3, int w1, int W1p, int resid, bool fl, hipStream_t st)
 {
-    dim3 g(grid_for(B * N * W1p));
+    dim3 g((unsigned)(B * N));
     if (fl)
-        hipLaunchKernelGGL((k_layer_epi<T, true>), g, dim3(256), 0, st, X, Pw, bias, Hin, Hout, ldh, B, N, TR, n3, w1,
+        hipLaunchKernelGGL((k_layer_epi<T, true>), g, dim3(256), 0, st, X, Pw, bias, Hin, Hout, ldh, N, TR, n3, w1,
                            W1p, resid);
     else
-        hipLaunchKernelGGL((k_layer_epi<T, false>), g, dim3(256), 0, st, X, Pw, bias, Hin, Hout, ldh, B, N, TR, n3, w1,
+        hipLaunchKernelGGL((k_layer_epi<T, false>), g, dim3(256), 0, st, X, Pw, bias, Hin, Hout, ldh, N, TR, n3, w1,
                            W1p, resid);
 }
 

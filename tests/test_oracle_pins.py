@@ -489,3 +489,19 @@ def test_vmc_gradient_hydrogenic_scale():
     grad = 2.0 * np.mean((e - e.mean()) * dl)
     se = 2.0 * np.std((e - e.mean()) * dl) / np.sqrt(B)
     assert abs(grad - (sc - z)) < 5 * se
+
+
+def test_orbital_matrices_reproduce_log_psi():
+    """The exported orbital matrices give back the oracle's log|psi| through a
+    library slogdet and the determinant sum."""
+    s = I.System("LiF-s", I.lif().nuc_xyz, I.lif().nuc_z, 3, 2, 2, 8, 4, 3, 4, (0, 1, 1, 0, 1), 0.5)
+    th = I.init_params(s, seed=91)
+    x = I.init_walkers(s, 6, seed=92)
+    o = O.Oracle(s)
+    A = o.orbital_matrices(th, x)
+    su, lu = np.linalg.slogdet(A[:, 0, :, :3, :3])
+    sd, ld = np.linalg.slogdet(A[:, 1, :, :2, :2])
+    psi = (su * sd * np.exp(lu + ld)).sum(1)
+    ref = o.log_psi(th, x)
+    np.testing.assert_allclose(np.log(np.abs(psi)), ref["log_abs"], atol=1e-11)
+    np.testing.assert_array_equal(np.sign(psi), ref["sign"])
