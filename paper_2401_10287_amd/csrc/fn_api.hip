@@ -169,13 +169,16 @@ size_t al(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of every buffer in the caller's workspace.
 struct Plan {
-    bool fl;
+    bool fl, save;
     int TR, rec;
     int64_t Bc;
-    size_t wx[FN_MAX_LAYERS], wg[FN_MAX_LAYERS], wh[2];
+    size_t wx[FN_MAX_LAYERS], wg[FN_MAX_LAYERS], wh[2], wb[2];
     int64_t wxpart[FN_MAX_LAYERS], wgpart[FN_MAX_LAYERS];   // elements per BF16 part
-    size_t H[2], GI, G, Pw, X, O, Phi[2], DR, xp, lpn, u;
+    size_t H[FN_MAX_LAYERS + 1], GI, G, Pw, X, O[2], Phi[2], DR, xp, lpn, u;
+    // backward
+    size_t Tl, GA[2], Ga[2], EP[2], Gy[2], Gz, SGz, Gh, Gg, GGI, PP, part, gacc, coeff;
     int64_t gi_layer_stride;   // elements
+    int64_t npp, part_elems;
     size_t total;
 };
 
@@ -185,15 +188,22 @@ fn_status make_plan(const Ctx &c, int64_t B, int op, Plan &p)
 {
     const Sys &s = c.s;
     if (op < FN_OP_LOG_PSI || op > FN_OP_PARAM_GRAD) return fail(FN_EINVAL, "unknown op");
+    p = Plan{};
     p.fl = op == FN_OP_LOCAL_ENERGY;
+    p.save = op == FN_OP_PARAM_GRAD;
     const int n3 = 3 * s.N;
     p.TR = p.fl ? fl_rows(s.N) : 1;
     p.rec = n3 + 3;
     const int nmax = std::max(s.nu, s.nd);
     if (pair_stream_lds(s, p.fl, c.esz) > 64 * 1024) return fail(FN_EUNSUPPORTED, "pair stream exceeds LDS");
     if (det_lds(nmax, n3, p.fl, sizeof(double)) > 64 * 1024) return fail(FN_EUNSUPPORTED, "determinant exceeds LDS");
+    if (p.save) {
+        if (s.w1 % 32 != 0) return fail(FN_EUNSUPPORTED, "parameter gradients need w1 to be a multiple of 32");
+        if (pair_backward_lds(s, c.esz) > 64 * 1024) return fail(FN_EUNSUPPORTED, "pair backward exceeds LDS");
+        if (det_backward_lds(nmax) > 64 * 1024) return fail(FN_EUNSUPPORTED, "determinant backward exceeds LDS");
+    }
     size_t o = 0;
-    const size_t se = gemm_elem(c.smode), he = gemm_elem(c.hmode);
+    const size_t se = gemm_elem(c.smode), he = gemm_elem(c.hmode), e = c.esz;
     const int np = gemm_parts(c.smode);
     for (int l = 0; l < s.L; ++l) {
         size_t nx = (size_t)s.w1 * (c.W.HWl[l] + c.W.GWl[l]), ng = (size_t)s.w1 * 2 * c.W.HWl[l];
@@ -206,36 +216,81 @@ fn_status make_plan(const Ctx &c, int64_t B, int op, Plan &p)
         int n = sp == 0 ? s.nu : s.nd;
         size_t nh = (size_t)s.K * n * c.W.W1p;
         p.wh[sp] = o; o = al(o + nh * he);
+        p.wb[sp] = o; if (p.save) o = al(o + (size_t)s.w1 * c.W.KNp[sp] * e);
     }
-    const size_t wbytes = o;
-    const size_t TR = p.TR, N = s.N, e = c.esz;
-    const size_t per_walker = 2 * N * TR * c.W.HWmax * e + s.L * N * TR * c.W.GWmax * e + TR * 2 * c.W.HWmax * e +
-                              TR * s.w1 * e + N * TR * s.w1 * e + nmax * TR * std::max(c.W.KNp[0], c.W.KNp[1]) * e +
-                              ((size_t)s.K * TR * (s.nu * s.nu + s.nd * s.nd)) * 8 + 2 * s.K * p.rec * 8 +
-                              (n3 + 2) * 8 + 16 * ALIGN / 64;
-    int64_t bc = (int64_t)(CHUNK_BYTES / per_walker);
+    // sizes that do not scale with the walker chunk
+    p.npp = s.L > 1 ? (c.P.c2[s.L - 2] + s.w2 - c.P.W2[0]) : 0;
+    int64_t pe = 0;
+    if (p.save) {
+        const int64_t kn_max = (int64_t)s.K * nmax;
+        pe = std::max<int64_t>(pe, (int64_t)s.w1 * std::max<int64_t>(std::max(c.W.HWmax, 2 * c.W.GWmax), kn_max));
+        pe = std::max<int64_t>(pe, kn_max * s.M * 10);
+        pe = std::max<int64_t>(pe, p.npp);
+        pe = std::max<int64_t>(pe, c.W.KNp[0] > c.W.KNp[1] ? c.W.KNp[0] : c.W.KNp[1]);
+        pe *= max_splits();
+    }
+    p.part_elems = pe;
+    p.part = o; o = al(o + (size_t)pe * e);
+    const int64_t P = c.P.total;
+    p.gacc = o; if (p.save) o = al(o + (size_t)P * 8);
+    p.coeff = o; if (p.save) o = al(o + (size_t)B * 8);
+    p.xp = o; o = al(o + (size_t)B * n3 * 8);
+    p.lpn = o; o = al(o + (size_t)B * 8);
+    p.u = o; o = al(o + (size_t)B * 8);
+
+    // per-walker buffers, laid out for a chunk of bc walkers
+    const size_t TR = p.TR, N = s.N;
+    const int nH = p.save ? s.L + 1 : 2;
+    struct Item { size_t *off; size_t bytes_per_walker; };
+    const size_t knp_max = std::max(c.W.KNp[0], c.W.KNp[1]);
+    Item items[] = {
+        {&p.GI, (size_t)s.L * N * TR * c.W.GWmax * e},
+        {&p.G, TR * 2 * c.W.HWmax * e},
+        {&p.Pw, TR * s.w1 * e},
+        {&p.X, N * TR * s.w1 * e},
+        {&p.O[0], (size_t)s.nu * TR * c.W.KNp[0] * e},
+        {&p.O[1], (size_t)s.nd * TR * c.W.KNp[1] * e},
+        {&p.Phi[0], (size_t)s.K * TR * s.nu * s.nu * 8},
+        {&p.Phi[1], (size_t)s.K * TR * s.nd * s.nd * 8},
+        {&p.DR, (size_t)2 * s.K * p.rec * 8},
+        {&p.Tl, p.save ? (size_t)s.L * N * s.w1 * e : 0},
+        {&p.GA[0], p.save ? (size_t)s.K * s.nu * s.nu * 8 : 0},
+        {&p.GA[1], p.save ? (size_t)s.K * s.nd * s.nd * 8 : 0},
+        {&p.Ga[0], p.save ? (size_t)s.nu * c.W.KNp[0] * e : 0},
+        {&p.Ga[1], p.save ? (size_t)s.nd * c.W.KNp[1] * e : 0},
+        {&p.EP[0], p.save ? (size_t)s.K * s.nu * s.M * 10 * e : 0},
+        {&p.EP[1], p.save ? (size_t)s.K * s.nd * s.M * 10 * e : 0},
+        {&p.Gy[0], p.save ? N * s.w1 * e : 0},
+        {&p.Gy[1], p.save ? N * s.w1 * e : 0},
+        {&p.Gz, p.save ? N * s.w1 * e : 0},
+        {&p.SGz, p.save ? (size_t)s.w1 * e : 0},
+        {&p.Gh, p.save ? N * c.W.HWmax * e : 0},
+        {&p.Gg, p.save ? 2 * c.W.HWmax * e : 0},
+        {&p.GGI, p.save ? (size_t)s.L * N * c.W.GWmax * e : 0},
+        {&p.PP, p.save ? N * (size_t)p.npp * e : 0},
+    };
+    (void)knp_max;
+    size_t per_walker = N * TR * c.W.HWmax * e * nH;
+    for (const Item &it : items) per_walker += it.bytes_per_walker;
+    per_walker += sizeof(items) / sizeof(items[0]) * 8;   // alignment slack
+    int64_t bc = (int64_t)(CHUNK_BYTES / std::max<size_t>(per_walker, 1));
     if (bc < 64) bc = 64;
     if (bc >= B) bc = B;
     else bc = bc / 64 * 64;
     if (bc < 1) bc = 1;
     p.Bc = bc;
-    const size_t rows = (size_t)bc * N * TR;
-    p.H[0] = o; o = al(o + rows * c.W.HWmax * e);
-    p.H[1] = o; o = al(o + rows * c.W.HWmax * e);
-    p.gi_layer_stride = (int64_t)(rows * c.W.GWmax);
-    p.GI = o; o = al(o + (size_t)s.L * rows * c.W.GWmax * e);
-    p.G = o; o = al(o + (size_t)bc * TR * 2 * c.W.HWmax * e);
-    p.Pw = o; o = al(o + (size_t)bc * TR * s.w1 * e);
-    p.X = o; o = al(o + rows * s.w1 * e);
-    p.O = o; o = al(o + (size_t)bc * nmax * TR * std::max(c.W.KNp[0], c.W.KNp[1]) * e);
-    p.Phi[0] = o; o = al(o + (size_t)bc * s.K * TR * s.nu * s.nu * 8);
-    p.Phi[1] = o; o = al(o + (size_t)bc * s.K * TR * s.nd * s.nd * 8);
-    p.DR = o; o = al(o + (size_t)bc * 2 * s.K * p.rec * 8);
-    p.xp = o; o = al(o + (size_t)B * n3 * 8);
-    p.lpn = o; o = al(o + (size_t)B * 8);
-    p.u = o; o = al(o + (size_t)B * 8);
+    for (Item &it : items) {
+        *it.off = o;
+        o = al(o + it.bytes_per_walker * (size_t)bc);
+    }
+    // stream activations: nH buffers of one chunk each (2 ping-pong, or L + 1 kept for the backward pass)
+    const size_t hbytes = al((size_t)bc * N * TR * c.W.HWmax * e);
+    for (int l = 0; l < nH; ++l) {
+        p.H[l] = o;
+        o += hbytes;
+    }
+    p.gi_layer_stride = (int64_t)((size_t)bc * N * TR * c.W.GWmax);
     p.total = o;
-    (void)wbytes;
     return FN_OK;
 }
 
@@ -251,97 +306,195 @@ void pack_weights(const Ctx &c, const Plan &p, const T *theta, char *ws, hipStre
         int n = sp == 0 ? s.nu : s.nd;
         if (n == 0) continue;
         launch_pack_head<T>(theta, c.P.w[sp], s.w1, c.W.W1p, s.K * n, c.hmode, ws + p.wh[sp], st);
+        if (p.save) launch_pack_head_bwd<T>(theta, c.P.w[sp], s.w1, s.K * n, c.W.KNp[sp], (T *)(ws + p.wb[sp]), st);
     }
 }
 
-// Forward pass over walkers [0, B) of x, chunk by chunk.  Weights are packed.
+// Forward pass of walkers [w0, w0 + b) (one chunk).  Weights are packed.  With
+// p.save the stream activations of every layer and the tanh outputs are kept
+// for the backward pass.
 template <typename T>
-void forward(const Ctx &c, const Plan &p, const T *theta, const double *x, int64_t B, double *log_abs, int8_t *sign,
-             double *e_loc, double *parts, char *ws, hipStream_t st)
+void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw, int64_t b, double *log_abs,
+                   int8_t *sign, double *e_loc, double *parts, char *ws, hipStream_t st)
 {
     const Sys &s = c.s;
     const int TR = p.TR, n3 = 3 * s.N;
     const bool fl = p.fl;
-    T *H[2] = {(T *)(ws + p.H[0]), (T *)(ws + p.H[1])};
+    auto Hbuf = [&](int l) -> T * { return (T *)(ws + p.H[p.save ? l : (l & 1)]); };
     T *GI = (T *)(ws + p.GI);
     T *G = (T *)(ws + p.G);
     T *Pw = (T *)(ws + p.Pw);
     T *X = (T *)(ws + p.X);
-    T *O = (T *)(ws + p.O);
     double *DR = (double *)(ws + p.DR);
     const int64_t ldh = c.W.HWmax, ldg = c.W.GWmax;
+    { Timed t_(K_FEATURES, st); launch_features<T>(s, xw, b, TR, c.W.HWl[0], ldh, Hbuf(0), st); }
+    {
+        Timed t_(K_PAIR, st);
+        launch_pair_stream<T>(s, xw, theta, c.P, b, TR, fl, ldg, p.gi_layer_stride, c.W.GWl[0],
+                              s.L > 1 ? c.W.GWl[1] : c.W.GWl[0], GI, st);
+    }
+    for (int l = 0; l < s.L; ++l) {
+        const int dh = layer_dh(s, l), HWl = c.W.HWl[l], GWl = c.W.GWl[l];
+        T *Hin = Hbuf(l), *Hout = Hbuf(l + 1);
+        { Timed t_(K_SPIN_MEAN, st); launch_spin_mean<T>(Hin, ldh, b, s.N, s.nu, TR, dh, HWl, G, st); }
+        GemmArgs ga{};
+        ga.A1 = G; ga.lda1 = 2 * HWl; ga.K1 = 2 * HWl;
+        ga.W = ws + p.wg[l]; ga.wpart = p.wgpart[l]; ga.ldw = 2 * HWl;
+        ga.C = Pw; ga.ldc = s.w1;
+        ga.rows = b * TR; ga.nout = s.w1;
+        ga.rows_per_group = ga.rows;
+        { Timed t_(K_WALKER_GEMM, st); (void)launch_gemm(c.smode, ga, st); }
+        bool fused = false;
+        if constexpr (std::is_same<T, float>::value) fused = !p.save && stream_layer_supported(c.smode, TR, c.W.W1p);
+        if constexpr (std::is_same<T, float>::value) if (fused) {
+            LayerArgs la{};
+            la.A1 = Hin; la.lda1 = ldh; la.K1 = HWl;
+            la.A2 = GI + (int64_t)l * p.gi_layer_stride; la.lda2 = ldg; la.K2 = GWl;
+            la.W = ws + p.wx[l]; la.wpart = p.wxpart[l]; la.ldw = HWl + GWl; la.nout = s.w1;
+            la.Pw = Pw; la.bias = theta + c.P.b[l];
+            la.Hout = Hout; la.ldh_out = ldh;
+            la.rows = b * s.N * TR; la.N = s.N; la.n3 = n3; la.w1 = s.w1; la.W1p = c.W.W1p;
+            la.resid = l >= 1 ? 1 : 0;
+            Timed t_(K_STREAM_GEMM, st);
+            launch_stream_layer(c.smode, la, TR, st);
+        }
+        if (!fused) {
+            GemmArgs gx{};
+            gx.A1 = Hin; gx.lda1 = ldh; gx.K1 = HWl;
+            gx.A2 = GI + (int64_t)l * p.gi_layer_stride; gx.lda2 = ldg; gx.K2 = GWl;
+            gx.W = ws + p.wx[l]; gx.wpart = p.wxpart[l]; gx.ldw = HWl + GWl;
+            gx.C = X; gx.ldc = s.w1;
+            gx.rows = b * s.N * TR; gx.nout = s.w1;
+            gx.rows_per_group = gx.rows;
+            { Timed t_(K_STREAM_GEMM, st); (void)launch_gemm(c.smode, gx, st); }
+            Timed t_(K_EPI, st);
+            T *Tout = p.save ? (T *)(ws + p.Tl) + (int64_t)l * b * s.N * s.w1 : nullptr;
+            launch_layer_epi<T>(X, Pw, theta + c.P.b[l], Hin, Hout, ldh, b, s.N, TR, n3, s.w1, c.W.W1p,
+                                l >= 1 ? 1 : 0, fl, Tout, st);
+        }
+    }
+    T *HL = Hbuf(s.L);
+    for (int sp = 0; sp < 2; ++sp) {
+        const int n = sp == 0 ? s.nu : s.nd, j0 = sp == 0 ? 0 : s.nu;
+        if (n == 0) continue;
+        T *O = (T *)(ws + p.O[sp]);
+        GemmArgs gh{};
+        gh.A1 = HL; gh.lda1 = ldh; gh.K1 = c.W.W1p;
+        gh.W = ws + p.wh[sp]; gh.ldw = c.W.W1p;
+        gh.C = O; gh.ldc = c.W.KNp[sp];
+        gh.rows = b * n * TR; gh.nout = s.K * n;
+        gh.rows_per_group = (int64_t)n * TR; gh.group_stride = (int64_t)s.N * TR; gh.row_offset = (int64_t)j0 * TR;
+        { Timed t_(K_HEAD_GEMM, st); (void)launch_gemm(c.hmode, gh, st); }
+        double *Phi = (double *)(ws + p.Phi[sp]);
+        {
+            Timed t_(K_ENV, st);
+            launch_envelope<T>(s, xw, theta, c.P.g[sp], c.P.pi[sp], c.P.sig[sp], sp, O, c.W.KNp[sp], b, TR, fl, Phi,
+                               st);
+        }
+        { Timed t_(K_DET, st); launch_det(Phi, b, s.K, n, TR, n3, sp, fl, DR, p.rec, st); }
+    }
+    Timed t_(K_COMBINE, st);
+    launch_combine(s, xw, DR, p.rec, b, c.vnn, log_abs, sign, e_loc, parts, fl, st);
+}
+
+template <typename T>
+void forward(const Ctx &c, const Plan &p, const T *theta, const double *x, int64_t B, double *log_abs, int8_t *sign,
+             double *e_loc, double *parts, char *ws, hipStream_t st)
+{
+    const int n3 = 3 * c.s.N;
     for (int64_t w0 = 0; w0 < B; w0 += p.Bc) {
         const int64_t b = std::min(p.Bc, B - w0);
-        const double *xw = x + w0 * n3;
-        { Timed t_(K_FEATURES, st); launch_features<T>(s, xw, b, TR, c.W.HWl[0], ldh, H[0], st); }
-        {
-            Timed t_(K_PAIR, st);
-            launch_pair_stream<T>(s, xw, theta, c.P, b, TR, fl, ldg, p.gi_layer_stride, c.W.GWl[0],
-                                  s.L > 1 ? c.W.GWl[1] : c.W.GWl[0], GI, st);
-        }
-        int cur = 0;
-        for (int l = 0; l < s.L; ++l) {
-            const int dh = layer_dh(s, l), HWl = c.W.HWl[l], GWl = c.W.GWl[l];
-            { Timed t_(K_SPIN_MEAN, st); launch_spin_mean<T>(H[cur], ldh, b, s.N, s.nu, TR, dh, HWl, G, st); }
-            GemmArgs ga{};
-            ga.A1 = G; ga.lda1 = 2 * HWl; ga.K1 = 2 * HWl;
-            ga.A2 = nullptr; ga.lda2 = 0; ga.K2 = 0;
-            ga.W = ws + p.wg[l]; ga.wpart = p.wgpart[l]; ga.ldw = 2 * HWl;
-            ga.C = Pw; ga.ldc = s.w1;
-            ga.rows = b * TR; ga.nout = s.w1;
-            ga.rows_per_group = ga.rows; ga.group_stride = 0; ga.row_offset = 0;
-            { Timed t_(K_WALKER_GEMM, st); (void)launch_gemm(c.smode, ga, st); }
-            bool fused = false;
-            if constexpr (std::is_same<T, float>::value) fused = stream_layer_supported(c.smode, TR, c.W.W1p);
-            if constexpr (std::is_same<T, float>::value) if (fused) {
-                LayerArgs la{};
-                la.A1 = H[cur]; la.lda1 = ldh; la.K1 = HWl;
-                la.A2 = GI + (int64_t)l * p.gi_layer_stride; la.lda2 = ldg; la.K2 = GWl;
-                la.W = ws + p.wx[l]; la.wpart = p.wxpart[l]; la.ldw = HWl + GWl; la.nout = s.w1;
-                la.Pw = Pw; la.bias = theta + c.P.b[l];
-                la.Hout = H[cur ^ 1]; la.ldh_out = ldh;
-                la.rows = b * s.N * TR; la.N = s.N; la.n3 = n3; la.w1 = s.w1; la.W1p = c.W.W1p;
-                la.resid = l >= 1 ? 1 : 0;
-                Timed t_(K_STREAM_GEMM, st);
-                launch_stream_layer(c.smode, la, TR, st);
-            }
-            if (!fused) {
-                GemmArgs gx{};
-                gx.A1 = H[cur]; gx.lda1 = ldh; gx.K1 = HWl;
-                gx.A2 = GI + (int64_t)l * p.gi_layer_stride; gx.lda2 = ldg; gx.K2 = GWl;
-                gx.W = ws + p.wx[l]; gx.wpart = p.wxpart[l]; gx.ldw = HWl + GWl;
-                gx.C = X; gx.ldc = s.w1;
-                gx.rows = b * s.N * TR; gx.nout = s.w1;
-                gx.rows_per_group = gx.rows; gx.group_stride = 0; gx.row_offset = 0;
-                { Timed t_(K_STREAM_GEMM, st); (void)launch_gemm(c.smode, gx, st); }
-                Timed t_(K_EPI, st);
-                launch_layer_epi<T>(X, Pw, theta + c.P.b[l], H[cur], H[cur ^ 1], ldh, b, s.N, TR, n3, s.w1, c.W.W1p,
-                                    l >= 1 ? 1 : 0, fl, st);
-            }
-            cur ^= 1;
-        }
-        for (int sp = 0; sp < 2; ++sp) {
-            const int n = sp == 0 ? s.nu : s.nd, j0 = sp == 0 ? 0 : s.nu;
-            if (n == 0) continue;
-            GemmArgs gh{};
-            gh.A1 = H[cur]; gh.lda1 = ldh; gh.K1 = c.W.W1p;
-            gh.A2 = nullptr; gh.K2 = 0;
-            gh.W = ws + p.wh[sp]; gh.wpart = 0; gh.ldw = c.W.W1p;
-            gh.C = O; gh.ldc = c.W.KNp[sp];
-            gh.rows = b * n * TR; gh.nout = s.K * n;
-            gh.rows_per_group = (int64_t)n * TR; gh.group_stride = (int64_t)s.N * TR; gh.row_offset = (int64_t)j0 * TR;
-            { Timed t_(K_HEAD_GEMM, st); (void)launch_gemm(c.hmode, gh, st); }
-            double *Phi = (double *)(ws + p.Phi[sp]);
-            {
-                Timed t_(K_ENV, st);
-                launch_envelope<T>(s, xw, theta, c.P.g[sp], c.P.pi[sp], c.P.sig[sp], sp, O, c.W.KNp[sp], b, TR, fl,
-                                   Phi, st);
-            }
-            { Timed t_(K_DET, st); launch_det(Phi, b, s.K, n, TR, n3, sp, fl, DR, p.rec, st); }
-        }
-        Timed t_(K_COMBINE, st);
-        launch_combine(s, xw, DR, p.rec, b, c.vnn, log_abs ? log_abs + w0 : nullptr, sign ? sign + w0 : nullptr,
-                       e_loc ? e_loc + w0 : nullptr, parts ? parts + 4 * w0 : nullptr, fl, st);
+        forward_chunk<T>(c, p, theta, x + w0 * n3, b, log_abs ? log_abs + w0 : nullptr, sign ? sign + w0 : nullptr,
+                         e_loc ? e_loc + w0 : nullptr, parts ? parts + 4 * w0 : nullptr, ws, st);
+    }
+}
+
+// Reverse pass for walkers [w0, w0 + b) after forward_chunk with p.save:
+// accumulates sum_p coeff_p d log|psi_p| / d theta into the FP64 buffer gacc.
+template <typename T>
+void backward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw, const double *coeff, int64_t b,
+                    char *ws, hipStream_t st)
+{
+    Timed t_(K_BACKWARD, st);
+    const Sys &s = c.s;
+    const int N = s.N, w1 = s.w1;
+    const int gmode = c.f64 ? GEMM_F64 : GEMM_F32;
+    double *gacc = (double *)(ws + p.gacc);
+    T *part = (T *)(ws + p.part);
+    const int64_t rows = b * N;
+    const int64_t ldh = c.W.HWmax, ldg = c.W.GWmax;
+    T *Gy = (T *)(ws + p.Gy[0]), *Gy2 = (T *)(ws + p.Gy[1]);
+    // determinants, envelope and orbital head, per spin
+    for (int sp = 0; sp < 2; ++sp) {
+        const int n = sp == 0 ? s.nu : s.nd, j0 = sp == 0 ? 0 : s.nu;
+        if (n == 0) continue;
+        const int kn = s.K * n, KNp = c.W.KNp[sp];
+        double *GA = (double *)(ws + p.GA[sp]);
+        T *Ga = (T *)(ws + p.Ga[sp]);
+        T *EP = (T *)(ws + p.EP[sp]);
+        launch_det_backward((const double *)(ws + p.Phi[sp]), (const double *)(ws + p.DR), coeff, b, s.K, n, sp, s.nu,
+                            s.nd, p.rec, GA, st);
+        launch_env_backward<T>(s, xw, theta, c.P.g[sp], c.P.pi[sp], c.P.sig[sp], sp, (const T *)(ws + p.O[sp]), KNp,
+                               GA, b, KNp, Ga, EP, st);
+        launch_colsum<T>(EP, (int64_t)kn * s.M * 10, kn * s.M * 10, b, part, gacc, c.P.pi[sp], 1, c.P.sig[sp], st);
+        launch_colsum<T>(Ga, KNp, kn, b * n, part, gacc, c.P.g[sp], 0, 0, st);
+        launch_tn<T>((const T *)(ws + p.H[s.L]), ldh, w1, Ga, KNp, kn, b * n, n, N, j0, part, gacc, c.P.w[sp], kn, st);
+        GemmArgs g{};
+        g.A1 = Ga; g.lda1 = KNp; g.K1 = KNp;
+        g.W = ws + p.wb[sp]; g.ldw = KNp;
+        g.C = Gy; g.ldc = w1;
+        g.rows = b * n; g.nout = w1;
+        g.rows_per_group = g.rows;
+        g.c_rows_per_group = n; g.c_group_stride = N; g.c_row_offset = j0;
+        (void)launch_gemm(gmode, g, st);
+    }
+    // one-electron layers, top down
+    T *Gz = (T *)(ws + p.Gz), *SGz = (T *)(ws + p.SGz), *Gh = (T *)(ws + p.Gh), *Gg = (T *)(ws + p.Gg);
+    T *G = (T *)(ws + p.G);
+    T *GGI = (T *)(ws + p.GGI);
+    for (int l = s.L - 1; l >= 0; --l) {
+        const int dh = layer_dh(s, l), dp = layer_dp(s, l), HWl = c.W.HWl[l];
+        const T *Hl = (const T *)(ws + p.H[l]);
+        const T *Tl = (const T *)(ws + p.Tl) + (int64_t)l * rows * w1;
+        const int64_t voff = c.P.V[l];
+        launch_bwd_gz<T>(Gy, Tl, b, N, w1, Gz, SGz, st);
+        launch_colsum<T>(Gz, w1, w1, rows, part, gacc, c.P.b[l], 0, 0, st);
+        launch_tn<T>(Hl, ldh, dh, Gz, w1, w1, rows, 0, 0, 0, part, gacc, voff, w1, st);
+        const T *GIl = (const T *)(ws + p.GI) + (int64_t)l * p.gi_layer_stride;
+        launch_tn<T>(GIl, ldg, 2 * dp, Gz, w1, w1, rows, 0, 0, 0, part, gacc, voff + (int64_t)3 * dh * w1, w1, st);
+        launch_spin_mean<T>(Hl, ldh, b, N, s.nu, 1, dh, HWl, G, st);
+        launch_tn<T>(G, 2 * HWl, dh, SGz, w1, w1, b, 0, 0, 0, part, gacc, voff + (int64_t)dh * w1, w1, st);
+        launch_tn<T>(G + HWl, 2 * HWl, dh, SGz, w1, w1, b, 0, 0, 0, part, gacc, voff + (int64_t)2 * dh * w1, w1, st);
+        // adjoints of the pair means (to the pair stream) and of h^l
+        GemmArgs gq{};
+        gq.A1 = Gz; gq.lda1 = w1; gq.K1 = w1;
+        gq.W = theta + voff + (int64_t)3 * dh * w1; gq.ldw = w1;
+        gq.C = GGI + (int64_t)l * p.gi_layer_stride; gq.ldc = ldg;
+        gq.rows = rows; gq.nout = 2 * dp;
+        gq.rows_per_group = rows;
+        (void)launch_gemm(gmode, gq, st);
+        if (l == 0) break;
+        GemmArgs gh{};
+        gh.A1 = Gz; gh.lda1 = w1; gh.K1 = w1;
+        gh.W = theta + voff; gh.ldw = w1;
+        gh.C = Gh; gh.ldc = dh;
+        gh.rows = rows; gh.nout = dh;
+        gh.rows_per_group = rows;
+        (void)launch_gemm(gmode, gh, st);
+        GemmArgs gg{};
+        gg.A1 = SGz; gg.lda1 = w1; gg.K1 = w1;
+        gg.W = theta + voff + (int64_t)dh * w1; gg.ldw = w1;
+        gg.C = Gg; gg.ldc = 2 * dh;
+        gg.rows = b; gg.nout = 2 * dh;
+        gg.rows_per_group = b;
+        (void)launch_gemm(gmode, gg, st);
+        launch_bwd_gh<T>(Gh, Gy, Gg, b, N, s.nu, dh, w1, 1, Gy2, st);
+        std::swap(Gy, Gy2);
+    }
+    if (s.L > 1) {
+        T *PP = (T *)(ws + p.PP);
+        launch_pair_backward<T>(s, xw, theta, c.P, b, GGI, ldg, p.gi_layer_stride, PP, p.npp, st);
+        launch_colsum<T>(PP, p.npp, (int)p.npp, rows, part, gacc, c.P.W2[0], 0, 0, st);
     }
 }
 
@@ -389,6 +542,32 @@ fn_status run_metropolis(const Ctx &c, const Plan &p, const void *theta, double 
         forward<T>(c, p, (const T *)theta, xp, B, lpn, nullptr, nullptr, nullptr, w, st);
         { Timed t_(K_ACCEPT, st); launch_accept(x, log_abs, xp, lpn, uu, B, n3, n_accept, st); }
     }
+    return hip_status();
+}
+
+template <typename T>
+fn_status run_backward(const Ctx &c, const Plan &p, const void *theta, const double *x, int64_t B,
+                       const double *coeff_in, const double *e_loc, double *stats, void *grad, void *ws, hipStream_t st)
+{
+    char *w = (char *)ws;
+    const T *th = (const T *)theta;
+    const int n3 = 3 * c.s.N;
+    double *gacc = (double *)(w + p.gacc);
+    const double *coeff = coeff_in;
+    if (e_loc) {
+        double *cf = (double *)(w + p.coeff);
+        launch_energy_stats(e_loc, B, stats, cf, st);
+        coeff = cf;
+    }
+    launch_zero_f64(gacc, c.P.total, st);
+    pack_weights<T>(c, p, th, w, st);
+    double *lp = (double *)(w + p.lpn);
+    for (int64_t w0 = 0; w0 < B; w0 += p.Bc) {
+        const int64_t b = std::min(p.Bc, B - w0);
+        forward_chunk<T>(c, p, th, x + w0 * n3, b, lp + w0, nullptr, nullptr, nullptr, w, st);
+        backward_chunk<T>(c, p, th, x + w0 * n3, coeff + w0, b, w, st);
+    }
+    launch_grad_out<T>(gacc, c.P.total, (T *)grad, st);
     return hip_status();
 }
 
@@ -487,19 +666,43 @@ fn_status vmc_metropolis_step_ext(const fn_config *cfg, const void *theta, doubl
                              stream);
 }
 
+static fn_status grad_common(const fn_config *cfg, const void *theta, const double *x, int64_t B,
+                             const double *coeff, const double *e_loc, double *stats, void *grad, void *ws,
+                             size_t ws_bytes, void *stream)
+{
+    Ctx c;
+    fn_status r = make_ctx(cfg, c);
+    if (r) return r;
+    if (B < 0) return fail(FN_EINVAL, "B < 0");
+    if (!grad || !theta) return fail(FN_EINVAL, "theta or grad is NULL");
+    if (((uintptr_t)theta) % 16) return fail(FN_EINVAL, "theta must be 16-byte aligned");
+    if (B > 0 && !x) return fail(FN_EINVAL, "x is NULL");
+    Plan p;
+    if ((r = make_plan(c, B, FN_OP_PARAM_GRAD, p))) return r;
+    if ((r = check_ws(p, ws, ws_bytes))) return r;
+    hipStream_t st = (hipStream_t)stream;
+    if (B == 0) {
+        launch_zero_f64((double *)((char *)ws + p.gacc), c.P.total, st);
+        if (c.f64) launch_grad_out<double>((double *)((char *)ws + p.gacc), c.P.total, (double *)grad, st);
+        else launch_grad_out<float>((double *)((char *)ws + p.gacc), c.P.total, (float *)grad, st);
+        return hip_status();
+    }
+    return c.f64 ? run_backward<double>(c, p, theta, x, B, coeff, e_loc, stats, grad, ws, st)
+                 : run_backward<float>(c, p, theta, x, B, coeff, e_loc, stats, grad, ws, st);
+}
+
 fn_status fn_param_grad(const fn_config *cfg, const void *theta, const double *x, int64_t B, const double *e_loc,
                         void *grad, double *stats, void *ws, size_t ws_bytes, void *stream)
 {
-    (void)cfg; (void)theta; (void)x; (void)B; (void)e_loc; (void)grad; (void)stats; (void)ws; (void)ws_bytes;
-    (void)stream;
-    return fail(FN_EUNSUPPORTED, "fn_param_grad is not built yet");
+    if (B > 0 && !e_loc) return fail(FN_EINVAL, "e_loc is NULL");
+    return grad_common(cfg, theta, x, B, nullptr, e_loc, stats, grad, ws, ws_bytes, stream);
 }
 
 fn_status fn_log_psi_vjp(const fn_config *cfg, const void *theta, const double *x, int64_t B, const double *coeff,
                          void *grad, void *ws, size_t ws_bytes, void *stream)
 {
-    (void)cfg; (void)theta; (void)x; (void)B; (void)coeff; (void)grad; (void)ws; (void)ws_bytes; (void)stream;
-    return fail(FN_EUNSUPPORTED, "fn_log_psi_vjp is not built yet");
+    if (B > 0 && !coeff) return fail(FN_EINVAL, "coeff is NULL");
+    return grad_common(cfg, theta, x, B, coeff, nullptr, nullptr, grad, ws, ws_bytes, stream);
 }
 
 const char *fn_last_error(void) { return g_err.c_str(); }

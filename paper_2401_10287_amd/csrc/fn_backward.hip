@@ -1,0 +1,587 @@
+// fn_backward.hip -- reverse pass of log|psi| with respect to the parameters,
+// weighted over walkers: grad = sum_p c_p d log|psi_p| / d theta.  With
+// c_p = 2 (E_p - mean E) / B this is the training gradient of Eq. 6 of the
+// paper; any other weights give the vector-Jacobian product of log|psi|.
+//
+// Adjoints, from the output down (value rows only, stream activations of the
+// one-electron layers saved by the forward pass, pair-stream activations
+// recomputed per electron):
+//   log|psi| = log|sum_k s_k exp(l_k)|:   d/d l_k = omega_k = psi_k / psi
+//   l_k = log|det A_k|:                   d/d A_k = A_k^-T
+//   A[i][j] = a_i(r_j) env_i(r_j):        d/d a = G env, d/d env = G a
+//   a = w . h_j^L + g, env = sum_m pi_m exp(-|Sigma_m (r_j - R_m)|)
+//   h^{l+1} = tanh(z) (+ h^l), z = [h_i, g_up, g_dn, g_i_up, g_i_dn] V + b
+//   pair layers h_ij^{l+1} = tanh(W2^T h_ij^l + c2) (+ h_ij^l), g_i = spin mean
+// Weight gradients are sums over walkers x electrons of outer products; they
+// are formed as split row reductions whose partial sums are added in a fixed
+// order, so the result does not depend on scheduling.
+#include "fn_internal.h"
+#include "fn_kernels.h"
+
+namespace fn {
+
+namespace {
+
+__device__ inline double wsum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+unsigned gridn(int64_t n, int bs = 256)
+{
+    int64_t g = (n + bs - 1) / bs;
+    if (g > (1 << 20)) g = 1 << 20;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// determinant adjoint: GA[w][k][i][j] = c_w omega_k (A_k^-1)[j][i]; one wave64
+// per (walker, determinant) of one spin.  Walkers on a node (psi = 0) and
+// singular determinants contribute nothing.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_det_backward(const double *Phi, const double *DR, const double *coeff,
+                                                     int64_t B, int K, int n, int sp, int nu, int nd, int rec,
+                                                     double *GA)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    double *LU = (double *)smem_raw;
+    double *Inv = LU + n * n;
+    int *perm = (int *)(Inv + n * n);
+    __shared__ double s_scale;
+    __shared__ int s_sing;
+    const int lane = threadIdx.x;
+    const int64_t w = blockIdx.x / K;
+    const int k = (int)(blockIdx.x % K);
+    if (w >= B) return;
+    const int64_t nn = (int64_t)n * n;
+    double *out = GA + (w * K + k) * nn;
+    if (lane == 0) {
+        const double *ru = DR + (w * 2 + 0) * (int64_t)K * rec, *rd = DR + (w * 2 + 1) * (int64_t)K * rec;
+        double lmax = -INFINITY;
+        for (int q = 0; q < K; ++q) {
+            double s = (nu > 0 ? ru[q * rec] : 1.0) * (nd > 0 ? rd[q * rec] : 1.0);
+            double l = (nu > 0 ? ru[q * rec + 1] : 0.0) + (nd > 0 ? rd[q * rec + 1] : 0.0);
+            if (s != 0.0 && l > lmax) lmax = l;
+        }
+        double S = 0.0, mine = 0.0;
+        if (lmax > -INFINITY)
+            for (int q = 0; q < K; ++q) {
+                double s = (nu > 0 ? ru[q * rec] : 1.0) * (nd > 0 ? rd[q * rec] : 1.0);
+                double l = (nu > 0 ? ru[q * rec + 1] : 0.0) + (nd > 0 ? rd[q * rec + 1] : 0.0);
+                double t = s != 0.0 ? s * exp(l - lmax) : 0.0;
+                S += t;
+                if (q == k) mine = t;
+            }
+        const bool ok = lmax > -INFINITY && S != 0.0 && S == S;
+        s_scale = ok ? coeff[w] * mine / S : 0.0;
+        s_sing = 0;
+    }
+    const double *A = Phi + (w * K + k) * nn;
+    for (int q = lane; q < n * n; q += 64) LU[q] = A[q];
+    for (int q = lane; q < n; q += 64) perm[q] = q;
+    __syncthreads();
+    for (int c = 0; c < n; ++c) {
+        if (lane == 0) {
+            int p = c;
+            double best = fabs(LU[c * n + c]);
+            for (int r = c + 1; r < n; ++r) {
+                double v = fabs(LU[r * n + c]);
+                if (v > best) { best = v; p = r; }
+            }
+            if (best == 0.0) s_sing = 1;
+            else if (p != c) {
+                for (int q = 0; q < n; ++q) { double t = LU[c * n + q]; LU[c * n + q] = LU[p * n + q]; LU[p * n + q] = t; }
+                int t = perm[c]; perm[c] = perm[p]; perm[p] = t;
+            }
+        }
+        __syncthreads();
+        if (s_sing) break;
+        const double ip = 1.0 / LU[c * n + c];
+        const int m = n - 1 - c;
+        for (int q = lane; q < m; q += 64) LU[(c + 1 + q) * n + c] *= ip;
+        __syncthreads();
+        for (int q = lane; q < m * m; q += 64) {
+            const int r = c + 1 + q / m, cc = c + 1 + q % m;
+            LU[r * n + cc] -= LU[r * n + c] * LU[c * n + cc];
+        }
+        __syncthreads();
+    }
+    if (s_sing || s_scale == 0.0) {
+        for (int q = lane; q < n * n; q += 64) out[q] = 0.0;
+        return;
+    }
+    // column c of A^-1 = U^-1 L^-1 P e_c, one column per lane
+    for (int c = lane; c < n; c += 64) {
+        for (int r = 0; r < n; ++r) Inv[r * n + c] = perm[r] == c ? 1.0 : 0.0;
+        for (int r = 1; r < n; ++r) {
+            double acc = Inv[r * n + c];
+            for (int q = 0; q < r; ++q) acc -= LU[r * n + q] * Inv[q * n + c];
+            Inv[r * n + c] = acc;
+        }
+        for (int r = n - 1; r >= 0; --r) {
+            double acc = Inv[r * n + c];
+            for (int q = r + 1; q < n; ++q) acc -= LU[r * n + q] * Inv[q * n + c];
+            Inv[r * n + c] = acc / LU[r * n + r];
+        }
+    }
+    __syncthreads();
+    const double sc = s_scale;
+    for (int q = lane; q < n * n; q += 64) {
+        const int i = q / n, j = q % n;
+        out[q] = sc * Inv[j * n + i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// envelope / orbital adjoint, one thread per (walker, orbital column):
+//   Ga[w n + j][col] = G env                       (adjoint of a = w . h + g)
+//   EP[w][col][m][0]   = sum_j G a exp(-q_m)             (pi_m)
+//   EP[w][col][m][1+3p+q] = sum_j -G a pi_m exp(-q_m) (Sigma d)_p d_q / q
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_env_backward(Sys s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof, int sp,
+                               const T *O, int64_t ldo, const double *GA, int64_t B, int KNp, T *Ga, T *EP)
+{
+    const int n = sp == 0 ? s.nu : s.nd, j0 = sp == 0 ? 0 : s.nu;
+    const int kn = s.K * n;
+    const int64_t total = B * KNp;
+    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < total; id += (int64_t)gridDim.x * blockDim.x) {
+        const int col = (int)(id % KNp);
+        const int64_t w = id / KNp;
+        if (col >= kn) {
+            for (int jj = 0; jj < n; ++jj) Ga[(w * n + jj) * KNp + col] = T(0);
+            continue;
+        }
+        const int k = col / n, io = col % n;
+        const double gcol = (double)theta[gof + col];
+        // adjoint of a for each electron j of this spin
+        for (int jj = 0; jj < n; ++jj) {
+            const double *xj = x + (w * s.N + j0 + jj) * 3;
+            double env = 0.0;
+            for (int m = 0; m < s.M; ++m) {
+                const T *Sg = theta + sigof + ((int64_t)col * s.M + m) * 9;
+                const double d0 = xj[0] - s.R[m][0], d1 = xj[1] - s.R[m][1], d2 = xj[2] - s.R[m][2];
+                double q2 = 0.0;
+                for (int p = 0; p < 3; ++p) {
+                    const double v = (double)Sg[3 * p] * d0 + (double)Sg[3 * p + 1] * d1 + (double)Sg[3 * p + 2] * d2;
+                    q2 += v * v;
+                }
+                env += (double)theta[piof + (int64_t)col * s.M + m] * exp(-sqrt(q2));
+            }
+            const double G = GA[((w * s.K + k) * n + io) * n + jj];
+            Ga[(w * n + jj) * KNp + col] = (T)(G * env);
+        }
+        // envelope parameters, summed over the electrons of this walker
+        for (int m = 0; m < s.M; ++m) {
+            const T *Sg = theta + sigof + ((int64_t)col * s.M + m) * 9;
+            const double pim = (double)theta[piof + (int64_t)col * s.M + m];
+            double gp = 0.0, gs[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            for (int jj = 0; jj < n; ++jj) {
+                const double *xj = x + (w * s.N + j0 + jj) * 3;
+                const double d[3] = {xj[0] - s.R[m][0], xj[1] - s.R[m][1], xj[2] - s.R[m][2]};
+                double sd[3];
+                for (int p = 0; p < 3; ++p) sd[p] = (double)Sg[3 * p] * d[0] + (double)Sg[3 * p + 1] * d[1] + (double)Sg[3 * p + 2] * d[2];
+                const double q = sqrt(sd[0] * sd[0] + sd[1] * sd[1] + sd[2] * sd[2]);
+                const double e = exp(-q);
+                const double a0 = (double)O[(w * n + jj) * ldo + col] + gcol;
+                const double G = GA[((w * s.K + k) * n + io) * n + jj];
+                const double ga = G * a0;
+                gp += ga * e;
+                const double f = -ga * pim * e / q;
+                for (int p = 0; p < 3; ++p)
+                    for (int qq = 0; qq < 3; ++qq) gs[3 * p + qq] += f * sd[p] * d[qq];
+            }
+            T *ep = EP + ((w * kn + col) * s.M + m) * 10;
+            ep[0] = (T)gp;
+            for (int e = 0; e < 9; ++e) ep[1 + e] = (T)gs[e];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// layer adjoints (value rows)
+// ---------------------------------------------------------------------------
+// Gz = Gy (1 - t^2) per electron row, SGz[w] = sum over the walker's electrons
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_gz(const T *__restrict__ Gy, const T *__restrict__ Tt, int N, int w1,
+                                                T *__restrict__ Gz, T *__restrict__ SGz)
+{
+    const int64_t w = blockIdx.x;
+    for (int o = threadIdx.x; o < w1; o += blockDim.x) {
+        T acc = T(0);
+        for (int i = 0; i < N; ++i) {
+            const int64_t r = (w * N + i) * w1 + o;
+            const T t = Tt[r];
+            const T g = Gy[r] * (T(1) - t * t);
+            Gz[r] = g;
+            acc += g;
+        }
+        SGz[w * w1 + o] = acc;
+    }
+}
+
+// adjoint of h^l: Gh (through V_h) + residual + spin-mean part Gg / n_spin
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_gh(const T *__restrict__ Gh, const T *__restrict__ Gy,
+                                                const T *__restrict__ Gg, int N, int nu, int dh, int w1, int resid,
+                                                T *__restrict__ Gout)
+{
+    const int64_t wi = blockIdx.x;
+    const int64_t w = wi / N;
+    const int i = (int)(wi % N);
+    const int sp = i < nu ? 0 : 1;
+    const T inv = T(1) / T(sp == 0 ? nu : N - nu);
+    for (int u = threadIdx.x; u < dh; u += blockDim.x) {
+        T v = Gh[wi * dh + u] + Gg[w * 2 * dh + sp * dh + u] * inv;
+        if (resid) v += Gy[wi * w1 + u];
+        Gout[wi * w1 + u] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pair stream adjoint: one workgroup per (walker, electron i) recomputes the
+// pair activations h_ij^l, then runs back through the pair layers with the
+// adjoints of the spin means g_i^l (GGI, ld ldg, columns [up | dn]) and
+// writes its share of dW2, dc2 (PP row, layout of theta from W2_0 on).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_pair_backward(Sys s, const double *x, const T *theta, ParamLayout P, int64_t B, const T *GGI,
+                                int64_t ldg, int64_t gg_layer_stride, T *PP, int64_t npp)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    const int wp = s.w2 > 4 ? s.w2 : 4;
+    const int N = s.N, L = s.L;
+    T *Hs = (T *)smem_raw;                    // [L][N][wp] pair activations
+    T *Ts = Hs + (size_t)L * N * wp;          // [L][N][wp] tanh outputs of the pair layers (index l = layer output)
+    T *G0 = Ts + (size_t)L * N * wp;          // [N][wp]
+    T *G1 = G0 + (size_t)N * wp;              // [N][wp]
+    const int64_t wi = blockIdx.x;
+    const int64_t w = wi / N;
+    const int i = (int)(wi % N);
+    if (w >= B) return;
+    const double *xw = x + w * 3 * N;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        T *p = Hs + j * wp;
+        for (int q = 0; q < wp; ++q) p[q] = T(0);
+        if (j != i) {
+            const double d0 = xw[3 * i] - xw[3 * j], d1 = xw[3 * i + 1] - xw[3 * j + 1], d2 = xw[3 * i + 2] - xw[3 * j + 2];
+            p[0] = (T)d0; p[1] = (T)d1; p[2] = (T)d2;
+            p[3] = (T)sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        }
+    }
+    __syncthreads();
+    for (int l = 0; l + 1 < L; ++l) {
+        const int dp = l == 0 ? 4 : s.w2;
+        const T *W2 = theta + P.W2[l];
+        const T *c2 = theta + P.c2[l];
+        for (int idx = threadIdx.x; idx < N * s.w2; idx += blockDim.x) {
+            const int j = idx / s.w2, o = idx % s.w2;
+            const T *in = Hs + ((size_t)l * N + j) * wp;
+            T z = c2[o];
+            for (int k = 0; k < dp; ++k) z += in[k] * W2[k * s.w2 + o];
+            const T t = tanh(z);
+            Ts[((size_t)(l + 1) * N + j) * wp + o] = t;
+            Hs[((size_t)(l + 1) * N + j) * wp + o] = t + (l >= 1 ? in[o] : T(0));
+        }
+        __syncthreads();
+    }
+    // adjoint of the top pair state from the top layer's spin means
+    const int nu = s.nu, nd = s.nd;
+    auto mean_adj = [&](int l, int j, int o) -> T {
+        const int dp = l == 0 ? 4 : s.w2;
+        if (o >= dp) return T(0);
+        const int spj = j < nu ? 0 : 1;
+        const int n = spj == 0 ? nu : nd;
+        return GGI[(int64_t)l * gg_layer_stride + wi * ldg + spj * dp + o] / T(n);
+    };
+    T *Gc = G0, *Gn = G1;
+    for (int idx = threadIdx.x; idx < N * wp; idx += blockDim.x) Gc[idx] = mean_adj(L - 1, idx / wp, idx % wp);
+    __syncthreads();
+    T *pp = PP + wi * npp;
+    for (int l = L - 1; l >= 1; --l) {
+        // pair layer l - 1 maps h^{l-1} (width dp) to h^l (width w2)
+        const int dp = l - 1 == 0 ? 4 : s.w2;
+        const T *W2 = theta + P.W2[l - 1];
+        // dz = G (1 - t^2), kept in Gn temporarily
+        for (int idx = threadIdx.x; idx < N * s.w2; idx += blockDim.x) {
+            const int j = idx / s.w2, o = idx % s.w2;
+            const T t = Ts[((size_t)l * N + j) * wp + o];
+            Gn[j * wp + o] = Gc[j * wp + o] * (T(1) - t * t);
+        }
+        __syncthreads();
+        // dW2[k][o] = sum_j h^{l-1}[j][k] dz[j][o], dc2[o] = sum_j dz[j][o]
+        const int64_t wof = P.W2[l - 1] - P.W2[0], cof = P.c2[l - 1] - P.W2[0];
+        for (int idx = threadIdx.x; idx < (dp + 1) * s.w2; idx += blockDim.x) {
+            const int k = idx / s.w2, o = idx % s.w2;
+            T acc = T(0);
+            if (k < dp)
+                for (int j = 0; j < N; ++j) acc += Hs[((size_t)(l - 1) * N + j) * wp + k] * Gn[j * wp + o];
+            else
+                for (int j = 0; j < N; ++j) acc += Gn[j * wp + o];
+            pp[k < dp ? wof + (int64_t)k * s.w2 + o : cof + o] = acc;
+        }
+        // adjoint of h^{l-1}: dz W2^T + residual + spin-mean part
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < N * wp; idx += blockDim.x) {
+            const int j = idx / wp, k = idx % wp;
+            T v = T(0);
+            if (k < dp) {
+                for (int o = 0; o < s.w2; ++o) v += Gn[j * wp + o] * W2[k * s.w2 + o];
+                if (l - 1 >= 1) v += Gc[j * wp + k];
+                v += mean_adj(l - 1, j, k);
+            }
+            Gc[idx] = v;   // safe: every thread reads only Gn and its own Gc entry
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// weight-gradient products C[a][b] = sum_r X[r][a] Y[r][b] (split over rows)
+// partial[s][a][b] for row range s; X rows may be remapped by groups.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_tn_partial(const T *X, int64_t ldx, int NA, const T *Y, int64_t ldy, int NB,
+                                                    int64_t R, int64_t per, int64_t stride, int64_t off,
+                                                    int64_t rows_per_split, T *part)
+{
+    __shared__ T sx[16][64 + 1];
+    __shared__ T sy[16][64 + 1];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int a0 = blockIdx.x * 64, b0 = blockIdx.y * 64;
+    const int64_t r0 = (int64_t)blockIdx.z * rows_per_split;
+    const int64_t r1 = r0 + rows_per_split < R ? r0 + rows_per_split : R;
+    T acc[4][4] = {};
+    for (int64_t rb = r0; rb < r1; rb += 16) {
+        for (int q = tid; q < 16 * 64; q += 256) {
+            const int rr = q / 64, c = q % 64;
+            const int64_t r = rb + rr;
+            T vx = T(0), vy = T(0);
+            if (r < r1) {
+                const int64_t xr = per > 0 ? remap_row(r, per, stride, off) : r;
+                if (a0 + c < NA) vx = X[xr * ldx + a0 + c];
+                if (b0 + c < NB) vy = Y[r * ldy + b0 + c];
+            }
+            sx[rr][c] = vx;
+            sy[rr][c] = vy;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+            T xa[4], yb[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) { xa[u] = sx[rr][ty * 4 + u]; yb[u] = sy[rr][tx * 4 + u]; }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += xa[u] * yb[v];
+        }
+        __syncthreads();
+    }
+    T *p = part + (int64_t)blockIdx.z * NA * NB;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int a = a0 + ty * 4 + u;
+        if (a >= NA) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int b = b0 + tx * 4 + v;
+            if (b < NB) p[(int64_t)a * NB + b] = acc[u][v];
+        }
+    }
+}
+
+// acc[dst(a, b)] += sum_s part[s][a][b]; dst = off + a * lda_out + b
+template <typename T>
+__global__ void k_tn_reduce(const T *part, int S, int NA, int NB, double *acc, int64_t off, int64_t lda_out)
+{
+    const int64_t n = (int64_t)NA * NB;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int s = 0; s < S; ++s) v += (double)part[(int64_t)s * n + q];
+        const int a = (int)(q / NB), b = (int)(q % NB);
+        acc[off + (int64_t)a * lda_out + b] += v;
+    }
+}
+
+// column sums: part[s][c] = sum over rows of split s of in[r][c]
+template <typename T>
+__global__ __launch_bounds__(256) void k_colsum_partial(const T *in, int64_t ld, int C, int64_t R,
+                                                        int64_t rows_per_split, T *part)
+{
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int ty = threadIdx.x >> 6;
+    __shared__ double red[4][64];
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
+    const int64_t r1 = r0 + rows_per_split < R ? r0 + rows_per_split : R;
+    double acc = 0.0;
+    if (c < C)
+        for (int64_t r = r0 + ty; r < r1; r += 4) acc += (double)in[r * ld + c];
+    red[ty][threadIdx.x & 63] = acc;
+    __syncthreads();
+    if (ty == 0 && c < C) part[(int64_t)blockIdx.y * C + c] = (T)(red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+// acc[map(c)] += sum_s part[s][c]; map: envelope partials [col][m][10] go to
+// pi [col][m] and Sigma [col][m][9]; otherwise acc[off + c]
+template <typename T>
+__global__ void k_colsum_reduce(const T *part, int S, int C, double *acc, int64_t off, int env_map, int64_t off2)
+{
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int s = 0; s < S; ++s) v += (double)part[(int64_t)s * C + c];
+        if (!env_map) {
+            acc[off + c] += v;
+        } else {
+            const int cm = c / 10, e = c % 10;      // cm = col * M + m
+            if (e == 0) acc[off + cm] += v;
+            else acc[off2 + (int64_t)cm * 9 + (e - 1)] += v;
+        }
+    }
+}
+
+__global__ void k_zero_f64(double *p, int64_t n)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) p[q] = 0.0;
+}
+
+template <typename T>
+__global__ void k_grad_out(const double *acc, int64_t n, T *grad)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) grad[q] = (T)acc[q];
+}
+
+// Wb[u][col] = w[u][col] for col < kn, 0 up to KNp (adjoint of the head)
+template <typename T>
+__global__ void k_pack_head_bwd(const T *theta, int64_t woff, int w1, int kn, int KNp, T *Wb)
+{
+    const int64_t n = (int64_t)w1 * KNp;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int u = (int)(q / KNp), col = (int)(q % KNp);
+        Wb[q] = col < kn ? theta[woff + (int64_t)u * kn + col] : T(0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+size_t det_backward_lds(int n) { return (size_t)2 * n * n * sizeof(double) + (size_t)n * sizeof(int) + 16; }
+
+void launch_det_backward(const double *Phi, const double *DR, const double *coeff, int64_t B, int K, int n, int sp,
+                         int nu, int nd, int rec, double *GA, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_det_backward, dim3((unsigned)(B * K)), dim3(64), det_backward_lds(n), st, Phi, DR, coeff, B, K,
+                       n, sp, nu, nd, rec, GA);
+}
+
+template <typename T>
+void launch_env_backward(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof,
+                         int sp, const T *O, int64_t ldo, const double *GA, int64_t B, int KNp, T *Ga, T *EP,
+                         hipStream_t st)
+{
+    hipLaunchKernelGGL(k_env_backward<T>, dim3(gridn(B * KNp, 128)), dim3(128), 0, st, s, x, theta, gof, piof, sigof,
+                       sp, O, ldo, GA, B, KNp, Ga, EP);
+}
+
+template <typename T>
+void launch_bwd_gz(const T *Gy, const T *Tt, int64_t B, int N, int w1, T *Gz, T *SGz, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bwd_gz<T>, dim3((unsigned)B), dim3(256), 0, st, Gy, Tt, N, w1, Gz, SGz);
+}
+
+template <typename T>
+void launch_bwd_gh(const T *Gh, const T *Gy, const T *Gg, int64_t B, int N, int nu, int dh, int w1, int resid, T *Gout,
+                   hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bwd_gh<T>, dim3((unsigned)(B * N)), dim3(256), 0, st, Gh, Gy, Gg, N, nu, dh, w1, resid, Gout);
+}
+
+size_t pair_backward_lds(const Sys &s, size_t elem)
+{
+    const int wp = s.w2 > 4 ? s.w2 : 4;
+    return ((size_t)2 * s.L * s.N * wp + 2 * (size_t)s.N * wp) * elem;
+}
+
+template <typename T>
+void launch_pair_backward(const Sys &s, const double *x, const T *theta, const ParamLayout &P, int64_t B, const T *GGI,
+                          int64_t ldg, int64_t gg_layer_stride, T *PP, int64_t npp, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pair_backward<T>, dim3((unsigned)(B * s.N)), dim3(256), pair_backward_lds(s, sizeof(T)), st, s,
+                       x, theta, P, B, GGI, ldg, gg_layer_stride, PP, npp);
+}
+
+int tn_splits(int64_t R)
+{
+    int64_t s = R / 512;
+    if (s < 1) s = 1;
+    if (s > 64) s = 64;
+    return (int)s;
+}
+
+template <typename T>
+void launch_tn(const T *X, int64_t ldx, int NA, const T *Y, int64_t ldy, int NB, int64_t R, int64_t per,
+               int64_t stride, int64_t off, T *part, double *acc, int64_t acc_off, int64_t lda_out, hipStream_t st)
+{
+    if (R <= 0 || NA <= 0 || NB <= 0) return;
+    const int S = tn_splits(R);
+    const int64_t rps = (R + S - 1) / S;
+    dim3 g((unsigned)((NA + 63) / 64), (unsigned)((NB + 63) / 64), (unsigned)S);
+    hipLaunchKernelGGL(k_tn_partial<T>, g, dim3(256), 0, st, X, ldx, NA, Y, ldy, NB, R, per, stride, off, rps, part);
+    hipLaunchKernelGGL(k_tn_reduce<T>, dim3(gridn((int64_t)NA * NB)), dim3(256), 0, st, part, S, NA, NB, acc, acc_off,
+                       lda_out);
+}
+
+template <typename T>
+void launch_colsum(const T *in, int64_t ld, int C, int64_t R, T *part, double *acc, int64_t off, int env_map,
+                   int64_t off2, hipStream_t st)
+{
+    if (R <= 0 || C <= 0) return;
+    const int S = tn_splits(R);
+    const int64_t rps = (R + S - 1) / S;
+    hipLaunchKernelGGL(k_colsum_partial<T>, dim3((unsigned)((C + 63) / 64), (unsigned)S), dim3(256), 0, st, in, ld, C, R,
+                       rps, part);
+    hipLaunchKernelGGL(k_colsum_reduce<T>, dim3(gridn(C)), dim3(256), 0, st, part, S, C, acc, off, env_map, off2);
+}
+
+int max_splits() { return 64; }
+
+void launch_zero_f64(double *p, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_f64, dim3(gridn(n)), dim3(256), 0, st, p, n);
+}
+
+template <typename T>
+void launch_grad_out(const double *acc, int64_t n, T *grad, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_grad_out<T>, dim3(gridn(n)), dim3(256), 0, st, acc, n, grad);
+}
+
+template <typename T>
+void launch_pack_head_bwd(const T *theta, int64_t woff, int w1, int kn, int KNp, T *Wb, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pack_head_bwd<T>, dim3(gridn((int64_t)w1 * KNp)), dim3(256), 0, st, theta, woff, w1, kn, KNp, Wb);
+}
+
+#define FN_BWD_INST(T)                                                                                               \
+    template void launch_env_backward<T>(const Sys &, const double *, const T *, int64_t, int64_t, int64_t, int,       \
+                                         const T *, int64_t, const double *, int64_t, int, T *, T *, hipStream_t);    \
+    template void launch_bwd_gz<T>(const T *, const T *, int64_t, int, int, T *, T *, hipStream_t);                   \
+    template void launch_bwd_gh<T>(const T *, const T *, const T *, int64_t, int, int, int, int, int, T *,           \
+                                   hipStream_t);                                                                      \
+    template void launch_pair_backward<T>(const Sys &, const double *, const T *, const ParamLayout &, int64_t,       \
+                                          const T *, int64_t, int64_t, T *, int64_t, hipStream_t);                    \
+    template void launch_tn<T>(const T *, int64_t, int, const T *, int64_t, int, int64_t, int64_t, int64_t, int64_t,  \
+                               T *, double *, int64_t, int64_t, hipStream_t);                                         \
+    template void launch_colsum<T>(const T *, int64_t, int, int64_t, T *, double *, int64_t, int, int64_t,           \
+                                   hipStream_t);                                                                      \
+    template void launch_grad_out<T>(const double *, int64_t, T *, hipStream_t);                                      \
+    template void launch_pack_head_bwd<T>(const T *, int64_t, int, int, int, T *, hipStream_t);
+
+FN_BWD_INST(float)
+FN_BWD_INST(double)
+
+}  // namespace fn

@@ -223,7 +223,9 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 int64_t row = m0 + wm * 64 + 16 * i + 4 * (lane >> 4) + e;
-                if (row < a.rows) C[row * a.ldc + col] = acc[i][j][e];
+                if (row >= a.rows) continue;
+                if (a.c_rows_per_group > 0) row = remap_row(row, a.c_rows_per_group, a.c_group_stride, a.c_row_offset);
+                C[row * a.ldc + col] = acc[i][j][e];
             }
         }
 }
@@ -281,6 +283,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs a)
     for (int i = 0; i < 4; ++i) {
         int64_t row = m0 + ty * 4 + i;
         if (row >= a.rows) continue;
+        if (a.c_rows_per_group > 0) row = remap_row(row, a.c_rows_per_group, a.c_group_stride, a.c_row_offset);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             int col = n0 + tx * 4 + j;

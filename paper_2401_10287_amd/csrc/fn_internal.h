@@ -94,8 +94,9 @@ inline Widths make_widths(const Sys &s)
 // Arguments of one matrix product C[r][o] = sum_k A[r][k] W[o][k] where A is
 // the row-wise concatenation [A1 | A2] (A2 may be empty) and W is stored
 // transposed (o major, k contiguous) in the product's operand type.  Row r of
-// A and C: group g = r / rows_per_group, q = r % rows_per_group; A's row is
-// g * group_stride + row_offset + q, C's row is r.
+// A: group g = r / rows_per_group, q = r % rows_per_group, A's row is
+// g * group_stride + row_offset + q.  C's row is r, or, when
+// c_rows_per_group > 0, the same mapping with the c_ fields.
 struct GemmArgs {
     const void *A1; int64_t lda1; int K1;
     const void *A2; int64_t lda2; int K2;
@@ -103,7 +104,14 @@ struct GemmArgs {
     void *C; int64_t ldc;
     int64_t rows; int nout;
     int64_t rows_per_group, group_stride, row_offset;
+    int64_t c_rows_per_group, c_group_stride, c_row_offset;
 };
+
+__host__ __device__ inline int64_t remap_row(int64_t r, int64_t per, int64_t stride, int64_t off)
+{
+    const int64_t g = r / per;
+    return g * stride + off + (r - g * per);
+}
 
 hipError_t launch_gemm(int mode, const GemmArgs &a, hipStream_t st);
 

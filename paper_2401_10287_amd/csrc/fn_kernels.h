@@ -1,5 +1,5 @@
-// fn_kernels.h -- launchers of the network kernels (fn_net.hip) and of the
-// Monte Carlo kernels (fn_mc.hip).
+// fn_kernels.h -- launchers of the network kernels (fn_net.hip), the backward
+// pass (fn_backward.hip) and the Monte Carlo kernels (fn_mc.hip).
 #pragma once
 #include "fn_internal.h"
 
@@ -21,7 +21,7 @@ void launch_spin_mean(const T *H, int64_t ldh, int64_t B, int N, int nu, int TR,
                       hipStream_t st);
 template <typename T>
 void launch_layer_epi(const T *X, const T *Pw, const T *bias, const T *Hin, T *Hout, int64_t ldh, int64_t B, int N,
-                      int TR, int n3, int w1, int W1p, int resid, bool fl, hipStream_t st);
+                      int TR, int n3, int w1, int W1p, int resid, bool fl, T *Tout, hipStream_t st);
 template <typename T>
 void launch_envelope(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof, int sp,
                      const T *O, int64_t ldo, int64_t B, int TR, bool fl, double *Phi, hipStream_t st);
@@ -30,6 +30,66 @@ void launch_det(const double *Phi, int64_t B, int K, int n, int TR, int n3, int 
                 hipStream_t st);
 void launch_combine(const Sys &s, const double *x, const double *DR, int rec, int64_t B, double vnn, double *log_abs,
                     int8_t *sign, double *e_loc, double *parts, bool fl, hipStream_t st);
+
+// backward (fn_backward.hip)
+size_t det_backward_lds(int n);
+void launch_det_backward(const double *Phi, const double *DR, const double *coeff, int64_t B, int K, int n, int sp,
+                         int nu, int nd, int rec, double *GA, hipStream_t st);
+template <typename T>
+void launch_env_backward(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof,
+                         int sp, const T *O, int64_t ldo, const double *GA, int64_t B, int KNp, T *Ga, T *EP,
+                         hipStream_t st);
+template <typename T>
+void launch_bwd_gz(const T *Gy, const T *Tt, int64_t B, int N, int w1, T *Gz, T *SGz, hipStream_t st);
+template <typename T>
+void launch_bwd_gh(const T *Gh, const T *Gy, const T *Gg, int64_t B, int N, int nu, int dh, int w1, int resid, T *Gout,
+                   hipStream_t st);
+size_t pair_backward_lds(const Sys &s, size_t elem);
+template <typename T>
+void launch_pair_backward(const Sys &s, const double *x, const T *theta, const ParamLayout &P, int64_t B, const T *GGI,
+                          int64_t ldg, int64_t gg_layer_stride, T *PP, int64_t npp, hipStream_t st);
+int max_splits();
+template <typename T>
+void launch_tn(const T *X, int64_t ldx, int NA, const T *Y, int64_t ldy, int NB, int64_t R, int64_t per,
+               int64_t stride, int64_t off, T *part, double *acc, int64_t acc_off, int64_t lda_out, hipStream_t st);
+template <typename T>
+void launch_colsum(const T *in, int64_t ld, int C, int64_t R, T *part, double *acc, int64_t off, int env_map,
+                   int64_t off2, hipStream_t st);
+void launch_zero_f64(double *p, int64_t n, hipStream_t st);
+template <typename T>
+void launch_grad_out(const double *acc, int64_t n, T *grad, hipStream_t st);
+template <typename T>
+void launch_pack_head_bwd(const T *theta, int64_t woff, int w1, int kn, int KNp, T *Wb, hipStream_t st);
+
+// backward (fn_backward.hip)
+size_t det_backward_lds(int n);
+void launch_det_backward(const double *Phi, const double *DR, const double *coeff, int64_t B, int K, int n, int sp,
+                         int nu, int nd, int rec, double *GA, hipStream_t st);
+template <typename T>
+void launch_env_backward(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof,
+                         int sp, const T *O, int64_t ldo, const double *GA, int64_t B, int KNp, T *Ga, T *EP,
+                         hipStream_t st);
+template <typename T>
+void launch_bwd_gz(const T *Gy, const T *Tt, int64_t B, int N, int w1, T *Gz, T *SGz, hipStream_t st);
+template <typename T>
+void launch_bwd_gh(const T *Gh, const T *Gy, const T *Gg, int64_t B, int N, int nu, int dh, int w1, int resid, T *Gout,
+                   hipStream_t st);
+size_t pair_backward_lds(const Sys &s, size_t elem);
+template <typename T>
+void launch_pair_backward(const Sys &s, const double *x, const T *theta, const ParamLayout &P, int64_t B, const T *GGI,
+                          int64_t ldg, int64_t gg_layer_stride, T *PP, int64_t npp, hipStream_t st);
+int max_splits();
+template <typename T>
+void launch_tn(const T *X, int64_t ldx, int NA, const T *Y, int64_t ldy, int NB, int64_t R, int64_t per,
+               int64_t stride, int64_t off, T *part, double *acc, int64_t acc_off, int64_t lda_out, hipStream_t st);
+template <typename T>
+void launch_colsum(const T *in, int64_t ld, int C, int64_t R, T *part, double *acc, int64_t off, int env_map,
+                   int64_t off2, hipStream_t st);
+void launch_zero_f64(double *p, int64_t n, hipStream_t st);
+template <typename T>
+void launch_grad_out(const double *acc, int64_t n, T *grad, hipStream_t st);
+template <typename T>
+void launch_pack_head_bwd(const T *theta, int64_t woff, int w1, int kn, int KNp, T *Wb, hipStream_t st);
 
 // Monte Carlo
 void launch_propose(const double *x, int64_t B, int n3, double sigma, uint64_t seed, uint64_t step, uint32_t stream_id,

@@ -257,7 +257,7 @@ template <typename T, bool FL>
 __global__ __launch_bounds__(256) void k_layer_epi(const T *__restrict__ X, const T *__restrict__ Pw,
                                                    const T *__restrict__ bias, const T *__restrict__ Hin,
                                                    T *__restrict__ Hout, int64_t ldh, int N, int TR, int n3, int w1,
-                                                   int W1p, int resid)
+                                                   int W1p, int resid, T *__restrict__ Tout)
 {
     const int wi = blockIdx.x;              // walker * N + electron
     const int w = wi / N;
@@ -273,6 +273,7 @@ __global__ __launch_bounds__(256) void k_layer_epi(const T *__restrict__ X, cons
         const T y0 = tanh(z0);
         const T d = T(1) - y0 * y0;
         Hout[r0 * ldh + o] = y0 + (resid ? Hin[r0 * ldh + o] : T(0));
+        if (Tout) Tout[r0 * w1 + o] = y0;
         if (FL) {
             T src = T(0);
             for (int t = 1; t <= n3; ++t) {
@@ -620,15 +621,15 @@ void launch_spin_mean(const T *H, int64_t ldh, int64_t B, int N, int nu, int TR,
 
 template <typename T>
 void launch_layer_epi(const T *X, const T *Pw, const T *bias, const T *Hin, T *Hout, int64_t ldh, int64_t B, int N,
-                      int TR, int n3, int w1, int W1p, int resid, bool fl, hipStream_t st)
+                      int TR, int n3, int w1, int W1p, int resid, bool fl, T *Tout, hipStream_t st)
 {
     dim3 g((unsigned)(B * N));
     if (fl)
         hipLaunchKernelGGL((k_layer_epi<T, true>), g, dim3(256), 0, st, X, Pw, bias, Hin, Hout, ldh, N, TR, n3, w1,
-                           W1p, resid);
+                           W1p, resid, Tout);
     else
         hipLaunchKernelGGL((k_layer_epi<T, false>), g, dim3(256), 0, st, X, Pw, bias, Hin, Hout, ldh, N, TR, n3, w1,
-                           W1p, resid);
+                           W1p, resid, Tout);
 }
 
 template <typename T>
@@ -682,7 +683,7 @@ void launch_combine(const Sys &s, const double *x, const double *DR, int rec, in
                                         bool, int64_t, int64_t, int, int, T *, hipStream_t);                        \
     template void launch_spin_mean<T>(const T *, int64_t, int64_t, int, int, int, int, int, T *, hipStream_t);      \
     template void launch_layer_epi<T>(const T *, const T *, const T *, const T *, T *, int64_t, int64_t, int, int,  \
-                                      int, int, int, int, bool, hipStream_t);                                       \
+                                      int, int, int, int, bool, T *, hipStream_t);                                  \
     template void launch_envelope<T>(const Sys &, const double *, const T *, int64_t, int64_t, int64_t, int,        \
                                      const T *, int64_t, int64_t, int, bool, double *, hipStream_t);
 

@@ -1,0 +1,175 @@
+"""Parity of the hand-written backward (d log|psi| / d theta, the gradient
+of Eq. 6) with the FP64 oracle's exact dual-number derivatives and with
+finite differences, through the C ABI and the autograd glue."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2401_10287_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2401_10287_amd import fnvmc
+    return torch, fnvmc
+
+
+def _group_indices(s):
+    """One parameter index from every tensor of the layout (away from its start)."""
+    idx = []
+    for name, (off, shape) in I.param_offsets(s).items():
+        if name == "_total":
+            continue
+        n = int(np.prod(shape))
+        idx.append(off + (7 * n) // 11)
+    return np.array(idx, dtype=np.int64)
+
+
+def _small_lif():
+    return I.System("LiF-s", I.lif().nuc_xyz, I.lif().nuc_z, 3, 3, 3, 32, 8, 4, 16, (0, 1, 1, 0, 1, 1), 0.5)
+
+
+def test_vjp_fp64_full_gradient_he():
+    """Every parameter of the He network: GPU FP64 backward = oracle (exact)."""
+    torch, fnvmc = _dev()
+    s = I.he()
+    th = I.init_params(s)
+    x = I.init_walkers(s, 12)
+    c = np.random.default_rng(3).standard_normal(12)
+    cfg = fnvmc.Config(s, "fp64")
+    g = fnvmc.fn_log_psi_vjp(cfg, torch.tensor(th, device="cuda"), torch.tensor(x, device="cuda"),
+                             torch.tensor(c, device="cuda"))
+    torch.cuda.synchronize()
+    d = O.Oracle(s).dlogpsi_dtheta(th, x, np.arange(th.size))
+    ref = c @ d
+    err = np.abs(g.cpu().numpy() - ref)
+    print("He fp64 full gradient: max abs err", err.max(), "max |g|", np.abs(ref).max())
+    np.testing.assert_allclose(g.cpu().numpy(), ref, rtol=1e-9, atol=1e-11 * np.abs(ref).max())
+
+
+def test_vjp_fp64_finite_differences():
+    """GPU FP64 gradient against central differences of the GPU's own log|psi|."""
+    torch, fnvmc = _dev()
+    s = _small_lif()
+    th = I.init_params(s, seed=5)
+    x = I.init_walkers(s, 16, seed=6)
+    c = np.random.default_rng(7).standard_normal(16)
+    cfg = fnvmc.Config(s, "fp64")
+    tt = torch.tensor(th, device="cuda")
+    xt = torch.tensor(x, device="cuda")
+    g = fnvmc.fn_log_psi_vjp(cfg, tt, xt, torch.tensor(c, device="cuda")).cpu().numpy()
+    for i in _group_indices(s):
+        h = 1e-5 * max(1.0, abs(th[i]))
+        tp, tm = tt.clone(), tt.clone()
+        tp[i] += h
+        tm[i] -= h
+        fp = fnvmc.fn_log_psi(cfg, tp, xt)[0].cpu().numpy()
+        fm = fnvmc.fn_log_psi(cfg, tm, xt)[0].cpu().numpy()
+        fd = c @ ((fp - fm) / (2 * h))
+        assert abs(g[i] - fd) <= 1e-6 * max(1.0, abs(fd)), (i, g[i], fd)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6", "fp64"])
+def test_vjp_against_oracle_lif(prec):
+    """LiF training configuration at reduced width and 32 walkers: one
+    parameter per tensor group and 4 random directions against the oracle."""
+    torch, fnvmc = _dev()
+    s = I.System("LiF-m", I.lif().nuc_xyz, I.lif().nuc_z, 6, 6, 4, 64, 16, 4, 32, I.lif().electron_site, 0.5)
+    cfg = fnvmc.Config(s, prec)
+    th0 = I.init_params(s, seed=9)
+    tt = torch.tensor(th0, dtype=cfg.param_dtype, device="cuda")
+    th = tt.double().cpu().numpy()
+    x = I.init_walkers(s, 32, seed=10)
+    c = np.random.default_rng(11).standard_normal(32) / 32
+    g = fnvmc.fn_log_psi_vjp(cfg, tt, torch.tensor(x, device="cuda"), torch.tensor(c, device="cuda"))
+    torch.cuda.synchronize()
+    g = g.double().cpu().numpy()
+    o = O.Oracle(s)
+    idx = _group_indices(s)
+    d = o.dlogpsi_dtheta(th, x, idx)
+    ref = c @ d
+    # bound relative to the size of the summed terms: FP32 rounding of the
+    # orbital entries is amplified near nodes (1/psi) exactly as in the
+    # local energy, so the FP32 bound is 5e-4 of sum_p |c_p d log|psi_p||
+    scale = np.abs(c) @ np.abs(d)
+    tol = 1e-9 if prec == "fp64" else 5e-4
+    err = np.abs(g[idx] - ref)
+    print(prec, "per-group max err / scale", (err / scale).max())
+    assert np.all(err <= tol * scale)
+    rng = np.random.default_rng(12)
+    for _ in range(4):
+        v = rng.standard_normal(th.size)
+        dl = o.log_psi(th, x, theta_dir=v)["dlog"]
+        ref_v = c @ dl
+        sc = np.abs(c) @ np.abs(dl)
+        print(prec, "direction: gpu", g @ v, "oracle", ref_v, "rel", abs(g @ v - ref_v) / sc)
+        assert abs(g @ v - ref_v) <= tol * sc
+
+
+def test_param_grad_is_eq6_and_autograd_agrees():
+    """fn_param_grad = sum_p 2 (E_p - mean) / B d log|psi_p| / d theta, its
+    statistics are the FP64 mean / variance / standard error, and the
+    torch.autograd path gives the same vector."""
+    torch, fnvmc = _dev()
+    from paper_2401_10287_amd import autograd as A
+    s = I.lih(256)
+    cfg = fnvmc.Config(s, "fp32")
+    tt = torch.tensor(I.init_params(s), dtype=torch.float32, device="cuda")
+    xt = torch.tensor(I.init_walkers(s), device="cuda")
+    e, lp, _ = fnvmc.fn_local_energy(cfg, tt, xt)
+    grad, stats = fnvmc.fn_param_grad(cfg, tt, xt, e)
+    en = e.cpu().numpy()
+    st = stats.cpu().numpy()
+    np.testing.assert_allclose(st, [en.mean(), en.var(), np.sqrt(en.var() / en.size)], rtol=1e-12)
+    coeff = torch.tensor(2 * (en - en.mean()) / en.size, device="cuda")
+    g2 = fnvmc.fn_log_psi_vjp(cfg, tt, xt, coeff)
+    np.testing.assert_allclose(grad.cpu().numpy(), g2.cpu().numpy(), rtol=1e-6, atol=1e-7)
+    th = tt.clone().requires_grad_(True)
+    loss = A.vmc_loss(cfg, th, xt, e)
+    loss.backward()
+    np.testing.assert_allclose(th.grad.cpu().numpy(), grad.cpu().numpy(), rtol=1e-5, atol=1e-7)
+    assert np.all(np.isfinite(grad.cpu().numpy()))
+
+
+def test_vjp_linear_and_deterministic_full_size():
+    """At the LiF training size (4096 walkers, 4 layers 256/32, 16 dets):
+    the backward is linear in the walker weights and bitwise reproducible."""
+    torch, fnvmc = _dev()
+    s = I.lif()
+    cfg = fnvmc.Config(s, "bf16x6")
+    tt = torch.tensor(I.init_params(s), dtype=torch.float32, device="cuda")
+    xt = torch.tensor(I.init_walkers(s), device="cuda")
+    rng = np.random.default_rng(13)
+    c1 = torch.tensor(rng.standard_normal(4096) / 4096, device="cuda")
+    c2 = torch.tensor(rng.standard_normal(4096) / 4096, device="cuda")
+    ws = fnvmc.Workspace()
+    g1 = fnvmc.fn_log_psi_vjp(cfg, tt, xt, c1, ws=ws)
+    g2 = fnvmc.fn_log_psi_vjp(cfg, tt, xt, c2, ws=ws)
+    g12 = fnvmc.fn_log_psi_vjp(cfg, tt, xt, c1 + c2, ws=ws)
+    g1b = fnvmc.fn_log_psi_vjp(cfg, tt, xt, c1, ws=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g1b)
+    a, b, ab = g1.double().cpu().numpy(), g2.double().cpu().numpy(), g12.double().cpu().numpy()
+    np.testing.assert_allclose(ab, a + b, rtol=1e-3, atol=1e-5 * np.abs(ab).max())
+
+
+def test_training_step_lif_full_size():
+    """The LiF training step: 10 Metropolis moves + local energy + backward
+    on 4096 walkers (BF16x6 streams); everything finite, statistics sane."""
+    torch, fnvmc = _dev()
+    s = I.lif()
+    cfg = fnvmc.Config(s, "bf16x6")
+    tt = torch.tensor(I.init_params(s), dtype=torch.float32, device="cuda")
+    xt = torch.tensor(I.init_walkers(s), device="cuda")
+    lp, _ = fnvmc.fn_log_psi(cfg, tt, xt)
+    acc = fnvmc.vmc_metropolis_step(cfg, tt, xt, lp, 10, 0.2, seed=I.METROPOLIS_SEED)
+    e, lp2, _ = fnvmc.fn_local_energy(cfg, tt, xt)
+    grad, stats = fnvmc.fn_param_grad(cfg, tt, xt, e)
+    torch.cuda.synchronize()
+    print("LiF step: acceptance", acc.float().mean().item() / 10, "E", stats.cpu().numpy())
+    assert torch.isfinite(grad).all()
+    assert 0.05 < acc.float().mean().item() / 10 < 0.99
+    np.testing.assert_allclose(lp.cpu().numpy(), lp2.cpu().numpy(), rtol=0, atol=1e-3)
