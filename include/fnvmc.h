@@ -164,6 +164,53 @@ fn_status fn_log_psi_vjp(const fn_config *cfg, const void *theta, const double *
 /* Message of the calling thread's last failed call ("" if none). */
 const char *fn_last_error(void);
 
+/* ------------------------------------------------------------------------
+   Serving: continuous batching of VMC jobs (walker batches of atoms and ions
+   of any electron count).  A job is B walkers of one system with its own
+   parameters, n_steps Metropolis moves as in vmc_metropolis_step (step
+   counter 0..n_steps-1, its own seed and stream_id) and then the batch
+   mean, variance (1/B) and standard error of the local energy (Eq. 1, 2)
+   plus the acceptance rate.
+   The server owns no device memory: every admitted job's walkers, log|psi|
+   and workspace live in the caller's device arena, whose size is the HBM
+   budget.  fn_server_step() retires finished jobs, admits queued jobs first
+   come first served while their footprint (fn_server_job_bytes) fits the
+   free arena and a stream is free, and enqueues the next quantum of
+   Metropolis steps of every running job on that job's stream, so the work
+   of different jobs overlaps on the device.  A job's results do not depend
+   on the other jobs.  theta and x0 of a job are read until it is done and
+   must stay valid until then.  The server creates one event and one pinned
+   4-double host buffer per stream.  Not safe against concurrent
+   fn_server_step calls on the same server from several threads.
+   ------------------------------------------------------------------------ */
+typedef struct fn_server fn_server;
+
+typedef struct {
+    int32_t state;          /* 0 queued, 1 running, 2 done, 3 failed          */
+    double mean, variance, std_error, acceptance;
+    double submit_s, admit_s, done_s;   /* host steady clock, seconds        */
+    int64_t footprint_bytes;
+} fn_job_result;
+
+/* Arena bytes one job of B walkers needs; 0 if cfg or B is invalid. */
+size_t fn_server_job_bytes(const fn_config *cfg, int64_t B);
+
+/* arena: device, 256-byte aligned, arena_bytes long.  streams: host array of
+   n_streams hipStream_t (one running job per stream).  quantum_steps:
+   Metropolis steps enqueued per job per fn_server_step. */
+fn_status fn_server_create(void *arena, size_t arena_bytes, void *const *streams, int32_t n_streams,
+                           int32_t quantum_steps, fn_server **out);
+/* Queue a job; FN_ENOMEM if it could never fit the arena.  theta: device
+   parameters (cfg's precision), x0: device [B][N][3] initial walkers. */
+fn_status fn_server_submit(fn_server *srv, const fn_config *cfg, const void *theta, const double *x0, int64_t B,
+                           int32_t n_steps, double sigma, uint64_t seed, uint32_t stream_id, int64_t *job);
+/* One scheduler step (non-blocking). */
+fn_status fn_server_step(fn_server *srv, int32_t *n_active, int32_t *n_queued);
+fn_status fn_server_result(fn_server *srv, int64_t job, fn_job_result *out);
+/* Waits for running jobs' streams, then frees the server. */
+fn_status fn_server_destroy(fn_server *srv);
+const char *fn_server_last_error(void);
+
 /* Diagnostics: per-kernel timing.  While enabled, every launch of the
    library's kernels is bracketed by two HIP events recorded on the launch
    stream (creating events is the one allocation the library makes, and

@@ -76,7 +76,8 @@ LIB_PATH = _LIB_PATH
 
 EXPORTED = ["fn_param_count", "fn_workspace_bytes", "fn_log_psi", "fn_local_energy", "vmc_metropolis_step",
             "vmc_metropolis_step_ext", "fn_param_grad", "fn_log_psi_vjp", "fn_last_error", "fn_timing_enable",
-            "fn_timing_reset", "fn_timing_read"]
+            "fn_timing_reset", "fn_timing_read", "fn_server_job_bytes", "fn_server_create", "fn_server_submit",
+            "fn_server_step", "fn_server_result", "fn_server_destroy", "fn_server_last_error"]
 KERNEL_CLASSES = ["stream_gemm", "walker_gemm", "head_gemm", "features", "pair_stream", "spin_mean", "layer_epilogue",
                   "envelope", "det", "combine", "pack", "propose", "accept", "backward"]
 

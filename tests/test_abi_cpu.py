@@ -77,3 +77,13 @@ def test_invalid_arguments_return_before_launch():
     assert st == fnvmc.FN_EINVAL
     # B == 0 is a no-op
     assert fnvmc.LIB.fn_log_psi(cfg.ptr, None, None, 0, None, None, None, 0, None) == fnvmc.FN_OK
+
+
+def test_server_job_footprint_host_side():
+    from paper_2401_10287_amd import serving
+    fnvmc = _fnvmc()
+    cfg = fnvmc.Config(I.atom_ion(9, 0), "bf16x6")
+    a = serving.job_bytes(cfg, 256)
+    b = serving.job_bytes(cfg, 4096)
+    assert 0 < a < b
+    assert b >= cfg.workspace_bytes(4096, fnvmc.FN_OP_LOCAL_ENERGY)

@@ -1,0 +1,101 @@
+"""Continuous batching (fn_server_*): results alone and in a mix are the
+same, admission follows the HBM footprint, and a served job equals the
+oracle's Metropolis chain and energy estimate."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2401_10287_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _mods():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2401_10287_amd import fnvmc, serving
+    return torch, fnvmc, serving
+
+
+def test_alone_equals_mix_and_plain_api():
+    torch, fnvmc, serving = _mods()
+    fac = serving.JobFactory("bf16x6", seed=5, sizes=(256, 1024))
+    jobs = [fac.job(k) for k in range(8)]
+    target = 3
+    cfg, th, x0, info = jobs[target]
+    # alone, one stream
+    srv = serving.Server(8 << 30, n_streams=1, quantum=5)
+    j = srv.submit(cfg, th, x0, 50, 0.2, seed=1, stream_id=target)
+    srv.drain([j])
+    alone = srv.result(j)
+    srv.close()
+    # in a mix of 8 jobs of different sizes on 4 streams, target arriving mid-stream
+    srv = serving.Server(16 << 30, n_streams=4, quantum=3)
+    ids = {}
+    for k in range(8):
+        c, t, x, _ = jobs[k]
+        ids[k] = srv.submit(c, t, x, 50, 0.2, seed=1, stream_id=k)
+        srv.step()
+    srv.drain(list(ids.values()))
+    mix = srv.result(ids[target])
+    others = [srv.result(ids[k]) for k in range(8)]
+    srv.close()
+    print("job", info, "alone", alone["mean"], alone["acceptance"], "mix", mix["mean"], mix["acceptance"])
+    assert alone["state"] == mix["state"] == "done"
+    assert all(o["state"] == "done" for o in others)
+    for key in ("mean", "variance", "std_error", "acceptance"):
+        assert alone[key] == mix[key], key
+    # the same job through the plain entry points
+    x = x0.clone()
+    lp, _ = fnvmc.fn_log_psi(cfg, th, x)
+    acc = fnvmc.vmc_metropolis_step(cfg, th, x, lp, 50, 0.2, seed=1, step0=0, stream_id=target)
+    e, _, _ = fnvmc.fn_local_energy(cfg, th, x)
+    en = e.cpu().numpy()
+    assert abs(en.mean() - alone["mean"]) <= 1e-12 * max(1.0, abs(en.mean()))
+    assert acc.sum().item() / (x.shape[0] * 50) == pytest.approx(alone["acceptance"], abs=1e-15)
+
+
+def test_admission_by_footprint():
+    torch, fnvmc, serving = _mods()
+    fac = serving.JobFactory("fp32", seed=7, sizes=(1024,))
+    jobs = [fac.job(k) for k in range(3)]
+    need = max(serving.job_bytes(c, x.shape[0]) for c, _, x, _ in jobs)
+    srv = serving.Server(need + 4096, n_streams=4, quantum=10)
+    ids = [srv.submit(c, t, x, 20, 0.2, seed=1, stream_id=k) for k, (c, t, x, _) in enumerate(jobs)]
+    active, queued = srv.step()
+    assert active == 1 and queued == 2
+    srv.drain(ids)
+    res = [srv.result(j) for j in ids]
+    assert all(r["state"] == "done" for r in res)
+    # first come first served: each job admitted after the previous finished
+    for a, b in zip(res, res[1:]):
+        assert b["admit_s"] >= a["done_s"] - 1e-3
+    big = serving.JobFactory("fp32", seed=8, sizes=(4096,)).job(0)
+    with pytest.raises(fnvmc.FnError):
+        srv.submit(big[0], big[1], big[2], 5, 0.2, seed=1, stream_id=9)
+    srv.close()
+
+
+def test_served_job_matches_oracle_fp64():
+    """A small FP64 job (Li+, 2 electrons, 2 layers 32/8, 256 walkers): the
+    chain equals the oracle's (same counters) and so does the energy mean."""
+    torch, fnvmc, serving = _mods()
+    s = I.atom_ion(3, 1, walkers=256, n_layers=2, w1=32, w2=8, n_det=2)
+    th = I.init_params(s, seed=77)
+    x = I.init_walkers(s, 256, seed=78)
+    cfg = fnvmc.Config(s, "fp64")
+    tt = torch.tensor(th, device="cuda")
+    xt = torch.tensor(x, device="cuda")
+    srv = serving.Server(1 << 30, n_streams=2, quantum=7)
+    j = srv.submit(cfg, tt, xt, 20, 0.2, seed=3, stream_id=11)
+    srv.drain([j])
+    r = srv.result(j)
+    srv.close()
+    o = O.Oracle(s)
+    la = o.log_psi(th, x)["log_abs"]
+    xo, lo, ao = o.metropolis(th, x, la, 20, 0.2, seed=3, step0=0, stream_id=11)
+    eo = o.local_energy(th, xo)["e_loc"]
+    print("served", r["mean"], r["acceptance"], "oracle", eo.mean(), ao.sum() / (256 * 20))
+    assert r["acceptance"] == pytest.approx(ao.sum() / (256 * 20), abs=0.5 / (256 * 20))
+    assert abs(r["mean"] - eo.mean()) <= 1e-6
+    assert r["variance"] == pytest.approx(eo.var(), rel=1e-6)
