@@ -32,8 +32,8 @@
  *     log|psi| = -inf, sign 0 and a NaN local energy.
  *   - Walker positions x are [B][N][3] FP64, electrons ordered spin-up first.
  *     theta is the flat parameter vector (layout below) in FP64 when
- *     precision == FN_FP64 and FP32 otherwise; gradients come back in the
- *     same type.
+ *     precision == FN_FP64 and FP32 otherwise, 16-byte aligned; gradients
+ *     come back in the same type.
  *
  * Flat parameter layout (M nuclei, L layers, widths w1/w2, K determinants):
  *   for l = 0..L-1 : V_l [d_in][w1]  rows ordered h_i, g_up, g_dn, g_i_up,
@@ -224,6 +224,13 @@ const char *fn_server_last_error(void);
 fn_status fn_timing_enable(int32_t on);
 fn_status fn_timing_reset(void);
 fn_status fn_timing_read(const char *name, double *total_ms, int64_t *launches);
+
+/* Tuning switches (process-wide, set before launching work):
+   "fused_layer" 0/1: one-electron layers as one fused kernel (product +
+   forward-Laplacian epilogue) where the row layout allows it, instead of a
+   product kernel followed by an epilogue kernel.  Both give the same
+   arithmetic up to the order of the final additions. */
+fn_status fn_tuning_set(const char *name, int64_t value);
 
 #ifdef __cplusplus
 }

@@ -345,7 +345,7 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
         ga.rows_per_group = ga.rows;
         { Timed t_(K_WALKER_GEMM, st); (void)launch_gemm(c.smode, ga, st); }
         bool fused = false;
-        if constexpr (std::is_same<T, float>::value) fused = !p.save && stream_layer_supported(c.smode, TR, c.W.W1p);
+        if constexpr (std::is_same<T, float>::value) fused = !p.save && stream_layer_supported(c.smode, TR, s.w1, c.W.W1p);
         if constexpr (std::is_same<T, float>::value) if (fused) {
             LayerArgs la{};
             la.A1 = Hin; la.lda1 = ldh; la.K1 = HWl;
@@ -601,6 +601,7 @@ fn_status fn_log_psi(const fn_config *cfg, const void *theta, const double *x, i
     if (B < 0) return fail(FN_EINVAL, "B < 0");
     if (B == 0) return FN_OK;
     if (!theta || !x || !log_abs_psi) return fail(FN_EINVAL, "theta, x or log_abs_psi is NULL");
+    if (((uintptr_t)theta) % 16) return fail(FN_EINVAL, "theta must be 16-byte aligned");
     Plan p;
     if ((r = make_plan(c, B, FN_OP_LOG_PSI, p))) return r;
     if ((r = check_ws(p, ws, ws_bytes))) return r;
@@ -618,6 +619,7 @@ fn_status fn_local_energy(const fn_config *cfg, const void *theta, const double 
     if (B < 0) return fail(FN_EINVAL, "B < 0");
     if (B == 0) return FN_OK;
     if (!theta || !x || !e_loc) return fail(FN_EINVAL, "theta, x or e_loc is NULL");
+    if (((uintptr_t)theta) % 16) return fail(FN_EINVAL, "theta must be 16-byte aligned");
     Plan p;
     if ((r = make_plan(c, B, FN_OP_LOCAL_ENERGY, p))) return r;
     if ((r = check_ws(p, ws, ws_bytes))) return r;
@@ -639,6 +641,7 @@ static fn_status metropolis_common(const fn_config *cfg, const void *theta, doub
     if (!(sigma >= 0.0) || !isfinite(sigma)) return fail(FN_EINVAL, "sigma must be finite and >= 0");
     if (B == 0 || n_steps == 0) return FN_OK;
     if (!theta || !x || !log_abs_psi) return fail(FN_EINVAL, "theta, x or log_abs_psi is NULL");
+    if (((uintptr_t)theta) % 16) return fail(FN_EINVAL, "theta must be 16-byte aligned");
     Plan p;
     if ((r = make_plan(c, B, FN_OP_METROPOLIS, p))) return r;
     if ((r = check_ws(p, ws, ws_bytes))) return r;
@@ -706,6 +709,16 @@ fn_status fn_log_psi_vjp(const fn_config *cfg, const void *theta, const double *
 }
 
 const char *fn_last_error(void) { return g_err.c_str(); }
+
+fn_status fn_tuning_set(const char *name, int64_t value)
+{
+    if (!name) return fail(FN_EINVAL, "NULL name");
+    if (strcmp(name, "fused_layer") == 0) {
+        fn::g_use_fused_layer = value != 0;
+        return FN_OK;
+    }
+    return fail(FN_EINVAL, std::string("unknown tuning switch ") + name);
+}
 
 fn_status fn_timing_enable(int32_t on)
 {

@@ -128,7 +128,8 @@ struct LayerArgs {
     int64_t rows; int N; int n3; int w1; int W1p; int resid;
 };
 
-bool stream_layer_supported(int mode, int TR, int W1p);
+bool stream_layer_supported(int mode, int TR, int w1, int W1p);
+extern bool g_use_fused_layer;
 void launch_stream_layer(int mode, const LayerArgs &a, int TR, hipStream_t st);
 
 // Rows per electron in forward-Laplacian form: 3N + 2 rounded up to 16, or

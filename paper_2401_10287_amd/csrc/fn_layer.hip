@@ -7,14 +7,14 @@
 //
 // Tiles: 128 rows x 128 columns per 256-thread workgroup; each wave64 owns a
 // 64 x 64 quarter as 4 x 4 blocks of 16 x 16 MFMA accumulators.  Operand
-// tiles of 32 reduction steps go through two LDS stages (one barrier per
-// step); split-BF16 operand fragments are loaded once and reused by every
-// product of parts.  Each electron owns TP rows (TP = 1 value only, or 16 /
-// 32 / 64), so an electron never straddles a wave's 64 rows.  The epilogue
-// runs on the accumulators in registers: the sum of the squared tangent rows
-// of an electron is reduced across the four lane groups of a 16-row block
-// with cross-lane shuffles, and the value and Laplacian rows are broadcast
-// the same way.  Output widths up to 256 columns (two halves).
+// tiles of 32 reduction steps are staged through LDS, the next tile's global
+// loads issued before the current tile's matrix instructions; split-BF16
+// operand fragments are loaded once and reused by every product of parts.
+// Each electron owns TP rows (TP = 1 value only, or 16 / 32 / 64), so an
+// electron never straddles a tile.  The epilogue parks the pre-activations
+// in LDS (over the operand stage) and finishes each (electron, column) pair
+// in one thread: value row, tangent rows and the Laplacian row with its
+// source sum_c dz_c^2.  Output widths up to 256 columns.
 #include "fn_internal.h"
 #include "fn_kernels.h"
 
@@ -50,39 +50,29 @@ constexpr int LDF = LBK + 4;
 
 }  // namespace
 
-// Block order: the two 128-column halves of one 128-row block get block ids
-// that differ by 8, so that (with workgroups dealt to the eight XCDs in turn)
-// both halves run on the same XCD and the second reads the rows from L2.
-__device__ inline void tile_of(int b, int &rb, int &cb)
-{
-    const int hi = b >> 4, rem = b & 15;
-    cb = rem >> 3;
-    rb = hi * 8 + (rem & 7);
-}
-
 template <int MODE, int TP>
 __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 {
     constexpr bool F32 = MODE == GEMM_F32;
     constexpr int NP = MODE == GEMM_BF16 ? 1 : (MODE == GEMM_BF16X3 ? 2 : (MODE == GEMM_BF16X6 ? 3 : 1));
-    // two LDS stages: stage s holds A then B
+    // one operand stage (A then B); the epilogue reuses it for a 128 x 64 tile
     constexpr int ASZ = F32 ? LBM * LDF * 4 : NP * LBM * LDH * 2;
     constexpr int BSZ = F32 ? LBN * LDF * 4 : NP * LBN * LDH * 2;
-    __shared__ __attribute__((aligned(16))) unsigned char smem[2 * (ASZ + BSZ)];
+    constexpr int XS = LBN + 4;                      // float4-aligned rows of the pre-activation tile
+    constexpr int XSZ = LBM * XS * 4;
+    constexpr int ESZ = XSZ + 256 * 16;              // tile + partial Laplacian sources
+    constexpr int SMEM = ASZ + BSZ > ESZ ? ASZ + BSZ : ESZ;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
 
-    int rb, cb;
-    tile_of(blockIdx.x, rb, cb);
-    const int64_t m0 = (int64_t)rb * LBM;
-    const int n0 = cb * LBN;
-    if (m0 >= a.rows || n0 >= a.W1p) return;
+    const int64_t m0 = (int64_t)blockIdx.x * LBM;
+    const int n0 = blockIdx.y * LBN;
+    if (n0 >= a.W1p) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int ktiles = (a.K1 + a.K2) / LBK;
     const float *__restrict__ A1 = a.A1;
     const float *__restrict__ A2 = a.A2;
 
-    // A tile: 4 float4 per thread (row f >> 3, columns 4 (f & 7));
-    // B tile: F32 4 float4 (row f >> 3), BF16 2 uint4 per part (row f >> 2)
     int64_t arow[4];
     bool aval[4];
 #pragma unroll
@@ -127,15 +117,14 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
                 }
         }
     };
-    auto store_tile = [&](int stage) {
-        unsigned char *base = smem + stage * (ASZ + BSZ);
+    auto store_tile = [&]() {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int f = tid + 256 * v;
             const int r = f >> 3, k = 4 * (f & 7);
             const float4 x = ra[v];
             if constexpr (F32) {
-                *(float4 *)((float *)base + r * LDF + k) = x;
+                *(float4 *)((float *)smem + r * LDF + k) = x;
             } else {
                 uint32_t h0[NP], h1[NP], h2[NP], h3[NP];
                 split<NP>(x.x, h0);
@@ -144,19 +133,19 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
                 split<NP>(x.w, h3);
 #pragma unroll
                 for (int q = 0; q < NP; ++q)
-                    *(uint2 *)((uint16_t *)base + q * LBM * LDH + r * LDH + k) =
+                    *(uint2 *)((uint16_t *)smem + q * LBM * LDH + r * LDH + k) =
                         make_uint2(h0[q] | (h1[q] << 16), h2[q] | (h3[q] << 16));
             }
         }
         if constexpr (F32) {
-            float *sB = (float *)(base + ASZ);
+            float *sB = (float *)(smem + ASZ);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int f = tid + 256 * v;
                 *(float4 *)&sB[(f >> 3) * LDF + 4 * (f & 7)] = rwf[v];
             }
         } else {
-            uint16_t *sB = (uint16_t *)(base + ASZ);
+            uint16_t *sB = (uint16_t *)(smem + ASZ);
 #pragma unroll
             for (int q = 0; q < NP; ++q)
 #pragma unroll
@@ -173,17 +162,15 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    if (ktiles > 0) {
-        load_tile(0);
-        store_tile(0);
-    }
+    if (ktiles > 0) load_tile(0);
     for (int kt = 0; kt < ktiles; ++kt) {
-        __syncthreads();                         // stage kt & 1 is complete, stage (kt + 1) & 1 is free
+        __syncthreads();
+        store_tile();
+        __syncthreads();
         if (kt + 1 < ktiles) load_tile(kt + 1);
-        const unsigned char *base = smem + (kt & 1) * (ASZ + BSZ);
         const int ar = wm * 64 + (lane & 15), br = wn * 64 + (lane & 15);
         if constexpr (F32) {
-            const float *sA = (const float *)base, *sB = (const float *)(base + ASZ);
+            const float *sA = (const float *)smem, *sB = (const float *)(smem + ASZ);
 #pragma unroll
             for (int kk = 0; kk < LBK / 4; ++kk) {
                 float fa[4], fb[4];
@@ -198,7 +185,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
             }
         } else {
-            const uint16_t *sA = (const uint16_t *)base, *sB = (const uint16_t *)(base + ASZ);
+            const uint16_t *sA = (const uint16_t *)smem, *sB = (const uint16_t *)(smem + ASZ);
             const int ko = 8 * (lane >> 4);
             bf16x8 ha[NP][4], hb[NP][4];
 #pragma unroll
@@ -208,7 +195,6 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) hb[q][j] = *(const bf16x8 *)&sB[q * LBN * LDH + (br + 16 * j) * LDH + ko];
             }
-            // products of parts (pa, pb) with pa + pb < NP, smallest first
 #pragma unroll
             for (int sum = NP - 1; sum >= 0; --sum)
 #pragma unroll
@@ -220,102 +206,137 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j], acc[i][j],
                                                                                 0, 0, 0);
         }
-        if (kt + 1 < ktiles) store_tile((kt + 1) & 1);
     }
 
-    // ---- epilogue: accumulator (i, j)[e] is row 64 wm + 16 i + 4 (lane >> 4) + e,
-    //      column n0 + 64 wn + 16 j + (lane & 15)
-    const int lg = lane >> 4, lc = lane & 15;
+    // ---- epilogue through LDS: the pre-activation tile replaces the operand
+    //      stage.  Work item = (electron, 4 columns, 16 rows): 256 items per
+    //      tile for TP = 16 / 32 / 64, float4 loads and stores, rows unrolled.
+    //      Pass 1: z = X + P (+ b on the value row) back into LDS and the
+    //      partial Laplacian source sum_c dz_c^2 of the item's rows; pass 2:
+    //      value, tangent and Laplacian rows plus the residual.
     const float *__restrict__ Pw = a.Pw;
     const float *__restrict__ bias = a.bias;
     const float *__restrict__ Hin = a.A1;
     float *__restrict__ Hout = a.Hout;
-    const int n3 = a.n3;
-    const int64_t mw = m0 + 64 * wm;
+    const int n3 = a.n3, tl = n3 + 1;
+    const int64_t rows_here = a.rows - m0 < LBM ? a.rows - m0 : LBM;
+    float *sX = (float *)smem;
+    __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int col = n0 + wn * 64 + 16 * j + lc;
-        if (col >= a.W1p) continue;
-        const bool real = col < a.w1;
-        const float bcol = real ? bias[col] : 0.f;
-        if constexpr (TP == 1) {
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int64_t R = mw + 16 * i + 4 * lg + e;
-                    if (R >= a.rows) continue;
-                    float y = 0.f;
-                    if (real) {
-                        const int64_t w = R / a.N;
-                        y = tanhf(acc[i][j][e] + Pw[w * a.w1 + col] + bcol);
-                        if (a.resid) y += Hin[R * a.lda1 + col];
-                    }
-                    Hout[R * a.ldh_out + col] = y;
+            for (int e = 0; e < 4; ++e)
+                sX[(wm * 64 + 16 * i + 4 * (lane >> 4) + e) * XS + wn * 64 + 16 * j + (lane & 15)] = acc[i][j][e];
+    __syncthreads();
+    auto f4add = [](float4 u, float4 v) { return make_float4(u.x + v.x, u.y + v.y, u.z + v.z, u.w + v.w); };
+    if constexpr (TP == 1) {
+        for (int q = tid; q < LBM * (LBN / 4); q += 256) {
+            const int r = q / (LBN / 4), cq = q % (LBN / 4);
+            const int col = n0 + 4 * cq;
+            const int64_t R = m0 + r;
+            if (r >= rows_here || col >= a.W1p) continue;
+            float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (col < a.w1) {
+                const int64_t w = R / a.N;
+                const float4 p = *(const float4 *)(Pw + w * a.w1 + col);
+                const float4 bb = *(const float4 *)(bias + col);
+                const float *x = sX + r * XS + 4 * cq;
+                y = make_float4(tanhf((x[0] + p.x) + bb.x), tanhf((x[1] + p.y) + bb.y), tanhf((x[2] + p.z) + bb.z),
+                                tanhf((x[3] + p.w) + bb.w));
+                if (a.resid) y = f4add(y, *(const float4 *)(Hin + R * a.lda1 + col));
+            }
+            *(float4 *)(Hout + R * a.ldh_out + col) = y;
+        }
+    } else {
+        constexpr int QPR = TP / 16;                   // 16-row chunks per electron
+        float4 *srcp = (float4 *)(smem + XSZ);         // [256] partial sources
+        const int q = tid;
+        const int el = q / (32 * QPR), rem = q % (32 * QPR);
+        const int cq = rem / QPR, rc = rem % QPR;
+        const int col = n0 + 4 * cq;
+        const int64_t Rb = m0 + (int64_t)el * TP;
+        const bool live = (int64_t)el * TP < rows_here && col < a.W1p;
+        const bool real = live && col < a.w1;
+        float *xc = sX + (el * TP) * XS + 4 * cq;
+        float4 src = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (real) {
+            const int64_t w = (Rb / TP) / a.N;
+            const float *pw = Pw + (w * TP) * (int64_t)a.w1 + col;
+            float4 p[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int t = 16 * rc + u;
+                p[u] = t <= tl ? *(const float4 *)(pw + (int64_t)t * a.w1) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            const float4 b4 = rc == 0 ? *(const float4 *)(bias + col) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int t = 16 * rc + u;
+                float *x = xc + t * XS;
+                float4 z = make_float4(x[0] + p[u].x, x[1] + p[u].y, x[2] + p[u].z, x[3] + p[u].w);
+                if (t == 0) z = f4add(z, b4);              // (X + P) + b, as the separate epilogue
+                x[0] = z.x; x[1] = z.y; x[2] = z.z; x[3] = z.w;
+                if (t >= 1 && t <= n3) {
+                    src.x += z.x * z.x; src.y += z.y * z.y; src.z += z.z * z.z; src.w += z.w * z.w;
                 }
-        } else {
-            constexpr int IB = TP / 16;                 // 16-row blocks per electron
-            const int tl = n3 + 1;                      // Laplacian row of an electron
-            const int ibl = tl >> 4, lgl = (tl >> 2) & 3, el = tl & 3;
+            }
+        }
+        srcp[q] = src;
+        __syncthreads();
+        if (live) {
+            float4 r4[16];
 #pragma unroll
-            for (int ib0 = 0; ib0 < 4; ib0 += IB) {
-                const int64_t Rb = mw + 16 * ib0;       // first row of this electron
-                if (Rb >= a.rows) continue;
-                const int64_t E = Rb / TP;
-                const int64_t w = E / a.N;
-                const float *pw = Pw + (w * TP) * (int64_t)a.w1 + col;
-                float z[IB][4];
-                float src = 0.f, cand = 0.f;
+            for (int u = 0; u < 16; ++u) {
+                const int t = 16 * rc + u;
+                r4[u] = real && a.resid && t <= tl ? *(const float4 *)(Hin + (Rb + t) * a.lda1 + col)
+                                                  : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-                for (int q = 0; q < IB; ++q)
+            for (int k = 0; k < QPR; ++k) s4 = f4add(s4, srcp[el * 32 * QPR + cq * QPR + k]);
+            const float *z0 = xc, *zl = xc + tl * XS;
+            float y0[4], dd[4], lap[4];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int t = 16 * q + 4 * lg + e;
-                        float v = acc[ib0 + q][j][e];
-                        if (real) v += pw[(int64_t)t * a.w1] + (t == 0 ? bcol : 0.f);
-                        z[q][e] = v;
-                        if (t >= 1 && t <= n3) src += v * v;
-                        if (q == ibl && e == el) cand = v;
-                    }
-                src += __shfl_xor(src, 16, 64);
-                src += __shfl_xor(src, 32, 64);
-                const float z0 = __shfl(z[0][0], lc, 64);
-                const float zl = __shfl(cand, 16 * lgl + lc, 64);
-                const float y0 = tanhf(z0);
-                const float d = 1.f - y0 * y0;
+            for (int c = 0; c < 4; ++c) {
+                y0[c] = tanhf(z0[c]);
+                dd[c] = 1.f - y0[c] * y0[c];
+                const float sc = c == 0 ? s4.x : (c == 1 ? s4.y : (c == 2 ? s4.z : s4.w));
+                lap[c] = dd[c] * zl[c] - 2.f * y0[c] * dd[c] * sc;
+            }
 #pragma unroll
-                for (int q = 0; q < IB; ++q)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int t = 16 * q + 4 * lg + e;
-                        const int64_t R = Rb + t;
-                        float y = 0.f;
-                        if (real && t <= tl) {
-                            y = t == 0 ? y0 : (t < tl ? d * z[q][e] : d * zl - 2.f * y0 * d * src);
-                            if (a.resid) y += Hin[R * a.lda1 + col];
-                        }
-                        Hout[R * a.ldh_out + col] = y;
-                    }
+            for (int u = 0; u < 16; ++u) {
+                const int t = 16 * rc + u;
+                const float *x = xc + t * XS;
+                float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (real && t <= tl) {
+                    if (t == 0) y = make_float4(y0[0], y0[1], y0[2], y0[3]);
+                    else if (t < tl) y = make_float4(dd[0] * x[0], dd[1] * x[1], dd[2] * x[2], dd[3] * x[3]);
+                    else y = make_float4(lap[0], lap[1], lap[2], lap[3]);
+                    y = f4add(y, r4[u]);
+                }
+                *(float4 *)(Hout + (Rb + t) * a.ldh_out + col) = y;
             }
         }
     }
 }
 
-// The fused layer is kept out of the default path until its operand pipeline
-// hides the load latency at this reduction depth (K = 320): measured slower
-// than the separate product + epilogue on LiH.
-bool g_use_fused_layer = false;
+// Default path for the stream layers in every MFMA mode whose row layout it
+// supports; the separate product + epilogue kernels remain for the others
+// (and for the backward pass, which keeps the tanh outputs).
+bool g_use_fused_layer = true;
 
-bool stream_layer_supported(int mode, int TR, int W1p)
+bool stream_layer_supported(int mode, int TR, int w1, int W1p)
 {
-    return g_use_fused_layer && mode != GEMM_F64 && W1p <= 2 * LBN && (TR == 1 || TR == 16 || TR == 32 || TR == 64);
+    return g_use_fused_layer && mode != GEMM_F64 && W1p <= 2 * LBN && w1 % 4 == 0 &&
+           (TR == 1 || TR == 16 || TR == 32 || TR == 64);
 }
 
 template <int MODE>
 static void launch_mode(const LayerArgs &a, int TR, hipStream_t st)
 {
-    const int64_t rblocks = (a.rows + LBM - 1) / LBM;
-    dim3 grid((unsigned)(((rblocks + 7) / 8) * 16));
+    dim3 grid((unsigned)((a.rows + LBM - 1) / LBM), (unsigned)((a.W1p + LBN - 1) / LBN));
     switch (TR) {
     case 1: hipLaunchKernelGGL((k_stream_layer<MODE, 1>), grid, dim3(256), 0, st, a); break;
     case 16: hipLaunchKernelGGL((k_stream_layer<MODE, 16>), grid, dim3(256), 0, st, a); break;

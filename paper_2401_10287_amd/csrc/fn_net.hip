@@ -249,6 +249,36 @@ __global__ __launch_bounds__(256) void k_spin_mean(const T *__restrict__ H, int6
     }
 }
 
+// FP32 rows, four columns per thread (HWl is a multiple of 32)
+template <>
+__global__ __launch_bounds__(256) void k_spin_mean<float>(const float *__restrict__ H, int64_t ldh, int N, int nu,
+                                                          int TR, int dh, int HWl, float *__restrict__ G)
+{
+    const int nd = N - nu;
+    const int wt = blockIdx.x;
+    const int w = wt / TR, t = wt - w * TR;
+    const float *h0 = H + ((int64_t)w * N * TR + t) * ldh;
+    const int64_t jstride = (int64_t)TR * ldh;
+    float *g = G + (int64_t)wt * 2 * HWl;
+    const float iu = nu > 0 ? 1.f / nu : 0.f, id = nd > 0 ? 1.f / nd : 0.f;
+    for (int c4 = threadIdx.x; c4 < HWl / 2; c4 += blockDim.x) {
+        const int col = 4 * c4;
+        const int sp = col >= HWl, k = col - sp * HWl;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (k < dh) {
+            const int j0 = sp ? nu : 0, j1 = sp ? N : nu;
+            for (int j = j0; j < j1; ++j) {
+                const float4 h = *(const float4 *)(h0 + j * jstride + k);
+                v.x += h.x; v.y += h.y; v.z += h.z; v.w += h.w;
+            }
+            const float sc = sp ? id : iu;
+            v.x *= sc; v.y *= sc; v.z *= sc; v.w *= sc;
+            // columns dh.. of the padded block are zero in H, so whole float4s are safe
+        }
+        *(float4 *)(g + col) = v;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // layer epilogue: z = X + P (per-walker part) + b (value row), y = tanh(z) in
 // forward-Laplacian form, plus the residual h_i when widths match (l >= 1).

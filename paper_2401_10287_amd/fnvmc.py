@@ -68,6 +68,8 @@ def _load():
     lib.fn_timing_reset.argtypes = []
     lib.fn_timing_read.restype = i32
     lib.fn_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.fn_tuning_set.restype = i32
+    lib.fn_tuning_set.argtypes = [ctypes.c_char_p, i64]
     return lib
 
 
@@ -76,7 +78,7 @@ LIB_PATH = _LIB_PATH
 
 EXPORTED = ["fn_param_count", "fn_workspace_bytes", "fn_log_psi", "fn_local_energy", "vmc_metropolis_step",
             "vmc_metropolis_step_ext", "fn_param_grad", "fn_log_psi_vjp", "fn_last_error", "fn_timing_enable",
-            "fn_timing_reset", "fn_timing_read", "fn_server_job_bytes", "fn_server_create", "fn_server_submit",
+            "fn_timing_reset", "fn_timing_read", "fn_tuning_set", "fn_server_job_bytes", "fn_server_create", "fn_server_submit",
             "fn_server_step", "fn_server_result", "fn_server_destroy", "fn_server_last_error"]
 KERNEL_CLASSES = ["stream_gemm", "walker_gemm", "head_gemm", "features", "pair_stream", "spin_mean", "layer_epilogue",
                   "envelope", "det", "combine", "pack", "propose", "accept", "backward"]
@@ -255,3 +257,7 @@ def fn_timing_read(name: str):
     ms, n = ctypes.c_double(), ctypes.c_int64()
     _check(LIB.fn_timing_read(name.encode(), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def fn_tuning_set(name: str, value: int) -> None:
+    _check(LIB.fn_tuning_set(name.encode(), int(value)))
