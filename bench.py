@@ -58,6 +58,42 @@ def time_steps(fn, steps, torch):
     return wall, lat
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2401_10287_amd", "csrc", "fn_layer.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lih_stream_layer_hbm_traffic.md")
+
+
+def copy_calibration():
+    """A plain device copy of 1 GiB, five times: the counter scale is what
+    FETCH_SIZE / WRITE_SIZE report for it divided by 1 GiB."""
+    import torch
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": 4 * n, "copies": 5}))
+
+
+def kernel_hash():
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """Bytes per launch of the stream layer from the committed counter
+    summary, or None when the kernel source changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    import re
+    txt = open(TRAFFIC_FILE).read()
+    m = re.search(r"kernel source sha256\[:16\]: `([0-9a-f]+)`", txt)
+    t = re.search(r"traffic per launch \(bytes\): `([0-9.e+]+)`", txt)
+    if not m or not t or m.group(1) != kernel_hash():
+        return None
+    return float(t.group(1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,7 +103,13 @@ def main():
     ap.add_argument("--walkers", type=int, default=4096)
     ap.add_argument("--sample", type=int, default=192, help="walkers checked against / timed on the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-jobs", type=int, default=120, help="jobs of the Poisson serving run (0: skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
@@ -174,13 +216,26 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "flops_per_launch": flops_per_launch,
             "avg_launch_us": avg_launch_s * 1e6,
             "launches": n_g,
             "kernel_share_of_step": ms_g / max(total_kernel_ms, 1e-9),
         },
     }
+    if args.serving_jobs > 0:
+        from paper_2401_10287_amd import serving
+        torch.cuda.synchronize()
+        sat = serving.run_load(max(20, args.serving_jobs // 3), None, args.precision)
+        load = serving.run_load(args.serving_jobs, 0.7 * sat["jobs_per_s"], args.precision)
+        print(f"[bench] serving: saturation {sat['jobs_per_s']:.1f} jobs/s; Poisson at 0.7x: "
+              f"p50 {load['p50_ms']:.1f} ms p99 {load['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+        line["config"]["serving"] = {
+            "workload": "Poisson stream of VMC jobs, atoms and ions Z 2..10, charge -1..+2, walker batches "
+                        "256/1024/4096, 50 Metropolis steps + energy estimate each, 4 layers 256/32, 16 dets",
+            "jobs": load["jobs"], "arrival_rate_jobs_per_s": load["rate"], "jobs_per_s": load["jobs_per_s"],
+            "saturation_jobs_per_s": sat["jobs_per_s"], "p50_latency_ms": load["p50_ms"],
+            "p99_latency_ms": load["p99_ms"], "failed": load["failed"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = {"value": samp / t_orc, "unit": "evals/s", "cores": O.num_threads(), "kind": "oracle",
                                 "sample": f"FP64 oracle local energy of the first {samp} of the {args.walkers} "

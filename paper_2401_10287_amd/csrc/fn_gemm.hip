@@ -54,20 +54,33 @@ __device__ inline void split_bf16(float x, uint32_t (&h)[NP])
     }
 }
 
-template <int MODE>
+template <int MODE, int BNT>
 __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
 {
     constexpr bool F32 = ModeInfo<MODE>::F32;
     constexpr int NP = ModeInfo<MODE>::NP;
+    // wave tiling: 2 x 2 waves of 64 x 64 for 128 columns, else 4 x 1 waves of 32 x BNT
+    constexpr int WI = BNT == 128 ? 4 : 2;          // 16-row blocks per wave
+    constexpr int WJ = BNT == 128 ? 4 : BNT / 16;   // 16-column blocks per wave
     __shared__ __attribute__((aligned(16))) float sAf[F32 ? BM * LDF : 1];
-    __shared__ __attribute__((aligned(16))) float sBf[F32 ? BN * LDF : 1];
+    __shared__ __attribute__((aligned(16))) float sBf[F32 ? BNT * LDF : 1];
     __shared__ __attribute__((aligned(16))) uint16_t sAh[F32 ? 8 : NP * BM * LDH];
-    __shared__ __attribute__((aligned(16))) uint16_t sBh[F32 ? 8 : NP * BN * LDH];
+    __shared__ __attribute__((aligned(16))) uint16_t sBh[F32 ? 8 : NP * BNT * LDH];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    const int64_t m0 = (int64_t)blockIdx.x * BM;
-    const int n0 = blockIdx.y * BN;
+    const int wm = BNT == 128 ? wave >> 1 : wave, wn = BNT == 128 ? wave & 1 : 0;
+    const int ncb = (a.nout + BNT - 1) / BNT;
+    int64_t rb;
+    int cb;
+    if (ncb <= 2) {
+        xcd_tile(blockIdx.x, ncb, rb, cb);
+    } else {
+        rb = blockIdx.x % ((a.rows + BM - 1) / BM);
+        cb = (int)(blockIdx.x / ((a.rows + BM - 1) / BM));
+    }
+    const int64_t m0 = rb * BM;
+    const int n0 = cb * BNT;
+    if (m0 >= a.rows || n0 >= a.nout) return;
     const int ktiles = (a.K1 + a.K2) / BK;
 
     // A rows loaded by this thread: 4 float4 per tile, row = f >> 3, k4 = f & 7
@@ -84,9 +97,11 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
     const float *A1 = (const float *)a.A1;
     const float *A2 = (const float *)a.A2;
 
+    constexpr int NWF = F32 ? (BNT * 8 + 255) / 256 : 1;      // float4 of B per thread
+    constexpr int NWH = F32 ? 1 : (BNT * 4 + 255) / 256;      // uint4 of B per thread per part
     float4 ra[4];
-    uint4 rwh[F32 ? 1 : 2 * NP];
-    float4 rwf[F32 ? 4 : 1];
+    uint4 rwh[F32 ? 1 : NWH * NP];
+    float4 rwf[NWF];
 
     auto load_tile = [&](int kt) {
         const int kb = kt * BK;
@@ -104,11 +119,11 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
         if constexpr (F32) {
             const float *W = (const float *)a.W;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
+            for (int v = 0; v < NWF; ++v) {
                 int f = tid + 256 * v;
                 int o = n0 + (f >> 3);
-                rwf[v] = o < a.nout ? *(const float4 *)(W + (int64_t)o * a.ldw + kb + 4 * (f & 7))
-                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+                rwf[v] = (f < BNT * 8 && o < a.nout) ? *(const float4 *)(W + (int64_t)o * a.ldw + kb + 4 * (f & 7))
+                                                     : make_float4(0.f, 0.f, 0.f, 0.f);
             }
         } else {
             // the NP weight parts are stored one after another, part stride a.wpart elements
@@ -116,11 +131,11 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
 #pragma unroll
             for (int q = 0; q < NP; ++q)
 #pragma unroll
-                for (int v = 0; v < 2; ++v) {
+                for (int v = 0; v < NWH; ++v) {
                     int f = tid + 256 * v;
                     int o = n0 + (f >> 2);
                     int64_t off = (int64_t)q * a.wpart + (int64_t)o * a.ldw + kb + 8 * (f & 3);
-                    rwh[q * 2 + v] = o < a.nout ? *(const uint4 *)(W + off) : make_uint4(0, 0, 0, 0);
+                    rwh[q * NWH + v] = (f < BNT * 4 && o < a.nout) ? *(const uint4 *)(W + off) : make_uint4(0, 0, 0, 0);
                 }
         }
     };
@@ -147,26 +162,26 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
         }
         if constexpr (F32) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
+            for (int v = 0; v < NWF; ++v) {
                 int f = tid + 256 * v;
-                *(float4 *)&sBf[(f >> 3) * LDF + 4 * (f & 7)] = rwf[v];
+                if (f < BNT * 8) *(float4 *)&sBf[(f >> 3) * LDF + 4 * (f & 7)] = rwf[v];
             }
         } else {
 #pragma unroll
             for (int q = 0; q < NP; ++q)
 #pragma unroll
-                for (int v = 0; v < 2; ++v) {
+                for (int v = 0; v < NWH; ++v) {
                     int f = tid + 256 * v;
-                    *(uint4 *)&sBh[q * BN * LDH + (f >> 2) * LDH + 8 * (f & 3)] = rwh[q * 2 + v];
+                    if (f < BNT * 4) *(uint4 *)&sBh[q * BNT * LDH + (f >> 2) * LDH + 8 * (f & 3)] = rwh[q * NWH + v];
                 }
         }
     };
 
-    f32x4 acc[4][4];
+    f32x4 acc[WI][WJ];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < WI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < WJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     if (ktiles > 0) load_tile(0);
     for (int kt = 0; kt < ktiles; ++kt) {
@@ -174,55 +189,56 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
         store_tile();
         __syncthreads();
         if (kt + 1 < ktiles) load_tile(kt + 1);
-        const int ar = wm * 64 + (lane & 15), br = wn * 64 + (lane & 15);
+        const int ar = wm * 16 * WI + (lane & 15), br = wn * 16 * WJ + (lane & 15);
         if constexpr (F32) {
 #pragma unroll
             for (int kk = 0; kk < BK / 4; ++kk) {
-                float fa[4], fb[4];
+                float fa[WI], fb[WJ];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) fa[i] = sAf[(ar + 16 * i) * LDF + 4 * kk + (lane >> 4)];
+                for (int i = 0; i < WI; ++i) fa[i] = sAf[(ar + 16 * i) * LDF + 4 * kk + (lane >> 4)];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) fb[j] = sBf[(br + 16 * j) * LDF + 4 * kk + (lane >> 4)];
+                for (int j = 0; j < WJ; ++j) fb[j] = sBf[(br + 16 * j) * LDF + 4 * kk + (lane >> 4)];
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < WI; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
+                    for (int j = 0; j < WJ; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
             }
         } else {
             const int ko = 8 * (lane >> 4);
+            bf16x8 ha[NP][WI], hb[NP][WJ];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+#pragma unroll
+                for (int i = 0; i < WI; ++i) ha[q][i] = *(const bf16x8 *)&sAh[q * BM * LDH + (ar + 16 * i) * LDH + ko];
+#pragma unroll
+                for (int j = 0; j < WJ; ++j) hb[q][j] = *(const bf16x8 *)&sBh[q * BNT * LDH + (br + 16 * j) * LDH + ko];
+            }
             // products of parts (pa, pb) with pa + pb < NP, smallest first
 #pragma unroll
-            for (int sum = NP - 1; sum >= 0; --sum) {
+            for (int sum = NP - 1; sum >= 0; --sum)
 #pragma unroll
-                for (int pa = 0; pa <= sum; ++pa) {
-                    const int pb = sum - pa;
-                    bf16x8 ha[4], hb[4];
+                for (int pa = 0; pa <= sum; ++pa)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) ha[i] = *(const bf16x8 *)&sAh[pa * BM * LDH + (ar + 16 * i) * LDH + ko];
+                    for (int i = 0; i < WI; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) hb[j] = *(const bf16x8 *)&sBh[pb * BN * LDH + (br + 16 * j) * LDH + ko];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[i], hb[j], acc[i][j], 0, 0, 0);
-                }
-            }
+                        for (int j = 0; j < WJ; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j], acc[i][j],
+                                                                                0, 0, 0);
         }
     }
 
     // accumulator (i, j) element e sits at row 16 i + 4 (lane >> 4) + e, column 16 j + (lane & 15)
     float *C = (float *)a.C;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < WI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            int col = n0 + wn * 64 + 16 * j + (lane & 15);
+        for (int j = 0; j < WJ; ++j) {
+            int col = n0 + wn * 16 * WJ + 16 * j + (lane & 15);
             if (col >= a.nout) continue;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                int64_t row = m0 + wm * 64 + 16 * i + 4 * (lane >> 4) + e;
+                int64_t row = m0 + wm * 16 * WI + 16 * i + 4 * (lane >> 4) + e;
                 if (row >= a.rows) continue;
                 if (a.c_rows_per_group > 0) row = remap_row(row, a.c_rows_per_group, a.c_group_stride, a.c_row_offset);
                 C[row * a.ldc + col] = acc[i][j][e];
@@ -292,18 +308,30 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs a)
     }
 }
 
+template <int BNT>
+static void launch_bn(int mode, const GemmArgs &a, hipStream_t st)
+{
+    const int64_t nrb = (a.rows + BM - 1) / BM;
+    const int ncb = (a.nout + BNT - 1) / BNT;
+    dim3 grid((unsigned)(ncb <= 2 ? xcd_grid(nrb, ncb) : nrb * ncb));
+    if (mode == GEMM_F32) hipLaunchKernelGGL((k_gemm_mfma<GEMM_F32, BNT>), grid, dim3(256), 0, st, a);
+    else if (mode == GEMM_BF16) hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16, BNT>), grid, dim3(256), 0, st, a);
+    else if (mode == GEMM_BF16X3) hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16X3, BNT>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16X6, BNT>), grid, dim3(256), 0, st, a);
+}
+
 hipError_t launch_gemm(int mode, const GemmArgs &a, hipStream_t st)
 {
     if (a.rows <= 0 || a.nout <= 0) return hipSuccess;
     if (mode == GEMM_F64) {
         dim3 grid((unsigned)((a.rows + 63) / 64), (unsigned)((a.nout + 63) / 64));
         hipLaunchKernelGGL(k_gemm_f64, grid, dim3(256), 0, st, a);
+    } else if (a.nout <= 32) {
+        launch_bn<32>(mode, a, st);
+    } else if (a.nout <= 64) {
+        launch_bn<64>(mode, a, st);
     } else {
-        dim3 grid((unsigned)((a.rows + BM - 1) / BM), (unsigned)((a.nout + BN - 1) / BN));
-        if (mode == GEMM_F32) hipLaunchKernelGGL(k_gemm_mfma<GEMM_F32>, grid, dim3(256), 0, st, a);
-        else if (mode == GEMM_BF16) hipLaunchKernelGGL(k_gemm_mfma<GEMM_BF16>, grid, dim3(256), 0, st, a);
-        else if (mode == GEMM_BF16X3) hipLaunchKernelGGL(k_gemm_mfma<GEMM_BF16X3>, grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL(k_gemm_mfma<GEMM_BF16X6>, grid, dim3(256), 0, st, a);
+        launch_bn<128>(mode, a, st);
     }
     return hipGetLastError();
 }

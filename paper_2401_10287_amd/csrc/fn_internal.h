@@ -107,6 +107,20 @@ struct GemmArgs {
     int64_t c_rows_per_group, c_group_stride, c_row_offset;
 };
 
+// Block order for a grid of row blocks x ncb column blocks (ncb = 1 or 2):
+// workgroups are dealt to the eight XCDs in turn, so the two column halves of
+// one row block get ids that differ by 8 -- same XCD, adjacent in time -- and
+// the second half finds the rows in that XCD's L2.
+__host__ __device__ inline void xcd_tile(int64_t b, int ncb, int64_t &rb, int &cb)
+{
+    if (ncb == 1) { rb = b; cb = 0; return; }
+    const int64_t hi = b >> 4, rem = b & 15;
+    cb = (int)(rem >> 3);
+    rb = hi * 8 + (rem & 7);
+}
+
+inline int64_t xcd_grid(int64_t nrb, int ncb) { return ncb == 1 ? nrb : ((nrb + 7) / 8) * 16; }
+
 __host__ __device__ inline int64_t remap_row(int64_t r, int64_t per, int64_t stride, int64_t off)
 {
     const int64_t g = r / per;

@@ -5,7 +5,8 @@
 // in forward-Laplacian form: value row y = tanh(z_0), tangent rows
 // (1 - y^2) dz_c, Laplacian row (1 - y^2) lap z - 2 y (1 - y^2) sum_c dz_c^2.
 //
-// Tiles: 128 rows x 128 columns per 256-thread workgroup; each wave64 owns a
+// Tiles: 128 rows x 128 columns per 256-thread workgroup, the two column
+// halves of a row block on one XCD back to back; each wave64 owns a
 // 64 x 64 quarter as 4 x 4 blocks of 16 x 16 MFMA accumulators.  Operand
 // tiles of 32 reduction steps are staged through LDS, the next tile's global
 // loads issued before the current tile's matrix instructions; split-BF16
@@ -64,9 +65,12 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
     constexpr int SMEM = ASZ + BSZ > ESZ ? ASZ + BSZ : ESZ;
     __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
 
-    const int64_t m0 = (int64_t)blockIdx.x * LBM;
-    const int n0 = blockIdx.y * LBN;
-    if (n0 >= a.W1p) return;
+    int64_t rb;
+    int cb;
+    xcd_tile(blockIdx.x, (a.W1p + LBN - 1) / LBN, rb, cb);
+    const int64_t m0 = rb * LBM;
+    const int n0 = cb * LBN;
+    if (m0 >= a.rows || n0 >= a.W1p) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int ktiles = (a.K1 + a.K2) / LBK;
@@ -336,7 +340,7 @@ bool stream_layer_supported(int mode, int TR, int w1, int W1p)
 template <int MODE>
 static void launch_mode(const LayerArgs &a, int TR, hipStream_t st)
 {
-    dim3 grid((unsigned)((a.rows + LBM - 1) / LBM), (unsigned)((a.W1p + LBN - 1) / LBN));
+    dim3 grid((unsigned)xcd_grid((a.rows + LBM - 1) / LBM, (a.W1p + LBN - 1) / LBN));
     switch (TR) {
     case 1: hipLaunchKernelGGL((k_stream_layer<MODE, 1>), grid, dim3(256), 0, st, a); break;
     case 16: hipLaunchKernelGGL((k_stream_layer<MODE, 16>), grid, dim3(256), 0, st, a); break;

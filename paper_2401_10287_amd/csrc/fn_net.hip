@@ -158,6 +158,10 @@ __global__ void k_pair_stream(Sys s, const double *x, const T *theta, ParamLayou
     const int wp = s.w2 > 4 ? s.w2 : 4;
     T *S0 = (T *)smem_raw;
     T *S1 = S0 + s.N * R * wp;
+    // all pair-layer weights and biases (theta from W2_0 on) staged in LDS
+    T *Wsm = S1 + s.N * R * wp;
+    const int64_t npw = s.L > 1 ? P.c2[s.L - 2] + s.w2 - P.W2[0] : 0;
+    for (int64_t q = threadIdx.x; q < npw; q += blockDim.x) Wsm[q] = theta[P.W2[0] + q];
     const int64_t wi = blockIdx.x;
     const int64_t w = wi / s.N;
     const int i = (int)(wi % s.N);
@@ -189,8 +193,8 @@ __global__ void k_pair_stream(Sys s, const double *x, const T *theta, ParamLayou
     for (int l = 0; l + 1 < s.L; ++l) {
         __syncthreads();
         const int dp = l == 0 ? 4 : s.w2;
-        const T *W2 = theta + P.W2[l];
-        const T *c2 = theta + P.c2[l];
+        const T *W2 = Wsm + (P.W2[l] - P.W2[0]);
+        const T *c2 = Wsm + (P.c2[l] - P.W2[0]);
         for (int idx = threadIdx.x; idx < s.N * s.w2; idx += blockDim.x) {
             const int j = idx / s.w2, o = idx % s.w2;
             const T *in = S0 + j * R * wp;
@@ -625,7 +629,9 @@ void launch_features(const Sys &s, const double *x, int64_t B, int TR, int HW0, 
 size_t pair_stream_lds(const Sys &s, bool fl, size_t elem)
 {
     int wp = s.w2 > 4 ? s.w2 : 4;
-    return 2 * (size_t)s.N * (fl ? 8 : 1) * wp * elem;
+    const ParamLayout P = make_layout(s);
+    const size_t npw = s.L > 1 ? (size_t)(P.c2[s.L - 2] + s.w2 - P.W2[0]) : 0;
+    return (2 * (size_t)s.N * (fl ? 8 : 1) * wp + npw) * elem;
 }
 
 template <typename T>

@@ -107,7 +107,7 @@ def test_log_psi(name, prec, walkers, tol):
     np.testing.assert_array_equal(sg.cpu().numpy(), ref["sign"])
 
 
-def _check_energy(e, parts, ref, tol, label, kappa=None):
+def _check_energy(e, parts, ref, tol, label, kappa=None, rel=1e-4):
     d = np.abs(e - ref["e_loc"])
     dm = abs(e.mean() - ref["e_loc"].mean())
     print(f"{label}: E_L max |d| {d.max():.2e} Ha, median {np.median(d):.2e}, p99 {np.percentile(d, 99):.2e}, "
@@ -117,12 +117,12 @@ def _check_energy(e, parts, ref, tol, label, kappa=None):
     bound = np.full_like(d, tol)
     if kappa is not None:
         kin = np.abs(ref["parts"][:, 0])
-        bound = (tol + 1e-4 * kin) * np.maximum(1.0, kappa / 10.0) ** 2
+        bound = (tol + rel * kin) * np.maximum(1.0, kappa / 10.0) ** 2
         n_ill = int((bound > 2 * tol).sum())
         order = np.argsort(-d)[:4]
         print(f"   {n_ill} walkers where conditioning dominates; worst (err, kappa, |E_kin|): "
               + ", ".join(f"({d[i]:.1e}, {kappa[i]:.0f}, {kin[i]:.1f})" for i in order))
-        assert np.median(d / (1.0 + kin)) <= 1e-5
+        assert np.median(d / (1.0 + kin)) <= rel / 10
     assert np.all(d <= bound), (d / bound).max()
     assert dm <= 1e-3
     return d
@@ -130,7 +130,8 @@ def _check_energy(e, parts, ref, tol, label, kappa=None):
 
 @pytest.mark.parametrize("name,prec,walkers,tol", [("He", "fp64", 256, 1e-7), ("He", "fp32", 256, 1e-3),
                                                    ("LiH", "fp32", 64, 1e-3), ("LiH", "fp64", 8, 1e-7),
-                                                   ("LiH", "bf16x6", 64, 1e-3), ("LiF", "fp32", 8, 1e-3),
+                                                   ("LiH", "bf16x6", 64, 1e-3), ("LiH", "bf16x3", 64, 1e-3),
+                                                   ("LiF", "fp32", 8, 1e-3),
                                                    ("LiF", "bf16x6", 8, 1e-3), ("H20", "fp32", 4, 1e-3)])
 def test_local_energy(name, prec, walkers, tol):
     s = SYSTEMS[name]()
@@ -140,7 +141,10 @@ def test_local_energy(name, prec, walkers, tol):
     o = O.Oracle(s)
     ref = o.local_energy(th, x)
     kap = None if prec == "fp64" else _kappa_sum(o, th, x)
-    _check_energy(e.cpu().numpy(), parts.cpu().numpy(), ref, tol, f"{name} {prec}", kap)
+    # BF16x3 carries about 17 bits of each operand (hi + lo parts) instead of
+    # 24: its conditioning coefficient is ten times the FP32 one
+    rel = 1e-3 if prec == "bf16x3" else 1e-4
+    _check_energy(e.cpu().numpy(), parts.cpu().numpy(), ref, tol, f"{name} {prec}", kap, rel)
 
 
 def test_local_energy_bf16_error_report():
