@@ -333,10 +333,12 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
         launch_pair_stream<T>(s, xw, theta, c.P, b, TR, fl, ldg, p.gi_layer_stride, c.W.GWl[0],
                               s.L > 1 ? c.W.GWl[1] : c.W.GWl[0], GI, st);
     }
+    bool g_ready = false;            // spin means of h^l already written by the previous layer
     for (int l = 0; l < s.L; ++l) {
         const int dh = layer_dh(s, l), HWl = c.W.HWl[l], GWl = c.W.GWl[l];
         T *Hin = Hbuf(l), *Hout = Hbuf(l + 1);
-        { Timed t_(K_SPIN_MEAN, st); launch_spin_mean<T>(Hin, ldh, b, s.N, s.nu, TR, dh, HWl, G, st); }
+        if (!g_ready) { Timed t_(K_SPIN_MEAN, st); launch_spin_mean<T>(Hin, ldh, b, s.N, s.nu, TR, dh, HWl, G, st); }
+        g_ready = false;
         GemmArgs ga{};
         ga.A1 = G; ga.lda1 = 2 * HWl; ga.K1 = 2 * HWl;
         ga.W = ws + p.wg[l]; ga.wpart = p.wgpart[l]; ga.ldw = 2 * HWl;
@@ -355,6 +357,13 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
             la.Hout = Hout; la.ldh_out = ldh;
             la.rows = b * s.N * TR; la.N = s.N; la.n3 = n3; la.w1 = s.w1; la.W1p = c.W.W1p;
             la.resid = l >= 1 ? 1 : 0;
+            // the walker GEMM of layer l + 1 reads G before this kernel's
+            // successor overwrites it, so G can take the next layer's means
+            if (l + 1 < s.L && stream_layer_whole_walkers(s.N, TR) && c.W.HWl[l + 1] == c.W.W1p) {
+                la.Gout = G;
+                la.nu = s.nu;
+                g_ready = true;
+            }
             Timed t_(K_STREAM_GEMM, st);
             launch_stream_layer(c.smode, la, TR, st);
         }

@@ -24,14 +24,6 @@ namespace fn {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
-__device__ inline uint32_t bf16_rne_bits(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;   // keep NaN a NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
-}
-
 constexpr int BM = 128, BN = 128, BK = 32;
 constexpr int LDH = BK + 8;   // LDS row stride of BF16 tiles (80 bytes)
 constexpr int LDF = BK + 4;   // LDS row stride of FP32 tiles (144 bytes)
@@ -41,18 +33,6 @@ struct ModeInfo {
     static constexpr bool F32 = MODE == GEMM_F32;
     static constexpr int NP = MODE == GEMM_BF16 ? 1 : (MODE == GEMM_BF16X3 ? 2 : (MODE == GEMM_BF16X6 ? 3 : 1));
 };
-
-// split x into NP BF16 parts x = p0 + p1 + ... (each the rounding of the rest)
-template <int NP>
-__device__ inline void split_bf16(float x, uint32_t (&h)[NP])
-{
-    float r = x;
-#pragma unroll
-    for (int q = 0; q < NP; ++q) {
-        h[q] = bf16_rne_bits(r);
-        r = r - __uint_as_float(h[q] << 16);
-    }
-}
 
 template <int MODE, int BNT>
 __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
@@ -149,15 +129,12 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
             if constexpr (F32) {
                 *(float4 *)&sAf[r * LDF + k] = x;
             } else {
-                uint32_t h0[NP], h1[NP], h2[NP], h3[NP];
-                split_bf16<NP>(x.x, h0);
-                split_bf16<NP>(x.y, h1);
-                split_bf16<NP>(x.z, h2);
-                split_bf16<NP>(x.w, h3);
+                uint32_t h01[NP], h23[NP];
+                split_bf16_pair<NP>(x.x, x.y, h01);
+                split_bf16_pair<NP>(x.z, x.w, h23);
 #pragma unroll
                 for (int q = 0; q < NP; ++q)
-                    *(uint2 *)&sAh[q * BM * LDH + r * LDH + k] =
-                        make_uint2(h0[q] | (h1[q] << 16), h2[q] | (h3[q] << 16));
+                    *(uint2 *)&sAh[q * BM * LDH + r * LDH + k] = make_uint2(h01[q], h23[q]);
             }
         }
         if constexpr (F32) {

@@ -64,6 +64,28 @@ inline ParamLayout make_layout(const Sys &s)
 // Matrix-product arithmetic.
 enum GemmMode { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16 = 2, GEMM_BF16X3 = 3, GEMM_BF16X6 = 4 };
 
+typedef __attribute__((__vector_size__(2 * sizeof(float)))) float f32x2_t;
+typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_t;
+
+// Split two FP32 values a, b into NP BF16 parts, x = p0 + p1 + ..., each part
+// the round-to-nearest-even of what the earlier parts leave (NaN stays NaN).
+// Part q of both values comes back packed in h[q], a in the low half; one
+// packed hardware conversion per part.
+template <int NP>
+__device__ inline void split_bf16_pair(float a, float b, uint32_t (&h)[NP])
+{
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const f32x2_t v = {a, b};
+        const uint32_t w = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+        h[q] = w;
+        if (q + 1 < NP) {
+            a -= __uint_as_float(w << 16);
+            b -= __uint_as_float(w & 0xffff0000u);
+        }
+    }
+}
+
 inline __host__ __device__ int gemm_parts(int mode) { return mode == GEMM_BF16 ? 1 : (mode == GEMM_BF16X3 ? 2 : (mode == GEMM_BF16X6 ? 3 : 1)); }
 
 // Padded widths.  Every product's reduction dimension is a multiple of 32.
@@ -140,11 +162,17 @@ struct LayerArgs {
     const float *Pw; const float *bias;
     float *Hout; int64_t ldh_out;
     int64_t rows; int N; int n3; int w1; int W1p; int resid;
+    // when a 128-row tile holds whole walkers (N * TR divides 128): also
+    // write the next layer's spin means [g_up | g_dn] of h^{l+1}, rows
+    // walker * TR + t, ld 2 * W1p (Gout = nullptr: skip)
+    float *Gout; int nu;
 };
 
 bool stream_layer_supported(int mode, int TR, int w1, int W1p);
 extern bool g_use_fused_layer;
 void launch_stream_layer(int mode, const LayerArgs &a, int TR, hipStream_t st);
+// 128-row tiles of the fused layer hold whole walkers
+inline bool stream_layer_whole_walkers(int N, int TR) { return N * TR <= 128 && 128 % (N * TR) == 0; }
 
 // Rows per electron in forward-Laplacian form: 3N + 2 rounded up to 16, or
 // to the next power of two (which the fused layer kernel handles) when that

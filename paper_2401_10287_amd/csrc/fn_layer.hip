@@ -26,25 +26,6 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 namespace {
 
-__device__ inline uint32_t bf16_bits(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
-}
-
-template <int NP>
-__device__ inline void split(float x, uint32_t (&h)[NP])
-{
-    float r = x;
-#pragma unroll
-    for (int q = 0; q < NP; ++q) {
-        h[q] = bf16_bits(r);
-        r = r - __uint_as_float(h[q] << 16);
-    }
-}
-
 constexpr int LBM = 128, LBN = 128, LBK = 32;
 constexpr int LDH = LBK + 8;
 constexpr int LDF = LBK + 4;
@@ -130,15 +111,12 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
             if constexpr (F32) {
                 *(float4 *)((float *)smem + r * LDF + k) = x;
             } else {
-                uint32_t h0[NP], h1[NP], h2[NP], h3[NP];
-                split<NP>(x.x, h0);
-                split<NP>(x.y, h1);
-                split<NP>(x.z, h2);
-                split<NP>(x.w, h3);
+                uint32_t h01[NP], h23[NP];
+                split_bf16_pair<NP>(x.x, x.y, h01);
+                split_bf16_pair<NP>(x.z, x.w, h23);
 #pragma unroll
                 for (int q = 0; q < NP; ++q)
-                    *(uint2 *)((uint16_t *)smem + q * LBM * LDH + r * LDH + k) =
-                        make_uint2(h0[q] | (h1[q] << 16), h2[q] | (h3[q] << 16));
+                    *(uint2 *)((uint16_t *)smem + q * LBM * LDH + r * LDH + k) = make_uint2(h01[q], h23[q]);
             }
         }
         if constexpr (F32) {
@@ -252,6 +230,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
                 if (a.resid) y = f4add(y, *(const float4 *)(Hin + R * a.lda1 + col));
             }
             *(float4 *)(Hout + R * a.ldh_out + col) = y;
+            if (a.Gout) *(float4 *)(sX + r * XS + 4 * cq) = y;
         }
     } else {
         constexpr int QPR = TP / 16;                   // 16-row chunks per electron
@@ -289,8 +268,9 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
         }
         srcp[q] = src;
         __syncthreads();
+        float4 r4[16];
+        float y0[4], dd[4], lap[4];
         if (live) {
-            float4 r4[16];
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int t = 16 * rc + u;
@@ -301,7 +281,6 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 #pragma unroll
             for (int k = 0; k < QPR; ++k) s4 = f4add(s4, srcp[el * 32 * QPR + cq * QPR + k]);
             const float *z0 = xc, *zl = xc + tl * XS;
-            float y0[4], dd[4], lap[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 y0[c] = tanhf(z0[c]);
@@ -309,6 +288,13 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
                 const float sc = c == 0 ? s4.x : (c == 1 ? s4.y : (c == 2 ? s4.z : s4.w));
                 lap[c] = dd[c] * zl[c] - 2.f * y0[c] * dd[c] * sc;
             }
+        }
+        // rows 0 and tl of an electron are read by all QPR threads of its
+        // column group before any of them parks its outputs over them
+        if constexpr (QPR > 1) {
+            if (a.Gout) __syncthreads();
+        }
+        if (live) {
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int t = 16 * rc + u;
@@ -321,7 +307,30 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
                     y = f4add(y, r4[u]);
                 }
                 *(float4 *)(Hout + (Rb + t) * a.ldh_out + col) = y;
+                if (a.Gout) *(float4 *)(xc + t * XS) = y;
             }
+        }
+    }
+    // spin means of the finished rows for the next layer (whole walkers per
+    // tile): item = (walker, row t, spin, 4 columns)
+    if (a.Gout) {
+        __syncthreads();
+        const int wpt = LBM / (a.N * TP);                 // walkers in this tile
+        const int nd = a.N - a.nu;
+        const float iu = a.nu > 0 ? 1.f / a.nu : 0.f, id = nd > 0 ? 1.f / nd : 0.f;
+        const int64_t ldg = 2 * (int64_t)a.W1p;
+        for (int q = tid; q < wpt * TP * 2 * (LBN / 4); q += 256) {
+            const int c4 = q % (LBN / 4), rest = q / (LBN / 4);
+            const int sp = rest % 2, wt = rest / 2;       // wt = walker-in-tile * TP + t
+            const int wl = wt / TP, t = wt % TP;
+            const int64_t wg = m0 / ((int64_t)a.N * TP) + wl;
+            if ((int64_t)(wl + 1) * a.N * TP > rows_here || n0 + 4 * c4 >= a.W1p) continue;
+            const int j0 = sp ? a.nu : 0, j1 = sp ? a.N : a.nu;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int j = j0; j < j1; ++j) v = f4add(v, *(const float4 *)(sX + ((wl * a.N + j) * TP + t) * XS + 4 * c4));
+            const float sc = sp ? id : iu;
+            *(float4 *)(a.Gout + (wg * TP + t) * ldg + sp * a.W1p + n0 + 4 * c4) =
+                make_float4(v.x * sc, v.y * sc, v.z * sc, v.w * sc);
         }
     }
 }

@@ -246,3 +246,29 @@ def test_metropolis_fp32_lih_decisions():
     assert same.mean() >= 0.95
     ok = same
     np.testing.assert_allclose(xt.cpu().numpy()[ok], xo[ok], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("name,prec,walkers", [("LiH", "fp32", 63), ("LiH", "bf16x6", 63), ("He", "fp32", 61)])
+def test_fused_and_separate_layer_paths(name, prec, walkers):
+    """The fused stream-layer kernel (product, forward-Laplacian epilogue and
+    the next layer's spin means in one launch) and the separate product /
+    epilogue / mean kernels, on a batch whose last 128-row tile is partly
+    filled: both within the oracle bounds, log|psi| and local energy."""
+    s = SYSTEMS[name]()
+    torch, fnvmc, cfg, tt, xt, th, x = _setup(s, prec, walkers)
+    o = O.Oracle(s)
+    ref_e = o.local_energy(th, x)
+    ref_l = o.log_psi(th, x)
+    kap = _kappa_sum(o, th, x)
+    C = _conditioning(o, s, th, x)
+    try:
+        for fused in (1, 0):
+            fnvmc.fn_tuning_set("fused_layer", fused)
+            e, lp, parts = fnvmc.fn_local_energy(cfg, tt, xt)
+            lv, sg = fnvmc.fn_log_psi(cfg, tt, xt)
+            torch.cuda.synchronize()
+            _check_energy(e.cpu().numpy(), parts.cpu().numpy(), ref_e, 1e-3, f"{name} {prec} fused={fused}", kap)
+            _check_logpsi(lv.cpu().numpy(), ref_l, 1e-5, f"{name} {prec} fused={fused}", C, False)
+            np.testing.assert_array_equal(sg.cpu().numpy(), ref_l["sign"])
+    finally:
+        fnvmc.fn_tuning_set("fused_layer", 1)
