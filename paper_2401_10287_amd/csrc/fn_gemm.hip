@@ -25,7 +25,7 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr int BM = 128, BN = 128, BK = 32;
-constexpr int LDH = BK + 8;   // LDS row stride of BF16 tiles (80 bytes)
+constexpr int LDH = BK;       // LDS row stride of BF16 tiles (64 bytes, chunk-swizzled by lds_chunk)
 constexpr int LDF = BK + 4;   // LDS row stride of FP32 tiles (144 bytes)
 
 template <int MODE>
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
                 split_bf16_pair<NP>(x.z, x.w, h23);
 #pragma unroll
                 for (int q = 0; q < NP; ++q)
-                    *(uint2 *)&sAh[q * BM * LDH + r * LDH + k] = make_uint2(h01[q], h23[q]);
+                    *(uint2 *)&sAh[q * BM * LDH + r * LDH + 8 * lds_chunk(r, k >> 3) + (k & 7)] = make_uint2(h01[q], h23[q]);
             }
         }
         if constexpr (F32) {
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
 #pragma unroll
                 for (int v = 0; v < NWH; ++v) {
                     int f = tid + 256 * v;
-                    if (f < BNT * 4) *(uint4 *)&sBh[q * BNT * LDH + (f >> 2) * LDH + 8 * (f & 3)] = rwh[q * NWH + v];
+                    if (f < BNT * 4) *(uint4 *)&sBh[q * BNT * LDH + (f >> 2) * LDH + 8 * lds_chunk(f >> 2, f & 3)] = rwh[q * NWH + v];
                 }
         }
     };
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
             }
         } else {
-            const int ko = 8 * (lane >> 4);
+            const int ko = 8 * lds_chunk(lane & 15, lane >> 4);   // rows ar + 16 i, br + 16 j share bits 0-3 with lane
             bf16x8 ha[NP][WI], hb[NP][WJ];
 #pragma unroll
             for (int q = 0; q < NP; ++q) {

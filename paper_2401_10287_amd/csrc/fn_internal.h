@@ -64,6 +64,13 @@ inline ParamLayout make_layout(const Sys &s)
 // Matrix-product arithmetic.
 enum GemmMode { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16 = 2, GEMM_BF16X3 = 3, GEMM_BF16X6 = 4 };
 
+// LDS layout of the BF16 operand tiles of the matrix-core kernels: rows of
+// 32 elements (four 16-byte chunks, no padding), chunk c of row r stored in
+// slot c ^ s(r), s(r) = ((r >> 1) ^ (r >> 2)) & 3.  Row stores in 8- or
+// 16-byte pieces and 16-byte fragment reads of 16 consecutive rows at one
+// chunk then fall on distinct banks.
+__host__ __device__ inline int lds_chunk(int r, int c) { return c ^ (((r >> 1) ^ (r >> 2)) & 3); }
+
 typedef __attribute__((__vector_size__(2 * sizeof(float)))) float f32x2_t;
 typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_t;
 

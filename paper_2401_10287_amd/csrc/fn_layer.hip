@@ -27,7 +27,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 namespace {
 
 constexpr int LBM = 128, LBN = 128, LBK = 32;
-constexpr int LDH = LBK + 8;
+constexpr int LDH = LBK;          // BF16 tile rows, chunk-swizzled (lds_chunk)
 constexpr int LDF = LBK + 4;
 
 }  // namespace
@@ -116,7 +116,8 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
                 split_bf16_pair<NP>(x.z, x.w, h23);
 #pragma unroll
                 for (int q = 0; q < NP; ++q)
-                    *(uint2 *)((uint16_t *)smem + q * LBM * LDH + r * LDH + k) = make_uint2(h01[q], h23[q]);
+                    *(uint2 *)((uint16_t *)smem + q * LBM * LDH + r * LDH + 8 * lds_chunk(r, k >> 3) + (k & 7)) =
+                        make_uint2(h01[q], h23[q]);
             }
         }
         if constexpr (F32) {
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 #pragma unroll
                 for (int v = 0; v < 2; ++v) {
                     const int f = tid + 256 * v;
-                    *(uint4 *)&sB[q * LBN * LDH + (f >> 2) * LDH + 8 * (f & 3)] = rwh[q * 2 + v];
+                    *(uint4 *)&sB[q * LBN * LDH + (f >> 2) * LDH + 8 * lds_chunk(f >> 2, f & 3)] = rwh[q * 2 + v];
                 }
         }
     };
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
             }
         } else {
             const uint16_t *sA = (const uint16_t *)smem, *sB = (const uint16_t *)(smem + ASZ);
-            const int ko = 8 * (lane >> 4);
+            const int ko = 8 * lds_chunk(lane & 15, lane >> 4);   // rows ar + 16 i, br + 16 j share bits 0-3 with lane
             bf16x8 ha[NP][4], hb[NP][4];
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
