@@ -310,7 +310,8 @@ hipError_t launch_gemm(int mode, const GemmArgs &a, hipStream_t st)
     } else {
         launch_bn<128>(mode, a, st);
     }
-    return hipGetLastError();
+    // peek, so that an earlier launch's error is still there for the caller's final check
+    return hipPeekAtLastError();
 }
 
 }  // namespace fn

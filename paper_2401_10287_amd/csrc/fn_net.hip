@@ -109,39 +109,45 @@ __global__ __launch_bounds__(256) void k_features(Sys s, const double *x, int TR
 }
 
 // ---------------------------------------------------------------------------
-// two-electron stream: one workgroup per (walker, electron i) runs the pairs
-// (i, j) through all pair layers and writes the spin means g_i_up, g_i_dn of
-// every layer as dense rows.  A pair feature depends on r_i and r_j only, so
-// a pair carries R = 8 rows: value, d/dr_i (3), d/dr_j (3), Laplacian.
+// two-electron stream: a workgroup takes WB consecutive (walker, electron i)
+// and runs their pairs (i, j) through all pair layers, writing the spin means
+// g_i_up, g_i_dn of every layer as dense rows.  A pair feature depends on r_i
+// and r_j only, so a pair carries R = 8 rows: value, d/dr_i (3), d/dr_j (3),
+// Laplacian.  The pair weights are staged in LDS once per workgroup, padded
+// to multiples of 4 (zero rows and columns); a thread owns one pair and 4
+// output columns for all R rows.
 // ---------------------------------------------------------------------------
 template <typename T, bool FL>
-__device__ void write_pair_means(const Sys &s, const T *S, int wp, int dp, int i, int TR, int GWl, int64_t ldg, T *gi)
+__device__ void write_pair_means(const Sys &s, const T *S, int wp, int ps, int dp, int i, int TR, int GWl, int64_t ldg,
+                                 T *gi)
 {
     constexpr int R = FL ? 8 : 1;
     const int n3 = 3 * s.N;
     const int rows = FL ? TR : 1;
-    for (int idx = threadIdx.x; idx < rows * GWl; idx += blockDim.x) {
-        const int t = idx / GWl, col = idx % GWl;
+    // a thread keeps one column and walks rows; the first (blockDim / GWl) GWl threads take part
+    const int tstep = blockDim.x / GWl;
+    if ((int)threadIdx.x >= tstep * GWl) return;
+    const int col = threadIdx.x % GWl;
+    const bool live = col < 2 * dp;
+    const int sp = live ? col / dp : 0, o = live ? col - sp * dp : 0;
+    const int n = sp == 0 ? s.nu : s.nd, j0 = sp == 0 ? 0 : s.nu;
+    const T inv = n > 0 ? T(1) / T(n) : T(0);
+    for (int t = threadIdx.x / GWl; t < rows; t += tstep) {
         T v = T(0);
-        if (col < 2 * dp && t <= n3 + 1) {
-            const int sp = col / dp, o = col % dp;
-            const int n = sp == 0 ? s.nu : s.nd, j0 = sp == 0 ? 0 : s.nu;
-            if (n > 0) {
-                const T inv = T(1) / T(n);
-                if (t == 0 || t == n3 + 1) {
-                    const int r = t == 0 ? 0 : R - 1;
+        if (live && n > 0 && t <= n3 + 1) {
+            if (t == 0 || t == n3 + 1) {
+                const int r = t == 0 ? 0 : R - 1;
+                T acc = T(0);
+                for (int j = j0; j < j0 + n; ++j) acc += S[j * ps + r * wp + o];
+                v = acc * inv;
+            } else {
+                const int c = t - 1, e = c / 3, a = c - 3 * e;
+                if (e == i) {
                     T acc = T(0);
-                    for (int j = j0; j < j0 + n; ++j) acc += S[(j * R + r) * wp + o];
+                    for (int j = j0; j < j0 + n; ++j) acc += S[j * ps + (1 + a) * wp + o];
                     v = acc * inv;
-                } else {
-                    const int c = t - 1, e = c / 3, a = c % 3;
-                    if (e == i) {
-                        T acc = T(0);
-                        for (int j = j0; j < j0 + n; ++j) acc += S[(j * R + 1 + a) * wp + o];
-                        v = acc * inv;
-                    } else if (e >= j0 && e < j0 + n) {
-                        v = S[(e * R + 4 + a) * wp + o] * inv;
-                    }
+                } else if (e >= j0 && e < j0 + n) {
+                    v = S[e * ps + (4 + a) * wp + o] * inv;
                 }
             }
         }
@@ -149,81 +155,185 @@ __device__ void write_pair_means(const Sys &s, const T *S, int wp, int dp, int i
     }
 }
 
-template <typename T, bool FL>
-__global__ void k_pair_stream(Sys s, const double *x, const T *theta, ParamLayout P, int64_t B, int TR, int64_t ldg,
-                              int64_t gi_layer_stride, int GW0, int GW1, T *GI)
+// OC consecutive LDS elements (16-, 8- or 4-byte aligned for FP32)
+template <typename T, int OC>
+__device__ inline void lds_ld(const T *p, T (&v)[OC])
+{
+#pragma unroll
+    for (int c = 0; c < OC; ++c) v[c] = p[c];
+}
+
+template <>
+__device__ inline void lds_ld<float, 4>(const float *p, float (&v)[4])
+{
+    const float4 q = *(const float4 *)p;
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+}
+
+template <>
+__device__ inline void lds_ld<float, 2>(const float *p, float (&v)[2])
+{
+    const float2 q = *(const float2 *)p;
+    v[0] = q.x; v[1] = q.y;
+}
+
+template <typename T, int OC>
+__device__ inline void lds_st(T *p, const T (&v)[OC])
+{
+#pragma unroll
+    for (int c = 0; c < OC; ++c) p[c] = v[c];
+}
+
+template <>
+__device__ inline void lds_st<float, 4>(float *p, const float (&v)[4])
+{
+    *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+template <>
+__device__ inline void lds_st<float, 2>(float *p, const float (&v)[2])
+{
+    *(float2 *)p = make_float2(v[0], v[1]);
+}
+
+// padded pair-weight block of layer l in LDS: [dp4][w2p] then bias [w2p]
+__host__ __device__ inline int pair_w_offset(const Sys &s, int l)
+{
+    const int w2p = round_up(s.w2, 4);
+    int o = 0;
+    for (int q = 0; q < l; ++q) o += (round_up(layer_dp(s, q), 4) + 1) * w2p;
+    return o;
+}
+
+template <typename T, bool FL, int OC>
+__global__ __launch_bounds__(256) void k_pair_stream(Sys s, const double *x, const T *theta, ParamLayout P, int64_t B,
+                                                     int TR, int64_t ldg, int64_t gi_layer_stride, int GW0, int GW1,
+                                                     int WB, T *GI)
 {
     constexpr int R = FL ? 8 : 1;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    const int wp = s.w2 > 4 ? s.w2 : 4;
+    const int w2p = round_up(s.w2, 4);
+    const int wp = w2p > 4 ? w2p : 4;                     // LDS row width of a pair
+    const int ps = R * wp + 128 / (int)sizeof(T);         // one pair; a 128-byte skew puts neighbouring pairs on other banks
+    const int per = s.N * ps;                             // one (walker, electron) in LDS
     T *S0 = (T *)smem_raw;
-    T *S1 = S0 + s.N * R * wp;
-    // all pair-layer weights and biases (theta from W2_0 on) staged in LDS
-    T *Wsm = S1 + s.N * R * wp;
-    const int64_t npw = s.L > 1 ? P.c2[s.L - 2] + s.w2 - P.W2[0] : 0;
-    for (int64_t q = threadIdx.x; q < npw; q += blockDim.x) Wsm[q] = theta[P.W2[0] + q];
-    const int64_t wi = blockIdx.x;
-    const int64_t w = wi / s.N;
-    const int i = (int)(wi % s.N);
-    if (w >= B) return;
-    const double *xw = x + w * 3 * s.N;
+    T *S1 = S0 + (int64_t)WB * per;
+    T *Wsm = S1 + (int64_t)WB * per;
+    const int tid = threadIdx.x;
+    for (int l = 0; l + 1 < s.L; ++l) {
+        const int dp = layer_dp(s, l), dp4 = round_up(dp, 4);
+        T *Wl = Wsm + pair_w_offset(s, l);
+        for (int q = tid; q < (dp4 + 1) * w2p; q += blockDim.x) {
+            const int k = q / w2p, o = q % w2p;
+            T v = T(0);
+            if (o < s.w2) {
+                if (k < dp) v = theta[P.W2[l] + (int64_t)k * s.w2 + o];
+                else if (k == dp4) v = theta[P.c2[l] + o];
+            }
+            Wl[q] = v;
+        }
+    }
+    const int64_t wi0 = (int64_t)blockIdx.x * WB;
+    const int nwi = B * s.N - wi0 < WB ? (int)(B * s.N - wi0) : WB;
+    const int rows = FL ? TR : 1;
 
-    // layer-0 pair features
-    for (int j = threadIdx.x; j < s.N; j += blockDim.x) {
-        T *p = S0 + j * R * wp;
-        for (int q = 0; q < R * wp; ++q) p[q] = T(0);
+    // layer-0 pair features (zero rows first, then the nonzero entries)
+    for (int q = tid; q < nwi * per; q += blockDim.x) S0[q] = T(0);
+    __syncthreads();
+    for (int q = tid; q < nwi * s.N; q += blockDim.x) {
+        const int bb = q / s.N, j = q % s.N;
+        const int64_t wi = wi0 + bb, w = wi / s.N;
+        const int i = (int)(wi % s.N);
+        const double *xw = x + w * 3 * s.N;
+        T *p = S0 + (int64_t)bb * per + j * ps;
         if (j == i) continue;
         double d[3] = {xw[3 * i] - xw[3 * j], xw[3 * i + 1] - xw[3 * j + 1], xw[3 * i + 2] - xw[3 * j + 2]};
         double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        for (int a = 0; a < 3; ++a) p[a] = (T)d[a];
+        for (int c = 0; c < 3; ++c) p[c] = (T)d[c];
         p[3] = (T)r;
         if constexpr (FL) {
-            for (int a = 0; a < 3; ++a) {
-                p[(1 + a) * wp + a] = T(1);
-                p[(1 + a) * wp + 3] = (T)(d[a] / r);
-                p[(4 + a) * wp + a] = T(-1);
-                p[(4 + a) * wp + 3] = (T)(-d[a] / r);
+            for (int c = 0; c < 3; ++c) {
+                p[(1 + c) * wp + c] = T(1);
+                p[(1 + c) * wp + 3] = (T)(d[c] / r);
+                p[(4 + c) * wp + c] = T(-1);
+                p[(4 + c) * wp + 3] = (T)(-d[c] / r);
             }
             p[7 * wp + 3] = (T)(4.0 / r);
         }
     }
     __syncthreads();
-    const int rows = FL ? TR : 1;
-    write_pair_means<T, FL>(s, S0, wp, 4, i, TR, GW0, ldg, GI + wi * rows * ldg);
+    for (int bb = 0; bb < nwi; ++bb) {
+        const int64_t wi = wi0 + bb;
+        write_pair_means<T, FL>(s, S0 + (int64_t)bb * per, wp, ps, 4, (int)(wi % s.N), TR, GW0, ldg, GI + wi * rows * ldg);
+    }
+    const int ocn = w2p / OC;                             // column groups of a pair
     for (int l = 0; l + 1 < s.L; ++l) {
         __syncthreads();
-        const int dp = l == 0 ? 4 : s.w2;
-        const T *W2 = Wsm + (P.W2[l] - P.W2[0]);
-        const T *c2 = Wsm + (P.c2[l] - P.W2[0]);
-        for (int idx = threadIdx.x; idx < s.N * s.w2; idx += blockDim.x) {
-            const int j = idx / s.w2, o = idx % s.w2;
-            const T *in = S0 + j * R * wp;
-            T xr[R];
+        const int dp4 = round_up(layer_dp(s, l), 4);
+        const T *Wl = Wsm + pair_w_offset(s, l);
+        const T *cl = Wl + dp4 * w2p;
+        for (int q = tid; q < nwi * s.N * ocn; q += blockDim.x) {
+            const int bb = q / (s.N * ocn), rem = q % (s.N * ocn);
+            const int j = rem / ocn, o0 = OC * (rem % ocn);
+            const T *in = S0 + (int64_t)bb * per + j * ps;
+            T acc[R][OC];
+            T bias[OC];
+            lds_ld<T, OC>(cl + o0, bias);
 #pragma unroll
-            for (int r = 0; r < R; ++r) xr[r] = r == 0 ? c2[o] : T(0);
-            for (int k = 0; k < dp; ++k) {
-                const T wv = W2[k * s.w2 + o];
+            for (int r = 0; r < R; ++r)
 #pragma unroll
-                for (int r = 0; r < R; ++r) xr[r] += in[r * wp + k] * wv;
-            }
-            const T y0 = tanh(xr[0]);
-            const T dd = T(1) - y0 * y0;
-            T *out = S1 + j * R * wp;
-            out[o] = y0 + (l >= 1 ? in[o] : T(0));
-            if constexpr (FL) {
-                T src = T(0);
+                for (int c = 0; c < OC; ++c) acc[r][c] = r == 0 ? bias[c] : T(0);
+            for (int k = 0; k < dp4; k += 4) {
+                T wv[4][OC];
 #pragma unroll
-                for (int r = 1; r < 7; ++r) {
-                    src += xr[r] * xr[r];
-                    out[r * wp + o] = dd * xr[r] + (l >= 1 ? in[r * wp + o] : T(0));
+                for (int kk = 0; kk < 4; ++kk) lds_ld<T, OC>(Wl + (k + kk) * w2p + o0, wv[kk]);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    T xv[4];
+                    lds_ld<T, 4>(in + r * wp + k, xv);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                        for (int c = 0; c < OC; ++c) acc[r][c] += xv[kk] * wv[kk][c];
                 }
-                out[7 * wp + o] = dd * xr[7] - T(2) * y0 * dd * src + (l >= 1 ? in[7 * wp + o] : T(0));
+            }
+            T *out = S1 + (int64_t)bb * per + j * ps;
+            T y0[OC], dd[OC], src[OC];
+#pragma unroll
+            for (int c = 0; c < OC; ++c) {
+                y0[c] = tanh(acc[0][c]);
+                dd[c] = T(1) - y0[c] * y0[c];
+                src[c] = T(0);
+            }
+            // rows stored OC columns at a time; residual rows read likewise
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                T res[OC];
+#pragma unroll
+                for (int c = 0; c < OC; ++c) res[c] = T(0);
+                if (l >= 1) lds_ld<T, OC>(in + r * wp + o0, res);
+                T v[OC];
+#pragma unroll
+                for (int c = 0; c < OC; ++c) {
+                    if (r == 0) {
+                        v[c] = y0[c] + res[c];
+                    } else if (r < 7) {
+                        src[c] += acc[r][c] * acc[r][c];
+                        v[c] = dd[c] * acc[r][c] + res[c];
+                    } else {
+                        v[c] = dd[c] * acc[R - 1][c] - T(2) * y0[c] * dd[c] * src[c] + res[c];
+                    }
+                }
+                lds_st<T, OC>(out + r * wp + o0, v);
             }
         }
         __syncthreads();
         T *t = S0; S0 = S1; S1 = t;
-        write_pair_means<T, FL>(s, S0, wp, s.w2, i, TR, GW1, ldg,
-                                GI + (int64_t)(l + 1) * gi_layer_stride + wi * rows * ldg);
+        for (int bb = 0; bb < nwi; ++bb) {
+            const int64_t wi = wi0 + bb;
+            write_pair_means<T, FL>(s, S0 + (int64_t)bb * per, wp, ps, s.w2, (int)(wi % s.N), TR, GW1, ldg,
+                                    GI + (int64_t)(l + 1) * gi_layer_stride + wi * rows * ldg);
+        }
     }
 }
 
@@ -626,26 +736,63 @@ void launch_features(const Sys &s, const double *x, int64_t B, int TR, int HW0, 
     hipLaunchKernelGGL(k_features<T>, dim3((unsigned)(B * s.N)), dim3(256), 0, st, s, x, TR, HW0, ldh, H);
 }
 
-size_t pair_stream_lds(const Sys &s, bool fl, size_t elem)
+// LDS of a pair-stream workgroup holding WB (walker, electron) rows
+static size_t pair_stream_lds_wb(const Sys &s, bool fl, size_t elem, int WB)
 {
-    int wp = s.w2 > 4 ? s.w2 : 4;
-    const ParamLayout P = make_layout(s);
-    const size_t npw = s.L > 1 ? (size_t)(P.c2[s.L - 2] + s.w2 - P.W2[0]) : 0;
-    return (2 * (size_t)s.N * (fl ? 8 : 1) * wp + npw) * elem;
+    const int w2p = round_up(s.w2, 4), wp = w2p > 4 ? w2p : 4;
+    const size_t per = (size_t)s.N * ((fl ? 8 : 1) * wp + 128 / elem);
+    return (2 * (size_t)WB * per + (size_t)pair_w_offset(s, s.L > 1 ? s.L - 1 : 0)) * elem;
+}
+
+size_t pair_stream_lds(const Sys &s, bool fl, size_t elem) { return pair_stream_lds_wb(s, fl, elem, 1); }
+
+// Output columns per thread (1, 2 or 4) and (walker, electron) rows per
+// workgroup: about 256 (pair, column group) items, within 64 KiB of LDS.
+static int pair_stream_oc(const Sys &s)
+{
+    const int w2p = round_up(s.w2, 4);
+    return s.N * w2p <= 256 ? 1 : (s.N * w2p <= 512 ? 2 : 4);
+}
+
+static int pair_stream_wb(const Sys &s, bool fl, size_t elem)
+{
+    const int items = s.N * (round_up(s.w2, 4) / pair_stream_oc(s));
+    int wb = items >= 256 ? 1 : 256 / items;
+    while (wb > 1 && pair_stream_lds_wb(s, fl, elem, wb) > 64 * 1024) --wb;
+    return wb;
+}
+
+template <typename T, bool FL>
+static void launch_pair_oc(const Sys &s, const double *x, const T *theta, const ParamLayout &P, int64_t B, int TR,
+                           int64_t ldg, int64_t gi_layer_stride, int GW0, int GW1, T *GI, hipStream_t st)
+{
+    const int wb = pair_stream_wb(s, FL, sizeof(T));
+    const size_t lds = pair_stream_lds_wb(s, FL, sizeof(T), wb);
+    dim3 grid((unsigned)((B * s.N + wb - 1) / wb));
+    switch (pair_stream_oc(s)) {
+    case 1:
+        hipLaunchKernelGGL((k_pair_stream<T, FL, 1>), grid, dim3(256), lds, st, s, x, theta, P, B, TR, ldg,
+                           gi_layer_stride, GW0, GW1, wb, GI);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_pair_stream<T, FL, 2>), grid, dim3(256), lds, st, s, x, theta, P, B, TR, ldg,
+                           gi_layer_stride, GW0, GW1, wb, GI);
+        break;
+    default:
+        hipLaunchKernelGGL((k_pair_stream<T, FL, 4>), grid, dim3(256), lds, st, s, x, theta, P, B, TR, ldg,
+                           gi_layer_stride, GW0, GW1, wb, GI);
+        break;
+    }
 }
 
 template <typename T>
 void launch_pair_stream(const Sys &s, const double *x, const T *theta, const ParamLayout &P, int64_t B, int TR,
                         bool fl, int64_t ldg, int64_t gi_layer_stride, int GW0, int GW1, T *GI, hipStream_t st)
 {
-    size_t lds = pair_stream_lds(s, fl, sizeof(T));
-    dim3 grid((unsigned)(B * s.N));
     if (fl)
-        hipLaunchKernelGGL((k_pair_stream<T, true>), grid, dim3(256), lds, st, s, x, theta, P, B, TR, ldg,
-                           gi_layer_stride, GW0, GW1, GI);
+        launch_pair_oc<T, true>(s, x, theta, P, B, TR, ldg, gi_layer_stride, GW0, GW1, GI, st);
     else
-        hipLaunchKernelGGL((k_pair_stream<T, false>), grid, dim3(256), lds, st, s, x, theta, P, B, TR, ldg,
-                           gi_layer_stride, GW0, GW1, GI);
+        launch_pair_oc<T, false>(s, x, theta, P, B, TR, ldg, gi_layer_stride, GW0, GW1, GI, st);
 }
 
 template <typename T>
