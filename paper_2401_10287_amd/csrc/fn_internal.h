@@ -181,16 +181,15 @@ void launch_stream_layer(int mode, const LayerArgs &a, int TR, hipStream_t st);
 // 128-row tiles of the fused layer hold whole walkers
 inline bool stream_layer_whole_walkers(int N, int TR) { return N * TR <= 128 && 128 % (N * TR) == 0; }
 
-// Rows per electron in forward-Laplacian form: 3N + 2 rounded up to 16, or
-// to the next power of two (which the fused layer kernel handles) when that
-// pads by at most a quarter more.
+// Rows per electron in forward-Laplacian form: 3N + 2 rounded up to the next
+// power of two up to 64 (N <= 20), the row counts whose electrons tile the
+// fused layer kernel's 128-row blocks; beyond that, rounded up to 16.
 inline int fl_rows(int N)
 {
     const int t = 3 * N + 2;
-    const int r16 = round_up(t, 16);
     int p2 = 16;
     while (p2 < t) p2 *= 2;
-    return (p2 <= 64 && 4 * p2 <= 5 * r16) ? p2 : r16;
+    return p2 <= 64 ? p2 : round_up(t, 16);
 }
 
 }  // namespace fn

@@ -616,6 +616,339 @@ __global__ __launch_bounds__(64) void k_det(const T *Phi, int64_t B, int K, int 
 }
 
 // ---------------------------------------------------------------------------
+// forward-Laplacian orbitals, envelope and determinant in one pass: one
+// wave64 per (walker, determinant k) of one spin.  The orbital matrix and its
+// direction derivatives (Eq. 4 with the product rule) are formed in LDS from
+// the head product O and the envelope, never stored to memory:
+//   A[i][j]   = a_ij e_ij,           a = orbital value, e = envelope,
+//   d_c A     = (d_c a) e + a d_c e  (d_c e nonzero only for c in electron j),
+//   lap A     = (lap a) e + a lap e + 2 grad_j a . grad_j e.
+// LU with partial pivoting gives sign and log|det A|; the directions are
+// solved in chunks of CD (CD n <= 64 columns, one per lane) and reduced to
+//   d log|det| / dx_c = tr M_c,  lap log|det| = tr(A^-1 lap A) - sum_c tr(M_c M_c),
+// M_c = A^-1 d_c A.  Record per (walker, spin, k): [sign, log|det|, grad[3N], lap].
+// Envelope, entries, LU and traces in FP64 for every precision.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int orbdet_cd(int n) { return n >= 64 ? 1 : 64 / n; }
+
+size_t orbdet_lds(int n)
+{
+    const size_t nn = (size_t)n * n;
+    return (7 * nn + (size_t)orbdet_cd(n) * nn) * sizeof(double) + (size_t)n * sizeof(int) + 16;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *theta, int64_t gof, int64_t piof,
+                                               int64_t sigof, int sp, const T *O, int64_t ldo, int64_t B, int TR,
+                                               double *DR, int rec)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    const int n = sp == 0 ? s.nu : s.nd, j0 = sp == 0 ? 0 : s.nu;
+    const int n3 = 3 * s.N, nn = n * n, CD = orbdet_cd(n);
+    double *LU = (double *)smem_raw;      // [n][n] orbitals x electrons, then its LU factors
+    double *EV = LU + nn;                 // envelope e
+    double *GE = EV + nn;                 // grad_j e [n][n][3]
+    double *LE = GE + 3 * nn;             // lap_j e
+    double *A0 = LE + nn;                 // orbital value a (with its bias)
+    double *Mc = A0 + nn;                 // [CD][n][n] solved directions of one chunk
+    int *perm = (int *)(Mc + (size_t)CD * nn);
+    __shared__ int s_sign, s_sing;
+    __shared__ double s_log;
+    const int lane = threadIdx.x;
+    const int64_t wk = blockIdx.x;
+    const int64_t w = wk / s.K;
+    const int k = (int)(wk % s.K);
+    if (w >= B) return;
+
+    // envelope and orbital value of every (orbital io, electron jj)
+    for (int q = lane; q < nn; q += 64) {
+        const int io = q / n, jj = q - io * n;
+        const int col = k * n + io, j = j0 + jj;
+        const double *xj = x + (w * s.N + j) * 3;
+        double env = 0.0, ge[3] = {0.0, 0.0, 0.0}, le = 0.0;
+        for (int m = 0; m < s.M; ++m) {
+            const T *Sgp = theta + sigof + ((int64_t)col * s.M + m) * 9;
+            double d[3] = {xj[0] - s.R[m][0], xj[1] - s.R[m][1], xj[2] - s.R[m][2]};
+            double sd[3], ad[3], Sg[9];
+            for (int e = 0; e < 9; ++e) Sg[e] = (double)Sgp[e];
+            for (int p = 0; p < 3; ++p) sd[p] = Sg[3 * p] * d[0] + Sg[3 * p + 1] * d[1] + Sg[3 * p + 2] * d[2];
+            for (int a = 0; a < 3; ++a) ad[a] = Sg[a] * sd[0] + Sg[3 + a] * sd[1] + Sg[6 + a] * sd[2];
+            const double qd = sqrt(sd[0] * sd[0] + sd[1] * sd[1] + sd[2] * sd[2]);
+            const double em = (double)theta[piof + (int64_t)col * s.M + m] * exp(-qd);
+            env += em;
+            double trS = 0.0;
+            for (int e = 0; e < 9; ++e) trS += Sg[e] * Sg[e];
+            const double iq = 1.0 / qd;
+            const double ad2 = ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2];
+            const double lq = (trS - ad2 * iq * iq) * iq;
+            const double gq2 = ad2 * iq * iq;
+            for (int a = 0; a < 3; ++a) ge[a] -= em * ad[a] * iq;
+            le += em * (gq2 - lq);
+        }
+        const double a0 = (double)O[((w * n + jj) * TR) * ldo + col] + (double)theta[gof + col];
+        EV[q] = env;
+        GE[3 * q] = ge[0]; GE[3 * q + 1] = ge[1]; GE[3 * q + 2] = ge[2];
+        LE[q] = le;
+        A0[q] = a0;
+        LU[q] = a0 * env;
+    }
+    for (int q = lane; q < n; q += 64) perm[q] = q;
+    if (lane == 0) { s_sign = 1; s_sing = 0; s_log = 0.0; }
+    __syncthreads();
+    for (int c = 0; c < n; ++c) {
+        if (lane == 0) {
+            int p = c;
+            double best = fabs(LU[c * n + c]);
+            for (int r = c + 1; r < n; ++r) {
+                const double v = fabs(LU[r * n + c]);
+                if (v > best) { best = v; p = r; }
+            }
+            if (best == 0.0) {
+                s_sing = 1;
+            } else {
+                if (p != c) {
+                    for (int q = 0; q < n; ++q) { double t = LU[c * n + q]; LU[c * n + q] = LU[p * n + q]; LU[p * n + q] = t; }
+                    int t = perm[c]; perm[c] = perm[p]; perm[p] = t;
+                    s_sign = -s_sign;
+                }
+                const double piv = LU[c * n + c];
+                if (piv < 0.0) s_sign = -s_sign;
+                s_log += log(fabs(piv));
+            }
+        }
+        __syncthreads();
+        if (s_sing) break;
+        const double ip = 1.0 / LU[c * n + c];
+        const int m = n - 1 - c;
+        for (int q = lane; q < m; q += 64) LU[(c + 1 + q) * n + c] *= ip;
+        __syncthreads();
+        for (int q = lane; q < m * m; q += 64) {
+            const int r = c + 1 + q / m, cc = c + 1 + q % m;
+            LU[r * n + cc] -= LU[r * n + c] * LU[c * n + cc];
+        }
+        __syncthreads();
+    }
+    double *out = DR + (w * 2 + sp) * (int64_t)s.K * rec + (int64_t)k * rec;
+    if (s_sing) {
+        for (int q = lane; q < rec; q += 64) out[q] = q == 0 ? 0.0 : (q == 1 ? -INFINITY : NAN);
+        return;
+    }
+    if (lane == 0) { out[0] = (double)s_sign; out[1] = s_log; }
+
+    double sq = 0.0, trl = 0.0;
+    for (int t0 = 0; t0 <= n3; t0 += CD) {
+        const int nd = n3 + 1 - t0 < CD ? n3 + 1 - t0 : CD;
+        // one column (direction d, electron jj) per lane: right-hand side
+        // D[perm[r]][jj], then the unit-lower and upper triangular solves
+        for (int q = lane; q < nd * n; q += 64) {
+            const int d = q / n, jj = q - d * n;
+            const int mt = t0 + d, j = j0 + jj;
+            const T *Oj = O + ((w * n + jj) * TR) * ldo + k * n;
+            double *v = Mc + d * nn;
+            for (int r = 0; r < n; ++r) {
+                const int io = perm[r], e = io * n + jj;
+                double dv;
+                if (mt < n3) {
+                    dv = EV[e] * (double)Oj[(1 + mt) * ldo + io];
+                    if (mt / 3 == j) dv += A0[e] * GE[3 * e + mt % 3];
+                } else {
+                    dv = EV[e] * (double)Oj[(n3 + 1) * ldo + io] + A0[e] * LE[e];
+                    for (int a = 0; a < 3; ++a) dv += 2.0 * (double)Oj[(1 + 3 * j + a) * ldo + io] * GE[3 * e + a];
+                }
+                v[r * n + jj] = dv;
+            }
+            for (int r = 1; r < n; ++r) {
+                double acc = v[r * n + jj];
+                for (int c = 0; c < r; ++c) acc -= LU[r * n + c] * v[c * n + jj];
+                v[r * n + jj] = acc;
+            }
+            for (int r = n - 1; r >= 0; --r) {
+                double acc = v[r * n + jj];
+                for (int c = r + 1; c < n; ++c) acc -= LU[r * n + c] * v[c * n + jj];
+                v[r * n + jj] = acc / LU[r * n + r];
+            }
+        }
+        __syncthreads();
+        // tr(M_c M_c) of the tangent directions, tr M of every direction
+        for (int q = lane; q < nd * nn; q += 64) {
+            const int d = q / nn, rest = q - d * nn;
+            if (t0 + d >= n3) continue;
+            const int r = rest / n, c = rest - r * n;
+            sq += Mc[d * nn + r * n + c] * Mc[d * nn + c * n + r];
+        }
+        if (lane < nd) {
+            double tr = 0.0;
+            for (int r = 0; r < n; ++r) tr += Mc[lane * nn + r * n + r];
+            if (t0 + lane < n3) out[2 + t0 + lane] = tr;
+            else trl = tr;
+        }
+        __syncthreads();
+    }
+    sq = wave_sum(sq);
+    trl = wave_sum(trl);
+    if (lane == 0) out[2 + n3] = trl - sq;
+}
+
+// Small spins (n <= 2): one thread per (walker, determinant k) with the
+// matrices in registers.  Same quantities as k_orbdet; here the directions
+// use the explicit inverse from the pivoted LU, M_c = A^-1 d_c A.
+template <typename T, int NS>
+__global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, const T *theta, int64_t gof,
+                                                      int64_t piof, int64_t sigof, int sp, const T *O, int64_t ldo,
+                                                      int64_t B, int TR, double *DR, int rec)
+{
+    const int j0 = sp == 0 ? 0 : s.nu;
+    const int n3 = 3 * s.N;
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= B * s.K) return;
+    const int64_t w = id / s.K;
+    const int k = (int)(id % s.K);
+    double ev[NS][NS], ge[NS][NS][3], le[NS][NS], a0[NS][NS], A[NS][NS];
+#pragma unroll
+    for (int io = 0; io < NS; ++io)
+#pragma unroll
+        for (int jj = 0; jj < NS; ++jj) {
+            const int col = k * NS + io, j = j0 + jj;
+            const double *xj = x + (w * s.N + j) * 3;
+            double env = 0.0, g3[3] = {0.0, 0.0, 0.0}, lp = 0.0;
+            for (int m = 0; m < s.M; ++m) {
+                const T *Sgp = theta + sigof + ((int64_t)col * s.M + m) * 9;
+                double d[3] = {xj[0] - s.R[m][0], xj[1] - s.R[m][1], xj[2] - s.R[m][2]};
+                double sd[3], ad[3], Sg[9];
+                for (int e = 0; e < 9; ++e) Sg[e] = (double)Sgp[e];
+                for (int p = 0; p < 3; ++p) sd[p] = Sg[3 * p] * d[0] + Sg[3 * p + 1] * d[1] + Sg[3 * p + 2] * d[2];
+                for (int a = 0; a < 3; ++a) ad[a] = Sg[a] * sd[0] + Sg[3 + a] * sd[1] + Sg[6 + a] * sd[2];
+                const double qd = sqrt(sd[0] * sd[0] + sd[1] * sd[1] + sd[2] * sd[2]);
+                const double em = (double)theta[piof + (int64_t)col * s.M + m] * exp(-qd);
+                env += em;
+                double trS = 0.0;
+                for (int e = 0; e < 9; ++e) trS += Sg[e] * Sg[e];
+                const double iq = 1.0 / qd;
+                const double ad2 = ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2];
+                const double lq = (trS - ad2 * iq * iq) * iq;
+                const double gq2 = ad2 * iq * iq;
+                for (int a = 0; a < 3; ++a) g3[a] -= em * ad[a] * iq;
+                lp += em * (gq2 - lq);
+            }
+            ev[io][jj] = env;
+            ge[io][jj][0] = g3[0]; ge[io][jj][1] = g3[1]; ge[io][jj][2] = g3[2];
+            le[io][jj] = lp;
+            a0[io][jj] = (double)O[((w * NS + jj) * TR) * ldo + col] + (double)theta[gof + col];
+            A[io][jj] = a0[io][jj] * env;
+        }
+    // LU with partial pivoting (rows = orbitals), then the inverse
+    int perm[NS];
+#pragma unroll
+    for (int r = 0; r < NS; ++r) perm[r] = r;
+    int sgn = 1;
+    double lg = 0.0;
+    bool sing = false;
+#pragma unroll
+    for (int c = 0; c < NS; ++c) {
+        int p = c;
+        double best = fabs(A[c][c]);
+#pragma unroll
+        for (int r = c + 1; r < NS; ++r)
+            if (fabs(A[r][c]) > best) { best = fabs(A[r][c]); p = r; }
+        if (best == 0.0) { sing = true; break; }
+        if (p != c) {
+#pragma unroll
+            for (int r = c + 1; r < NS; ++r)
+                if (r == p) {
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) { const double t = A[c][q]; A[c][q] = A[r][q]; A[r][q] = t; }
+                    const int t = perm[c]; perm[c] = perm[r]; perm[r] = t;
+                }
+            sgn = -sgn;
+        }
+        const double piv = A[c][c];
+        if (piv < 0.0) sgn = -sgn;
+        lg += log(fabs(piv));
+        const double ip = 1.0 / piv;
+#pragma unroll
+        for (int r = c + 1; r < NS; ++r) {
+            A[r][c] *= ip;
+#pragma unroll
+            for (int q = c + 1; q < NS; ++q) A[r][q] -= A[r][c] * A[c][q];
+        }
+    }
+    double *out = DR + (w * 2 + sp) * (int64_t)s.K * rec + (int64_t)k * rec;
+    if (sing) {
+        out[0] = 0.0;
+        out[1] = -INFINITY;
+        for (int q = 2; q < rec; ++q) out[q] = NAN;
+        return;
+    }
+    out[0] = (double)sgn;
+    out[1] = lg;
+    // inverse: column e of A^-1 solves (LU) y = P e_e
+    double Ai[NS][NS];
+#pragma unroll
+    for (int e = 0; e < NS; ++e) {
+        double v[NS];
+#pragma unroll
+        for (int r = 0; r < NS; ++r) v[r] = perm[r] == e ? 1.0 : 0.0;
+#pragma unroll
+        for (int r = 1; r < NS; ++r)
+#pragma unroll
+            for (int c = 0; c < r; ++c) v[r] -= A[r][c] * v[c];
+#pragma unroll
+        for (int r = NS - 1; r >= 0; --r) {
+#pragma unroll
+            for (int c = r + 1; c < NS; ++c) v[r] -= A[r][c] * v[c];
+            v[r] /= A[r][r];
+        }
+#pragma unroll
+        for (int r = 0; r < NS; ++r) Ai[r][e] = v[r];
+    }
+    // directions: D = d_c A (tangents) or lap A; M = A^-1 D
+    const T *Ob = O + (w * NS * TR) * ldo + k * NS;      // row (jj, t) at (jj TR + t) ldo
+    double sq = 0.0, trl = 0.0;
+    for (int mt = 0; mt <= n3; ++mt) {
+        double D[NS][NS];
+#pragma unroll
+        for (int io = 0; io < NS; ++io)
+#pragma unroll
+            for (int jj = 0; jj < NS; ++jj) {
+                const int j = j0 + jj;
+                const T *Oj = Ob + (int64_t)jj * TR * ldo + io;
+                double dv;
+                if (mt < n3) {
+                    dv = ev[io][jj] * (double)Oj[(1 + mt) * ldo];
+                    if (mt / 3 == j) dv += a0[io][jj] * ge[io][jj][mt % 3];
+                } else {
+                    dv = ev[io][jj] * (double)Oj[(n3 + 1) * ldo] + a0[io][jj] * le[io][jj];
+                    for (int a = 0; a < 3; ++a) dv += 2.0 * (double)Oj[(1 + 3 * j + a) * ldo] * ge[io][jj][a];
+                }
+                D[io][jj] = dv;
+            }
+        double M[NS][NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+#pragma unroll
+            for (int c = 0; c < NS; ++c) {
+                double acc = 0.0;
+#pragma unroll
+                for (int r = 0; r < NS; ++r) acc += Ai[i][r] * D[r][c];
+                M[i][c] = acc;
+            }
+        double tr = 0.0;
+#pragma unroll
+        for (int i = 0; i < NS; ++i) tr += M[i][i];
+        if (mt < n3) {
+            out[2 + mt] = tr;
+#pragma unroll
+            for (int i = 0; i < NS; ++i)
+#pragma unroll
+                for (int c = 0; c < NS; ++c) sq += M[i][c] * M[c][i];
+        } else {
+            trl = tr;
+        }
+    }
+    out[2 + n3] = trl - sq;
+}
+
+// ---------------------------------------------------------------------------
 // per walker, FP64: psi = sum_k s_k exp(l_k), l_k = l_k_up + l_k_dn;
 // log|psi| = l_max + log|sum_k s_k exp(l_k - l_max)|, weights
 // w_k = s_k exp(l_k - l_max) / sum; E_kin = -1/2 (lap psi)/psi
@@ -846,6 +1179,28 @@ void launch_det(const double *Phi, int64_t B, int K, int n, int TR, int n3, int 
         hipLaunchKernelGGL((k_det<T, false>), g, dim3(64), lds, st, Phi, B, K, n, TR, n3, sp, DR, rec);
 }
 
+template <typename T>
+void launch_orbdet(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof, int sp,
+                   const T *O, int64_t ldo, int64_t B, int TR, double *DR, int rec, hipStream_t st)
+{
+    const int n = sp == 0 ? s.nu : s.nd;
+    const dim3 gs((unsigned)((B * s.K + 255) / 256));
+    switch (n) {
+    case 1:
+        hipLaunchKernelGGL((k_orbdet_small<T, 1>), gs, dim3(256), 0, st, s, x, theta, gof, piof, sigof, sp, O, ldo, B,
+                           TR, DR, rec);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_orbdet_small<T, 2>), gs, dim3(256), 0, st, s, x, theta, gof, piof, sigof, sp, O, ldo, B,
+                           TR, DR, rec);
+        break;
+    default:
+        hipLaunchKernelGGL(k_orbdet<T>, dim3((unsigned)(B * s.K)), dim3(64), orbdet_lds(n), st, s, x, theta, gof,
+                           piof, sigof, sp, O, ldo, B, TR, DR, rec);
+        break;
+    }
+}
+
 void launch_combine(const Sys &s, const double *x, const double *DR, int rec, int64_t B, double vnn, double *log_abs,
                     int8_t *sign, double *e_loc, double *parts, bool fl, hipStream_t st)
 {
@@ -868,7 +1223,9 @@ void launch_combine(const Sys &s, const double *x, const double *DR, int rec, in
     template void launch_layer_epi<T>(const T *, const T *, const T *, const T *, T *, int64_t, int64_t, int, int,  \
                                       int, int, int, int, bool, T *, hipStream_t);                                  \
     template void launch_envelope<T>(const Sys &, const double *, const T *, int64_t, int64_t, int64_t, int,        \
-                                     const T *, int64_t, int64_t, int, bool, double *, hipStream_t);
+                                     const T *, int64_t, int64_t, int, bool, double *, hipStream_t);                \
+    template void launch_orbdet<T>(const Sys &, const double *, const T *, int64_t, int64_t, int64_t, int,          \
+                                   const T *, int64_t, int64_t, int, double *, int, hipStream_t);
 
 FN_INST(float)
 FN_INST(double)
