@@ -151,7 +151,9 @@ fn_status make_ctx(const fn_config *cfg, Ctx &c)
                     : (c.prec == FN_FP32 ? GEMM_F32
                                          : (c.prec == FN_BF16_MIXED ? GEMM_BF16
                                                                     : (c.prec == FN_BF16X3_MIXED ? GEMM_BF16X3 : GEMM_BF16X6)));
-    c.hmode = c.f64 ? GEMM_F64 : GEMM_F32;
+    // orbital head: FP32 operands; the six-product BF16 split carries them to
+    // FP32 accuracy on the matrix cores, so that mode uses it here as well
+    c.hmode = c.f64 ? GEMM_F64 : (c.smode == GEMM_BF16X6 ? GEMM_BF16X6 : GEMM_F32);
     double vnn = 0.0;
     for (int m = 0; m < s.M; ++m)
         for (int q = m + 1; q < s.M; ++q) {
@@ -216,7 +218,7 @@ fn_status make_plan(const Ctx &c, int64_t B, int op, Plan &p)
     for (int sp = 0; sp < 2; ++sp) {
         int n = sp == 0 ? s.nu : s.nd;
         size_t nh = (size_t)s.K * n * c.W.W1p;
-        p.wh[sp] = o; o = al(o + nh * he);
+        p.wh[sp] = o; o = al(o + nh * he * gemm_parts(c.hmode));
         p.wb[sp] = o; if (p.save) o = al(o + (size_t)s.w1 * c.W.KNp[sp] * e);
     }
     // sizes that do not scale with the walker chunk
@@ -390,7 +392,7 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
         T *O = (T *)(ws + p.O[sp]);
         GemmArgs gh{};
         gh.A1 = HL; gh.lda1 = ldh; gh.K1 = c.W.W1p;
-        gh.W = ws + p.wh[sp]; gh.ldw = c.W.W1p;
+        gh.W = ws + p.wh[sp]; gh.ldw = c.W.W1p; gh.wpart = (int64_t)s.K * n * c.W.W1p;
         gh.C = O; gh.ldc = c.W.KNp[sp];
         gh.rows = b * n * TR; gh.nout = s.K * n;
         gh.rows_per_group = (int64_t)n * TR; gh.group_stride = (int64_t)s.N * TR; gh.row_offset = (int64_t)j0 * TR;
