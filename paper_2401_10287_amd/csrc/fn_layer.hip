@@ -204,17 +204,21 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
     const int n3 = a.n3, tl = n3 + 1;
     const int64_t rows_here = a.rows - m0 < LBM ? a.rows - m0 : LBM;
     float *sX = (float *)smem;
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                sX[(wm * 64 + 16 * i + 4 * (lane >> 4) + e) * XS + wn * 64 + 16 * j + (lane & 15)] = acc[i][j][e];
-    __syncthreads();
     auto f4add = [](float4 u, float4 v) { return make_float4(u.x + v.x, u.y + v.y, u.z + v.z, u.w + v.w); };
+    // park the accumulators: the pre-activation tile replaces the operand stage
+    auto park = [&]() {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    sX[(wm * 64 + 16 * i + 4 * (lane >> 4) + e) * XS + wn * 64 + 16 * j + (lane & 15)] = acc[i][j][e];
+        __syncthreads();
+    };
     if constexpr (TP == 1) {
+        park();
         for (int q = tid; q < LBM * (LBN / 4); q += 256) {
             const int r = q / (LBN / 4), cq = q % (LBN / 4);
             const int col = n0 + 4 * cq;
@@ -244,17 +248,29 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
         const bool live = (int64_t)el * TP < rows_here && col < a.W1p;
         const bool real = live && col < a.w1;
         float *xc = sX + (el * TP) * XS + 4 * cq;
-        float4 src = make_float4(0.f, 0.f, 0.f, 0.f);
+        // the item's per-walker rows and residual rows are requested before
+        // the accumulators are parked, so their latency overlaps the parking
+        float4 p[16], r4[16];
+        float4 b4 = make_float4(0.f, 0.f, 0.f, 0.f);
         if (real) {
             const int64_t w = (Rb / TP) / a.N;
             const float *pw = Pw + (w * TP) * (int64_t)a.w1 + col;
-            float4 p[16];
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int t = 16 * rc + u;
                 p[u] = t <= tl ? *(const float4 *)(pw + (int64_t)t * a.w1) : make_float4(0.f, 0.f, 0.f, 0.f);
             }
-            const float4 b4 = rc == 0 ? *(const float4 *)(bias + col) : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (rc == 0) b4 = *(const float4 *)(bias + col);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int t = 16 * rc + u;
+            r4[u] = real && a.resid && t <= tl ? *(const float4 *)(Hin + (Rb + t) * a.lda1 + col)
+                                              : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        park();
+        float4 src = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (real) {
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int t = 16 * rc + u;
@@ -269,15 +285,8 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
         }
         srcp[q] = src;
         __syncthreads();
-        float4 r4[16];
         float y0[4], dd[4], lap[4];
         if (live) {
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int t = 16 * rc + u;
-                r4[u] = real && a.resid && t <= tl ? *(const float4 *)(Hin + (Rb + t) * a.lda1 + col)
-                                                  : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
             float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
             for (int k = 0; k < QPR; ++k) s4 = f4add(s4, srcp[el * 32 * QPR + cq * QPR + k]);
