@@ -27,6 +27,13 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 namespace {
 
 constexpr int LBM = 128, LBN = 128, LBK = 32;
+
+// bitwise select (m all ones or zero) without a branch
+__device__ inline float4 mask4(float4 x, uint32_t m)
+{
+    return make_float4(__uint_as_float(__float_as_uint(x.x) & m), __uint_as_float(__float_as_uint(x.y) & m),
+                       __uint_as_float(__float_as_uint(x.z) & m), __uint_as_float(__float_as_uint(x.w) & m));
+}
 constexpr int LDH = LBK;          // BF16 tile rows, chunk-swizzled (lds_chunk)
 constexpr int LDF = LBK + 4;
 
@@ -58,12 +65,29 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
     const float *__restrict__ A1 = a.A1;
     const float *__restrict__ A2 = a.A2;
 
-    int64_t arow[4];
-    bool aval[4];
+    // per-thread element offsets of the float4s this thread loads: activation
+    // rows (clamped to a valid row; out-of-range rows load and are zeroed) for
+    // either operand part, and weight rows
+    int64_t offa1[4], offa2[4];
+    uint32_t aval[4];                                // all ones for an in-range row, else 0
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        arow[v] = m0 + ((tid + 256 * v) >> 3);
-        aval[v] = arow[v] < a.rows;
+        const int f = tid + 256 * v;
+        const int64_t row = m0 + (f >> 3);
+        aval[v] = row < a.rows ? 0xffffffffu : 0u;
+        const int64_t rr = row < a.rows ? row : m0;
+        offa1[v] = rr * a.lda1 + 4 * (f & 7);
+        offa2[v] = rr * a.lda2 + 4 * (f & 7);
+    }
+    constexpr int NBV = F32 ? 4 : 2;                 // weight vectors per thread (per part)
+    int64_t offw[NBV];
+    uint32_t wval[NBV];
+#pragma unroll
+    for (int v = 0; v < NBV; ++v) {
+        const int f = tid + 256 * v;
+        const int o = F32 ? n0 + (f >> 3) : n0 + (f >> 2);
+        wval[v] = o < a.nout ? 0xffffffffu : 0u;
+        offw[v] = (int64_t)(o < a.nout ? o : n0) * a.ldw + (F32 ? 4 * (f & 7) : 8 * (f & 3));
     }
     float4 ra[4];
     uint4 rwh[F32 ? 1 : 2 * NP];
@@ -71,35 +95,28 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 
     auto load_tile = [&](int kt) {
         const int kb = kt * LBK;
+        // a reduction tile lies wholly in one operand part (K1 is a multiple of LBK)
+        if (kb < a.K1) {
+            const float *base = A1 + kb;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int f = tid + 256 * v;
-            const int k = kb + 4 * (f & 7);
-            float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (aval[v]) val = *(const float4 *)(k < a.K1 ? A1 + arow[v] * a.lda1 + k : A2 + arow[v] * a.lda2 + (k - a.K1));
-            ra[v] = val;
-        }
-        if constexpr (F32) {
-            const float *W = (const float *)a.W;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int f = tid + 256 * v;
-                const int o = n0 + (f >> 3);
-                rwf[v] = o < a.nout ? *(const float4 *)(W + (int64_t)o * a.ldw + kb + 4 * (f & 7))
-                                    : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
+            for (int v = 0; v < 4; ++v) ra[v] = *(const float4 *)(base + offa1[v]);
         } else {
-            const uint16_t *W = (const uint16_t *)a.W;
+            const float *base = A2 + (kb - a.K1);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ra[v] = *(const float4 *)(base + offa2[v]);
+        }
+        // loads are unconditional (clamped rows); out-of-range rows are
+        // zeroed when stored, so no load sits behind a branch
+        if constexpr (F32) {
+            const float *W = (const float *)a.W + kb;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) rwf[v] = *(const float4 *)(W + offw[v]);
+        } else {
+            const uint16_t *W = (const uint16_t *)a.W + kb;
 #pragma unroll
             for (int q = 0; q < NP; ++q)
 #pragma unroll
-                for (int v = 0; v < 2; ++v) {
-                    const int f = tid + 256 * v;
-                    const int o = n0 + (f >> 2);
-                    rwh[q * 2 + v] = o < a.nout ? *(const uint4 *)(W + (int64_t)q * a.wpart + (int64_t)o * a.ldw + kb +
-                                                                   8 * (f & 3))
-                                                : make_uint4(0, 0, 0, 0);
-                }
+                for (int v = 0; v < 2; ++v) rwh[q * 2 + v] = *(const uint4 *)(W + (int64_t)q * a.wpart + offw[v]);
         }
     };
     auto store_tile = [&]() {
@@ -107,7 +124,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
         for (int v = 0; v < 4; ++v) {
             const int f = tid + 256 * v;
             const int r = f >> 3, k = 4 * (f & 7);
-            const float4 x = ra[v];
+            const float4 x = mask4(ra[v], aval[v]);
             if constexpr (F32) {
                 *(float4 *)((float *)smem + r * LDF + k) = x;
             } else {
@@ -125,7 +142,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int f = tid + 256 * v;
-                *(float4 *)&sB[(f >> 3) * LDF + 4 * (f & 7)] = rwf[v];
+                *(float4 *)&sB[(f >> 3) * LDF + 4 * (f & 7)] = mask4(rwf[v], wval[v]);
             }
         } else {
             uint16_t *sB = (uint16_t *)(smem + ASZ);
@@ -134,7 +151,9 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 #pragma unroll
                 for (int v = 0; v < 2; ++v) {
                     const int f = tid + 256 * v;
-                    *(uint4 *)&sB[q * LBN * LDH + (f >> 2) * LDH + 8 * lds_chunk(f >> 2, f & 3)] = rwh[q * 2 + v];
+                    *(uint4 *)&sB[q * LBN * LDH + (f >> 2) * LDH + 8 * lds_chunk(f >> 2, f & 3)] =
+                        make_uint4(rwh[q * 2 + v].x & wval[v], rwh[q * 2 + v].y & wval[v], rwh[q * 2 + v].z & wval[v],
+                                   rwh[q * 2 + v].w & wval[v]);
                 }
         }
     };
