@@ -237,24 +237,45 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
         __syncthreads();
     };
     if constexpr (TP == 1) {
+        // a thread keeps one column quad and walks 16 rows (8 apart); the
+        // per-walker rows are requested before parking, the residual rows
+        // right after, so both latencies overlap other work
+        const int cq = tid & 31, r0 = tid >> 5;
+        const int col = n0 + 4 * cq;
+        const bool colreal = col < a.w1;
+        const int colc = colreal ? col : 0;
+        const uint32_t cm = colreal ? 0xffffffffu : 0u;
+        const float4 bb = mask4(*(const float4 *)(bias + colc), cm);
+        float4 pv[16];
+#pragma unroll
+        for (int it = 0; it < 16; ++it) {
+            const int r = r0 + 8 * it;
+            const int64_t R = m0 + (r < rows_here ? r : 0);
+            pv[it] = *(const float4 *)(Pw + (R / a.N) * a.w1 + colc);
+        }
         park();
-        for (int q = tid; q < LBM * (LBN / 4); q += 256) {
-            const int r = q / (LBN / 4), cq = q % (LBN / 4);
-            const int col = n0 + 4 * cq;
-            const int64_t R = m0 + r;
-            if (r >= rows_here || col >= a.W1p) continue;
-            float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (col < a.w1) {
-                const int64_t w = R / a.N;
-                const float4 p = *(const float4 *)(Pw + w * a.w1 + col);
-                const float4 bb = *(const float4 *)(bias + col);
-                const float *x = sX + r * XS + 4 * cq;
-                y = make_float4(tanhf((x[0] + p.x) + bb.x), tanhf((x[1] + p.y) + bb.y), tanhf((x[2] + p.z) + bb.z),
-                                tanhf((x[3] + p.w) + bb.w));
-                if (a.resid) y = f4add(y, *(const float4 *)(Hin + R * a.lda1 + col));
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            float4 rv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int r = r0 + 8 * (8 * h + u);
+                const int64_t R = m0 + (r < rows_here ? r : 0);
+                rv[u] = a.resid ? *(const float4 *)(Hin + R * a.lda1 + colc) : make_float4(0.f, 0.f, 0.f, 0.f);
             }
-            *(float4 *)(Hout + R * a.ldh_out + col) = y;
-            if (a.Gout) *(float4 *)(sX + r * XS + 4 * cq) = y;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int r = r0 + 8 * (8 * h + u);
+                const float *x = sX + r * XS + 4 * cq;
+                const float4 p4 = pv[8 * h + u];
+                float4 y = make_float4(tanhf((x[0] + p4.x) + bb.x), tanhf((x[1] + p4.y) + bb.y),
+                                       tanhf((x[2] + p4.z) + bb.z), tanhf((x[3] + p4.w) + bb.w));
+                y = mask4(f4add(y, rv[u]), cm);
+                if (r < rows_here && col < a.W1p) {
+                    *(float4 *)(Hout + (m0 + r) * a.ldh_out + col) = y;
+                    if (a.Gout) *(float4 *)(sX + r * XS + 4 * cq) = y;
+                }
+            }
         }
     } else {
         constexpr int QPR = TP / 16;                   // 16-row chunks per electron
