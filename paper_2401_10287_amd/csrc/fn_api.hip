@@ -198,7 +198,7 @@ fn_status make_plan(const Ctx &c, int64_t B, int op, Plan &p)
     p.rec = n3 + 3;
     const int nmax = std::max(s.nu, s.nd);
     if (pair_stream_lds(s, p.fl, c.esz) > 64 * 1024) return fail(FN_EUNSUPPORTED, "pair stream exceeds LDS");
-    if ((p.fl ? orbdet_lds(nmax) : det_lds(nmax, n3, false, sizeof(double))) > 64 * 1024)
+    if ((p.save ? det_lds(nmax, n3, false, sizeof(double)) : orbdet_lds(nmax, p.fl)) > 64 * 1024)
         return fail(FN_EUNSUPPORTED, "determinant exceeds LDS");
     if (p.save) {
         if (s.w1 % 32 != 0) return fail(FN_EUNSUPPORTED, "parameter gradients need w1 to be a multiple of 32");
@@ -253,8 +253,8 @@ fn_status make_plan(const Ctx &c, int64_t B, int op, Plan &p)
         {&p.X, N * TR * s.w1 * e},
         {&p.O[0], (size_t)s.nu * TR * c.W.KNp[0] * e},
         {&p.O[1], (size_t)s.nd * TR * c.W.KNp[1] * e},
-        {&p.Phi[0], p.fl ? 0 : (size_t)s.K * TR * s.nu * s.nu * 8},   // forward-Laplacian: formed in LDS
-        {&p.Phi[1], p.fl ? 0 : (size_t)s.K * TR * s.nd * s.nd * 8},
+        {&p.Phi[0], p.save ? (size_t)s.K * TR * s.nu * s.nu * 8 : 0},   // stored for the backward only
+        {&p.Phi[1], p.save ? (size_t)s.K * TR * s.nd * s.nd * 8 : 0},
         {&p.DR, (size_t)2 * s.K * p.rec * 8},
         {&p.Tl, p.save ? (size_t)s.L * N * s.w1 * e : 0},
         {&p.GA[0], p.save ? (size_t)s.K * s.nu * s.nu * 8 : 0},
@@ -397,11 +397,12 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
         gh.rows = b * n * TR; gh.nout = s.K * n;
         gh.rows_per_group = (int64_t)n * TR; gh.group_stride = (int64_t)s.N * TR; gh.row_offset = (int64_t)j0 * TR;
         { Timed t_(K_HEAD_GEMM, st); (void)launch_gemm(c.hmode, gh, st); }
-        if (fl) {
-            // forward-Laplacian form: orbital matrices formed and factorised in LDS
+        if (fl || !p.save) {
+            // orbital matrices formed and factorised in LDS or registers; only
+            // the backward needs them stored
             Timed t_(K_DET, st);
-            launch_orbdet<T>(s, xw, theta, c.P.g[sp], c.P.pi[sp], c.P.sig[sp], sp, O, c.W.KNp[sp], b, TR, DR, p.rec,
-                             st);
+            launch_orbdet<T>(s, xw, theta, c.P.g[sp], c.P.pi[sp], c.P.sig[sp], sp, O, c.W.KNp[sp], b, TR, fl, DR,
+                             p.rec, st);
             continue;
         }
         double *Phi = (double *)(ws + p.Phi[sp]);

@@ -26,10 +26,10 @@ template <typename T>
 void launch_envelope(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof, int sp,
                      const T *O, int64_t ldo, int64_t B, int TR, bool fl, double *Phi, hipStream_t st);
 size_t det_lds(int n, int n3, bool fl, size_t elem);
-size_t orbdet_lds(int n);
+size_t orbdet_lds(int n, bool fl);
 template <typename T>
 void launch_orbdet(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof, int sp,
-                   const T *O, int64_t ldo, int64_t B, int TR, double *DR, int rec, hipStream_t st);
+                   const T *O, int64_t ldo, int64_t B, int TR, bool fl, double *DR, int rec, hipStream_t st);
 void launch_det(const double *Phi, int64_t B, int K, int n, int TR, int n3, int sp, bool fl, double *DR, int rec,
                 hipStream_t st);
 void launch_combine(const Sys &s, const double *x, const double *DR, int rec, int64_t B, double vnn, double *log_abs,

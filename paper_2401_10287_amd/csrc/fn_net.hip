@@ -631,13 +631,14 @@ __global__ __launch_bounds__(64) void k_det(const T *Phi, int64_t B, int K, int 
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int orbdet_cd(int n) { return n >= 64 ? 1 : 64 / n; }
 
-size_t orbdet_lds(int n)
+size_t orbdet_lds(int n, bool fl)
 {
     const size_t nn = (size_t)n * n;
-    return (7 * nn + (size_t)orbdet_cd(n) * nn) * sizeof(double) + (size_t)n * sizeof(int) + 16;
+    return ((fl ? 7 * nn + (size_t)orbdet_cd(n) * nn : nn)) * sizeof(double) + (size_t)n * sizeof(int) + 16;
 }
 
-template <typename T>
+// FL = false: value only (envelope, LU, sign and log|det|), LDS holds the matrix only
+template <typename T, bool FL>
 __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *theta, int64_t gof, int64_t piof,
                                                int64_t sigof, int sp, const T *O, int64_t ldo, int64_t B, int TR,
                                                double *DR, int rec)
@@ -651,7 +652,7 @@ __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *
     double *LE = GE + 3 * nn;             // lap_j e
     double *A0 = LE + nn;                 // orbital value a (with its bias)
     double *Mc = A0 + nn;                 // [CD][n][n] solved directions of one chunk
-    int *perm = (int *)(Mc + (size_t)CD * nn);
+    int *perm = (int *)(FL ? (double *)(Mc + (size_t)CD * nn) : LU + nn);
     __shared__ int s_sign, s_sing;
     __shared__ double s_log;
     const int lane = threadIdx.x;
@@ -676,20 +677,24 @@ __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *
             const double qd = sqrt(sd[0] * sd[0] + sd[1] * sd[1] + sd[2] * sd[2]);
             const double em = (double)theta[piof + (int64_t)col * s.M + m] * exp(-qd);
             env += em;
-            double trS = 0.0;
-            for (int e = 0; e < 9; ++e) trS += Sg[e] * Sg[e];
-            const double iq = 1.0 / qd;
-            const double ad2 = ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2];
-            const double lq = (trS - ad2 * iq * iq) * iq;
-            const double gq2 = ad2 * iq * iq;
-            for (int a = 0; a < 3; ++a) ge[a] -= em * ad[a] * iq;
-            le += em * (gq2 - lq);
+            if constexpr (FL) {
+                double trS = 0.0;
+                for (int e = 0; e < 9; ++e) trS += Sg[e] * Sg[e];
+                const double iq = 1.0 / qd;
+                const double ad2 = ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2];
+                const double lq = (trS - ad2 * iq * iq) * iq;
+                const double gq2 = ad2 * iq * iq;
+                for (int a = 0; a < 3; ++a) ge[a] -= em * ad[a] * iq;
+                le += em * (gq2 - lq);
+            }
         }
         const double a0 = (double)O[((w * n + jj) * TR) * ldo + col] + (double)theta[gof + col];
-        EV[q] = env;
-        GE[3 * q] = ge[0]; GE[3 * q + 1] = ge[1]; GE[3 * q + 2] = ge[2];
-        LE[q] = le;
-        A0[q] = a0;
+        if constexpr (FL) {
+            EV[q] = env;
+            GE[3 * q] = ge[0]; GE[3 * q + 1] = ge[1]; GE[3 * q + 2] = ge[2];
+            LE[q] = le;
+            A0[q] = a0;
+        }
         LU[q] = a0 * env;
     }
     for (int q = lane; q < n; q += 64) perm[q] = q;
@@ -734,6 +739,7 @@ __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *
         return;
     }
     if (lane == 0) { out[0] = (double)s_sign; out[1] = s_log; }
+    if constexpr (!FL) return;
 
     double sq = 0.0, trl = 0.0;
     for (int t0 = 0; t0 <= n3; t0 += CD) {
@@ -792,7 +798,7 @@ __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *
 // Small spins (n <= 2): one thread per (walker, determinant k) with the
 // matrices in registers.  Same quantities as k_orbdet; here the directions
 // use the explicit inverse from the pivoted LU, M_c = A^-1 d_c A.
-template <typename T, int NS>
+template <typename T, int NS, bool FL>
 __global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, const T *theta, int64_t gof,
                                                       int64_t piof, int64_t sigof, int sp, const T *O, int64_t ldo,
                                                       int64_t B, int TR, double *DR, int rec)
@@ -821,14 +827,16 @@ __global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, co
                 const double qd = sqrt(sd[0] * sd[0] + sd[1] * sd[1] + sd[2] * sd[2]);
                 const double em = (double)theta[piof + (int64_t)col * s.M + m] * exp(-qd);
                 env += em;
-                double trS = 0.0;
-                for (int e = 0; e < 9; ++e) trS += Sg[e] * Sg[e];
-                const double iq = 1.0 / qd;
-                const double ad2 = ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2];
-                const double lq = (trS - ad2 * iq * iq) * iq;
-                const double gq2 = ad2 * iq * iq;
-                for (int a = 0; a < 3; ++a) g3[a] -= em * ad[a] * iq;
-                lp += em * (gq2 - lq);
+                if constexpr (FL) {
+                    double trS = 0.0;
+                    for (int e = 0; e < 9; ++e) trS += Sg[e] * Sg[e];
+                    const double iq = 1.0 / qd;
+                    const double ad2 = ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2];
+                    const double lq = (trS - ad2 * iq * iq) * iq;
+                    const double gq2 = ad2 * iq * iq;
+                    for (int a = 0; a < 3; ++a) g3[a] -= em * ad[a] * iq;
+                    lp += em * (gq2 - lq);
+                }
             }
             ev[io][jj] = env;
             ge[io][jj][0] = g3[0]; ge[io][jj][1] = g3[1]; ge[io][jj][2] = g3[2];
@@ -881,6 +889,7 @@ __global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, co
     }
     out[0] = (double)sgn;
     out[1] = lg;
+    if constexpr (!FL) return;
     // inverse: column e of A^-1 solves (LU) y = P e_e
     double Ai[NS][NS];
 #pragma unroll
@@ -1080,7 +1089,8 @@ static size_t pair_stream_lds_wb(const Sys &s, bool fl, size_t elem, int WB)
 size_t pair_stream_lds(const Sys &s, bool fl, size_t elem) { return pair_stream_lds_wb(s, fl, elem, 1); }
 
 // Output columns per thread (1, 2 or 4) and (walker, electron) rows per
-// workgroup: about 256 (pair, column group) items, within 64 KiB of LDS.
+// workgroup: about 256 (pair, column group) items (1024 in value-only form),
+// within 64 KiB of LDS.
 static int pair_stream_oc(const Sys &s)
 {
     const int w2p = round_up(s.w2, 4);
@@ -1089,8 +1099,11 @@ static int pair_stream_oc(const Sys &s)
 
 static int pair_stream_wb(const Sys &s, bool fl, size_t elem)
 {
+    // value rows only: a few items per thread, so the weight staging is shared
+    // by more rows
+    const int target = fl ? 256 : 1024;
     const int items = s.N * (round_up(s.w2, 4) / pair_stream_oc(s));
-    int wb = items >= 256 ? 1 : 256 / items;
+    int wb = items >= target ? 1 : target / items;
     while (wb > 1 && pair_stream_lds_wb(s, fl, elem, wb) > 64 * 1024) --wb;
     return wb;
 }
@@ -1179,26 +1192,34 @@ void launch_det(const double *Phi, int64_t B, int K, int n, int TR, int n3, int 
         hipLaunchKernelGGL((k_det<T, false>), g, dim3(64), lds, st, Phi, B, K, n, TR, n3, sp, DR, rec);
 }
 
-template <typename T>
-void launch_orbdet(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof, int sp,
-                   const T *O, int64_t ldo, int64_t B, int TR, double *DR, int rec, hipStream_t st)
+template <typename T, bool FL>
+static void launch_orbdet_fl(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof,
+                             int sp, const T *O, int64_t ldo, int64_t B, int TR, double *DR, int rec, hipStream_t st)
 {
     const int n = sp == 0 ? s.nu : s.nd;
     const dim3 gs((unsigned)((B * s.K + 255) / 256));
     switch (n) {
     case 1:
-        hipLaunchKernelGGL((k_orbdet_small<T, 1>), gs, dim3(256), 0, st, s, x, theta, gof, piof, sigof, sp, O, ldo, B,
-                           TR, DR, rec);
+        hipLaunchKernelGGL((k_orbdet_small<T, 1, FL>), gs, dim3(256), 0, st, s, x, theta, gof, piof, sigof, sp, O, ldo,
+                           B, TR, DR, rec);
         break;
     case 2:
-        hipLaunchKernelGGL((k_orbdet_small<T, 2>), gs, dim3(256), 0, st, s, x, theta, gof, piof, sigof, sp, O, ldo, B,
-                           TR, DR, rec);
+        hipLaunchKernelGGL((k_orbdet_small<T, 2, FL>), gs, dim3(256), 0, st, s, x, theta, gof, piof, sigof, sp, O, ldo,
+                           B, TR, DR, rec);
         break;
     default:
-        hipLaunchKernelGGL(k_orbdet<T>, dim3((unsigned)(B * s.K)), dim3(64), orbdet_lds(n), st, s, x, theta, gof,
-                           piof, sigof, sp, O, ldo, B, TR, DR, rec);
+        hipLaunchKernelGGL((k_orbdet<T, FL>), dim3((unsigned)(B * s.K)), dim3(64), orbdet_lds(n, FL), st, s, x, theta,
+                           gof, piof, sigof, sp, O, ldo, B, TR, DR, rec);
         break;
     }
+}
+
+template <typename T>
+void launch_orbdet(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof, int sp,
+                   const T *O, int64_t ldo, int64_t B, int TR, bool fl, double *DR, int rec, hipStream_t st)
+{
+    if (fl) launch_orbdet_fl<T, true>(s, x, theta, gof, piof, sigof, sp, O, ldo, B, TR, DR, rec, st);
+    else launch_orbdet_fl<T, false>(s, x, theta, gof, piof, sigof, sp, O, ldo, B, TR, DR, rec, st);
 }
 
 void launch_combine(const Sys &s, const double *x, const double *DR, int rec, int64_t B, double vnn, double *log_abs,
@@ -1225,7 +1246,7 @@ void launch_combine(const Sys &s, const double *x, const double *DR, int rec, in
     template void launch_envelope<T>(const Sys &, const double *, const T *, int64_t, int64_t, int64_t, int,        \
                                      const T *, int64_t, int64_t, int, bool, double *, hipStream_t);                \
     template void launch_orbdet<T>(const Sys &, const double *, const T *, int64_t, int64_t, int64_t, int,          \
-                                   const T *, int64_t, int64_t, int, double *, int, hipStream_t);
+                                   const T *, int64_t, int64_t, int, bool, double *, int, hipStream_t);
 
 FN_INST(float)
 FN_INST(double)
