@@ -795,7 +795,7 @@ __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *
     if (lane == 0) out[2 + n3] = trl - sq;
 }
 
-// Small spins (n <= 2): one thread per (walker, determinant k) with the
+// Small spins: one thread per (walker, determinant k) with the
 // matrices in registers.  Same quantities as k_orbdet; here the directions
 // use the explicit inverse from the pivoted LU, M_c = A^-1 d_c A.
 template <typename T, int NS, bool FL>
@@ -1192,26 +1192,43 @@ void launch_det(const double *Phi, int64_t B, int K, int n, int TR, int n3, int 
         hipLaunchKernelGGL((k_det<T, false>), g, dim3(64), lds, st, Phi, B, K, n, TR, n3, sp, DR, rec);
 }
 
+template <typename T, int NS, bool FL>
+static void launch_small(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof, int sp,
+                         const T *O, int64_t ldo, int64_t B, int TR, double *DR, int rec, hipStream_t st)
+{
+    const dim3 gs((unsigned)((B * s.K + 255) / 256));
+    hipLaunchKernelGGL((k_orbdet_small<T, NS, FL>), gs, dim3(256), 0, st, s, x, theta, gof, piof, sigof, sp, O, ldo, B,
+                       TR, DR, rec);
+}
+
+// one thread per determinant where its matrices fit in registers: n <= 2 in
+// forward-Laplacian form, n <= 8 for the value alone; one wave otherwise
 template <typename T, bool FL>
 static void launch_orbdet_fl(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof,
                              int sp, const T *O, int64_t ldo, int64_t B, int TR, double *DR, int rec, hipStream_t st)
 {
     const int n = sp == 0 ? s.nu : s.nd;
-    const dim3 gs((unsigned)((B * s.K + 255) / 256));
+#define FN_SMALL(NS)                                                                                        \
+    case NS: launch_small<T, NS, FL>(s, x, theta, gof, piof, sigof, sp, O, ldo, B, TR, DR, rec, st); return;
     switch (n) {
-    case 1:
-        hipLaunchKernelGGL((k_orbdet_small<T, 1, FL>), gs, dim3(256), 0, st, s, x, theta, gof, piof, sigof, sp, O, ldo,
-                           B, TR, DR, rec);
-        break;
-    case 2:
-        hipLaunchKernelGGL((k_orbdet_small<T, 2, FL>), gs, dim3(256), 0, st, s, x, theta, gof, piof, sigof, sp, O, ldo,
-                           B, TR, DR, rec);
-        break;
-    default:
-        hipLaunchKernelGGL((k_orbdet<T, FL>), dim3((unsigned)(B * s.K)), dim3(64), orbdet_lds(n, FL), st, s, x, theta,
-                           gof, piof, sigof, sp, O, ldo, B, TR, DR, rec);
-        break;
+        FN_SMALL(1)
+        FN_SMALL(2)
+    default: break;
     }
+    if constexpr (!FL) {
+        switch (n) {
+            FN_SMALL(3)
+            FN_SMALL(4)
+            FN_SMALL(5)
+            FN_SMALL(6)
+            FN_SMALL(7)
+            FN_SMALL(8)
+        default: break;
+        }
+    }
+#undef FN_SMALL
+    hipLaunchKernelGGL((k_orbdet<T, FL>), dim3((unsigned)(B * s.K)), dim3(64), orbdet_lds(n, FL), st, s, x, theta, gof,
+                       piof, sigof, sp, O, ldo, B, TR, DR, rec);
 }
 
 template <typename T>

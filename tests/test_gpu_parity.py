@@ -272,3 +272,20 @@ def test_fused_and_separate_layer_paths(name, prec, walkers):
             np.testing.assert_array_equal(sg.cpu().numpy(), ref_l["sign"])
     finally:
         fnvmc.fn_tuning_set("fused_layer", 1)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_log_psi_spin_sizes(prec, tol):
+    """Value-only determinant kernels for every spin size up to 10 (one
+    thread per determinant up to 8 electrons, one wave beyond): atoms with
+    N = 5..20 electrons (spins 3/2 .. 10/10), 2 layers 64/16, 4 determinants."""
+    for z, q in ((5, 0), (7, 0), (8, 0), (10, 0), (11, 0), (13, 0), (15, 0), (16, 0), (20, 0)):
+        s = I.atom_ion(z, q, walkers=24, n_layers=2, w1=64, w2=16, n_det=4)
+        torch, fnvmc, cfg, tt, xt, th, x = _setup(s, prec, 24)
+        lp, sg = fnvmc.fn_log_psi(cfg, tt, xt)
+        torch.cuda.synchronize()
+        o = O.Oracle(s)
+        ref = o.log_psi(th, x)
+        _check_logpsi(lp.cpu().numpy(), ref, tol, f"Z={z} ({s.n_up},{s.n_dn}) {prec}", _conditioning(o, s, th, x),
+                      prec == "fp64")
+        np.testing.assert_array_equal(sg.cpu().numpy(), ref["sign"])
