@@ -303,12 +303,15 @@ hipError_t launch_gemm(int mode, const GemmArgs &a, hipStream_t st)
     if (mode == GEMM_F64) {
         dim3 grid((unsigned)((a.rows + 63) / 64), (unsigned)((a.nout + 63) / 64));
         hipLaunchKernelGGL(k_gemm_f64, grid, dim3(256), 0, st, a);
-    } else if (a.nout <= 32) {
-        launch_bn<32>(mode, a, st);
-    } else if (a.nout <= 64) {
-        launch_bn<64>(mode, a, st);
     } else {
-        launch_bn<128>(mode, a, st);
+        // narrowest column tile that covers the output, and narrower still
+        // when 128-column tiles would leave CUs idle (latency-bound small grids)
+        const int64_t nrb = (a.rows + BM - 1) / BM;
+        const int bn = a.nout <= 32 ? 32 : (a.nout <= 64 ? 64 : 128);
+        const int64_t blocks = nrb * ((a.nout + bn - 1) / bn);
+        if (bn == 32 || (blocks < 256 && nrb * ((a.nout + 31) / 32) <= 1024)) launch_bn<32>(mode, a, st);
+        else if (bn == 64) launch_bn<64>(mode, a, st);
+        else launch_bn<128>(mode, a, st);
     }
     // peek, so that an earlier launch's error is still there for the caller's final check
     return hipPeekAtLastError();
