@@ -26,7 +26,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 namespace {
 
-constexpr int LBM = 128, LBN = 128, LBK = 32;
+constexpr int LBM = 128, LBK = 32;
 
 // bitwise select (m all ones or zero) without a branch
 __device__ inline float4 mask4(float4 x, uint32_t m)
@@ -39,9 +39,13 @@ constexpr int LDF = LBK + 4;
 
 }  // namespace
 
-template <int MODE, int TP>
+// LBN = 128: 2 x 2 waves of 64 x 64; LBN = 32 (value rows only, for grids
+// that would leave CUs idle): 4 x 1 waves of 32 x 32.
+template <int MODE, int TP, int LBN>
 __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 {
+    static_assert(LBN == 128 || (LBN == 32 && TP == 1), "column tile");
+    constexpr int WI = LBN == 128 ? 4 : 2, WJ = LBN == 128 ? 4 : 2;   // 16 x 16 blocks per wave
     constexpr bool F32 = MODE == GEMM_F32;
     constexpr int NP = MODE == GEMM_BF16 ? 1 : (MODE == GEMM_BF16X3 ? 2 : (MODE == GEMM_BF16X6 ? 3 : 1));
     // one operand stage (A then B); the epilogue reuses it for a 128 x 64 tile
@@ -55,12 +59,18 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 
     int64_t rb;
     int cb;
-    xcd_tile(blockIdx.x, (a.W1p + LBN - 1) / LBN, rb, cb);
+    if constexpr (LBN == 128) {
+        xcd_tile(blockIdx.x, (a.W1p + LBN - 1) / LBN, rb, cb);
+    } else {
+        const int64_t nrb = (a.rows + LBM - 1) / LBM;     // row blocks, then column blocks
+        rb = blockIdx.x % nrb;
+        cb = (int)(blockIdx.x / nrb);
+    }
     const int64_t m0 = rb * LBM;
     const int n0 = cb * LBN;
     if (m0 >= a.rows || n0 >= a.W1p) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = LBN == 128 ? wave >> 1 : wave, wn = LBN == 128 ? wave & 1 : 0;
     const int ktiles = (a.K1 + a.K2) / LBK;
     const float *__restrict__ A1 = a.A1;
     const float *__restrict__ A2 = a.A2;
@@ -79,19 +89,22 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
         offa1[v] = rr * a.lda1 + 4 * (f & 7);
         offa2[v] = rr * a.lda2 + 4 * (f & 7);
     }
-    constexpr int NBV = F32 ? 4 : 2;                 // weight vectors per thread (per part)
+    // weight vectors per thread (per part): FP32 LBN x 8 float4, BF16 LBN x 4 uint4
+    constexpr int NBT = F32 ? LBN * 8 : LBN * 4;
+    constexpr int NBV = (NBT + 255) / 256;
     int64_t offw[NBV];
     uint32_t wval[NBV];
 #pragma unroll
     for (int v = 0; v < NBV; ++v) {
         const int f = tid + 256 * v;
         const int o = F32 ? n0 + (f >> 3) : n0 + (f >> 2);
-        wval[v] = o < a.nout ? 0xffffffffu : 0u;
-        offw[v] = (int64_t)(o < a.nout ? o : n0) * a.ldw + (F32 ? 4 * (f & 7) : 8 * (f & 3));
+        const bool ok = f < NBT && o < a.nout;
+        wval[v] = ok ? 0xffffffffu : 0u;
+        offw[v] = (int64_t)(ok ? o : n0) * a.ldw + (F32 ? 4 * (f & 7) : 8 * (f & 3));
     }
     float4 ra[4];
-    uint4 rwh[F32 ? 1 : 2 * NP];
-    float4 rwf[F32 ? 4 : 1];
+    uint4 rwh[F32 ? 1 : NBV * NP];
+    float4 rwf[F32 ? NBV : 1];
 
     auto load_tile = [&](int kt) {
         const int kb = kt * LBK;
@@ -110,13 +123,13 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
         if constexpr (F32) {
             const float *W = (const float *)a.W + kb;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) rwf[v] = *(const float4 *)(W + offw[v]);
+            for (int v = 0; v < NBV; ++v) rwf[v] = *(const float4 *)(W + offw[v]);
         } else {
             const uint16_t *W = (const uint16_t *)a.W + kb;
 #pragma unroll
             for (int q = 0; q < NP; ++q)
 #pragma unroll
-                for (int v = 0; v < 2; ++v) rwh[q * 2 + v] = *(const uint4 *)(W + (int64_t)q * a.wpart + offw[v]);
+                for (int v = 0; v < NBV; ++v) rwh[q * NBV + v] = *(const uint4 *)(W + (int64_t)q * a.wpart + offw[v]);
         }
     };
     auto store_tile = [&]() {
@@ -140,29 +153,30 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
         if constexpr (F32) {
             float *sB = (float *)(smem + ASZ);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
+            for (int v = 0; v < NBV; ++v) {
                 const int f = tid + 256 * v;
-                *(float4 *)&sB[(f >> 3) * LDF + 4 * (f & 7)] = mask4(rwf[v], wval[v]);
+                if (f < NBT) *(float4 *)&sB[(f >> 3) * LDF + 4 * (f & 7)] = mask4(rwf[v], wval[v]);
             }
         } else {
             uint16_t *sB = (uint16_t *)(smem + ASZ);
 #pragma unroll
             for (int q = 0; q < NP; ++q)
 #pragma unroll
-                for (int v = 0; v < 2; ++v) {
+                for (int v = 0; v < NBV; ++v) {
                     const int f = tid + 256 * v;
-                    *(uint4 *)&sB[q * LBN * LDH + (f >> 2) * LDH + 8 * lds_chunk(f >> 2, f & 3)] =
-                        make_uint4(rwh[q * 2 + v].x & wval[v], rwh[q * 2 + v].y & wval[v], rwh[q * 2 + v].z & wval[v],
-                                   rwh[q * 2 + v].w & wval[v]);
+                    const uint4 w = rwh[q * NBV + v];
+                    if (f < NBT)
+                        *(uint4 *)&sB[q * LBN * LDH + (f >> 2) * LDH + 8 * lds_chunk(f >> 2, f & 3)] =
+                            make_uint4(w.x & wval[v], w.y & wval[v], w.z & wval[v], w.w & wval[v]);
                 }
         }
     };
 
-    f32x4 acc[4][4];
+    f32x4 acc[WI][WJ];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < WI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < WJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     if (ktiles > 0) load_tile(0);
     for (int kt = 0; kt < ktiles; ++kt) {
@@ -170,41 +184,41 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
         store_tile();
         __syncthreads();
         if (kt + 1 < ktiles) load_tile(kt + 1);
-        const int ar = wm * 64 + (lane & 15), br = wn * 64 + (lane & 15);
+        const int ar = wm * 16 * WI + (lane & 15), br = wn * 16 * WJ + (lane & 15);
         if constexpr (F32) {
             const float *sA = (const float *)smem, *sB = (const float *)(smem + ASZ);
 #pragma unroll
             for (int kk = 0; kk < LBK / 4; ++kk) {
-                float fa[4], fb[4];
+                float fa[WI], fb[WJ];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) fa[i] = sA[(ar + 16 * i) * LDF + 4 * kk + (lane >> 4)];
+                for (int i = 0; i < WI; ++i) fa[i] = sA[(ar + 16 * i) * LDF + 4 * kk + (lane >> 4)];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) fb[j] = sB[(br + 16 * j) * LDF + 4 * kk + (lane >> 4)];
+                for (int j = 0; j < WJ; ++j) fb[j] = sB[(br + 16 * j) * LDF + 4 * kk + (lane >> 4)];
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < WI; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
+                    for (int j = 0; j < WJ; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
             }
         } else {
             const uint16_t *sA = (const uint16_t *)smem, *sB = (const uint16_t *)(smem + ASZ);
             const int ko = 8 * lds_chunk(lane & 15, lane >> 4);   // rows ar + 16 i, br + 16 j share bits 0-3 with lane
-            bf16x8 ha[NP][4], hb[NP][4];
+            bf16x8 ha[NP][WI], hb[NP][WJ];
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) ha[q][i] = *(const bf16x8 *)&sA[q * LBM * LDH + (ar + 16 * i) * LDH + ko];
+                for (int i = 0; i < WI; ++i) ha[q][i] = *(const bf16x8 *)&sA[q * LBM * LDH + (ar + 16 * i) * LDH + ko];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) hb[q][j] = *(const bf16x8 *)&sB[q * LBN * LDH + (br + 16 * j) * LDH + ko];
+                for (int j = 0; j < WJ; ++j) hb[q][j] = *(const bf16x8 *)&sB[q * LBN * LDH + (br + 16 * j) * LDH + ko];
             }
 #pragma unroll
             for (int sum = NP - 1; sum >= 0; --sum)
 #pragma unroll
                 for (int pa = 0; pa <= sum; ++pa)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
+                    for (int i = 0; i < WI; ++i)
 #pragma unroll
-                        for (int j = 0; j < 4; ++j)
+                        for (int j = 0; j < WJ; ++j)
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j], acc[i][j],
                                                                                 0, 0, 0);
         }
@@ -228,46 +242,49 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
     auto park = [&]() {
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < WI; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < WJ; ++j)
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    sX[(wm * 64 + 16 * i + 4 * (lane >> 4) + e) * XS + wn * 64 + 16 * j + (lane & 15)] = acc[i][j][e];
+                    sX[(wm * 16 * WI + 16 * i + 4 * (lane >> 4) + e) * XS + wn * 16 * WJ + 16 * j + (lane & 15)] =
+                        acc[i][j][e];
         __syncthreads();
     };
     if constexpr (TP == 1) {
         // a thread keeps one column quad and walks 16 rows (8 apart); the
         // per-walker rows are requested before parking, the residual rows
         // right after, so both latencies overlap other work
-        const int cq = tid & 31, r0 = tid >> 5;
+        constexpr int CQN = LBN / 4, RS = 256 / CQN, NR = LBM / RS;   // rows r0 + RS it, it < NR
+        constexpr int HB = NR > 8 ? 8 : NR;                               // residual rows per batch
+        const int cq = tid % CQN, r0 = tid / CQN;
         const int col = n0 + 4 * cq;
         const bool colreal = col < a.w1;
         const int colc = colreal ? col : 0;
         const uint32_t cm = colreal ? 0xffffffffu : 0u;
         const float4 bb = mask4(*(const float4 *)(bias + colc), cm);
-        float4 pv[16];
+        float4 pv[NR];
 #pragma unroll
-        for (int it = 0; it < 16; ++it) {
-            const int r = r0 + 8 * it;
+        for (int it = 0; it < NR; ++it) {
+            const int r = r0 + RS * it;
             const int64_t R = m0 + (r < rows_here ? r : 0);
             pv[it] = *(const float4 *)(Pw + (R / a.N) * a.w1 + colc);
         }
         park();
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            float4 rv[8];
+        for (int h = 0; h < NR / HB; ++h) {
+            float4 rv[HB];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int r = r0 + 8 * (8 * h + u);
+            for (int u = 0; u < HB; ++u) {
+                const int r = r0 + RS * (HB * h + u);
                 const int64_t R = m0 + (r < rows_here ? r : 0);
                 rv[u] = a.resid ? *(const float4 *)(Hin + R * a.lda1 + colc) : make_float4(0.f, 0.f, 0.f, 0.f);
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int r = r0 + 8 * (8 * h + u);
+            for (int u = 0; u < HB; ++u) {
+                const int r = r0 + RS * (HB * h + u);
                 const float *x = sX + r * XS + 4 * cq;
-                const float4 p4 = pv[8 * h + u];
+                const float4 p4 = pv[HB * h + u];
                 float4 y = make_float4(tanhf((x[0] + p4.x) + bb.x), tanhf((x[1] + p4.y) + bb.y),
                                        tanhf((x[2] + p4.z) + bb.z), tanhf((x[3] + p4.w) + bb.w));
                 y = mask4(f4add(y, rv[u]), cm);
@@ -277,7 +294,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
                 }
             }
         }
-    } else {
+    } else if constexpr (LBN == 128) {
         constexpr int QPR = TP / 16;                   // 16-row chunks per electron
         float4 *srcp = (float4 *)(smem + XSZ);         // [256] partial sources
         const int q = tid;
@@ -392,19 +409,28 @@ bool g_use_fused_layer = true;
 
 bool stream_layer_supported(int mode, int TR, int w1, int W1p)
 {
-    return g_use_fused_layer && mode != GEMM_F64 && W1p <= 2 * LBN && w1 % 4 == 0 &&
+    return g_use_fused_layer && mode != GEMM_F64 && W1p <= 256 && w1 % 4 == 0 &&
            (TR == 1 || TR == 16 || TR == 32 || TR == 64);
 }
 
 template <int MODE>
 static void launch_mode(const LayerArgs &a, int TR, hipStream_t st)
 {
-    dim3 grid((unsigned)xcd_grid((a.rows + LBM - 1) / LBM, (a.W1p + LBN - 1) / LBN));
+    const int64_t nrb = (a.rows + LBM - 1) / LBM;
+    const int64_t blocks = xcd_grid(nrb, (a.W1p + 127) / 128);
+    // value rows in a grid too small to fill the CUs: 32-column tiles, so
+    // each workgroup's reduction steps carry a quarter of the matrix work
+    if (TR == 1 && blocks <= 512) {
+        dim3 grid((unsigned)(nrb * ((a.W1p + 31) / 32)));
+        hipLaunchKernelGGL((k_stream_layer<MODE, 1, 32>), grid, dim3(256), 0, st, a);
+        return;
+    }
+    dim3 grid((unsigned)blocks);
     switch (TR) {
-    case 1: hipLaunchKernelGGL((k_stream_layer<MODE, 1>), grid, dim3(256), 0, st, a); break;
-    case 16: hipLaunchKernelGGL((k_stream_layer<MODE, 16>), grid, dim3(256), 0, st, a); break;
-    case 32: hipLaunchKernelGGL((k_stream_layer<MODE, 32>), grid, dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_stream_layer<MODE, 64>), grid, dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_stream_layer<MODE, 1, 128>), grid, dim3(256), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_stream_layer<MODE, 16, 128>), grid, dim3(256), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_stream_layer<MODE, 32, 128>), grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_stream_layer<MODE, 64, 128>), grid, dim3(256), 0, st, a); break;
     }
 }
 
