@@ -70,8 +70,9 @@ typedef int32_t fn_status;
    BF16 high and low part and three BF16 products accumulated in FP32.
    FN_BF16X6_MIXED: each operand split into three BF16 parts and the six
    products whose part indices sum to at most 2, accumulated in FP32 (FP32
-   operand precision on the BF16 matrix cores).  In every mode the
-   envelope, the determinants and their derivative traces run in FP64. */
+   operand precision on the BF16 matrix cores); the orbital head uses the
+   same split.  In every mode the envelope, the determinants and their
+   derivative traces run in FP64. */
 #define FN_FP64 0
 #define FN_FP32 1
 #define FN_BF16_MIXED 2

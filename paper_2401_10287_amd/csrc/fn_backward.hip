@@ -243,30 +243,40 @@ __global__ __launch_bounds__(256) void k_bwd_gh(const T *__restrict__ Gh, const 
 }
 
 // ---------------------------------------------------------------------------
-// pair stream adjoint: one workgroup per (walker, electron i) recomputes the
-// pair activations h_ij^l, then runs back through the pair layers with the
-// adjoints of the spin means g_i^l (GGI, ld ldg, columns [up | dn]) and
-// writes its share of dW2, dc2 (PP row, layout of theta from W2_0 on).
+// pair stream adjoint: a workgroup takes WB consecutive (walker, electron i),
+// recomputes their pair activations h_ij^l, runs back through the pair layers
+// with the adjoints of the spin means g_i^l (GGI, ld ldg, columns [up | dn])
+// and writes the summed share of dW2, dc2 of its rows (one PP row per
+// workgroup, layout of theta from W2_0 on; rows summed in a fixed order).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_pair_backward(Sys s, const double *x, const T *theta, ParamLayout P, int64_t B, const T *GGI,
-                                int64_t ldg, int64_t gg_layer_stride, T *PP, int64_t npp)
+__global__ __launch_bounds__(256) void k_pair_backward(Sys s, const double *x, const T *theta, ParamLayout P, int64_t B,
+                                                       const T *GGI, int64_t ldg, int64_t gg_layer_stride, int WB,
+                                                       T *PP, int64_t npp)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int wp = s.w2 > 4 ? s.w2 : 4;
     const int N = s.N, L = s.L;
-    T *Hs = (T *)smem_raw;                    // [L][N][wp] pair activations
-    T *Ts = Hs + (size_t)L * N * wp;          // [L][N][wp] tanh outputs of the pair layers (index l = layer output)
-    T *G0 = Ts + (size_t)L * N * wp;          // [N][wp]
-    T *G1 = G0 + (size_t)N * wp;              // [N][wp]
-    const int64_t wi = blockIdx.x;
-    const int64_t w = wi / N;
-    const int i = (int)(wi % N);
-    if (w >= B) return;
-    const double *xw = x + w * 3 * N;
-    for (int j = threadIdx.x; j < N; j += blockDim.x) {
-        T *p = Hs + j * wp;
-        for (int q = 0; q < wp; ++q) p[q] = T(0);
+    const int per = (2 * L + 2) * N * wp;     // one (walker, electron) row
+    // pair weights and biases (theta from W2_0 on) staged after the rows
+    T *Wsm = (T *)smem_raw + (size_t)WB * per;
+    const int64_t npw = L > 1 ? P.c2[L - 2] + s.w2 - P.W2[0] : 0;
+    for (int64_t q = threadIdx.x; q < npw; q += blockDim.x) Wsm[q] = theta[P.W2[0] + q];
+    const int64_t wi0 = (int64_t)blockIdx.x * WB;
+    const int nwi = B * N - wi0 < WB ? (int)(B * N - wi0) : WB;
+    // per row: Hs [L][N][wp] activations, Ts [L][N][wp] tanh outputs (index l =
+    // layer output), G0 / G1 [N][wp] adjoints
+    auto Hs = [&](int bb, int l, int j) { return (T *)smem_raw + (size_t)bb * per + ((size_t)l * N + j) * wp; };
+    auto Ts = [&](int bb, int l, int j) { return (T *)smem_raw + (size_t)bb * per + ((size_t)(L + l) * N + j) * wp; };
+    auto Gb = [&](int bb, int q, int j) { return (T *)smem_raw + (size_t)bb * per + ((size_t)(2 * L + q) * N + j) * wp; };
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int q = tid; q < nwi * N; q += nt) {
+        const int bb = q / N, j = q % N;
+        const int64_t wi = wi0 + bb, w = wi / N;
+        const int i = (int)(wi % N);
+        const double *xw = x + w * 3 * N;
+        T *p = Hs(bb, 0, j);
+        for (int e = 0; e < wp; ++e) p[e] = T(0);
         if (j != i) {
             const double d0 = xw[3 * i] - xw[3 * j], d1 = xw[3 * i + 1] - xw[3 * j + 1], d2 = xw[3 * i + 2] - xw[3 * j + 2];
             p[0] = (T)d0; p[1] = (T)d1; p[2] = (T)d2;
@@ -276,65 +286,66 @@ __global__ void k_pair_backward(Sys s, const double *x, const T *theta, ParamLay
     __syncthreads();
     for (int l = 0; l + 1 < L; ++l) {
         const int dp = l == 0 ? 4 : s.w2;
-        const T *W2 = theta + P.W2[l];
-        const T *c2 = theta + P.c2[l];
-        for (int idx = threadIdx.x; idx < N * s.w2; idx += blockDim.x) {
-            const int j = idx / s.w2, o = idx % s.w2;
-            const T *in = Hs + ((size_t)l * N + j) * wp;
+        const T *W2 = Wsm + (P.W2[l] - P.W2[0]);
+        const T *c2 = Wsm + (P.c2[l] - P.W2[0]);
+        for (int q = tid; q < nwi * N * s.w2; q += nt) {
+            const int o = q % s.w2, bj = q / s.w2, j = bj % N, bb = bj / N;
+            const T *in = Hs(bb, l, j);
             T z = c2[o];
             for (int k = 0; k < dp; ++k) z += in[k] * W2[k * s.w2 + o];
             const T t = tanh(z);
-            Ts[((size_t)(l + 1) * N + j) * wp + o] = t;
-            Hs[((size_t)(l + 1) * N + j) * wp + o] = t + (l >= 1 ? in[o] : T(0));
+            Ts(bb, l + 1, j)[o] = t;
+            Hs(bb, l + 1, j)[o] = t + (l >= 1 ? in[o] : T(0));
         }
         __syncthreads();
     }
-    // adjoint of the top pair state from the top layer's spin means
     const int nu = s.nu, nd = s.nd;
-    auto mean_adj = [&](int l, int j, int o) -> T {
+    auto mean_adj = [&](int bb, int l, int j, int o) -> T {
         const int dp = l == 0 ? 4 : s.w2;
         if (o >= dp) return T(0);
         const int spj = j < nu ? 0 : 1;
         const int n = spj == 0 ? nu : nd;
-        return GGI[(int64_t)l * gg_layer_stride + wi * ldg + spj * dp + o] / T(n);
+        return GGI[(int64_t)l * gg_layer_stride + (wi0 + bb) * ldg + spj * dp + o] / T(n);
     };
-    T *Gc = G0, *Gn = G1;
-    for (int idx = threadIdx.x; idx < N * wp; idx += blockDim.x) Gc[idx] = mean_adj(L - 1, idx / wp, idx % wp);
+    // adjoint of the top pair state from the top layer's spin means (G0)
+    for (int q = tid; q < nwi * N * wp; q += nt) {
+        const int o = q % wp, bj = q / wp, j = bj % N, bb = bj / N;
+        Gb(bb, 0, j)[o] = mean_adj(bb, L - 1, j, o);
+    }
     __syncthreads();
-    T *pp = PP + wi * npp;
+    T *pp = PP + (int64_t)blockIdx.x * npp;
     for (int l = L - 1; l >= 1; --l) {
         // pair layer l - 1 maps h^{l-1} (width dp) to h^l (width w2)
         const int dp = l - 1 == 0 ? 4 : s.w2;
-        const T *W2 = theta + P.W2[l - 1];
-        // dz = G (1 - t^2), kept in Gn temporarily
-        for (int idx = threadIdx.x; idx < N * s.w2; idx += blockDim.x) {
-            const int j = idx / s.w2, o = idx % s.w2;
-            const T t = Ts[((size_t)l * N + j) * wp + o];
-            Gn[j * wp + o] = Gc[j * wp + o] * (T(1) - t * t);
+        const T *W2 = Wsm + (P.W2[l - 1] - P.W2[0]);
+        // dz = G (1 - t^2) into G1
+        for (int q = tid; q < nwi * N * s.w2; q += nt) {
+            const int o = q % s.w2, bj = q / s.w2, j = bj % N, bb = bj / N;
+            const T t = Ts(bb, l, j)[o];
+            Gb(bb, 1, j)[o] = Gb(bb, 0, j)[o] * (T(1) - t * t);
         }
         __syncthreads();
-        // dW2[k][o] = sum_j h^{l-1}[j][k] dz[j][o], dc2[o] = sum_j dz[j][o]
+        // dW2[k][o] = sum over the rows and pairs of h^{l-1}[k] dz[o], dc2[o] = sum dz[o]
         const int64_t wof = P.W2[l - 1] - P.W2[0], cof = P.c2[l - 1] - P.W2[0];
-        for (int idx = threadIdx.x; idx < (dp + 1) * s.w2; idx += blockDim.x) {
-            const int k = idx / s.w2, o = idx % s.w2;
+        for (int q = tid; q < (dp + 1) * s.w2; q += nt) {
+            const int k = q / s.w2, o = q % s.w2;
             T acc = T(0);
-            if (k < dp)
-                for (int j = 0; j < N; ++j) acc += Hs[((size_t)(l - 1) * N + j) * wp + k] * Gn[j * wp + o];
-            else
-                for (int j = 0; j < N; ++j) acc += Gn[j * wp + o];
+            for (int bb = 0; bb < nwi; ++bb)
+                for (int j = 0; j < N; ++j) acc += (k < dp ? Hs(bb, l - 1, j)[k] : T(1)) * Gb(bb, 1, j)[o];
             pp[k < dp ? wof + (int64_t)k * s.w2 + o : cof + o] = acc;
         }
-        // adjoint of h^{l-1}: dz W2^T + residual + spin-mean part
+        // adjoint of h^{l-1}: dz W2^T + residual + spin-mean part (into G0)
         __syncthreads();
-        for (int idx = threadIdx.x; idx < N * wp; idx += blockDim.x) {
-            const int j = idx / wp, k = idx % wp;
+        for (int q = tid; q < nwi * N * wp; q += nt) {
+            const int k = q % wp, bj = q / wp, j = bj % N, bb = bj / N;
             T v = T(0);
             if (k < dp) {
-                for (int o = 0; o < s.w2; ++o) v += Gn[j * wp + o] * W2[k * s.w2 + o];
-                if (l - 1 >= 1) v += Gc[j * wp + k];
-                v += mean_adj(l - 1, j, k);
+                const T *dz = Gb(bb, 1, j);
+                for (int o = 0; o < s.w2; ++o) v += dz[o] * W2[k * s.w2 + o];
+                if (l - 1 >= 1) v += Gb(bb, 0, j)[k];
+                v += mean_adj(bb, l - 1, j, k);
             }
-            Gc[idx] = v;   // safe: every thread reads only Gn and its own Gc entry
+            Gb(bb, 0, j)[k] = v;   // a thread reads only G1 and its own G0 entry
         }
         __syncthreads();
     }
@@ -500,18 +511,34 @@ void launch_bwd_gh(const T *Gh, const T *Gy, const T *Gg, int64_t B, int N, int 
     hipLaunchKernelGGL(k_bwd_gh<T>, dim3((unsigned)(B * N)), dim3(256), 0, st, Gh, Gy, Gg, N, nu, dh, w1, resid, Gout);
 }
 
-size_t pair_backward_lds(const Sys &s, size_t elem)
+static size_t pair_backward_lds_wb(const Sys &s, size_t elem, int wb)
 {
     const int wp = s.w2 > 4 ? s.w2 : 4;
-    return ((size_t)2 * s.L * s.N * wp + 2 * (size_t)s.N * wp) * elem;
+    const ParamLayout P = make_layout(s);
+    const size_t npw = s.L > 1 ? (size_t)(P.c2[s.L - 2] + s.w2 - P.W2[0]) : 0;
+    return ((size_t)wb * (2 * (size_t)s.L + 2) * s.N * wp + npw) * elem;
+}
+
+size_t pair_backward_lds(const Sys &s, size_t elem) { return pair_backward_lds_wb(s, elem, 1); }
+
+// (walker, electron) rows per workgroup: about 256 (pair, column) items,
+// within 64 KiB of LDS
+int pair_backward_wb(const Sys &s, size_t elem)
+{
+    const int items = s.N * s.w2;
+    int wb = items >= 256 ? 1 : 256 / items;
+    while (wb > 1 && pair_backward_lds_wb(s, elem, wb) > 64 * 1024) --wb;
+    return wb;
 }
 
 template <typename T>
 void launch_pair_backward(const Sys &s, const double *x, const T *theta, const ParamLayout &P, int64_t B, const T *GGI,
                           int64_t ldg, int64_t gg_layer_stride, T *PP, int64_t npp, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pair_backward<T>, dim3((unsigned)(B * s.N)), dim3(256), pair_backward_lds(s, sizeof(T)), st, s,
-                       x, theta, P, B, GGI, ldg, gg_layer_stride, PP, npp);
+    const int wb = pair_backward_wb(s, sizeof(T));
+    hipLaunchKernelGGL(k_pair_backward<T>, dim3((unsigned)((B * s.N + wb - 1) / wb)), dim3(256),
+                       pair_backward_lds_wb(s, sizeof(T), wb), st, s, x, theta, P, B, GGI, ldg, gg_layer_stride, wb,
+                       PP, npp);
 }
 
 int tn_splits(int64_t R)

@@ -49,6 +49,7 @@ template <typename T>
 void launch_bwd_gh(const T *Gh, const T *Gy, const T *Gg, int64_t B, int N, int nu, int dh, int w1, int resid, T *Gout,
                    hipStream_t st);
 size_t pair_backward_lds(const Sys &s, size_t elem);
+int pair_backward_wb(const Sys &s, size_t elem);      // (walker, electron) rows per workgroup
 template <typename T>
 void launch_pair_backward(const Sys &s, const double *x, const T *theta, const ParamLayout &P, int64_t B, const T *GGI,
                           int64_t ldg, int64_t gg_layer_stride, T *PP, int64_t npp, hipStream_t st);
@@ -79,6 +80,7 @@ template <typename T>
 void launch_bwd_gh(const T *Gh, const T *Gy, const T *Gg, int64_t B, int N, int nu, int dh, int w1, int resid, T *Gout,
                    hipStream_t st);
 size_t pair_backward_lds(const Sys &s, size_t elem);
+int pair_backward_wb(const Sys &s, size_t elem);      // (walker, electron) rows per workgroup
 template <typename T>
 void launch_pair_backward(const Sys &s, const double *x, const T *theta, const ParamLayout &P, int64_t B, const T *GGI,
                           int64_t ldg, int64_t gg_layer_stride, T *PP, int64_t npp, hipStream_t st);

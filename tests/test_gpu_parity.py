@@ -289,3 +289,21 @@ def test_log_psi_spin_sizes(prec, tol):
         _check_logpsi(lp.cpu().numpy(), ref, tol, f"Z={z} ({s.n_up},{s.n_dn}) {prec}", _conditioning(o, s, th, x),
                       prec == "fp64")
         np.testing.assert_array_equal(sg.cpu().numpy(), ref["sign"])
+
+
+def test_log_psi_full_size_sampled():
+    """Value rows at the Metropolis batch sizes: H20 with 8192 walkers (the
+    128-column layer tiles) and LiH with 4096 (32-column tiles for grids that
+    would leave CUs idle), each checked on sampled walkers against the oracle."""
+    for name, walkers in (("H20", 8192), ("LiH", 4096)):
+        s = SYSTEMS[name]()
+        idx = np.random.default_rng(9).choice(walkers, 16, replace=False)
+        for prec in ("fp32", "bf16x6"):
+            torch, fnvmc, cfg, tt, xt, th, x = _setup(s, prec, walkers)
+            lp, sg = fnvmc.fn_log_psi(cfg, tt, xt)
+            torch.cuda.synchronize()
+            o = O.Oracle(s)
+            ref = o.log_psi(th, x[idx])
+            _check_logpsi(lp.cpu().numpy()[idx], ref, 1e-5, f"{name} {walkers} {prec} sampled",
+                          _conditioning(o, s, th, x[idx]), False)
+            np.testing.assert_array_equal(sg.cpu().numpy()[idx], ref["sign"])
