@@ -45,6 +45,7 @@ const char *const kclass_names[K_NCLASS] = {"stream_gemm", "walker_gemm", "head_
 struct TimeRec { int cls; hipEvent_t a, b; };
 std::mutex g_tmu;
 bool g_timing = false;
+int g_timing_only = -1;            // record one class only (-1: every class)
 std::vector<TimeRec> g_recs;
 std::vector<hipEvent_t> g_free_events;
 double g_tot_ms[K_NCLASS];
@@ -69,7 +70,7 @@ struct Timed {
     hipEvent_t a = nullptr;
     Timed(int c, hipStream_t s) : cls(c), st(s)
     {
-        if (!g_timing) return;
+        if (!g_timing || (g_timing_only >= 0 && c != g_timing_only)) return;
         std::lock_guard<std::mutex> lk(g_tmu);
         a = take_event();
         if (a) (void)hipEventRecord(a, st);
@@ -302,14 +303,37 @@ void pack_weights(const Ctx &c, const Plan &p, const T *theta, char *ws, hipStre
 {
     Timed t_(K_PACK, st);
     const Sys &s = c.s;
-    for (int l = 0; l < s.L; ++l)
-        launch_pack_layer<T>(theta, c.P.V[l], layer_dh(s, l), layer_dp(s, l), s.w1, c.W.HWl[l], c.W.GWl[l], c.smode,
-                             ws + p.wx[l], ws + p.wg[l], st);
+    PackList pl{};
+    int64_t begin = 0;
+    auto add = [&](const PackSeg &g) {
+        pl.seg[pl.n] = g;
+        pl.seg[pl.n].begin = begin;
+        begin += g.count;
+        ++pl.n;
+    };
+    for (int l = 0; l < s.L; ++l) {
+        PackSeg g{};
+        g.kind = 0; g.mode = c.smode; g.off = c.P.V[l];
+        g.dh = layer_dh(s, l); g.dp = layer_dp(s, l); g.w1 = s.w1; g.HWl = c.W.HWl[l]; g.GWl = c.W.GWl[l];
+        g.count = (int64_t)s.w1 * (g.HWl + g.GWl) + (int64_t)s.w1 * 2 * g.HWl;
+        g.d0 = ws + p.wx[l]; g.d1 = ws + p.wg[l];
+        add(g);
+    }
     for (int sp = 0; sp < 2; ++sp) {
-        int n = sp == 0 ? s.nu : s.nd;
+        const int n = sp == 0 ? s.nu : s.nd;
         if (n == 0) continue;
-        launch_pack_head<T>(theta, c.P.w[sp], s.w1, c.W.W1p, s.K * n, c.hmode, ws + p.wh[sp], st);
-        if (p.save) launch_pack_head_bwd<T>(theta, c.P.w[sp], s.w1, s.K * n, c.W.KNp[sp], (T *)(ws + p.wb[sp]), st);
+        PackSeg g{};
+        g.kind = 1; g.mode = c.hmode; g.off = c.P.w[sp];
+        g.w1 = s.w1; g.W1p = c.W.W1p; g.kn = s.K * n;
+        g.count = (int64_t)g.kn * g.W1p;
+        g.d0 = ws + p.wh[sp];
+        add(g);
+    }
+    launch_pack<T>(theta, pl, st);
+    for (int sp = 0; sp < 2; ++sp) {
+        const int n = sp == 0 ? s.nu : s.nd;
+        if (n > 0 && p.save)
+            launch_pack_head_bwd<T>(theta, c.P.w[sp], s.w1, s.K * n, c.W.KNp[sp], (T *)(ws + p.wb[sp]), st);
     }
 }
 
@@ -747,6 +771,21 @@ fn_status fn_timing_enable(int32_t on)
     std::lock_guard<std::mutex> lk(g_tmu);
     g_timing = on != 0;
     return FN_OK;
+}
+
+fn_status fn_timing_select(const char *name)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!name) {
+        g_timing_only = -1;
+        return FN_OK;
+    }
+    for (int k = 0; k < K_NCLASS; ++k)
+        if (strcmp(name, kclass_names[k]) == 0) {
+            g_timing_only = k;
+            return FN_OK;
+        }
+    return fail(FN_EINVAL, std::string("unknown kernel class ") + name);
 }
 
 fn_status fn_timing_reset(void)

@@ -5,11 +5,21 @@
 
 namespace fn {
 
+// Packing of the forward operands from the flat parameter vector: one
+// segment per layer (kind 0: per-electron block Wx into d0, per-walker block
+// Wg into d1) and per spin head (kind 1: Wh into d0), in the product's
+// operand type (mode); segment q covers elements [begin, begin + count).
+struct PackSeg {
+    int64_t begin, count, off;
+    int kind, mode, dh, dp, w1, HWl, GWl, kn, W1p;
+    void *d0, *d1;
+};
+struct PackList {
+    int n;
+    PackSeg seg[FN_MAX_LAYERS + 2];
+};
 template <typename T>
-void launch_pack_layer(const T *theta, int64_t voff, int dh, int dp, int w1, int HWl, int GWl, int mode, void *wx,
-                       void *wg, hipStream_t st);
-template <typename T>
-void launch_pack_head(const T *theta, int64_t woff, int w1, int W1p, int kn, int mode, void *wh, hipStream_t st);
+void launch_pack(const T *theta, const PackList &pl, hipStream_t st);
 template <typename T>
 void launch_features(const Sys &s, const double *x, int64_t B, int TR, int HW0, int64_t ldh, T *H, hipStream_t st);
 size_t pair_stream_lds(const Sys &s, bool fl, size_t elem);

@@ -35,43 +35,52 @@ __device__ inline void put_w(int mode, void *base, int64_t part, int64_t idx, T 
     }
 }
 
-// Wx [w1][HWl + GWl]: per-electron inputs [h_i | g_i_up | g_i_dn];
-// Wg [w1][2 HWl]: per-walker inputs [g_up | g_dn].
+// Element t of a layer block.  Wx [w1][HWl + GWl]: per-electron inputs
+// [h_i | g_i_up | g_i_dn]; Wg [w1][2 HWl]: per-walker inputs [g_up | g_dn].
 template <typename T>
-__global__ void k_pack_layer(const T *theta, int64_t voff, int dh, int dp, int w1, int HWl, int GWl, int mode,
-                             void *wx, void *wg)
+__device__ inline void pack_layer_elem(const T *theta, const PackSeg &g, int64_t t)
 {
-    const int64_t kx = HWl + GWl, kg = 2 * HWl;
-    const int64_t nx = (int64_t)w1 * kx, ng = (int64_t)w1 * kg;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nx + ng; t += (int64_t)gridDim.x * blockDim.x) {
-        if (t < nx) {
-            int o = (int)(t / kx), k = (int)(t % kx);
-            int row = -1;
-            if (k < dh) row = k;
-            else if (k >= HWl && k < HWl + 2 * dp) row = 3 * dh + (k - HWl);
-            T v = row >= 0 ? theta[voff + (int64_t)row * w1 + o] : T(0);
-            put_w<T>(mode, wx, nx, t, v);
-        } else {
-            int64_t u = t - nx;
-            int o = (int)(u / kg), k = (int)(u % kg);
-            int row = -1;
-            if (k < dh) row = dh + k;
-            else if (k >= HWl && k < HWl + dh) row = 2 * dh + (k - HWl);
-            T v = row >= 0 ? theta[voff + (int64_t)row * w1 + o] : T(0);
-            put_w<T>(mode, wg, ng, u, v);
-        }
+    const int64_t kx = g.HWl + g.GWl, kg = 2 * g.HWl;
+    const int64_t nx = (int64_t)g.w1 * kx, ng = (int64_t)g.w1 * kg;
+    if (t < nx) {
+        const int o = (int)(t / kx), k = (int)(t % kx);
+        int row = -1;
+        if (k < g.dh) row = k;
+        else if (k >= g.HWl && k < g.HWl + 2 * g.dp) row = 3 * g.dh + (k - g.HWl);
+        const T v = row >= 0 ? theta[g.off + (int64_t)row * g.w1 + o] : T(0);
+        put_w<T>(g.mode, g.d0, nx, t, v);
+    } else {
+        const int64_t u = t - nx;
+        const int o = (int)(u / kg), k = (int)(u % kg);
+        int row = -1;
+        if (k < g.dh) row = g.dh + k;
+        else if (k >= g.HWl && k < g.HWl + g.dh) row = 2 * g.dh + (k - g.HWl);
+        const T v = row >= 0 ? theta[g.off + (int64_t)row * g.w1 + o] : T(0);
+        put_w<T>(g.mode, g.d1, ng, u, v);
     }
 }
 
-// Wh [K n][W1p] from w [w1][K n]
+// Element t of a head block: Wh [K n][W1p] from w [w1][K n]
 template <typename T>
-__global__ void k_pack_head(const T *theta, int64_t woff, int w1, int W1p, int kn, int mode, void *wh)
+__device__ inline void pack_head_elem(const T *theta, const PackSeg &g, int64_t t)
 {
-    const int64_t n = (int64_t)kn * W1p;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-        int col = (int)(t / W1p), k = (int)(t % W1p);
-        T v = k < w1 ? theta[woff + (int64_t)k * kn + col] : T(0);
-        put_w<T>(mode, wh, n, t, v);
+    const int64_t n = (int64_t)g.kn * g.W1p;
+    const int col = (int)(t / g.W1p), k = (int)(t % g.W1p);
+    const T v = k < g.w1 ? theta[g.off + (int64_t)k * g.kn + col] : T(0);
+    put_w<T>(g.mode, g.d0, n, t, v);
+}
+
+// every forward operand block in one launch; segment q covers the element
+// range [begin_q, begin_q + count_q) of one index space
+template <typename T>
+__global__ void k_pack(const T *theta, PackList pl, int64_t total)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        int q = 0;
+        while (q + 1 < pl.n && i >= pl.seg[q + 1].begin) ++q;
+        const PackSeg &g = pl.seg[q];
+        if (g.kind == 0) pack_layer_elem<T>(theta, g, i - g.begin);
+        else pack_head_elem<T>(theta, g, i - g.begin);
     }
 }
 
@@ -1057,19 +1066,11 @@ static unsigned grid_for(int64_t n, int bs = 256)
 }
 
 template <typename T>
-void launch_pack_layer(const T *theta, int64_t voff, int dh, int dp, int w1, int HWl, int GWl, int mode, void *wx,
-                       void *wg, hipStream_t st)
+void launch_pack(const T *theta, const PackList &pl, hipStream_t st)
 {
-    int64_t n = (int64_t)w1 * (HWl + GWl) + (int64_t)w1 * 2 * HWl;
-    hipLaunchKernelGGL(k_pack_layer<T>, dim3(grid_for(n)), dim3(256), 0, st, theta, voff, dh, dp, w1, HWl, GWl, mode,
-                       wx, wg);
-}
-
-template <typename T>
-void launch_pack_head(const T *theta, int64_t woff, int w1, int W1p, int kn, int mode, void *wh, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_pack_head<T>, dim3(grid_for((int64_t)kn * W1p)), dim3(256), 0, st, theta, woff, w1, W1p, kn,
-                       mode, wh);
+    if (pl.n <= 0) return;
+    const int64_t total = pl.seg[pl.n - 1].begin + pl.seg[pl.n - 1].count;
+    hipLaunchKernelGGL(k_pack<T>, dim3(grid_for(total)), dim3(256), 0, st, theta, pl, total);
 }
 
 template <typename T>
@@ -1251,9 +1252,7 @@ void launch_combine(const Sys &s, const double *x, const double *DR, int rec, in
 }
 
 #define FN_INST(T)                                                                                                  \
-    template void launch_pack_layer<T>(const T *, int64_t, int, int, int, int, int, int, void *, void *,            \
-                                       hipStream_t);                                                                \
-    template void launch_pack_head<T>(const T *, int64_t, int, int, int, int, void *, hipStream_t);                 \
+    template void launch_pack<T>(const T *, const PackList &, hipStream_t);                                          \
     template void launch_features<T>(const Sys &, const double *, int64_t, int, int, int64_t, T *, hipStream_t);    \
     template void launch_pair_stream<T>(const Sys &, const double *, const T *, const ParamLayout &, int64_t, int,   \
                                         bool, int64_t, int64_t, int, int, T *, hipStream_t);                        \

@@ -64,6 +64,8 @@ def _load():
     lib.fn_last_error.argtypes = []
     lib.fn_timing_enable.restype = i32
     lib.fn_timing_enable.argtypes = [i32]
+    lib.fn_timing_select.restype = i32
+    lib.fn_timing_select.argtypes = [ctypes.c_char_p]
     lib.fn_timing_reset.restype = i32
     lib.fn_timing_reset.argtypes = []
     lib.fn_timing_read.restype = i32
@@ -78,7 +80,7 @@ LIB_PATH = _LIB_PATH
 
 EXPORTED = ["fn_param_count", "fn_workspace_bytes", "fn_log_psi", "fn_local_energy", "vmc_metropolis_step",
             "vmc_metropolis_step_ext", "fn_param_grad", "fn_log_psi_vjp", "fn_last_error", "fn_timing_enable",
-            "fn_timing_reset", "fn_timing_read", "fn_tuning_set", "fn_server_job_bytes", "fn_server_create", "fn_server_submit",
+            "fn_timing_select", "fn_timing_reset", "fn_timing_read", "fn_tuning_set", "fn_server_job_bytes", "fn_server_create", "fn_server_submit",
             "fn_server_step", "fn_server_result", "fn_server_destroy", "fn_server_last_error"]
 KERNEL_CLASSES = ["stream_gemm", "walker_gemm", "head_gemm", "features", "pair_stream", "spin_mean", "layer_epilogue",
                   "envelope", "det", "combine", "pack", "propose", "accept", "backward"]
@@ -246,6 +248,11 @@ def fn_log_psi_vjp(cfg: Config, theta: torch.Tensor, x: torch.Tensor, coeff: tor
 
 def fn_timing_enable(on: bool) -> None:
     _check(LIB.fn_timing_enable(1 if on else 0))
+
+
+def fn_timing_select(name: Optional[str]) -> None:
+    """Record only the kernel class `name` while timing is enabled (None: every class)."""
+    _check(LIB.fn_timing_select(None if name is None else name.encode()))
 
 
 def fn_timing_reset() -> None:

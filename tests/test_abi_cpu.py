@@ -87,3 +87,12 @@ def test_server_job_footprint_host_side():
     b = serving.job_bytes(cfg, 4096)
     assert 0 < a < b
     assert b >= cfg.workspace_bytes(4096, fnvmc.FN_OP_LOCAL_ENERGY)
+
+
+def test_timing_class_names_checked_on_host():
+    fnvmc = _fnvmc()
+    assert fnvmc.LIB.fn_timing_select(b"no_such_kernel") == fnvmc.FN_EINVAL
+    assert b"no_such_kernel" in fnvmc.LIB.fn_last_error()
+    for k in fnvmc.KERNEL_CLASSES:
+        assert fnvmc.LIB.fn_timing_select(k.encode()) == fnvmc.FN_OK
+    assert fnvmc.LIB.fn_timing_select(None) == fnvmc.FN_OK
