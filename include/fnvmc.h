@@ -234,7 +234,11 @@ fn_status fn_timing_read(const char *name, double *total_ms, int64_t *launches);
    "fused_layer" 0/1: one-electron layers as one fused kernel (product +
    forward-Laplacian epilogue) where the row layout allows it, instead of a
    product kernel followed by an epilogue kernel.  Both give the same
-   arithmetic up to the order of the final additions. */
+   arithmetic up to the order of the final additions.
+   "pair_oc" 0/1/2/4: output columns per thread of the two-electron stream
+   kernel (0: chosen by N and w2).  "pair_items" 0..4096: (pair, column
+   group) items per workgroup of that kernel (0: chosen by the form); the
+   workgroup's LDS use caps it.  Neither changes the arithmetic. */
 fn_status fn_tuning_set(const char *name, int64_t value);
 
 #ifdef __cplusplus

@@ -763,6 +763,16 @@ fn_status fn_tuning_set(const char *name, int64_t value)
         fn::g_use_fused_layer = value != 0;
         return FN_OK;
     }
+    if (strcmp(name, "pair_oc") == 0) {
+        if (value != 0 && value != 1 && value != 2 && value != 4) return fail(FN_EINVAL, "pair_oc: 0, 1, 2 or 4");
+        fn::g_pair_oc = (int)value;
+        return FN_OK;
+    }
+    if (strcmp(name, "pair_items") == 0) {
+        if (value < 0 || value > 4096) return fail(FN_EINVAL, "pair_items: 0..4096");
+        fn::g_pair_items = (int)value;
+        return FN_OK;
+    }
     return fail(FN_EINVAL, std::string("unknown tuning switch ") + name);
 }
 

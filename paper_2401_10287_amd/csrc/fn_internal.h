@@ -177,6 +177,9 @@ struct LayerArgs {
 
 bool stream_layer_supported(int mode, int TR, int w1, int W1p);
 extern bool g_use_fused_layer;
+// pair-stream launch shape: output columns per thread (0: by size) and
+// (pair, column group) items per workgroup (0: by form)
+extern int g_pair_oc, g_pair_items;
 void launch_stream_layer(int mode, const LayerArgs &a, int TR, hipStream_t st);
 // 128-row tiles of the fused layer hold whole walkers
 inline bool stream_layer_whole_walkers(int N, int TR) { return N * TR <= 128 && 128 % (N * TR) == 0; }

@@ -133,6 +133,47 @@ __device__ void write_pair_means(const Sys &s, const T *S, int wp, int ps, int d
     constexpr int R = FL ? 8 : 1;
     const int n3 = 3 * s.N;
     const int rows = FL ? TR : 1;
+    if constexpr (std::is_same<T, float>::value) {
+        if (dp % 4 == 0) {
+            // a thread keeps four columns of one spin block (float4 reads of
+            // the 16-byte aligned pair rows, float4 stores) and walks rows
+            const int cqn = GWl / 4, tstep = blockDim.x / cqn;
+            if ((int)threadIdx.x >= tstep * cqn) return;
+            const int col = 4 * ((int)threadIdx.x % cqn);
+            const bool live = col < 2 * dp;
+            const int sp = live ? col / dp : 0, o = live ? col - sp * dp : 0;
+            const int n = sp == 0 ? s.nu : s.nd, j0 = sp == 0 ? 0 : s.nu;
+            const float inv = n > 0 ? 1.f / (float)n : 0.f;
+            auto ld4 = [&](int j, int r) { return *(const float4 *)(S + j * ps + r * wp + o); };
+            for (int t = threadIdx.x / cqn; t < rows; t += tstep) {
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (live && n > 0 && t <= n3 + 1) {
+                    int r = -1;                   // summed row of every pair of the spin, or -1
+                    int e = -1;                   // single pair (i, e) for another electron's direction
+                    if (t == 0 || t == n3 + 1) {
+                        r = t == 0 ? 0 : R - 1;
+                    } else {
+                        const int c = t - 1, ee = c / 3, a = c - 3 * ee;
+                        if (ee == i) r = 1 + a;
+                        else if (ee >= j0 && ee < j0 + n) { e = ee; r = 4 + a; }
+                    }
+                    if (e >= 0) {
+                        const float4 q = ld4(e, r);
+                        v = make_float4(q.x * inv, q.y * inv, q.z * inv, q.w * inv);
+                    } else if (r >= 0) {
+                        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+                        for (int j = j0; j < j0 + n; ++j) {
+                            const float4 q = ld4(j, r);
+                            acc.x += q.x; acc.y += q.y; acc.z += q.z; acc.w += q.w;
+                        }
+                        v = make_float4(acc.x * inv, acc.y * inv, acc.z * inv, acc.w * inv);
+                    }
+                }
+                *(float4 *)(gi + (int64_t)t * ldg + col) = v;
+            }
+            return;
+        }
+    }
     // a thread keeps one column and walks rows; the first (blockDim / GWl) GWl threads take part
     const int tstep = blockDim.x / GWl;
     if ((int)threadIdx.x >= tstep * GWl) return;
@@ -204,6 +245,15 @@ __device__ inline void lds_st<float, 2>(float *p, const float (&v)[2])
 {
     *(float2 *)p = make_float2(v[0], v[1]);
 }
+
+// explicit fused multiply-add, so that every launch shape of the pair kernel
+// rounds alike
+template <typename T>
+__device__ inline T fmat(T a, T b, T c);
+template <>
+__device__ inline float fmat<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <>
+__device__ inline double fmat<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // padded pair-weight block of layer l in LDS: [dp4][w2p] then bias [w2p]
 __host__ __device__ inline int pair_w_offset(const Sys &s, int l)
@@ -303,7 +353,7 @@ __global__ __launch_bounds__(256) void k_pair_stream(Sys s, const double *x, con
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-                        for (int c = 0; c < OC; ++c) acc[r][c] += xv[kk] * wv[kk][c];
+                        for (int c = 0; c < OC; ++c) acc[r][c] = fmat(xv[kk], wv[kk][c], acc[r][c]);
                 }
             }
             T *out = S1 + (int64_t)bb * per + j * ps;
@@ -311,7 +361,7 @@ __global__ __launch_bounds__(256) void k_pair_stream(Sys s, const double *x, con
 #pragma unroll
             for (int c = 0; c < OC; ++c) {
                 y0[c] = tanh(acc[0][c]);
-                dd[c] = T(1) - y0[c] * y0[c];
+                dd[c] = fmat(-y0[c], y0[c], T(1));
                 src[c] = T(0);
             }
             // rows stored OC columns at a time; residual rows read likewise
@@ -327,10 +377,11 @@ __global__ __launch_bounds__(256) void k_pair_stream(Sys s, const double *x, con
                     if (r == 0) {
                         v[c] = y0[c] + res[c];
                     } else if (r < 7) {
-                        src[c] += acc[r][c] * acc[r][c];
-                        v[c] = dd[c] * acc[r][c] + res[c];
+                        src[c] = fmat(acc[r][c], acc[r][c], src[c]);
+                        v[c] = fmat(dd[c], acc[r][c], res[c]);
                     } else {
-                        v[c] = dd[c] * acc[R - 1][c] - T(2) * y0[c] * dd[c] * src[c] + res[c];
+                        const T q = T(-2) * y0[c] * dd[c];
+                        v[c] = fmat(dd[c], acc[R - 1][c], fmat(q, src[c], res[c]));
                     }
                 }
                 lds_st<T, OC>(out + r * wp + o0, v);
@@ -1090,20 +1141,23 @@ static size_t pair_stream_lds_wb(const Sys &s, bool fl, size_t elem, int WB)
 size_t pair_stream_lds(const Sys &s, bool fl, size_t elem) { return pair_stream_lds_wb(s, fl, elem, 1); }
 
 // Output columns per thread (1, 2 or 4) and (walker, electron) rows per
-// workgroup: about 256 (pair, column group) items (1024 in value-only form),
-// within 64 KiB of LDS.
-static int pair_stream_oc(const Sys &s)
+// workgroup: about 256 (pair, column group) items, within 64 KiB of LDS.  The
+// forward-Laplacian form takes fewer columns per thread for small N * w2
+// (more threads share the LDS rows of a pair); the value form takes 4.
+int g_pair_oc = 0, g_pair_items = 0;
+
+static int pair_stream_oc(const Sys &s, bool fl)
 {
+    if (g_pair_oc) return g_pair_oc;
+    if (!fl) return 4;                                    // value rows: fewest LDS reads per product
     const int w2p = round_up(s.w2, 4);
     return s.N * w2p <= 256 ? 1 : (s.N * w2p <= 512 ? 2 : 4);
 }
 
 static int pair_stream_wb(const Sys &s, bool fl, size_t elem)
 {
-    // value rows only: a few items per thread, so the weight staging is shared
-    // by more rows
-    const int target = fl ? 256 : 1024;
-    const int items = s.N * (round_up(s.w2, 4) / pair_stream_oc(s));
+    const int target = g_pair_items ? g_pair_items : 256;
+    const int items = s.N * (round_up(s.w2, 4) / pair_stream_oc(s, fl));
     int wb = items >= target ? 1 : target / items;
     while (wb > 1 && pair_stream_lds_wb(s, fl, elem, wb) > 64 * 1024) --wb;
     return wb;
@@ -1116,7 +1170,7 @@ static void launch_pair_oc(const Sys &s, const double *x, const T *theta, const 
     const int wb = pair_stream_wb(s, FL, sizeof(T));
     const size_t lds = pair_stream_lds_wb(s, FL, sizeof(T), wb);
     dim3 grid((unsigned)((B * s.N + wb - 1) / wb));
-    switch (pair_stream_oc(s)) {
+    switch (pair_stream_oc(s, FL)) {
     case 1:
         hipLaunchKernelGGL((k_pair_stream<T, FL, 1>), grid, dim3(256), lds, st, s, x, theta, P, B, TR, ldg,
                            gi_layer_stride, GW0, GW1, wb, GI);

@@ -274,6 +274,36 @@ def test_fused_and_separate_layer_paths(name, prec, walkers):
         fnvmc.fn_tuning_set("fused_layer", 1)
 
 
+@pytest.mark.parametrize("name,walkers", [("LiH", 61), ("LiF", 13)])
+def test_pair_launch_shapes_bitwise(name, walkers):
+    """The two-electron stream kernel's launch shape (output columns per
+    thread, rows per workgroup) does not change its arithmetic: local
+    energies and log|psi| are bitwise equal over every shape, and the
+    default shape is within the oracle bounds."""
+    s = SYSTEMS[name]()
+    torch, fnvmc, cfg, tt, xt, th, x = _setup(s, "bf16x6", walkers)
+    o = O.Oracle(s)
+    ref = None
+    try:
+        for oc, items in ((0, 0), (1, 0), (2, 0), (4, 0), (4, 64), (1, 512), (2, 1024)):
+            fnvmc.fn_tuning_set("pair_oc", oc)
+            fnvmc.fn_tuning_set("pair_items", items)
+            e, lp, _ = fnvmc.fn_local_energy(cfg, tt, xt)
+            lv, _ = fnvmc.fn_log_psi(cfg, tt, xt)
+            torch.cuda.synchronize()
+            got = (e.cpu().numpy(), lp.cpu().numpy(), lv.cpu().numpy())
+            if ref is None:
+                ref = got
+                _check_energy(got[0], None, o.local_energy(th, x), 1e-3, f"{name} default pair shape",
+                              _kappa_sum(o, th, x))
+            else:
+                for a, b in zip(got, ref):
+                    np.testing.assert_array_equal(a, b, err_msg=f"{name} pair_oc={oc} pair_items={items}")
+    finally:
+        fnvmc.fn_tuning_set("pair_oc", 0)
+        fnvmc.fn_tuning_set("pair_items", 0)
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
 def test_log_psi_spin_sizes(prec, tol):
     """Value-only determinant kernels for every spin size up to 10 (one
