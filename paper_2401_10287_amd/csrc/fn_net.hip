@@ -87,33 +87,54 @@ __global__ void k_pack(const T *theta, PackList pl, int64_t total)
 // ---------------------------------------------------------------------------
 // electron-nucleus input features [r_i - R_m, |r_i - R_m|] with their rows
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_features(Sys s, const double *x, int TR, int HW0, int64_t ldh, T *H)
+// four consecutive columns of a row (16-byte aligned)
+__device__ inline void store4(float *p, float a, float b, float c, float d) { *(float4 *)p = make_float4(a, b, c, d); }
+__device__ inline void store4(double *p, double a, double b, double c, double d)
 {
-    const int wi = blockIdx.x;              // walker * N + electron
-    const int i = wi % s.N;
+    ((double2 *)p)[0] = make_double2(a, b);
+    ((double2 *)p)[1] = make_double2(c, d);
+}
+
+// One item per (walker, electron, row t, nucleus m): the four columns
+// [r_i - R_m, |r_i - R_m|] of that row, the distance formed once in FP64.
+// Columns of m >= M (padding up to HW0) are zero.
+template <typename T>
+__global__ __launch_bounds__(256) void k_features(Sys s, const double *x, int64_t B, int TR, int HW0, int64_t ldh,
+                                                  T *H)
+{
+    const int mq = HW0 / 4;
     const int n3 = 3 * s.N;
-    const double *xi = x + (int64_t)wi * 3;
-    for (int q = threadIdx.x; q < TR * HW0; q += blockDim.x) {
-        const int t = q / HW0, k = q - t * HW0;
-        T v = T(0);
-        if (k < 4 * s.M && t <= n3 + 1) {
-            const int m = k >> 2, f = k & 3;
-            const double d0 = xi[0] - s.R[m][0], d1 = xi[1] - s.R[m][1], d2 = xi[2] - s.R[m][2];
-            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            if (t == 0) {
-                v = (T)(f == 0 ? d0 : (f == 1 ? d1 : (f == 2 ? d2 : r)));
-            } else if (t <= n3) {
-                const int c = t - 1, e = c / 3, a = c - 3 * e;
-                if (e == i) {
+    const int64_t total = B * s.N * TR * mq;
+    for (int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; it < total;
+         it += (int64_t)gridDim.x * blockDim.x) {
+        const int m = (int)(it % mq);
+        const int64_t row = it / mq;                  // (walker * N + electron) * TR + t
+        const int t = (int)(row % TR);
+        const int64_t wi = row / TR;
+        const int i = (int)(wi % s.N);
+        T v[4] = {T(0), T(0), T(0), T(0)};
+        if (m < s.M && t <= n3 + 1) {
+            int a = -1;                               // tangent row of this electron's coordinate a
+            if (t >= 1 && t <= n3) {
+                const int c = t - 1, e = c / 3;
+                if (e == i) a = c - 3 * e;
+            }
+            if (t == 0 || t == n3 + 1 || a >= 0) {
+                const double *xi = x + wi * 3;
+                const double d0 = xi[0] - s.R[m][0], d1 = xi[1] - s.R[m][1], d2 = xi[2] - s.R[m][2];
+                const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                if (t == 0) {
+                    v[0] = (T)d0; v[1] = (T)d1; v[2] = (T)d2; v[3] = (T)r;
+                } else if (t == n3 + 1) {
+                    v[3] = (T)(2.0 / r);
+                } else {
                     const double da = a == 0 ? d0 : (a == 1 ? d1 : d2);
-                    v = f == 3 ? (T)(da / r) : (f == a ? T(1) : T(0));
+                    v[a] = T(1);
+                    v[3] = (T)(da / r);
                 }
-            } else if (f == 3) {
-                v = (T)(2.0 / r);
             }
         }
-        H[((int64_t)wi * TR + t) * ldh + k] = v;
+        store4(H + row * ldh + 4 * m, v[0], v[1], v[2], v[3]);
     }
 }
 
@@ -398,20 +419,24 @@ __global__ __launch_bounds__(256) void k_pair_stream(Sys s, const double *x, con
 }
 
 // ---------------------------------------------------------------------------
-// spin means of the one-electron stream: G[w][t] = [g_up | g_dn]
+// spin means of the one-electron stream: G[w][t] = [g_up | g_dn]; one item
+// per (walker row, output column), FP32 rows four columns per item
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_spin_mean(const T *__restrict__ H, int64_t ldh, int N, int nu, int TR,
-                                                   int dh, int HWl, T *__restrict__ G)
+__global__ __launch_bounds__(256) void k_spin_mean(const T *__restrict__ H, int64_t ldh, int64_t B, int N, int nu,
+                                                   int TR, int dh, int HWl, T *__restrict__ G)
 {
     const int nd = N - nu;
-    const int wt = blockIdx.x;              // walker * TR + t
-    const int w = wt / TR, t = wt - w * TR;
-    const T *h0 = H + ((int64_t)w * N * TR + t) * ldh;
-    const int64_t jstride = (int64_t)TR * ldh;
-    T *g = G + (int64_t)wt * 2 * HWl;
     const T iu = nu > 0 ? T(1) / T(nu) : T(0), id = nd > 0 ? T(1) / T(nd) : T(0);
-    for (int col = threadIdx.x; col < 2 * HWl; col += blockDim.x) {
+    const int64_t total = B * TR * 2 * HWl;
+    for (int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; it < total;
+         it += (int64_t)gridDim.x * blockDim.x) {
+        const int col = (int)(it % (2 * HWl));
+        const int64_t wt = it / (2 * HWl);            // walker * TR + t
+        const int64_t w = wt / TR;
+        const int t = (int)(wt - w * TR);
+        const T *h0 = H + (w * N * TR + t) * ldh;
+        const int64_t jstride = (int64_t)TR * ldh;
         const int sp = col >= HWl, k = col - sp * HWl;
         T v = T(0);
         if (k < dh) {
@@ -419,24 +444,26 @@ __global__ __launch_bounds__(256) void k_spin_mean(const T *__restrict__ H, int6
             for (int j = j0; j < j1; ++j) v += h0[j * jstride + k];
             v *= sp ? id : iu;
         }
-        g[col] = v;
+        G[wt * 2 * HWl + col] = v;
     }
 }
 
-// FP32 rows, four columns per thread (HWl is a multiple of 32)
 template <>
-__global__ __launch_bounds__(256) void k_spin_mean<float>(const float *__restrict__ H, int64_t ldh, int N, int nu,
-                                                          int TR, int dh, int HWl, float *__restrict__ G)
+__global__ __launch_bounds__(256) void k_spin_mean<float>(const float *__restrict__ H, int64_t ldh, int64_t B, int N,
+                                                          int nu, int TR, int dh, int HWl, float *__restrict__ G)
 {
     const int nd = N - nu;
-    const int wt = blockIdx.x;
-    const int w = wt / TR, t = wt - w * TR;
-    const float *h0 = H + ((int64_t)w * N * TR + t) * ldh;
-    const int64_t jstride = (int64_t)TR * ldh;
-    float *g = G + (int64_t)wt * 2 * HWl;
     const float iu = nu > 0 ? 1.f / nu : 0.f, id = nd > 0 ? 1.f / nd : 0.f;
-    for (int c4 = threadIdx.x; c4 < HWl / 2; c4 += blockDim.x) {
-        const int col = 4 * c4;
+    const int cq = HWl / 2;                           // float4s in [g_up | g_dn] (HWl is a multiple of 32)
+    const int64_t total = B * TR * cq;
+    for (int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; it < total;
+         it += (int64_t)gridDim.x * blockDim.x) {
+        const int col = 4 * (int)(it % cq);
+        const int64_t wt = it / cq;
+        const int64_t w = wt / TR;
+        const int t = (int)(wt - w * TR);
+        const float *h0 = H + (w * N * TR + t) * ldh;
+        const int64_t jstride = (int64_t)TR * ldh;
         const int sp = col >= HWl, k = col - sp * HWl;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (k < dh) {
@@ -449,7 +476,7 @@ __global__ __launch_bounds__(256) void k_spin_mean<float>(const float *__restric
             v.x *= sc; v.y *= sc; v.z *= sc; v.w *= sc;
             // columns dh.. of the padded block are zero in H, so whole float4s are safe
         }
-        *(float4 *)(g + col) = v;
+        *(float4 *)(G + wt * 2 * HWl + col) = v;
     }
 }
 
@@ -1127,7 +1154,8 @@ void launch_pack(const T *theta, const PackList &pl, hipStream_t st)
 template <typename T>
 void launch_features(const Sys &s, const double *x, int64_t B, int TR, int HW0, int64_t ldh, T *H, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_features<T>, dim3((unsigned)(B * s.N)), dim3(256), 0, st, s, x, TR, HW0, ldh, H);
+    hipLaunchKernelGGL(k_features<T>, dim3(grid_for(B * s.N * TR * (HW0 / 4))), dim3(256), 0, st, s, x, B, TR, HW0,
+                       ldh, H);
 }
 
 // LDS of a pair-stream workgroup holding WB (walker, electron) rows
@@ -1200,7 +1228,8 @@ template <typename T>
 void launch_spin_mean(const T *H, int64_t ldh, int64_t B, int N, int nu, int TR, int dh, int HWl, T *G,
                       hipStream_t st)
 {
-    hipLaunchKernelGGL(k_spin_mean<T>, dim3((unsigned)(B * TR)), dim3(256), 0, st, H, ldh, N, nu, TR, dh, HWl, G);
+    const int64_t items = B * TR * (sizeof(T) == 4 ? HWl / 2 : 2 * HWl);
+    hipLaunchKernelGGL(k_spin_mean<T>, dim3(grid_for(items)), dim3(256), 0, st, H, ldh, B, N, nu, TR, dh, HWl, G);
 }
 
 template <typename T>
