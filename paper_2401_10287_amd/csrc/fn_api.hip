@@ -176,6 +176,7 @@ struct Plan {
     int TR, rec;
     int64_t Bc;
     size_t wx[FN_MAX_LAYERS], wg[FN_MAX_LAYERS], wh[2], wb[2];
+    size_t wpair;        // FP32 pair weights in the matrix-core pair kernel's layout (FP32 parameters only)
     int64_t wxpart[FN_MAX_LAYERS], wgpart[FN_MAX_LAYERS];   // elements per BF16 part
     size_t H[FN_MAX_LAYERS + 1], GI, G, Pw, X, O[2], Phi[2], DR, xp, lpn, u;
     // backward
@@ -216,6 +217,8 @@ fn_status make_plan(const Ctx &c, int64_t B, int op, Plan &p)
         p.wx[l] = o; o = al(o + nx * se * np);
         p.wg[l] = o; o = al(o + ng * se * np);
     }
+    p.wpair = o;
+    if (c.esz == sizeof(float)) o = al(o + (size_t)pair_mfma_woff(s, s.L > 1 ? s.L - 1 : 0) * sizeof(float));
     for (int sp = 0; sp < 2; ++sp) {
         int n = sp == 0 ? s.nu : s.nd;
         size_t nh = (size_t)s.K * n * c.W.W1p;
@@ -329,6 +332,17 @@ void pack_weights(const Ctx &c, const Plan &p, const T *theta, char *ws, hipStre
         g.d0 = ws + p.wh[sp];
         add(g);
     }
+    if (sizeof(T) == sizeof(float)) {
+        const int wc = round_up(s.w2, 16);
+        for (int l = 0; l + 1 < s.L; ++l) {
+            PackSeg g{};
+            g.kind = 2; g.mode = GEMM_F32; g.off = c.P.W2[l]; g.off2 = c.P.c2[l];
+            g.dp = layer_dp(s, l); g.w2 = s.w2; g.wc = wc; g.ks = pair_mfma_kp(s, l) + 4;
+            g.count = (int64_t)wc * g.ks + wc;
+            g.d0 = ws + p.wpair + (size_t)pair_mfma_woff(s, l) * sizeof(float);
+            add(g);
+        }
+    }
     launch_pack<T>(theta, pl, st);
     for (int sp = 0; sp < 2; ++sp) {
         const int n = sp == 0 ? s.nu : s.nd;
@@ -358,7 +372,8 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
     {
         Timed t_(K_PAIR, st);
         launch_pair_stream<T>(s, xw, theta, c.P, b, TR, fl, ldg, p.gi_layer_stride, c.W.GWl[0],
-                              s.L > 1 ? c.W.GWl[1] : c.W.GWl[0], GI, st);
+                              s.L > 1 ? c.W.GWl[1] : c.W.GWl[0],
+                              sizeof(T) == sizeof(float) ? (const float *)(ws + p.wpair) : nullptr, GI, st);
     }
     bool g_ready = false;            // spin means of h^l already written by the previous layer
     for (int l = 0; l < s.L; ++l) {
@@ -761,6 +776,10 @@ fn_status fn_tuning_set(const char *name, int64_t value)
     if (!name) return fail(FN_EINVAL, "NULL name");
     if (strcmp(name, "fused_layer") == 0) {
         fn::g_use_fused_layer = value != 0;
+        return FN_OK;
+    }
+    if (strcmp(name, "pair_mfma") == 0) {
+        fn::g_pair_mfma = value != 0;
         return FN_OK;
     }
     if (strcmp(name, "pair_oc") == 0) {

@@ -72,6 +72,7 @@ enum GemmMode { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16 = 2, GEMM_BF16X3 = 3, GEMM
 __host__ __device__ inline int lds_chunk(int r, int c) { return c ^ (((r >> 1) ^ (r >> 2)) & 3); }
 
 typedef __attribute__((__vector_size__(2 * sizeof(float)))) float f32x2_t;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;     // one 16 x 16 MFMA accumulator per lane
 typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_t;
 
 // Split two FP32 values a, b into NP BF16 parts, x = p0 + p1 + ..., each part
@@ -180,6 +181,8 @@ extern bool g_use_fused_layer;
 // pair-stream launch shape: output columns per thread (0: by size) and
 // (pair, column group) items per workgroup (0: by form)
 extern int g_pair_oc, g_pair_items;
+// FP32 pair layers on the matrix cores (false: vector kernel)
+extern bool g_pair_mfma;
 void launch_stream_layer(int mode, const LayerArgs &a, int TR, hipStream_t st);
 // 128-row tiles of the fused layer hold whole walkers
 inline bool stream_layer_whole_walkers(int N, int TR) { return N * TR <= 128 && 128 % (N * TR) == 0; }

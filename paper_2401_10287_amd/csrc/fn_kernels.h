@@ -9,23 +9,40 @@ namespace fn {
 // segment per layer (kind 0: per-electron block Wx into d0, per-walker block
 // Wg into d1) and per spin head (kind 1: Wh into d0), in the product's
 // operand type (mode); segment q covers elements [begin, begin + count).
+// Kind 2: FP32 pair block of one pair layer in the matrix-core pair
+// kernel's layout (transposed weights Wt[wc][ks] from off, then the bias
+// [wc] from off2) into d0.
 struct PackSeg {
-    int64_t begin, count, off;
-    int kind, mode, dh, dp, w1, HWl, GWl, kn, W1p;
+    int64_t begin, count, off, off2;
+    int kind, mode, dh, dp, w1, HWl, GWl, kn, W1p, w2, wc, ks;
     void *d0, *d1;
 };
 struct PackList {
     int n;
-    PackSeg seg[FN_MAX_LAYERS + 2];
+    PackSeg seg[2 * FN_MAX_LAYERS + 2];
 };
 template <typename T>
 void launch_pack(const T *theta, const PackList &pl, hipStream_t st);
 template <typename T>
 void launch_features(const Sys &s, const double *x, int64_t B, int TR, int HW0, int64_t ldh, T *H, hipStream_t st);
 size_t pair_stream_lds(const Sys &s, bool fl, size_t elem);
+// Matrix-core pair kernel layout of the pair weights: per pair layer l the
+// transposed weights Wt[wc][KP_l + 4] (wc = w2 rounded up to 16, KP_l = d_p
+// of layer l rounded up to 16), then the bias [wc]; pair_mfma_woff(s, l) is
+// the float offset of layer l's block, pair_mfma_woff(s, L - 1) the total.
+__host__ __device__ inline int pair_mfma_kp(const Sys &s, int l) { return round_up(layer_dp(s, l), 16); }
+__host__ __device__ inline int pair_mfma_woff(const Sys &s, int l)
+{
+    const int wc = round_up(s.w2, 16);
+    int o = 0;
+    for (int q = 0; q < l; ++q) o += wc * (pair_mfma_kp(s, q) + 4) + wc;
+    return o;
+}
+// wpair: the packed pair weights above (FP32 parameters), or nullptr
 template <typename T>
 void launch_pair_stream(const Sys &s, const double *x, const T *theta, const ParamLayout &P, int64_t B, int TR,
-                        bool fl, int64_t ldg, int64_t gi_layer_stride, int GW0, int GW1, T *GI, hipStream_t st);
+                        bool fl, int64_t ldg, int64_t gi_layer_stride, int GW0, int GW1, const float *wpair, T *GI,
+                        hipStream_t st);
 template <typename T>
 void launch_spin_mean(const T *H, int64_t ldh, int64_t B, int N, int nu, int TR, int dh, int HWl, T *G,
                       hipStream_t st);

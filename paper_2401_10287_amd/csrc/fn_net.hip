@@ -70,6 +70,21 @@ __device__ inline void pack_head_elem(const T *theta, const PackSeg &g, int64_t 
     put_w<T>(g.mode, g.d0, n, t, v);
 }
 
+// Element t of a pair block (FP32, matrix-core pair kernel layout)
+template <typename T>
+__device__ inline void pack_pair_elem(const T *theta, const PackSeg &g, int64_t t)
+{
+    T v = T(0);
+    if (t < (int64_t)g.wc * g.ks) {
+        const int o = (int)(t / g.ks), k = (int)(t % g.ks);
+        if (o < g.w2 && k < g.dp) v = theta[g.off + (int64_t)k * g.w2 + o];
+    } else {
+        const int o = (int)(t - (int64_t)g.wc * g.ks);
+        if (o < g.w2) v = theta[g.off2 + o];
+    }
+    ((float *)g.d0)[t] = (float)v;
+}
+
 // every forward operand block in one launch; segment q covers the element
 // range [begin_q, begin_q + count_q) of one index space
 template <typename T>
@@ -80,7 +95,8 @@ __global__ void k_pack(const T *theta, PackList pl, int64_t total)
         while (q + 1 < pl.n && i >= pl.seg[q + 1].begin) ++q;
         const PackSeg &g = pl.seg[q];
         if (g.kind == 0) pack_layer_elem<T>(theta, g, i - g.begin);
-        else pack_head_elem<T>(theta, g, i - g.begin);
+        else if (g.kind == 1) pack_head_elem<T>(theta, g, i - g.begin);
+        else pack_pair_elem<T>(theta, g, i - g.begin);
     }
 }
 
@@ -223,6 +239,53 @@ __device__ void write_pair_means(const Sys &s, const T *S, int wp, int ps, int d
             }
         }
         gi[(int64_t)t * ldg + col] = v;
+    }
+}
+
+// The same rows for the nwi (walker, electron) rows of a workgroup at once,
+// FP32 with dp a multiple of 4: one item per (row, output row t, four
+// columns), so every thread takes part however few rows each has.  S holds
+// row bb at S + bb * per; gi0 is the layer's output base.
+template <bool FL>
+__device__ void write_pair_means_wg(const Sys &s, const float *S, int per, int wp, int ps, int dp, int64_t wi0,
+                                    int nwi, int TR, int GWl, int64_t ldg, float *gi0)
+{
+    constexpr int R = FL ? 8 : 1;
+    const int n3 = 3 * s.N, rows = FL ? TR : 1, cqn = GWl / 4;
+    const int items = nwi * rows * cqn;
+    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+        const int col = 4 * (it % cqn), rt = it / cqn;
+        const int t = rt % rows, bb = rt / rows;
+        const int64_t wi = wi0 + bb;
+        const int i = (int)(wi % s.N);
+        const float *Sb = S + (int64_t)bb * per;
+        const bool live = col < 2 * dp;
+        const int sp = live ? col / dp : 0, o = live ? col - sp * dp : 0;
+        const int n = sp == 0 ? s.nu : s.nd, j0 = sp == 0 ? 0 : s.nu;
+        const float inv = n > 0 ? 1.f / (float)n : 0.f;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (live && n > 0 && t <= n3 + 1) {
+            int r = -1, e = -1;
+            if (t == 0 || t == n3 + 1) {
+                r = t == 0 ? 0 : R - 1;
+            } else {
+                const int c = t - 1, ee = c / 3, a = c - 3 * ee;
+                if (ee == i) r = 1 + a;
+                else if (ee >= j0 && ee < j0 + n) { e = ee; r = 4 + a; }
+            }
+            if (e >= 0) {
+                const float4 q = *(const float4 *)(Sb + e * ps + r * wp + o);
+                v = make_float4(q.x * inv, q.y * inv, q.z * inv, q.w * inv);
+            } else if (r >= 0) {
+                float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+                for (int j = j0; j < j0 + n; ++j) {
+                    const float4 q = *(const float4 *)(Sb + j * ps + r * wp + o);
+                    acc.x += q.x; acc.y += q.y; acc.z += q.z; acc.w += q.w;
+                }
+                v = make_float4(acc.x * inv, acc.y * inv, acc.z * inv, acc.w * inv);
+            }
+        }
+        *(float4 *)(gi0 + (wi * rows + t) * ldg + col) = v;
     }
 }
 
@@ -415,6 +478,142 @@ __global__ __launch_bounds__(256) void k_pair_stream(Sys s, const double *x, con
             write_pair_means<T, FL>(s, S0 + (int64_t)bb * per, wp, ps, s.w2, (int)(wi % s.N), TR, GW1, ldg,
                                     GI + (int64_t)(l + 1) * gi_layer_stride + wi * rows * ldg);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// two-electron stream on the matrix cores, FP32 operands: the layers of
+// k_pair_stream with each pair layer a product of 16-row blocks of pair rows
+// (two pairs of 8 forward-Laplacian rows, or 16 value rows) with the
+// transposed weights, v_mfma_f32_16x16x4f32 with four reduction steps per
+// float4 read.  A wave owns whole row blocks and updates them in place after
+// all of its reads.  Forward-Laplacian epilogue: lane groups 0/2 hold rows
+// 0-3 of a pair (value, tangents 1-3), groups 1/3 rows 4-7 (tangents 4-6,
+// Laplacian); one exchange between the two (lane ^ 16) gives both the tanh
+// value and the source sum_c dz_c^2.
+// LDS: rows of wc + 4 floats (wc = w2 rounded up to 16), pair j of
+// (walker, electron) b at rows (b N + j) R ..; per pair layer the transposed
+// weights Wt[wc][KP + 4] (KP = d_p rounded up to 16), then the bias [wc].
+// ---------------------------------------------------------------------------
+template <bool FL>
+__global__ __launch_bounds__(256) void k_pair_mfma(Sys s, const double *x, const float *__restrict__ Wpk,
+                                                   int64_t B, int TR, int64_t ldg, int64_t gi_layer_stride, int GW0,
+                                                   int GW1, int WB, float *GI)
+{
+    constexpr int R = FL ? 8 : 1;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    const int wc = round_up(s.w2, 16), RS = wc + 4, ps = R * RS, per = s.N * ps;
+    const int ncb = wc / 16;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, li = lane & 15;
+    const int64_t wi0 = (int64_t)blockIdx.x * WB;
+    const int nwi = B * s.N - wi0 < WB ? (int)(B * s.N - wi0) : WB;
+    const int rows = FL ? TR : 1;
+    const int nrow = nwi * s.N * R;                       // pair rows held here
+    const int nblk = (nrow + 15) / 16;
+    const int rows_alloc = round_up(WB * s.N * R, 16);
+    float *S = (float *)smem_raw;
+    float *Wsm = S + (int64_t)rows_alloc * RS;
+
+    // packed weights: a plain copy (the block is a multiple of 16 floats)
+    const int wtot = pair_mfma_woff(s, s.L > 1 ? s.L - 1 : 0);
+    for (int q = 4 * tid; q < wtot; q += 4 * blockDim.x) *(float4 *)(Wsm + q) = *(const float4 *)(Wpk + q);
+    for (int q = 4 * tid; q < rows_alloc * RS; q += 4 * blockDim.x) *(float4 *)(S + q) = make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+    // layer-0 pair features
+    for (int q = tid; q < nwi * s.N; q += blockDim.x) {
+        const int bb = q / s.N, j = q % s.N;
+        const int64_t wi = wi0 + bb, w = wi / s.N;
+        const int i = (int)(wi % s.N);
+        if (j == i) continue;
+        const double *xw = x + w * 3 * s.N;
+        float *p = S + (int64_t)bb * per + j * ps;
+        const double d[3] = {xw[3 * i] - xw[3 * j], xw[3 * i + 1] - xw[3 * j + 1], xw[3 * i + 2] - xw[3 * j + 2]};
+        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        for (int c = 0; c < 3; ++c) p[c] = (float)d[c];
+        p[3] = (float)r;
+        if constexpr (FL) {
+            for (int c = 0; c < 3; ++c) {
+                p[(1 + c) * RS + c] = 1.f;
+                p[(1 + c) * RS + 3] = (float)(d[c] / r);
+                p[(4 + c) * RS + c] = -1.f;
+                p[(4 + c) * RS + 3] = (float)(-d[c] / r);
+            }
+            p[7 * RS + 3] = (float)(4.0 / r);
+        }
+    }
+    __syncthreads();
+    write_pair_means_wg<FL>(s, S, per, RS, ps, 4, wi0, nwi, TR, GW0, ldg, GI);
+    for (int l = 0; l + 1 < s.L; ++l) {
+        __syncthreads();
+        const int KP = pair_mfma_kp(s, l), KS = KP + 4;
+        const float *Wl = Wsm + pair_mfma_woff(s, l);
+        const float *bl = Wl + wc * KS;
+        const bool resid = l >= 1;
+        for (int blk = wave; blk < nblk; blk += 4) {
+            const int r0 = blk * 16;
+            f32x4 acc[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const float bv = cb < ncb ? bl[cb * 16 + li] : 0.f;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[cb][e] = (!FL || ((g & 1) == 0 && e == 0)) ? bv : 0.f;
+            }
+            const float *arow = S + (int64_t)(r0 + li) * RS + 4 * g;
+            for (int kb = 0; kb < KP; kb += 16) {
+                const float4 a4 = *(const float4 *)(arow + kb);
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    if (cb < ncb) {
+                        const float4 b4 = *(const float4 *)(Wl + (cb * 16 + li) * KS + kb + 4 * g);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.x, b4.x, acc[cb], 0, 0, 0);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.y, b4.y, acc[cb], 0, 0, 0);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.z, b4.z, acc[cb], 0, 0, 0);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.w, b4.w, acc[cb], 0, 0, 0);
+                    }
+                }
+            }
+            // every read of this block is done: write its rows in place
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                if (cb >= ncb) continue;
+                const int col = cb * 16 + li;
+                float *o = S + (int64_t)(r0 + 4 * g) * RS + col;
+                float res[4], v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) res[e] = resid ? o[e * RS] : 0.f;
+                const float a0 = acc[cb][0], a1 = acc[cb][1], a2 = acc[cb][2], a3 = acc[cb][3];
+                if constexpr (FL) {
+                    const bool ev = (g & 1) == 0;
+                    const float part = ev ? fmat(a3, a3, fmat(a2, a2, a1 * a1)) : fmat(a2, a2, fmat(a1, a1, a0 * a0));
+                    const float y0c = tanhf(a0);
+                    const float part_o = __shfl_xor(part, 16);
+                    const float y0_o = __shfl_xor(y0c, 16);
+                    const float y0 = ev ? y0c : y0_o;
+                    const float src = ev ? part + part_o : part_o + part;
+                    const float dd = fmat(-y0, y0, 1.f);
+                    if (ev) {
+                        v[0] = y0 + res[0];
+                        v[1] = fmat(dd, a1, res[1]);
+                        v[2] = fmat(dd, a2, res[2]);
+                        v[3] = fmat(dd, a3, res[3]);
+                    } else {
+                        v[0] = fmat(dd, a0, res[0]);
+                        v[1] = fmat(dd, a1, res[1]);
+                        v[2] = fmat(dd, a2, res[2]);
+                        v[3] = fmat(dd, a3, fmat(-2.f * y0 * dd, src, res[3]));
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] = tanhf(acc[cb][e]) + res[e];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (r0 + 4 * g + e < nrow) o[e * RS] = v[e];
+            }
+        }
+        __syncthreads();
+        write_pair_means_wg<FL>(s, S, per, RS, ps, s.w2, wi0, nwi, TR, GW1, ldg,
+                                GI + (int64_t)(l + 1) * gi_layer_stride);
     }
 }
 
@@ -1214,10 +1413,55 @@ static void launch_pair_oc(const Sys &s, const double *x, const T *theta, const 
     }
 }
 
+// matrix-core pair kernel: LDS of WB (walker, electron) rows, pair rows per
+// workgroup about g_pair_items (default 128 in the forward-Laplacian form,
+// 64 in the value form: two or one row blocks per wave) within 64 KiB
+bool g_pair_mfma = true;
+
+static size_t pair_mfma_lds_wb(const Sys &s, bool fl, int WB)
+{
+    const int wc = round_up(s.w2, 16);
+    const size_t rows = (size_t)round_up(WB * s.N * (fl ? 8 : 1), 16);
+    return (rows * (wc + 4) + (size_t)pair_mfma_woff(s, s.L > 1 ? s.L - 1 : 0)) * sizeof(float);
+}
+
+static bool pair_mfma_ok(const Sys &s, bool fl)
+{
+    return g_pair_mfma && s.w2 <= 64 && s.w2 % 4 == 0 && pair_mfma_lds_wb(s, fl, 1) <= 64 * 1024;
+}
+
+static int pair_mfma_wb(const Sys &s, bool fl)
+{
+    const int rows = s.N * (fl ? 8 : 1);
+    const int target = g_pair_items ? g_pair_items : (fl ? 128 : 64);
+    int wb = rows >= target ? 1 : target / rows;
+    while (wb > 1 && pair_mfma_lds_wb(s, fl, wb) > 64 * 1024) --wb;
+    return wb;
+}
+
+template <bool FL>
+static void launch_pair_mfma(const Sys &s, const double *x, const float *wpair, int64_t B, int TR, int64_t ldg,
+                             int64_t gi_layer_stride, int GW0, int GW1, float *GI, hipStream_t st)
+{
+    const int wb = pair_mfma_wb(s, FL);
+    const size_t lds = pair_mfma_lds_wb(s, FL, wb);
+    dim3 grid((unsigned)((B * s.N + wb - 1) / wb));
+    hipLaunchKernelGGL((k_pair_mfma<FL>), grid, dim3(256), lds, st, s, x, wpair, B, TR, ldg, gi_layer_stride, GW0,
+                       GW1, wb, GI);
+}
+
 template <typename T>
 void launch_pair_stream(const Sys &s, const double *x, const T *theta, const ParamLayout &P, int64_t B, int TR,
-                        bool fl, int64_t ldg, int64_t gi_layer_stride, int GW0, int GW1, T *GI, hipStream_t st)
+                        bool fl, int64_t ldg, int64_t gi_layer_stride, int GW0, int GW1, const float *wpair, T *GI,
+                        hipStream_t st)
 {
+    if constexpr (std::is_same<T, float>::value) {
+        if (wpair && pair_mfma_ok(s, fl)) {
+            if (fl) launch_pair_mfma<true>(s, x, wpair, B, TR, ldg, gi_layer_stride, GW0, GW1, GI, st);
+            else launch_pair_mfma<false>(s, x, wpair, B, TR, ldg, gi_layer_stride, GW0, GW1, GI, st);
+            return;
+        }
+    }
     if (fl)
         launch_pair_oc<T, true>(s, x, theta, P, B, TR, ldg, gi_layer_stride, GW0, GW1, GI, st);
     else
@@ -1338,7 +1582,7 @@ void launch_combine(const Sys &s, const double *x, const double *DR, int rec, in
     template void launch_pack<T>(const T *, const PackList &, hipStream_t);                                          \
     template void launch_features<T>(const Sys &, const double *, int64_t, int, int, int64_t, T *, hipStream_t);    \
     template void launch_pair_stream<T>(const Sys &, const double *, const T *, const ParamLayout &, int64_t, int,   \
-                                        bool, int64_t, int64_t, int, int, T *, hipStream_t);                        \
+                                        bool, int64_t, int64_t, int, int, const float *, T *, hipStream_t);         \
     template void launch_spin_mean<T>(const T *, int64_t, int64_t, int, int, int, int, int, T *, hipStream_t);      \
     template void launch_layer_epi<T>(const T *, const T *, const T *, const T *, T *, int64_t, int64_t, int, int,  \
                                       int, int, int, int, bool, T *, hipStream_t);                                  \

@@ -275,31 +275,41 @@ def test_fused_and_separate_layer_paths(name, prec, walkers):
 
 
 @pytest.mark.parametrize("name,walkers", [("LiH", 61), ("LiF", 13)])
-def test_pair_launch_shapes_bitwise(name, walkers):
-    """The two-electron stream kernel's launch shape (output columns per
-    thread, rows per workgroup) does not change its arithmetic: local
-    energies and log|psi| are bitwise equal over every shape, and the
-    default shape is within the oracle bounds."""
+def test_pair_kernels_and_launch_shapes(name, walkers):
+    """Both two-electron stream kernels (FP32 matrix-core products, and the
+    vector kernel) are within the oracle bounds, log|psi| and local energy;
+    within each kernel the launch shape (rows per workgroup; output columns
+    per thread of the vector kernel) does not change the arithmetic: results
+    are bitwise equal over every shape."""
     s = SYSTEMS[name]()
     torch, fnvmc, cfg, tt, xt, th, x = _setup(s, "bf16x6", walkers)
     o = O.Oracle(s)
-    ref = None
+    ref_e = o.local_energy(th, x)
+    ref_l = o.log_psi(th, x)
+    kap = _kappa_sum(o, th, x)
+    C = _conditioning(o, s, th, x)
+    shapes = {1: ((0, 0), (0, 64), (0, 1024)),
+              0: ((0, 0), (1, 0), (2, 0), (4, 0), (4, 64), (1, 512), (2, 1024))}
     try:
-        for oc, items in ((0, 0), (1, 0), (2, 0), (4, 0), (4, 64), (1, 512), (2, 1024)):
-            fnvmc.fn_tuning_set("pair_oc", oc)
-            fnvmc.fn_tuning_set("pair_items", items)
-            e, lp, _ = fnvmc.fn_local_energy(cfg, tt, xt)
-            lv, _ = fnvmc.fn_log_psi(cfg, tt, xt)
-            torch.cuda.synchronize()
-            got = (e.cpu().numpy(), lp.cpu().numpy(), lv.cpu().numpy())
-            if ref is None:
-                ref = got
-                _check_energy(got[0], None, o.local_energy(th, x), 1e-3, f"{name} default pair shape",
-                              _kappa_sum(o, th, x))
-            else:
-                for a, b in zip(got, ref):
-                    np.testing.assert_array_equal(a, b, err_msg=f"{name} pair_oc={oc} pair_items={items}")
+        for mfma, cases in shapes.items():
+            fnvmc.fn_tuning_set("pair_mfma", mfma)
+            first = None
+            for oc, items in cases:
+                fnvmc.fn_tuning_set("pair_oc", oc)
+                fnvmc.fn_tuning_set("pair_items", items)
+                e, lp, parts = fnvmc.fn_local_energy(cfg, tt, xt)
+                lv, _ = fnvmc.fn_log_psi(cfg, tt, xt)
+                torch.cuda.synchronize()
+                got = (e.cpu().numpy(), lp.cpu().numpy(), lv.cpu().numpy())
+                if first is None:
+                    first = got
+                    _check_energy(got[0], parts.cpu().numpy(), ref_e, 1e-3, f"{name} pair_mfma={mfma}", kap)
+                    _check_logpsi(got[2], ref_l, 1e-5, f"{name} pair_mfma={mfma}", C, False)
+                else:
+                    for a, b in zip(got, first):
+                        np.testing.assert_array_equal(a, b, err_msg=f"{name} mfma={mfma} oc={oc} items={items}")
     finally:
+        fnvmc.fn_tuning_set("pair_mfma", 1)
         fnvmc.fn_tuning_set("pair_oc", 0)
         fnvmc.fn_tuning_set("pair_items", 0)
 
