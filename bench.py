@@ -26,6 +26,9 @@ sys.path.insert(0, ROOT)
 METRIC = "local-energy evals/s on 1 GPU (mixed vs plain FP32 at dE<=1 mHa); p50/p99 latency"
 PEAK_TFLOPS = {"bf16": 2516.6, "bf16x3": 2516.6, "bf16x6": 2516.6, "fp32": 157.3, "fp64": 78.6}
 DTYPE = {"bf16": "bf16", "bf16x3": "bf16", "bf16x6": "bf16", "fp32": "f32", "fp64": "f64"}
+# matrix-core products executed per algorithmic product (operand splits)
+PRODUCTS = {"bf16": 1, "bf16x3": 3, "bf16x6": 6, "fp32": 1, "fp64": 1}
+HBM_PEAK_GBPS = 8000.0
 
 
 def stream_gemm_flops(s, walkers):
@@ -197,6 +200,8 @@ def main():
     achieved = flops_per_launch / avg_launch_s / 1e12
     peak = PEAK_TFLOPS[args.precision]
     total_kernel_ms = sum(v[0] for v in kern.values())
+    # the committed counter summary covers the default workload (bf16x6, 4096 walkers)
+    traffic = measured_traffic() if (args.precision == "bf16x6" and args.walkers == 4096) else None
     nb = results["breakdown_steps"]
 
     line = {
@@ -238,7 +243,11 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": measured_traffic(),
+            "traffic": traffic,
+            "products_per_algorithmic_product": PRODUCTS[args.precision],
+            "executed_frac": achieved * PRODUCTS[args.precision] / peak,
+            "hbm_GBps": None if traffic is None else traffic / avg_launch_s / 1e9,
+            "hbm_frac": None if traffic is None else traffic / avg_launch_s / 1e9 / HBM_PEAK_GBPS,
             "flops_per_launch": flops_per_launch,
             "avg_launch_us": avg_launch_s * 1e6,
             "launches": n_g,
