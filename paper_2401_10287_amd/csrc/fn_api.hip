@@ -385,8 +385,12 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
         ga.A1 = G; ga.lda1 = 2 * HWl; ga.K1 = 2 * HWl;
         ga.W = ws + p.wg[l]; ga.wpart = p.wgpart[l]; ga.ldw = 2 * HWl;
         ga.C = Pw; ga.ldc = s.w1;
-        ga.rows = b * TR; ga.nout = s.w1;
-        ga.rows_per_group = ga.rows;
+        // rows value .. Laplacian of each walker only: both epilogues read
+        // no padding row of the per-walker part
+        const int tr_live = fl ? n3 + 2 : TR;
+        ga.rows = b * tr_live; ga.nout = s.w1;
+        ga.rows_per_group = tr_live; ga.group_stride = TR;
+        ga.c_rows_per_group = tr_live; ga.c_group_stride = TR;
         { Timed t_(K_WALKER_GEMM, st); (void)launch_gemm(c.smode, ga, st); }
         bool fused = false;
         if constexpr (std::is_same<T, float>::value) fused = !p.save && stream_layer_supported(c.smode, TR, s.w1, c.W.W1p);

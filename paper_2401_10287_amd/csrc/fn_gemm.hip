@@ -206,19 +206,20 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
     }
 
     // accumulator (i, j) element e sits at row 16 i + 4 (lane >> 4) + e, column 16 j + (lane & 15)
+    // (each output row is mapped once)
     float *C = (float *)a.C;
 #pragma unroll
     for (int i = 0; i < WI; ++i)
 #pragma unroll
-        for (int j = 0; j < WJ; ++j) {
-            int col = n0 + wn * 16 * WJ + 16 * j + (lane & 15);
-            if (col >= a.nout) continue;
+        for (int e = 0; e < 4; ++e) {
+            int64_t row = m0 + wm * 16 * WI + 16 * i + 4 * (lane >> 4) + e;
+            if (row >= a.rows) continue;
+            if (a.c_rows_per_group > 0) row = remap_row(row, a.c_rows_per_group, a.c_group_stride, a.c_row_offset);
+            float *crow = C + row * a.ldc;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                int64_t row = m0 + wm * 16 * WI + 16 * i + 4 * (lane >> 4) + e;
-                if (row >= a.rows) continue;
-                if (a.c_rows_per_group > 0) row = remap_row(row, a.c_rows_per_group, a.c_group_stride, a.c_row_offset);
-                C[row * a.ldc + col] = acc[i][j][e];
+            for (int j = 0; j < WJ; ++j) {
+                const int col = n0 + wn * 16 * WJ + 16 * j + (lane & 15);
+                if (col < a.nout) crow[col] = acc[i][j][e];
             }
         }
 }

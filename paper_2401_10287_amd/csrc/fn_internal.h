@@ -153,7 +153,8 @@ inline int64_t xcd_grid(int64_t nrb, int ncb) { return ncb == 1 ? nrb : ((nrb + 
 
 __host__ __device__ inline int64_t remap_row(int64_t r, int64_t per, int64_t stride, int64_t off)
 {
-    const int64_t g = r / per;
+    // 32-bit division when both fit (the common case; 64-bit division is a long sequence on the GPU)
+    const int64_t g = ((r | per) >> 31) == 0 ? (int64_t)((uint32_t)r / (uint32_t)per) : r / per;
     return g * stride + off + (r - g * per);
 }
 
