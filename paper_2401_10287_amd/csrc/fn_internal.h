@@ -5,7 +5,12 @@
 //   row 0             value
 //   row 1 + c         d/dx_c, c = 3 e + a over all 3N electron coordinates
 //   row 3N + 1        Laplacian (sum over all 3N coordinates)
-//   rows 3N+2..TR-1   zero padding (TR is a multiple of 16)
+//   rows 3N+2..TR-1   padding (TR is a multiple of 16): zero in the input
+//                     features; the fused layer kernel neither fetches nor
+//                     writes them, and every consumer either reads rows up
+//                     to 3N+1 only or keeps them row-local (a matrix
+//                     product's padding output rows are never read into a
+//                     live row)
 // In value-only mode (Metropolis, gradient) TR = 1.
 #pragma once
 #include <hip/hip_runtime.h>

@@ -40,11 +40,15 @@ constexpr int LDF = LBK + 4;
 }  // namespace
 
 // LBN = 128: 2 x 2 waves of 64 x 64; LBN = 32 (value rows only, for grids
-// that would leave CUs idle): 4 x 1 waves of 32 x 32.
-template <int MODE, int TP, int LBN>
+// that would leave CUs idle): 4 x 1 waves of 32 x 32.  LIVE: 16-row blocks
+// of an electron that hold live rows (value .. Laplacian); with TP = 64 a
+// wave's four row blocks are one electron's, and blocks past LIVE (padding
+// only, zero in and out) take no matrix instructions.
+template <int MODE, int TP, int LBN, int LIVE>
 __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 {
     static_assert(LBN == 128 || (LBN == 32 && TP == 1), "column tile");
+    static_assert(LIVE == (TP + 15) / 16 || (TP == 64 && LBN == 128 && LIVE == 3), "live row blocks");
     constexpr int WI = LBN == 128 ? 4 : 2, WJ = LBN == 128 ? 4 : 2;   // 16 x 16 blocks per wave
     constexpr bool F32 = MODE == GEMM_F32;
     constexpr int NP = MODE == GEMM_BF16 ? 1 : (MODE == GEMM_BF16X3 ? 2 : (MODE == GEMM_BF16X6 ? 3 : 1));
@@ -78,14 +82,20 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
     // per-thread element offsets of the float4s this thread loads: activation
     // rows (clamped to a valid row; out-of-range rows load and are zeroed) for
     // either operand part, and weight rows
+    // Padding rows (past an electron's Laplacian row) are not fetched: they
+    // take the address of that Laplacian row, which another lane fetches
+    // anyway, and are zeroed like out-of-range rows.
     int64_t offa1[4], offa2[4];
-    uint32_t aval[4];                                // all ones for an in-range row, else 0
+    uint32_t aval[4];                                // all ones for a live in-range row, else 0
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int f = tid + 256 * v;
         const int64_t row = m0 + (f >> 3);
-        aval[v] = row < a.rows ? 0xffffffffu : 0u;
-        const int64_t rr = row < a.rows ? row : m0;
+        const int lr = TP > 1 ? (f >> 3) % TP : 0;    // row within the electron (tiles start at electrons)
+        const bool pad = TP > 1 && lr > a.n3 + 1;
+        aval[v] = row < a.rows && !pad ? 0xffffffffu : 0u;
+        int64_t rr = m0;
+        if (row < a.rows) rr = pad ? row - (lr - (a.n3 + 1)) : row;
         offa1[v] = rr * a.lda1 + 4 * (f & 7);
         offa2[v] = rr * a.lda2 + 4 * (f & 7);
     }
@@ -191,14 +201,16 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
             for (int kk = 0; kk < LBK / 4; ++kk) {
                 float fa[WI], fb[WJ];
 #pragma unroll
-                for (int i = 0; i < WI; ++i) fa[i] = sA[(ar + 16 * i) * LDF + 4 * kk + (lane >> 4)];
+                for (int i = 0; i < WI; ++i)
+                    if (i < LIVE || TP != 64) fa[i] = sA[(ar + 16 * i) * LDF + 4 * kk + (lane >> 4)];
 #pragma unroll
                 for (int j = 0; j < WJ; ++j) fb[j] = sB[(br + 16 * j) * LDF + 4 * kk + (lane >> 4)];
 #pragma unroll
                 for (int i = 0; i < WI; ++i)
 #pragma unroll
                     for (int j = 0; j < WJ; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
+                        if (i < LIVE || TP != 64)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
             }
         } else {
             const uint16_t *sA = (const uint16_t *)smem, *sB = (const uint16_t *)(smem + ASZ);
@@ -207,7 +219,9 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
 #pragma unroll
-                for (int i = 0; i < WI; ++i) ha[q][i] = *(const bf16x8 *)&sA[q * LBM * LDH + (ar + 16 * i) * LDH + ko];
+                for (int i = 0; i < WI; ++i)
+                    if (i < LIVE || TP != 64)
+                        ha[q][i] = *(const bf16x8 *)&sA[q * LBM * LDH + (ar + 16 * i) * LDH + ko];
 #pragma unroll
                 for (int j = 0; j < WJ; ++j) hb[q][j] = *(const bf16x8 *)&sB[q * LBN * LDH + (br + 16 * j) * LDH + ko];
             }
@@ -219,8 +233,9 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
                     for (int i = 0; i < WI; ++i)
 #pragma unroll
                         for (int j = 0; j < WJ; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j], acc[i][j],
-                                                                                0, 0, 0);
+                            if (i < LIVE || TP != 64)
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j],
+                                                                                    acc[i][j], 0, 0, 0);
         }
     }
 
@@ -373,7 +388,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
                     else y = make_float4(lap[0], lap[1], lap[2], lap[3]);
                     y = f4add(y, r4[u]);
                 }
-                *(float4 *)(Hout + (Rb + t) * a.ldh_out + col) = y;
+                if (t <= tl) *(float4 *)(Hout + (Rb + t) * a.ldh_out + col) = y;   // padding rows are not written
                 if (a.Gout) *(float4 *)(xc + t * XS) = y;
             }
         }
@@ -422,15 +437,19 @@ static void launch_mode(const LayerArgs &a, int TR, hipStream_t st)
     // each workgroup's reduction steps carry a quarter of the matrix work
     if (TR == 1 && blocks <= 512) {
         dim3 grid((unsigned)(nrb * ((a.W1p + 31) / 32)));
-        hipLaunchKernelGGL((k_stream_layer<MODE, 1, 32>), grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_stream_layer<MODE, 1, 32, 1>), grid, dim3(256), 0, st, a);
         return;
     }
     dim3 grid((unsigned)blocks);
     switch (TR) {
-    case 1: hipLaunchKernelGGL((k_stream_layer<MODE, 1, 128>), grid, dim3(256), 0, st, a); break;
-    case 16: hipLaunchKernelGGL((k_stream_layer<MODE, 16, 128>), grid, dim3(256), 0, st, a); break;
-    case 32: hipLaunchKernelGGL((k_stream_layer<MODE, 32, 128>), grid, dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_stream_layer<MODE, 64, 128>), grid, dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_stream_layer<MODE, 1, 128, 1>), grid, dim3(256), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_stream_layer<MODE, 16, 128, 1>), grid, dim3(256), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_stream_layer<MODE, 32, 128, 2>), grid, dim3(256), 0, st, a); break;
+    default:
+        // rows value .. Laplacian (3N + 2) within the first three row blocks
+        if (a.n3 + 2 <= 48) hipLaunchKernelGGL((k_stream_layer<MODE, 64, 128, 3>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_stream_layer<MODE, 64, 128, 4>), grid, dim3(256), 0, st, a);
+        break;
     }
 }
 

@@ -618,22 +618,24 @@ __global__ __launch_bounds__(256) void k_pair_mfma(Sys s, const double *x, const
 }
 
 // ---------------------------------------------------------------------------
-// spin means of the one-electron stream: G[w][t] = [g_up | g_dn]; one item
+// spin means of the one-electron stream: G[w][t] = [g_up | g_dn] for the rows
+// t of each walker up to its Laplacian row (live); one item
 // per (walker row, output column), FP32 rows four columns per item
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_spin_mean(const T *__restrict__ H, int64_t ldh, int64_t B, int N, int nu,
-                                                   int TR, int dh, int HWl, T *__restrict__ G)
+                                                   int TR, int live, int dh, int HWl, T *__restrict__ G)
 {
     const int nd = N - nu;
     const T iu = nu > 0 ? T(1) / T(nu) : T(0), id = nd > 0 ? T(1) / T(nd) : T(0);
-    const int64_t total = B * TR * 2 * HWl;
+    const int64_t total = B * live * 2 * HWl;
     for (int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; it < total;
          it += (int64_t)gridDim.x * blockDim.x) {
         const int col = (int)(it % (2 * HWl));
-        const int64_t wt = it / (2 * HWl);            // walker * TR + t
-        const int64_t w = wt / TR;
-        const int t = (int)(wt - w * TR);
+        const int64_t wl = it / (2 * HWl);            // walker * live + t
+        const int64_t w = wl / live;
+        const int t = (int)(wl - w * live);
+        const int64_t wt = w * TR + t;
         const T *h0 = H + (w * N * TR + t) * ldh;
         const int64_t jstride = (int64_t)TR * ldh;
         const int sp = col >= HWl, k = col - sp * HWl;
@@ -649,18 +651,20 @@ __global__ __launch_bounds__(256) void k_spin_mean(const T *__restrict__ H, int6
 
 template <>
 __global__ __launch_bounds__(256) void k_spin_mean<float>(const float *__restrict__ H, int64_t ldh, int64_t B, int N,
-                                                          int nu, int TR, int dh, int HWl, float *__restrict__ G)
+                                                          int nu, int TR, int live, int dh, int HWl,
+                                                          float *__restrict__ G)
 {
     const int nd = N - nu;
     const float iu = nu > 0 ? 1.f / nu : 0.f, id = nd > 0 ? 1.f / nd : 0.f;
     const int cq = HWl / 2;                           // float4s in [g_up | g_dn] (HWl is a multiple of 32)
-    const int64_t total = B * TR * cq;
+    const int64_t total = B * live * cq;
     for (int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; it < total;
          it += (int64_t)gridDim.x * blockDim.x) {
         const int col = 4 * (int)(it % cq);
-        const int64_t wt = it / cq;
-        const int64_t w = wt / TR;
-        const int t = (int)(wt - w * TR);
+        const int64_t wl = it / cq;                   // walker * live + t
+        const int64_t w = wl / live;
+        const int t = (int)(wl - w * live);
+        const int64_t wt = w * TR + t;
         const float *h0 = H + (w * N * TR + t) * ldh;
         const int64_t jstride = (int64_t)TR * ldh;
         const int sp = col >= HWl, k = col - sp * HWl;
@@ -1472,8 +1476,11 @@ template <typename T>
 void launch_spin_mean(const T *H, int64_t ldh, int64_t B, int N, int nu, int TR, int dh, int HWl, T *G,
                       hipStream_t st)
 {
-    const int64_t items = B * TR * (sizeof(T) == 4 ? HWl / 2 : 2 * HWl);
-    hipLaunchKernelGGL(k_spin_mean<T>, dim3(grid_for(items)), dim3(256), 0, st, H, ldh, B, N, nu, TR, dh, HWl, G);
+    // rows value .. Laplacian only (the mean-field product reads no padding row)
+    const int live = TR == 1 ? 1 : 3 * N + 2;
+    const int64_t items = B * live * (sizeof(T) == 4 ? HWl / 2 : 2 * HWl);
+    hipLaunchKernelGGL(k_spin_mean<T>, dim3(grid_for(items)), dim3(256), 0, st, H, ldh, B, N, nu, TR, live, dh, HWl,
+                       G);
 }
 
 template <typename T>
