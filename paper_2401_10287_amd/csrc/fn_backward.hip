@@ -406,6 +406,74 @@ __global__ __launch_bounds__(256) void k_tn_partial(const T *X, int64_t ldx, int
     }
 }
 
+// FP32 on the matrix cores: the same 64 x 64 output tile, each wave a
+// 32 x 32 quadrant (2 x 2 accumulators of v_mfma_f32_16x16x4f32, rows as the
+// reduction dimension), rows staged 64 at a time; X^T and Y are both read
+// straight from the row-major LDS tiles (lane: column lane & 15, row lane >> 4).
+template <>
+__global__ __launch_bounds__(256) void k_tn_partial<float>(const float *X, int64_t ldx, int NA, const float *Y,
+                                                          int64_t ldy, int NB, int64_t R, int64_t per,
+                                                          int64_t stride, int64_t off, int64_t rows_per_split,
+                                                          float *part)
+{
+    constexpr int RC = 64, LS = 64 + 4;
+    __shared__ float sx[RC][LS];
+    __shared__ float sy[RC][LS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int a0 = blockIdx.x * 64, b0 = blockIdx.y * 64;
+    const int qa = (wave >> 1) * 32, qb = (wave & 1) * 32;
+    const int64_t r0 = (int64_t)blockIdx.z * rows_per_split;
+    const int64_t r1 = r0 + rows_per_split < R ? r0 + rows_per_split : R;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t rb = r0; rb < r1; rb += RC) {
+        for (int q = tid; q < RC * 64; q += 256) {
+            const int rr = q / 64, c = q % 64;
+            const int64_t r = rb + rr;
+            float vx = 0.f, vy = 0.f;
+            if (r < r1) {
+                const int64_t xr = per > 0 ? remap_row(r, per, stride, off) : r;
+                if (a0 + c < NA) vx = X[xr * ldx + a0 + c];
+                if (b0 + c < NB) vy = Y[r * ldy + b0 + c];
+            }
+            sx[rr][c] = vx;
+            sy[rr][c] = vy;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < RC / 4; ++kk) {
+            const int rr = 4 * kk + (lane >> 4);
+            float fa[2], fb[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) fa[i] = sx[rr][qa + 16 * i + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) fb[j] = sy[rr][qb + 16 * j + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // accumulator (i, j) element e: a = qa + 16 i + 4 (lane >> 4) + e, b = qb + 16 j + (lane & 15)
+    float *p = part + (int64_t)blockIdx.z * NA * NB;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int a = a0 + qa + 16 * i + 4 * (lane >> 4) + e;
+            if (a >= NA) continue;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int b = b0 + qb + 16 * j + (lane & 15);
+                if (b < NB) p[(int64_t)a * NB + b] = acc[i][j][e];
+            }
+        }
+}
+
 // acc[dst(a, b)] += sum_s part[s][a][b]; dst = off + a * lda_out + b
 template <typename T>
 __global__ void k_tn_reduce(const T *part, int S, int NA, int NB, double *acc, int64_t off, int64_t lda_out)
