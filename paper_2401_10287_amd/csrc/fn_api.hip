@@ -556,10 +556,11 @@ void backward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *x
     }
     if (s.L > 1) {
         T *PP = (T *)(ws + p.PP);
-        launch_pair_backward<T>(s, xw, theta, c.P, b, GGI, ldg, p.gi_layer_stride, PP, p.npp, st);
         // one PP row per pair-backward workgroup
-        const int wb = pair_backward_wb(s, c.esz);
-        launch_colsum<T>(PP, p.npp, (int)p.npp, (rows + wb - 1) / wb, part, gacc, c.P.W2[0], 0, 0, st);
+        const int64_t npr = launch_pair_backward<T>(s, xw, theta, c.P, b, GGI, ldg, p.gi_layer_stride,
+                                                    sizeof(T) == sizeof(float) ? (const float *)(ws + p.wpair) : nullptr,
+                                                    PP, p.npp, st);
+        launch_colsum<T>(PP, p.npp, (int)p.npp, npr, part, gacc, c.P.W2[0], 0, 0, st);
     }
 }
 

@@ -15,6 +15,8 @@
 // Weight gradients are sums over walkers x electrons of outer products; they
 // are formed as split row reductions whose partial sums are added in a fixed
 // order, so the result does not depend on scheduling.
+#include <type_traits>
+
 #include "fn_internal.h"
 #include "fn_kernels.h"
 
@@ -352,6 +354,193 @@ __global__ __launch_bounds__(256) void k_pair_backward(Sys s, const double *x, c
 }
 
 // ---------------------------------------------------------------------------
+// pair stream adjoint on the matrix cores (FP32 parameters): the quantities
+// of k_pair_backward for WB (walker, electron) rows at once, each pair
+// layer's three products as v_mfma_f32_16x16x4f32 over 16-row blocks of
+// pairs:
+//   forward recompute   z = h W2 + c2     (A: pair rows, B: packed W2^T)
+//   activation adjoint  g = dz W2^T       (A: dz rows, B: W2 read from W2^T)
+//   weight gradient     dW2 = h^T dz      (pairs are the reduction)
+// LDS: the packed pair weights (matrix-core pair kernel layout), then slabs of
+// round_up(WB N, 16) pair rows x (wc + 4) floats: features F, tanh outputs
+// T_1 .. T_{L-1}, adjoint G, and D (the running activation during the
+// recompute, dz afterwards).  The recompute repeats the forward kernel's
+// operations in its order, and activations h^1 = T_1, h^l = T_l + h^{l-1}
+// are rebuilt in the forward's order, so both equal the forward's values bit
+// for bit.  Rows past the pairs held here get a zero adjoint.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pair_backward_mfma(Sys s, const double *x, const float *__restrict__ Wpk,
+                                                            ParamLayout P, int64_t B, const float *GGI, int64_t ldg,
+                                                            int64_t gg_layer_stride, int WB, float *PP, int64_t npp)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    __shared__ float red[256];
+    const int wc = round_up(s.w2, 16), RS = wc + 4, ncb = wc / 16;
+    const int L = s.L, N = s.N;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, li = lane & 15;
+    const int64_t wi0 = (int64_t)blockIdx.x * WB;
+    const int nwi = B * N - wi0 < WB ? (int)(B * N - wi0) : WB;
+    const int np = nwi * N;                           // pairs held here
+    const int nal = round_up(WB * N, 16);             // rows per slab
+    const int nblk = (np + 15) / 16;
+    const int wtot = pair_mfma_woff(s, L - 1);
+    float *Wsm = (float *)smem_raw;
+    float *F = Wsm + wtot;
+    auto Ts = [&](int l) { return F + (int64_t)l * nal * RS; };   // l = 1 .. L - 1
+    float *G = F + (int64_t)L * nal * RS;
+    float *D = G + (int64_t)nal * RS;
+    for (int q = 4 * tid; q < wtot; q += 4 * blockDim.x) *(float4 *)(Wsm + q) = *(const float4 *)(Wpk + q);
+    for (int q = 4 * tid; q < (L + 2) * nal * RS; q += 4 * blockDim.x)
+        *(float4 *)(F + q) = make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+    for (int q = tid; q < np; q += blockDim.x) {
+        const int bb = q / N, j = q % N;
+        const int64_t wi = wi0 + bb, w = wi / N;
+        const int i = (int)(wi % N);
+        if (j == i) continue;
+        const double *xw = x + w * 3 * N;
+        const double d0 = xw[3 * i] - xw[3 * j], d1 = xw[3 * i + 1] - xw[3 * j + 1], d2 = xw[3 * i + 2] - xw[3 * j + 2];
+        float *pf = F + (int64_t)q * RS, *pd = D + (int64_t)q * RS;
+        pf[0] = pd[0] = (float)d0;
+        pf[1] = pd[1] = (float)d1;
+        pf[2] = pd[2] = (float)d2;
+        pf[3] = pd[3] = (float)sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    }
+    __syncthreads();
+    // forward recompute; D carries h^l
+    for (int l = 0; l + 1 < L; ++l) {
+        const int KP = pair_mfma_kp(s, l), KS = KP + 4;
+        const float *Wl = Wsm + pair_mfma_woff(s, l);
+        const float *bl = Wl + wc * KS;
+        float *Tn = Ts(l + 1);
+        for (int blk = wave; blk < nblk; blk += 4) {
+            const int r0 = blk * 16;
+            f32x4 acc[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const float bv = cb < ncb ? bl[cb * 16 + li] : 0.f;
+                acc[cb] = f32x4{bv, bv, bv, bv};
+            }
+            const float *arow = D + (int64_t)(r0 + li) * RS + 4 * g;
+            for (int kb = 0; kb < KP; kb += 16) {
+                const float4 a4 = *(const float4 *)(arow + kb);
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    if (cb < ncb) {
+                        const float4 b4 = *(const float4 *)(Wl + (cb * 16 + li) * KS + kb + 4 * g);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.x, b4.x, acc[cb], 0, 0, 0);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.y, b4.y, acc[cb], 0, 0, 0);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.z, b4.z, acc[cb], 0, 0, 0);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.w, b4.w, acc[cb], 0, 0, 0);
+                    }
+                }
+            }
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                if (cb >= ncb) continue;
+                const int64_t o = (int64_t)(r0 + 4 * g) * RS + cb * 16 + li;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float tv = tanhf(acc[cb][e]);
+                    Tn[o + e * RS] = tv;
+                    D[o + e * RS] = tv + (l >= 1 ? D[o + e * RS] : 0.f);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const int nu = s.nu, nd = s.nd;
+    auto mean_adj = [&](int l, int p, int o) -> float {
+        const int dp = layer_dp(s, l);
+        if (o >= dp || p >= np) return 0.f;
+        const int j = p % N, spj = j < nu ? 0 : 1;
+        const int n = spj == 0 ? nu : nd;
+        return GGI[(int64_t)l * gg_layer_stride + (wi0 + p / N) * ldg + spj * dp + o] / (float)n;
+    };
+    for (int q = tid; q < nal * wc; q += blockDim.x) {
+        const int p = q / wc, o = q % wc;
+        G[(int64_t)p * RS + o] = mean_adj(L - 1, p, o);
+    }
+    __syncthreads();
+    float *pp = PP + (int64_t)blockIdx.x * npp;
+    const int nparts = blockDim.x / wc;
+    for (int l = L - 1; l >= 1; --l) {
+        // pair layer l - 1 maps h^{l-1} (width dp) to h^l (width w2)
+        const int dp = layer_dp(s, l - 1), KP = pair_mfma_kp(s, l - 1), KS = KP + 4;
+        const float *Wl = Wsm + pair_mfma_woff(s, l - 1);
+        const float *Tl = Ts(l);
+        for (int q = tid; q < nal * wc; q += blockDim.x) {
+            const int64_t e = (int64_t)(q / wc) * RS + q % wc;
+            const float tv = Tl[e];
+            D[e] = G[e] * (1.f - tv * tv);
+        }
+        __syncthreads();
+        // dW2[k][o] = sum over pairs of h^{l-1}[k] dz[o]
+        const int nkb = KP / 16;
+        for (int ob = wave; ob < nkb * ncb; ob += 4) {
+            const int kbk = ob / ncb, cb = ob % ncb;
+            const int k = kbk * 16 + li, o = cb * 16 + li;
+            f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int pb = 0; pb < nal; pb += 4) {
+                const int64_t r = (int64_t)(pb + g) * RS;
+                float h;
+                if (l - 1 == 0) {
+                    h = F[r + k];
+                } else {
+                    h = Ts(1)[r + k];
+                    for (int m = 2; m <= l - 1; ++m) h = Ts(m)[r + k] + h;
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(h, D[r + o], acc, 0, 0, 0);
+            }
+            const int64_t wof = P.W2[l - 1] - P.W2[0];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int kk = kbk * 16 + 4 * g + e;
+                if (kk < dp && o < s.w2) pp[wof + (int64_t)kk * s.w2 + o] = acc[e];
+            }
+        }
+        // dc2[o] = sum over pairs of dz[o]: partial sums here, total below
+        if (tid < nparts * wc) {
+            const int o = tid % wc;
+            float v = 0.f;
+            for (int p = tid / wc; p < np; p += nparts) v += D[(int64_t)p * RS + o];
+            red[tid] = v;
+        }
+        // adjoint of h^{l-1}: dz W2^T + residual + spin-mean part (into G)
+        for (int blk = wave; blk < nblk; blk += 4) {
+            const int r0 = blk * 16;
+            const float *arow = D + (int64_t)(r0 + li) * RS + 4 * g;
+            for (int kbk = 0; kbk < nkb; ++kbk) {
+                f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int ob = 0; ob < wc; ob += 16) {
+                    const float4 a4 = *(const float4 *)(arow + ob);
+                    const float *wb = Wl + (ob + 4 * g) * KS + kbk * 16 + li;   // W2[k][o] = W2^T[o][k]
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.x, wb[0], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.y, wb[KS], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.z, wb[2 * KS], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.w, wb[3 * KS], acc, 0, 0, 0);
+                }
+                const int k = kbk * 16 + li;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int p = r0 + 4 * g + e;
+                    float *gp = G + (int64_t)p * RS + k;
+                    float v = 0.f;
+                    if (k < dp && p < np) v = acc[e] + (l - 1 >= 1 ? *gp : 0.f) + mean_adj(l - 1, p, k);
+                    *gp = v;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < s.w2) {
+            float v = 0.f;
+            for (int q = 0; q < nparts; ++q) v += red[q * wc + tid];
+            pp[(P.c2[l - 1] - P.W2[0]) + tid] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // weight-gradient products C[a][b] = sum_r X[r][a] Y[r][b] (split over rows)
 // partial[s][a][b] for row range s; X rows may be remapped by groups.
 // ---------------------------------------------------------------------------
@@ -599,14 +788,41 @@ int pair_backward_wb(const Sys &s, size_t elem)
     return wb;
 }
 
-template <typename T>
-void launch_pair_backward(const Sys &s, const double *x, const T *theta, const ParamLayout &P, int64_t B, const T *GGI,
-                          int64_t ldg, int64_t gg_layer_stride, T *PP, int64_t npp, hipStream_t st)
+// matrix-core adjoint: LDS of WB (walker, electron) rows; about 64 pairs per
+// workgroup (one row block per wave) within 64 KiB
+static size_t pair_backward_mfma_lds(const Sys &s, int wb)
 {
+    const int wc = round_up(s.w2, 16);
+    const size_t nal = (size_t)round_up(wb * s.N, 16);
+    return ((size_t)pair_mfma_woff(s, s.L - 1) + (size_t)(s.L + 2) * nal * (wc + 4)) * sizeof(float);
+}
+
+static int pair_backward_mfma_wb(const Sys &s)
+{
+    int wb = s.N >= 64 ? 1 : 64 / s.N;
+    while (wb > 1 && pair_backward_mfma_lds(s, wb) > 64 * 1024) --wb;
+    return wb;
+}
+
+template <typename T>
+int64_t launch_pair_backward(const Sys &s, const double *x, const T *theta, const ParamLayout &P, int64_t B,
+                             const T *GGI, int64_t ldg, int64_t gg_layer_stride, const float *wpair, T *PP,
+                             int64_t npp, hipStream_t st)
+{
+    if constexpr (std::is_same<T, float>::value) {
+        if (wpair && g_pair_mfma && s.w2 <= 64 && s.w2 % 4 == 0 && pair_backward_mfma_lds(s, 1) <= 64 * 1024) {
+            const int wb = pair_backward_mfma_wb(s);
+            const int64_t grid = (B * s.N + wb - 1) / wb;
+            hipLaunchKernelGGL(k_pair_backward_mfma, dim3((unsigned)grid), dim3(256), pair_backward_mfma_lds(s, wb), st,
+                               s, x, wpair, P, B, GGI, ldg, gg_layer_stride, wb, PP, npp);
+            return grid;
+        }
+    }
     const int wb = pair_backward_wb(s, sizeof(T));
-    hipLaunchKernelGGL(k_pair_backward<T>, dim3((unsigned)((B * s.N + wb - 1) / wb)), dim3(256),
-                       pair_backward_lds_wb(s, sizeof(T), wb), st, s, x, theta, P, B, GGI, ldg, gg_layer_stride, wb,
-                       PP, npp);
+    const int64_t grid = (B * s.N + wb - 1) / wb;
+    hipLaunchKernelGGL(k_pair_backward<T>, dim3((unsigned)grid), dim3(256), pair_backward_lds_wb(s, sizeof(T), wb), st,
+                       s, x, theta, P, B, GGI, ldg, gg_layer_stride, wb, PP, npp);
+    return grid;
 }
 
 int tn_splits(int64_t R)
@@ -667,8 +883,8 @@ void launch_pack_head_bwd(const T *theta, int64_t woff, int w1, int kn, int KNp,
     template void launch_bwd_gz<T>(const T *, const T *, int64_t, int, int, T *, T *, hipStream_t);                   \
     template void launch_bwd_gh<T>(const T *, const T *, const T *, int64_t, int, int, int, int, int, T *,           \
                                    hipStream_t);                                                                      \
-    template void launch_pair_backward<T>(const Sys &, const double *, const T *, const ParamLayout &, int64_t,       \
-                                          const T *, int64_t, int64_t, T *, int64_t, hipStream_t);                    \
+    template int64_t launch_pair_backward<T>(const Sys &, const double *, const T *, const ParamLayout &, int64_t,    \
+                                             const T *, int64_t, int64_t, const float *, T *, int64_t, hipStream_t);  \
     template void launch_tn<T>(const T *, int64_t, int, const T *, int64_t, int, int64_t, int64_t, int64_t, int64_t,  \
                                T *, double *, int64_t, int64_t, hipStream_t);                                         \
     template void launch_colsum<T>(const T *, int64_t, int, int64_t, T *, double *, int64_t, int, int64_t,           \

@@ -76,41 +76,15 @@ template <typename T>
 void launch_bwd_gh(const T *Gh, const T *Gy, const T *Gg, int64_t B, int N, int nu, int dh, int w1, int resid, T *Gout,
                    hipStream_t st);
 size_t pair_backward_lds(const Sys &s, size_t elem);
-int pair_backward_wb(const Sys &s, size_t elem);      // (walker, electron) rows per workgroup
+int pair_backward_wb(const Sys &s, size_t elem);      // (walker, electron) rows per vector-kernel workgroup
+// Pair-stream adjoint: writes one row of npp weight-gradient shares per
+// workgroup into PP and returns the number of rows written.  wpair: the pair
+// weights packed for the matrix-core pair kernel (FP32 parameters), or
+// nullptr for the vector kernel.
 template <typename T>
-void launch_pair_backward(const Sys &s, const double *x, const T *theta, const ParamLayout &P, int64_t B, const T *GGI,
-                          int64_t ldg, int64_t gg_layer_stride, T *PP, int64_t npp, hipStream_t st);
-int max_splits();
-template <typename T>
-void launch_tn(const T *X, int64_t ldx, int NA, const T *Y, int64_t ldy, int NB, int64_t R, int64_t per,
-               int64_t stride, int64_t off, T *part, double *acc, int64_t acc_off, int64_t lda_out, hipStream_t st);
-template <typename T>
-void launch_colsum(const T *in, int64_t ld, int C, int64_t R, T *part, double *acc, int64_t off, int env_map,
-                   int64_t off2, hipStream_t st);
-void launch_zero_f64(double *p, int64_t n, hipStream_t st);
-template <typename T>
-void launch_grad_out(const double *acc, int64_t n, T *grad, hipStream_t st);
-template <typename T>
-void launch_pack_head_bwd(const T *theta, int64_t woff, int w1, int kn, int KNp, T *Wb, hipStream_t st);
-
-// backward (fn_backward.hip)
-size_t det_backward_lds(int n);
-void launch_det_backward(const double *Phi, const double *DR, const double *coeff, int64_t B, int K, int n, int sp,
-                         int nu, int nd, int rec, double *GA, hipStream_t st);
-template <typename T>
-void launch_env_backward(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof,
-                         int sp, const T *O, int64_t ldo, const double *GA, int64_t B, int KNp, T *Ga, T *EP,
-                         hipStream_t st);
-template <typename T>
-void launch_bwd_gz(const T *Gy, const T *Tt, int64_t B, int N, int w1, T *Gz, T *SGz, hipStream_t st);
-template <typename T>
-void launch_bwd_gh(const T *Gh, const T *Gy, const T *Gg, int64_t B, int N, int nu, int dh, int w1, int resid, T *Gout,
-                   hipStream_t st);
-size_t pair_backward_lds(const Sys &s, size_t elem);
-int pair_backward_wb(const Sys &s, size_t elem);      // (walker, electron) rows per workgroup
-template <typename T>
-void launch_pair_backward(const Sys &s, const double *x, const T *theta, const ParamLayout &P, int64_t B, const T *GGI,
-                          int64_t ldg, int64_t gg_layer_stride, T *PP, int64_t npp, hipStream_t st);
+int64_t launch_pair_backward(const Sys &s, const double *x, const T *theta, const ParamLayout &P, int64_t B,
+                             const T *GGI, int64_t ldg, int64_t gg_layer_stride, const float *wpair, T *PP, int64_t npp,
+                             hipStream_t st);
 int max_splits();
 template <typename T>
 void launch_tn(const T *X, int64_t ldx, int NA, const T *Y, int64_t ldy, int NB, int64_t R, int64_t per,
