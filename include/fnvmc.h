@@ -235,8 +235,10 @@ fn_status fn_timing_read(const char *name, double *total_ms, int64_t *launches);
    forward-Laplacian epilogue) where the row layout allows it, instead of a
    product kernel followed by an epilogue kernel.  Both give the same
    arithmetic up to the order of the final additions.
-   "pair_mfma" 0/1: FP32 pair layers as matrix-core products (default 1)
-   or on the vector ALUs; the two differ in summation order only.
+   "pair_mfma" 0/1: FP32 pair layers, and their adjoint in the parameter
+   gradient, as matrix-core products (default 1) or on the vector ALUs; the
+   two differ in summation order only.  Unknown names and out-of-range
+   values return FN_EINVAL.
    "pair_oc" 0/1/2/4: output columns per thread of the vector pair kernel
    (0: chosen by N and w2).  "pair_items" 0..4096: (pair, column group)
    items per workgroup of the vector kernel, pair rows per workgroup of the
