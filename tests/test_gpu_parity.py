@@ -347,3 +347,51 @@ def test_log_psi_full_size_sampled():
             _check_logpsi(lp.cpu().numpy()[idx], ref, 1e-5, f"{name} {walkers} {prec} sampled",
                           _conditioning(o, s, th, x[idx]), False)
             np.testing.assert_array_equal(sg.cpu().numpy()[idx], ref["sign"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
+def test_degenerate_walkers_stay_isolated(prec):
+    """Walkers at the singular points of the features: two same-spin
+    electrons coinciding (a node of psi: log|psi| far below the rest, or
+    -inf), an electron on a nucleus, an up and a down electron coinciding.
+    Their forward-Laplacian local energy is non-finite on both sides (the
+    tangent of a zero distance is 0/0); their value-form log|psi| is finite
+    except at the node and matches the oracle.  The other walkers of the
+    batch match the oracle and their own results in a batch without the
+    degenerate ones; a batch of one walker matches the oracle."""
+    s = I.lih()
+    torch, fnvmc, cfg, tt, xt, th, x = _setup(s, prec, 7)
+    x = x.copy()
+    x[0, 1] = x[0, 0]                      # up, up: node
+    x[1, 2] = s.nuc_xyz[0]                 # electron on the Li nucleus
+    x[2, 2] = x[2, 0]                      # down on up: not a node
+    xt = torch.tensor(x, dtype=torch.float64, device="cuda")
+    o = O.Oracle(s)
+    ref_l = o.log_psi(th, x)
+    ref_e = o.local_energy(th, x)
+    lp, sg = fnvmc.fn_log_psi(cfg, tt, xt)
+    e, _, _ = fnvmc.fn_local_energy(cfg, tt, xt)
+    torch.cuda.synchronize()
+    lp, sg, e = lp.cpu().numpy(), sg.cpu().numpy(), e.cpu().numpy()
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    print(f"{prec}: log|psi| GPU {lp[:3]} oracle {ref_l['log_abs'][:3]}; E_L GPU {e[:3]} oracle {ref_e['e_loc'][:3]}")
+    assert not np.isnan(lp[0]) and lp[0] < -20.0 and ref_l["log_abs"][0] < -20.0
+    C = _conditioning(o, s, th, x[1:3])      # the node walker's matrices are singular
+    for w in (1, 2):
+        slack = 0.0 if prec == "fp64" else 2e-7 * C[w - 1]
+        assert abs(lp[w] - ref_l["log_abs"][w]) <= tol * max(1.0, abs(ref_l["log_abs"][w])) + slack, w
+        assert sg[w] == ref_l["sign"][w]
+    assert not np.isfinite(e[:3]).any() and not np.isfinite(ref_e["e_loc"][:3]).any()
+    good = np.arange(3, 7)
+    etol = 1e-7 if prec == "fp64" else 1e-3 + 1e-4 * np.abs(ref_e["parts"][good, 0])
+    assert np.isfinite(e[good]).all()
+    assert (np.abs(e[good] - ref_e["e_loc"][good]) <= etol).all()
+    # the same walkers without the degenerate ones, and one walker alone
+    e2, _, _ = fnvmc.fn_local_energy(cfg, tt, xt[3:].contiguous())
+    e1, lp1, _ = fnvmc.fn_local_energy(cfg, tt, xt[5:6].contiguous())
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(e2.cpu().numpy(), e[good], rtol=1e-9, atol=1e-9)
+    assert abs(e1.cpu().numpy()[0] - ref_e["e_loc"][5]) <= (1e-7 if prec == "fp64" else 1e-3 + 1e-4 * abs(ref_e["parts"][5, 0]))
+    C5 = _conditioning(o, s, th, x[5:6])[0]
+    assert abs(lp1.cpu().numpy()[0] - ref_l["log_abs"][5]) <= (tol * max(1.0, abs(ref_l["log_abs"][5]))
+                                                               + (0.0 if prec == "fp64" else 2e-7 * C5))
