@@ -618,18 +618,27 @@ __global__ __launch_bounds__(256) void k_tn_partial<float>(const float *X, int64
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // a thread keeps column tid & 63 and rows tid / 64 + 4 u of a stage; all
+    // of its loads are issued before the first store to LDS
+    const int c = tid & 63, rq = tid >> 6;
+    const bool cx = a0 + c < NA, cy = b0 + c < NB;
     for (int64_t rb = r0; rb < r1; rb += RC) {
-        for (int q = tid; q < RC * 64; q += 256) {
-            const int rr = q / 64, c = q % 64;
-            const int64_t r = rb + rr;
-            float vx = 0.f, vy = 0.f;
+        float vx[RC / 4], vy[RC / 4];
+#pragma unroll
+        for (int u = 0; u < RC / 4; ++u) {
+            const int64_t r = rb + rq + 4 * u;
+            vx[u] = 0.f;
+            vy[u] = 0.f;
             if (r < r1) {
                 const int64_t xr = per > 0 ? remap_row(r, per, stride, off) : r;
-                if (a0 + c < NA) vx = X[xr * ldx + a0 + c];
-                if (b0 + c < NB) vy = Y[r * ldy + b0 + c];
+                if (cx) vx[u] = X[xr * ldx + a0 + c];
+                if (cy) vy[u] = Y[r * ldy + b0 + c];
             }
-            sx[rr][c] = vx;
-            sy[rr][c] = vy;
+        }
+#pragma unroll
+        for (int u = 0; u < RC / 4; ++u) {
+            sx[rq + 4 * u][c] = vx[u];
+            sy[rq + 4 * u][c] = vy[u];
         }
         __syncthreads();
 #pragma unroll 4
@@ -687,8 +696,10 @@ __global__ __launch_bounds__(256) void k_colsum_partial(const T *in, int64_t ld,
     const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
     const int64_t r1 = r0 + rows_per_split < R ? r0 + rows_per_split : R;
     double acc = 0.0;
-    if (c < C)
+    if (c < C) {
+#pragma unroll 8
         for (int64_t r = r0 + ty; r < r1; r += 4) acc += (double)in[r * ld + c];
+    }
     red[ty][threadIdx.x & 63] = acc;
     __syncthreads();
     if (ty == 0 && c < C) part[(int64_t)blockIdx.y * C + c] = (T)(red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x]);
