@@ -138,6 +138,114 @@ __global__ __launch_bounds__(64) void k_det_backward(const double *Phi, const do
     }
 }
 
+// The same for spins of at most NS electrons with one thread per (walker,
+// determinant k): the LU factors in registers, the inverse formed one column
+// at a time (column c of A^-1 is row c of the output), every operation in the
+// order of the wave kernel.
+template <int NS>
+__global__ __launch_bounds__(256) void k_det_backward_small(const double *Phi, const double *DR, const double *coeff,
+                                                            int64_t B, int K, int n, int nu, int nd, int rec,
+                                                            double *GA)
+{
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= B * K) return;
+    const int64_t w = id / K;
+    const int k = (int)(id % K);
+    const int64_t nn = (int64_t)n * n;
+    double *out = GA + (w * K + k) * nn;
+    const double *ru = DR + (w * 2 + 0) * (int64_t)K * rec, *rd = DR + (w * 2 + 1) * (int64_t)K * rec;
+    double lmax = -INFINITY;
+    for (int q = 0; q < K; ++q) {
+        const double s = (nu > 0 ? ru[q * rec] : 1.0) * (nd > 0 ? rd[q * rec] : 1.0);
+        const double l = (nu > 0 ? ru[q * rec + 1] : 0.0) + (nd > 0 ? rd[q * rec + 1] : 0.0);
+        if (s != 0.0 && l > lmax) lmax = l;
+    }
+    double S = 0.0, mine = 0.0;
+    if (lmax > -INFINITY)
+        for (int q = 0; q < K; ++q) {
+            const double s = (nu > 0 ? ru[q * rec] : 1.0) * (nd > 0 ? rd[q * rec] : 1.0);
+            const double l = (nu > 0 ? ru[q * rec + 1] : 0.0) + (nd > 0 ? rd[q * rec + 1] : 0.0);
+            const double t = s != 0.0 ? s * exp(l - lmax) : 0.0;
+            S += t;
+            if (q == k) mine = t;
+        }
+    const bool ok = lmax > -INFINITY && S != 0.0 && S == S;
+    const double sc = ok ? coeff[w] * mine / S : 0.0;
+    double LU[NS][NS];
+    int perm[NS];
+    const double *A = Phi + (w * K + k) * nn;
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+        perm[r] = r;
+#pragma unroll
+        for (int c = 0; c < NS; ++c) LU[r][c] = r < n && c < n ? A[r * n + c] : 0.0;
+    }
+    bool sing = false;
+#pragma unroll
+    for (int c = 0; c < NS; ++c) {
+        if (c >= n || sing) continue;
+        int p = c;
+        double best = fabs(LU[c][c]);
+#pragma unroll
+        for (int r = c + 1; r < NS; ++r) {
+            if (r >= n) continue;
+            const double v = fabs(LU[r][c]);
+            if (v > best) { best = v; p = r; }
+        }
+        if (best == 0.0) { sing = true; continue; }
+        if (p != c) {
+            // row swap with a register-indexed partner: select over the rows
+#pragma unroll
+            for (int r = c + 1; r < NS; ++r) {
+                if (r == p) {
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) { const double t = LU[c][q]; LU[c][q] = LU[r][q]; LU[r][q] = t; }
+                    const int t = perm[c]; perm[c] = perm[r]; perm[r] = t;
+                }
+            }
+        }
+        const double ip = 1.0 / LU[c][c];
+#pragma unroll
+        for (int r = c + 1; r < NS; ++r)
+            if (r < n) LU[r][c] *= ip;
+#pragma unroll
+        for (int r = c + 1; r < NS; ++r)
+#pragma unroll
+            for (int cc = c + 1; cc < NS; ++cc)
+                if (r < n && cc < n) LU[r][cc] -= LU[r][c] * LU[c][cc];
+    }
+    if (sing || sc == 0.0) {
+        for (int q = 0; q < nn; ++q) out[q] = 0.0;
+        return;
+    }
+    for (int c = 0; c < n; ++c) {
+        double v[NS];
+#pragma unroll
+        for (int r = 0; r < NS; ++r) v[r] = perm[r] == c ? 1.0 : 0.0;
+#pragma unroll
+        for (int r = 1; r < NS; ++r) {
+            if (r >= n) continue;
+            double acc = v[r];
+#pragma unroll
+            for (int q = 0; q < r; ++q) acc -= LU[r][q] * v[q];
+            v[r] = acc;
+        }
+#pragma unroll
+        for (int r = NS - 1; r >= 0; --r) {
+            if (r >= n) continue;
+            double acc = v[r];
+#pragma unroll
+            for (int q = r + 1; q < NS; ++q)
+                if (q < n) acc -= LU[r][q] * v[q];
+            v[r] = acc / LU[r][r];
+        }
+        // out[i][j] = sc (A^-1)[j][i]: column c of A^-1 is row c of out
+#pragma unroll
+        for (int r = 0; r < NS; ++r)
+            if (r < n) out[c * n + r] = sc * v[r];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // envelope / orbital adjoint, one thread per (walker, orbital column):
 //   Ga[w n + j][col] = G env                       (adjoint of a = w . h + g)
@@ -753,6 +861,21 @@ size_t det_backward_lds(int n) { return (size_t)2 * n * n * sizeof(double) + (si
 void launch_det_backward(const double *Phi, const double *DR, const double *coeff, int64_t B, int K, int n, int sp,
                          int nu, int nd, int rec, double *GA, hipStream_t st)
 {
+    const unsigned g = (unsigned)((B * K + 255) / 256);
+    switch (n) {
+#define FN_DBS(NS) \
+    case NS: hipLaunchKernelGGL(k_det_backward_small<NS>, dim3(g), dim3(256), 0, st, Phi, DR, coeff, B, K, n, nu, nd, rec, GA); return;
+        FN_DBS(1)
+        FN_DBS(2)
+        FN_DBS(3)
+        FN_DBS(4)
+        FN_DBS(5)
+        FN_DBS(6)
+        FN_DBS(7)
+        FN_DBS(8)
+#undef FN_DBS
+    default: break;
+    }
     hipLaunchKernelGGL(k_det_backward, dim3((unsigned)(B * K)), dim3(64), det_backward_lds(n), st, Phi, DR, coeff, B, K,
                        n, sp, nu, nd, rec, GA);
 }
