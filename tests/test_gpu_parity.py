@@ -107,7 +107,7 @@ def test_log_psi(name, prec, walkers, tol):
     np.testing.assert_array_equal(sg.cpu().numpy(), ref["sign"])
 
 
-def _check_energy(e, parts, ref, tol, label, kappa=None, rel=1e-4):
+def _check_energy(e, parts, ref, tol, label, kappa=None, rel=1e-4, mean_tol=1e-3):
     d = np.abs(e - ref["e_loc"])
     dm = abs(e.mean() - ref["e_loc"].mean())
     print(f"{label}: E_L max |d| {d.max():.2e} Ha, median {np.median(d):.2e}, p99 {np.percentile(d, 99):.2e}, "
@@ -124,7 +124,8 @@ def _check_energy(e, parts, ref, tol, label, kappa=None, rel=1e-4):
               + ", ".join(f"({d[i]:.1e}, {kappa[i]:.0f}, {kin[i]:.1f})" for i in order))
         assert np.median(d / (1.0 + kin)) <= rel / 10
     assert np.all(d <= bound), (d / bound).max()
-    assert dm <= 1e-3
+    if mean_tol is not None:
+        assert dm <= mean_tol
     return d
 
 
@@ -395,3 +396,34 @@ def test_degenerate_walkers_stay_isolated(prec):
     C5 = _conditioning(o, s, th, x[5:6])[0]
     assert abs(lp1.cpu().numpy()[0] - ref_l["log_abs"][5]) <= (tol * max(1.0, abs(ref_l["log_abs"][5]))
                                                                + (0.0 if prec == "fp64" else 2e-7 * C5))
+
+
+def test_serving_types_local_energy_bf16x6():
+    """Every atom / ion type of the serving mix (Z 2..10, charge -1..+2:
+    N = 1..11, spin channels down to empty) in the mixed mode: log|psi| and
+    the forward-Laplacian local energy of a few walkers within the oracle
+    bounds (per walker with the conditioning terms; the 1 mHa mean over the
+    walkers with kappa <= 10)."""
+    worst_l, worst_e = 0.0, 0.0
+    for z, q in I.serving_job_types():
+        s = I.atom_ion(z, q, walkers=6)
+        torch, fnvmc, cfg, tt, xt, th, x = _setup(s, "bf16x6", 6)
+        o = O.Oracle(s)
+        ref_l = o.log_psi(th, x)
+        ref_e = o.local_energy(th, x)
+        lp, sg = fnvmc.fn_log_psi(cfg, tt, xt)
+        e, lp2, parts = fnvmc.fn_local_energy(cfg, tt, xt)
+        torch.cuda.synchronize()
+        label = f"Z={z} q={q:+d} ({s.n_up},{s.n_dn})"
+        _check_logpsi(lp.cpu().numpy(), ref_l, 1e-5, label, _conditioning(o, s, th, x), False)
+        np.testing.assert_array_equal(sg.cpu().numpy(), ref_l["sign"])
+        kap = _kappa_sum(o, th, x)
+        # six walkers: one near a node (large kappa) can carry the batch mean, so
+        # the 1 mHa mean is taken over the well-conditioned walkers only
+        d = _check_energy(e.cpu().numpy(), parts.cpu().numpy(), ref_e, 1e-3, label, kap, mean_tol=None)
+        good = kap <= 10.0
+        if good.any():
+            assert abs(e.cpu().numpy()[good].mean() - ref_e["e_loc"][good].mean()) <= 1e-3, label
+        worst_e = max(worst_e, float(d.max()))
+        worst_l = max(worst_l, float(np.abs(lp.cpu().numpy() - ref_l["log_abs"]).max()))
+    print(f"serving types: worst |d log psi| {worst_l:.2e}, worst |d E_L| {worst_e:.2e} Ha")
