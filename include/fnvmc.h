@@ -153,7 +153,11 @@ fn_status vmc_metropolis_step_ext(const fn_config *cfg, const void *theta, doubl
    grad = sum_p (2/B)(e_loc_p - E) d log|psi_p| / d theta.
    e_loc: device [B] FP64.  grad: device [P] out (theta's type).
    stats: device [3] FP64 out (mean, variance with 1/B, standard error
-   sqrt(var/B)), may be NULL. */
+   sqrt(var/B)), may be NULL.  The call takes positions and energies only:
+   it recomputes the value-form stream activations (one row per electron,
+   not the forward-Laplacian rows) in its own forward pass, keeps each
+   layer's rows in the workspace for the backward, and the pair adjoint
+   recomputes the pair activations from the positions. */
 fn_status fn_param_grad(const fn_config *cfg, const void *theta, const double *x, int64_t B, const double *e_loc,
                         void *grad, double *stats, void *ws, size_t ws_bytes, void *stream);
 
