@@ -783,6 +783,10 @@ fn_status fn_tuning_set(const char *name, int64_t value)
         fn::g_use_fused_layer = value != 0;
         return FN_OK;
     }
+    if (strcmp(name, "layer_dma") == 0) {
+        fn::g_layer_dma = value != 0;
+        return FN_OK;
+    }
     if (strcmp(name, "pair_mfma") == 0) {
         fn::g_pair_mfma = value != 0;
         return FN_OK;

@@ -11,6 +11,10 @@
 // tiles of 32 reduction steps are staged through LDS, the next tile's global
 // loads issued before the current tile's matrix instructions; split-BF16
 // operand fragments are loaded once and reused by every product of parts.
+// In the split-BF16 modes the copies go straight from global memory into a
+// two-stage LDS ring (FP32 activations, pre-split weights), and each wave
+// splits its activation fragments as it reads them; otherwise the loads are
+// staged through registers and split once as they are stored.
 // Each electron owns TP rows (TP = 1 value only, or 16 / 32 / 64), so an
 // electron never straddles a tile.  The epilogue parks the pre-activations
 // in LDS (over the operand stage) and finishes each (electron, column) pair
@@ -44,10 +48,15 @@ constexpr int LDF = LBK + 4;
 // of an electron that hold live rows (value .. Laplacian); with TP = 64 a
 // wave's four row blocks are one electron's, and blocks past LIVE (padding
 // only, zero in and out) take no matrix instructions.
-template <int MODE, int TP, int LBN, int LIVE>
+// DMA: split-BF16 modes with 128-column tiles only.  Activation tiles (FP32)
+// and weight tiles (BF16 parts) go from global memory straight into one of
+// two LDS stages; each wave splits its own activation fragments when it
+// reads them.  One barrier per reduction step, no register staging.
+template <int MODE, int TP, int LBN, int LIVE, bool DMA>
 __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 {
     static_assert(LBN == 128 || (LBN == 32 && TP == 1), "column tile");
+    static_assert(!DMA || (LBN == 128 && MODE != GEMM_F32), "staged copies");
     static_assert(LIVE == (TP + 15) / 16 || (TP == 64 && LBN == 128 && LIVE == 3), "live row blocks");
     constexpr int WI = LBN == 128 ? 4 : 2, WJ = LBN == 128 ? 4 : 2;   // 16 x 16 blocks per wave
     constexpr bool F32 = MODE == GEMM_F32;
@@ -58,7 +67,10 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
     constexpr int XS = LBN + 4;                      // float4-aligned rows of the pre-activation tile
     constexpr int XSZ = LBM * XS * 4;
     constexpr int ESZ = XSZ + 256 * 16;              // tile + partial Laplacian sources
-    constexpr int SMEM = ASZ + BSZ > ESZ ? ASZ + BSZ : ESZ;
+    constexpr int AST = LBM * LBK * 4;               // DMA stage: FP32 activations, then NP weight parts
+    constexpr int STG = AST + NP * LBN * LBK * 2;
+    constexpr int MSZ = DMA ? 2 * STG : ASZ + BSZ;
+    constexpr int SMEM = MSZ > ESZ ? MSZ : ESZ;
     __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
 
     int64_t rb;
@@ -188,6 +200,124 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 #pragma unroll
         for (int j = 0; j < WJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    if constexpr (DMA) {
+        // per lane: the 16-byte chunk it copies in each of the wave's 1 KB
+        // blocks.  Activations: block b = 4 wave + j holds rows 8 b .. 8 b + 7,
+        // chunk c of row r at position c ^ (r & 7).  Weights: block (part q,
+        // 2 wave + j) holds rows 16 (2 wave + j) .. + 15, chunk c at
+        // lds_chunk(r, c).  Rows are clamped as in the register path; rows
+        // that do not exist or are padding only feed accumulator rows that
+        // the epilogue never reads.
+        int64_t da1[4], da2[4], dw[2];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = 8 * (4 * wave + j) + (lane >> 3);
+            const int c = (lane & 7) ^ (r & 7);
+            const int64_t row = m0 + r;
+            const int lr = TP > 1 ? r % TP : 0;
+            const bool pad = TP > 1 && lr > a.n3 + 1;
+            int64_t rr = m0;
+            if (row < a.rows) rr = pad ? row - (lr - (a.n3 + 1)) : row;
+            da1[j] = rr * a.lda1 + 4 * c;
+            da2[j] = rr * a.lda2 + 4 * c;
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int r = 16 * (2 * wave + j) + (lane >> 2);
+            const int c = lds_chunk(r, lane & 3);
+            const int o = n0 + r;
+            dw[j] = (int64_t)(o < a.nout ? o : n0) * a.ldw + 8 * c;
+        }
+        auto dma = [&](int kt, int sgi) {
+            const int kb = kt * LBK;
+            unsigned char *stg = smem + sgi * STG;
+            const float *base = kb < a.K1 ? A1 + kb : A2 + (kb - a.K1);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                __builtin_amdgcn_global_load_lds((const void *)(base + (kb < a.K1 ? da1[j] : da2[j])),
+                                                 (__attribute__((address_space(3))) void *)(stg + (4 * wave + j) * 1024),
+                                                 16, 0, 0);
+            const uint16_t *W = (const uint16_t *)a.W + kb;
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    __builtin_amdgcn_global_load_lds(
+                        (const void *)(W + (int64_t)q * a.wpart + dw[j]),
+                        (__attribute__((address_space(3))) void *)(stg + AST + q * LBN * LBK * 2 + (2 * wave + j) * 1024),
+                        16, 0, 0);
+        };
+        if (ktiles > 0) dma(0, 0);
+        const int ar = wm * 16 * WI + (lane & 15), br = wn * 16 * WJ + (lane & 15);
+        const int ko = 8 * lds_chunk(lane & 15, lane >> 4);
+        const int h = lane >> 4, sw = lane & 7;          // rows ar + 16 i share bits 0-2 with lane
+        for (int kt = 0; kt < ktiles; ++kt) {
+            __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0): this lane's copies of step kt have landed
+            __syncthreads();                         // everyone's have; step kt - 1's stage is free
+            // every fragment of step kt is read into registers before the
+            // copies of step kt + 1 are issued, so no read of this stage
+            // has to wait for those copies
+            const unsigned char *stg = smem + (kt & 1) * STG;
+            const float *sA = (const float *)stg;
+            const uint16_t *sB = (const uint16_t *)(stg + AST);
+            float4 xa[WI][2];
+            bf16x8 ha[NP][WI], hb[NP][WJ];
+#pragma unroll
+            for (int i = 0; i < WI; ++i)
+                if (i < LIVE || TP != 64) {
+                    const float *rowp = sA + (ar + 16 * i) * LBK;
+                    xa[i][0] = *(const float4 *)(rowp + 4 * ((2 * h) ^ sw));
+                    xa[i][1] = *(const float4 *)(rowp + 4 * ((2 * h + 1) ^ sw));
+                }
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+#pragma unroll
+                for (int j = 0; j < WJ; ++j) hb[q][j] = *(const bf16x8 *)&sB[q * LBN * LDH + (br + 16 * j) * LDH + ko];
+            if (kt + 1 < ktiles) dma(kt + 1, (kt + 1) & 1);
+#pragma unroll
+            for (int i = 0; i < WI; ++i)
+                if (i < LIVE || TP != 64) {
+                    const float4 x0 = xa[i][0], x1 = xa[i][1];
+                    uint32_t p0[NP], p1[NP], p2[NP], p3[NP];
+                    split_bf16_pair<NP>(x0.x, x0.y, p0);
+                    split_bf16_pair<NP>(x0.z, x0.w, p1);
+                    split_bf16_pair<NP>(x1.x, x1.y, p2);
+                    split_bf16_pair<NP>(x1.z, x1.w, p3);
+#pragma unroll
+                    for (int q = 0; q < NP; ++q) {
+                        const uint4 u = make_uint4(p0[q], p1[q], p2[q], p3[q]);
+                        ha[q][i] = __builtin_bit_cast(bf16x8, u);
+                    }
+                }
+#pragma unroll
+            for (int sum = NP - 1; sum >= 0; --sum)
+#pragma unroll
+                for (int pa = 0; pa <= sum; ++pa)
+#pragma unroll
+                    for (int i = 0; i < WI; ++i)
+#pragma unroll
+                        for (int j = 0; j < WJ; ++j)
+                            if (i < LIVE || TP != 64)
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j],
+                                                                                    acc[i][j], 0, 0, 0);
+            // schedule: the first parts' conversions, then each matrix
+            // instruction of the first NP - 1 product groups followed by a
+            // share of the next parts' conversions (about 20 vector
+            // instructions per row block and part), then the rest
+            {
+                constexpr int NB = TP == 64 ? LIVE : WI, G = NB * WJ, VM = (20 * NB + G - 1) / G;
+                __builtin_amdgcn_sched_group_barrier(0x002, 4 * NB, 0);
+#pragma unroll
+                for (int g = 0; g < NP - 1; ++g)
+#pragma unroll
+                    for (int m = 0; m < G; ++m) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x002, VM, 0);
+                    }
+                __builtin_amdgcn_sched_group_barrier(0x008, G * (NP * (NP + 1) / 2 - (NP - 1)), 0);
+            }
+        }
+    } else {
     if (ktiles > 0) load_tile(0);
     for (int kt = 0; kt < ktiles; ++kt) {
         __syncthreads();
@@ -237,6 +367,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
                                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j],
                                                                                     acc[i][j], 0, 0, 0);
         }
+    }
     }
 
     // ---- epilogue through LDS: the pre-activation tile replaces the operand
@@ -428,6 +559,27 @@ bool stream_layer_supported(int mode, int TR, int w1, int W1p)
            (TR == 1 || TR == 16 || TR == 32 || TR == 64);
 }
 
+// Split-BF16 modes with 128-column tiles stage their operands by direct
+// global-to-LDS copies (two stages); the register-staged path stays for
+// FP32, the 32-column value tiles, and as the tuning switch "layer_dma" = 0.
+// Both give bitwise the same results.
+bool g_layer_dma = true;
+
+template <int MODE, bool DMA>
+static void launch_tiles(const LayerArgs &a, int TR, dim3 grid, hipStream_t st)
+{
+    switch (TR) {
+    case 1: hipLaunchKernelGGL((k_stream_layer<MODE, 1, 128, 1, DMA>), grid, dim3(256), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_stream_layer<MODE, 16, 128, 1, DMA>), grid, dim3(256), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_stream_layer<MODE, 32, 128, 2, DMA>), grid, dim3(256), 0, st, a); break;
+    default:
+        // rows value .. Laplacian (3N + 2) within the first three row blocks
+        if (a.n3 + 2 <= 48) hipLaunchKernelGGL((k_stream_layer<MODE, 64, 128, 3, DMA>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_stream_layer<MODE, 64, 128, 4, DMA>), grid, dim3(256), 0, st, a);
+        break;
+    }
+}
+
 template <int MODE>
 static void launch_mode(const LayerArgs &a, int TR, hipStream_t st)
 {
@@ -437,20 +589,16 @@ static void launch_mode(const LayerArgs &a, int TR, hipStream_t st)
     // each workgroup's reduction steps carry a quarter of the matrix work
     if (TR == 1 && blocks <= 512) {
         dim3 grid((unsigned)(nrb * ((a.W1p + 31) / 32)));
-        hipLaunchKernelGGL((k_stream_layer<MODE, 1, 32, 1>), grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_stream_layer<MODE, 1, 32, 1, false>), grid, dim3(256), 0, st, a);
         return;
     }
-    dim3 grid((unsigned)blocks);
-    switch (TR) {
-    case 1: hipLaunchKernelGGL((k_stream_layer<MODE, 1, 128, 1>), grid, dim3(256), 0, st, a); break;
-    case 16: hipLaunchKernelGGL((k_stream_layer<MODE, 16, 128, 1>), grid, dim3(256), 0, st, a); break;
-    case 32: hipLaunchKernelGGL((k_stream_layer<MODE, 32, 128, 2>), grid, dim3(256), 0, st, a); break;
-    default:
-        // rows value .. Laplacian (3N + 2) within the first three row blocks
-        if (a.n3 + 2 <= 48) hipLaunchKernelGGL((k_stream_layer<MODE, 64, 128, 3>), grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((k_stream_layer<MODE, 64, 128, 4>), grid, dim3(256), 0, st, a);
-        break;
+    if constexpr (MODE != GEMM_F32) {
+        if (g_layer_dma) {
+            launch_tiles<MODE, true>(a, TR, dim3((unsigned)blocks), st);
+            return;
+        }
     }
+    launch_tiles<MODE, false>(a, TR, dim3((unsigned)blocks), st);
 }
 
 void launch_stream_layer(int mode, const LayerArgs &a, int TR, hipStream_t st)

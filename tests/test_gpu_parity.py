@@ -315,6 +315,37 @@ def test_pair_kernels_and_launch_shapes(name, walkers):
         fnvmc.fn_tuning_set("pair_items", 0)
 
 
+@pytest.mark.parametrize("prec", ["bf16x6", "bf16x3", "bf16"])
+def test_layer_operand_staging_bitwise(prec):
+    """The fused layer's two ways of staging operand tiles (direct
+    global-to-LDS copies into a two-stage ring, or loads through registers)
+    give bitwise equal log|psi| and local energies: 16, 64 (three live row
+    blocks) and 64 (four) rows per electron with ragged last tiles, and value
+    rows in grids large enough for 128-column tiles.  The default (direct
+    copy) path is the one the oracle tests in this file check."""
+    cases = (("LiH", 301, True), ("LiF", 37, True), ("H20", 13, True), ("H20", 8192, False), ("LiH", 16381, False))
+    try:
+        for name, walkers, fl in cases:
+            s = SYSTEMS[name]()
+            torch, fnvmc, cfg, tt, xt, th, x = _setup(s, prec, walkers)
+            got = {}
+            for dma in (1, 0):
+                fnvmc.fn_tuning_set("layer_dma", dma)
+                print(f"staging {name} B={walkers} {prec} fl={fl} dma={dma}", flush=True)
+                if fl:
+                    e, lp, _ = fnvmc.fn_local_energy(cfg, tt, xt, want_parts=False)
+                    torch.cuda.synchronize()
+                    got[dma] = (e.cpu().numpy(), lp.cpu().numpy())
+                else:
+                    lp, sg = fnvmc.fn_log_psi(cfg, tt, xt)
+                    torch.cuda.synchronize()
+                    got[dma] = (lp.cpu().numpy(), sg.cpu().numpy())
+            for a, b in zip(got[1], got[0]):
+                np.testing.assert_array_equal(a, b, err_msg=f"{name} B={walkers} {prec} fl={fl}")
+    finally:
+        fnvmc.fn_tuning_set("layer_dma", 1)
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
 def test_log_psi_spin_sizes(prec, tol):
     """Value-only determinant kernels for every spin size up to 10 (one
