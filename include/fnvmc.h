@@ -239,9 +239,10 @@ fn_status fn_timing_read(const char *name, double *total_ms, int64_t *launches);
    forward-Laplacian epilogue) where the row layout allows it, instead of a
    product kernel followed by an epilogue kernel.  Both give the same
    arithmetic up to the order of the final additions.
-   "layer_dma" 0/1: in the split-BF16 modes, stage the fused layer's
-   operand tiles by direct global-to-LDS copies into a two-stage ring
-   (default 1) or through registers; results are bitwise equal.
+   "layer_dma" 0/1: in the split-BF16 modes, stage the operand tiles of
+   the fused layer and of the 128-column products by direct global-to-LDS
+   copies into a two-stage ring (default 1) or through registers; results
+   are bitwise equal.
    "pair_mfma" 0/1: FP32 pair layers, and their adjoint in the parameter
    gradient, as matrix-core products (default 1) or on the vector ALUs; the
    two differ in summation order only.  Unknown names and out-of-range

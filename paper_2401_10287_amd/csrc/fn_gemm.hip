@@ -10,7 +10,9 @@
 // accumulators.  Operand tiles of 32 reduction steps are staged through LDS
 // (the A tile converted from FP32 to the product's operand type on the way in)
 // and the next tile's global loads are issued before the current tile's
-// matrix instructions.
+// matrix instructions.  128-column tiles in the split-BF16 modes copy their
+// operand tiles straight from global memory into a two-stage LDS ring
+// instead, and each wave splits its activation fragments as it reads them.
 //   GEMM_F32    v_mfma_f32_16x16x4_f32, FP32 operands
 //   GEMM_BF16   v_mfma_f32_16x16x32_bf16, BF16 operands (round to nearest even)
 //   GEMM_BF16X3 x = hi + lo split of each FP32 operand, hi*hi + hi*lo + lo*hi
@@ -24,7 +26,7 @@ namespace fn {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
-constexpr int BM = 128, BN = 128, BK = 32;
+constexpr int BM = 128, BK = 32;
 constexpr int LDH = BK;       // LDS row stride of BF16 tiles (64 bytes, chunk-swizzled by lds_chunk)
 constexpr int LDF = BK + 4;   // LDS row stride of FP32 tiles (144 bytes)
 
@@ -34,18 +36,25 @@ struct ModeInfo {
     static constexpr int NP = MODE == GEMM_BF16 ? 1 : (MODE == GEMM_BF16X3 ? 2 : (MODE == GEMM_BF16X6 ? 3 : 1));
 };
 
-template <int MODE, int BNT>
+// DMA (split-BF16 modes, 128-column tiles, K1 a multiple of 32): operand
+// tiles by direct global-to-LDS copies into a two-stage ring, FP32
+// activations split by each wave as it reads its fragments (the layout of
+// the fused layer kernel's staged path); bitwise equal to the register path.
+template <int MODE, int BNT, bool DMA>
 __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
 {
     constexpr bool F32 = ModeInfo<MODE>::F32;
     constexpr int NP = ModeInfo<MODE>::NP;
+    static_assert(!DMA || (BNT == 128 && !F32), "staged copies");
     // wave tiling: 2 x 2 waves of 64 x 64 for 128 columns, else 4 x 1 waves of 32 x BNT
     constexpr int WI = BNT == 128 ? 4 : 2;          // 16-row blocks per wave
     constexpr int WJ = BNT == 128 ? 4 : BNT / 16;   // 16-column blocks per wave
+    constexpr int AST = BM * BK * 4, STG = AST + NP * BNT * BK * 2;
     __shared__ __attribute__((aligned(16))) float sAf[F32 ? BM * LDF : 1];
     __shared__ __attribute__((aligned(16))) float sBf[F32 ? BNT * LDF : 1];
-    __shared__ __attribute__((aligned(16))) uint16_t sAh[F32 ? 8 : NP * BM * LDH];
-    __shared__ __attribute__((aligned(16))) uint16_t sBh[F32 ? 8 : NP * BNT * LDH];
+    __shared__ __attribute__((aligned(16))) uint16_t sAh[F32 || DMA ? 8 : NP * BM * LDH];
+    __shared__ __attribute__((aligned(16))) uint16_t sBh[F32 || DMA ? 8 : NP * BNT * LDH];
+    __shared__ __attribute__((aligned(16))) unsigned char sR[DMA ? 2 * STG : 16];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = BNT == 128 ? wave >> 1 : wave, wn = BNT == 128 ? wave & 1 : 0;
@@ -160,6 +169,108 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
 #pragma unroll
         for (int j = 0; j < WJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    if constexpr (DMA) {
+        // per lane: its 16-byte chunk of each of the wave's 1 KB blocks
+        // (activations: 4 blocks of 8 rows, chunk c of row r at c ^ (r & 7);
+        // weights: 2 blocks of 16 rows per part, chunk c at lds_chunk(r, c)).
+        // Rows past the end copy row m0 and weight rows past nout copy row
+        // n0; they only feed outputs that are not stored.
+        int64_t da1[4], da2[4], dw[2];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = 8 * (4 * wave + j) + (lane >> 3);
+            const int c = (lane & 7) ^ (r & 7);
+            const int64_t rr = m0 + r < a.rows ? m0 + r : m0;
+            const int64_t g = rr / a.rows_per_group, q = rr - g * a.rows_per_group;
+            const int64_t ar = g * a.group_stride + a.row_offset + q;
+            da1[j] = ar * a.lda1 + 4 * c;
+            da2[j] = ar * a.lda2 + 4 * c;
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int r = 16 * (2 * wave + j) + (lane >> 2);
+            const int o = n0 + r;
+            dw[j] = (int64_t)(o < a.nout ? o : n0) * a.ldw + 8 * lds_chunk(r, lane & 3);
+        }
+        auto dma = [&](int kt, int sgi) {
+            const int kb = kt * BK;
+            unsigned char *stg = sR + sgi * STG;
+            const float *base = kb < a.K1 ? A1 + kb : A2 + (kb - a.K1);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                __builtin_amdgcn_global_load_lds((const void *)(base + (kb < a.K1 ? da1[j] : da2[j])),
+                                                 (__attribute__((address_space(3))) void *)(stg + (4 * wave + j) * 1024),
+                                                 16, 0, 0);
+            const uint16_t *W = (const uint16_t *)a.W + kb;
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    __builtin_amdgcn_global_load_lds(
+                        (const void *)(W + (int64_t)q * a.wpart + dw[j]),
+                        (__attribute__((address_space(3))) void *)(stg + AST + q * BNT * BK * 2 + (2 * wave + j) * 1024),
+                        16, 0, 0);
+        };
+        if (ktiles > 0) dma(0, 0);
+        const int ar = wm * 16 * WI + (lane & 15), br = wn * 16 * WJ + (lane & 15);
+        const int ko = 8 * lds_chunk(lane & 15, lane >> 4);
+        const int h = lane >> 4, sw = lane & 7;
+        for (int kt = 0; kt < ktiles; ++kt) {
+            __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0): this lane's copies of step kt have landed
+            __syncthreads();                         // everyone's have; step kt - 1's stage is free
+            const unsigned char *stg = sR + (kt & 1) * STG;
+            const float *sA = (const float *)stg;
+            const uint16_t *sB = (const uint16_t *)(stg + AST);
+            float4 xa[WI][2];
+            bf16x8 ha[NP][WI], hb[NP][WJ];
+#pragma unroll
+            for (int i = 0; i < WI; ++i) {
+                const float *rowp = sA + (ar + 16 * i) * BK;
+                xa[i][0] = *(const float4 *)(rowp + 4 * ((2 * h) ^ sw));
+                xa[i][1] = *(const float4 *)(rowp + 4 * ((2 * h + 1) ^ sw));
+            }
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+#pragma unroll
+                for (int j = 0; j < WJ; ++j) hb[q][j] = *(const bf16x8 *)&sB[q * BNT * LDH + (br + 16 * j) * LDH + ko];
+            if (kt + 1 < ktiles) dma(kt + 1, (kt + 1) & 1);
+#pragma unroll
+            for (int i = 0; i < WI; ++i) {
+                uint32_t p0[NP], p1[NP], p2[NP], p3[NP];
+                split_bf16_pair<NP>(xa[i][0].x, xa[i][0].y, p0);
+                split_bf16_pair<NP>(xa[i][0].z, xa[i][0].w, p1);
+                split_bf16_pair<NP>(xa[i][1].x, xa[i][1].y, p2);
+                split_bf16_pair<NP>(xa[i][1].z, xa[i][1].w, p3);
+#pragma unroll
+                for (int q = 0; q < NP; ++q) ha[q][i] = __builtin_bit_cast(bf16x8, make_uint4(p0[q], p1[q], p2[q], p3[q]));
+            }
+#pragma unroll
+            for (int sum = NP - 1; sum >= 0; --sum)
+#pragma unroll
+                for (int pa = 0; pa <= sum; ++pa)
+#pragma unroll
+                    for (int i = 0; i < WI; ++i)
+#pragma unroll
+                        for (int j = 0; j < WJ; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j], acc[i][j],
+                                                                                0, 0, 0);
+            // the first parts' conversions, then each matrix instruction of
+            // the first NP - 1 product groups with a share of the next parts'
+            // conversions, then the rest
+            {
+                constexpr int G = WI * WJ, VM = (20 * WI + G - 1) / G;
+                __builtin_amdgcn_sched_group_barrier(0x002, 4 * WI, 0);
+#pragma unroll
+                for (int g = 0; g < NP - 1; ++g)
+#pragma unroll
+                    for (int m = 0; m < G; ++m) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x002, VM, 0);
+                    }
+                __builtin_amdgcn_sched_group_barrier(0x008, G * (NP * (NP + 1) / 2 - (NP - 1)), 0);
+            }
+        }
+    } else {
     if (ktiles > 0) load_tile(0);
     for (int kt = 0; kt < ktiles; ++kt) {
         __syncthreads();
@@ -203,6 +314,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j], acc[i][j],
                                                                                 0, 0, 0);
         }
+    }
     }
 
     // accumulator (i, j) element e sits at row 16 i + 4 (lane >> 4) + e, column 16 j + (lane & 15)
@@ -292,10 +404,18 @@ static void launch_bn(int mode, const GemmArgs &a, hipStream_t st)
     const int64_t nrb = (a.rows + BM - 1) / BM;
     const int ncb = (a.nout + BNT - 1) / BNT;
     dim3 grid((unsigned)(ncb <= 2 ? xcd_grid(nrb, ncb) : nrb * ncb));
-    if (mode == GEMM_F32) hipLaunchKernelGGL((k_gemm_mfma<GEMM_F32, BNT>), grid, dim3(256), 0, st, a);
-    else if (mode == GEMM_BF16) hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16, BNT>), grid, dim3(256), 0, st, a);
-    else if (mode == GEMM_BF16X3) hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16X3, BNT>), grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16X6, BNT>), grid, dim3(256), 0, st, a);
+    if constexpr (BNT == 128) {
+        if (g_layer_dma && mode != GEMM_F32 && a.K1 % BK == 0) {
+            if (mode == GEMM_BF16) hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16, 128, true>), grid, dim3(256), 0, st, a);
+            else if (mode == GEMM_BF16X3) hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16X3, 128, true>), grid, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16X6, 128, true>), grid, dim3(256), 0, st, a);
+            return;
+        }
+    }
+    if (mode == GEMM_F32) hipLaunchKernelGGL((k_gemm_mfma<GEMM_F32, BNT, false>), grid, dim3(256), 0, st, a);
+    else if (mode == GEMM_BF16) hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16, BNT, false>), grid, dim3(256), 0, st, a);
+    else if (mode == GEMM_BF16X3) hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16X3, BNT, false>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16X6, BNT, false>), grid, dim3(256), 0, st, a);
 }
 
 hipError_t launch_gemm(int mode, const GemmArgs &a, hipStream_t st)

@@ -317,13 +317,15 @@ def test_pair_kernels_and_launch_shapes(name, walkers):
 
 @pytest.mark.parametrize("prec", ["bf16x6", "bf16x3", "bf16"])
 def test_layer_operand_staging_bitwise(prec):
-    """The fused layer's two ways of staging operand tiles (direct
-    global-to-LDS copies into a two-stage ring, or loads through registers)
-    give bitwise equal log|psi| and local energies: 16, 64 (three live row
-    blocks) and 64 (four) rows per electron with ragged last tiles, and value
-    rows in grids large enough for 128-column tiles.  The default (direct
+    """The two ways of staging operand tiles of the fused layer and the
+    128-column products (direct global-to-LDS copies into a two-stage ring, or
+    loads through registers) give bitwise equal log|psi| and local energies:
+    16, 64 (three live row blocks) and 64 (four) rows per electron with ragged
+    last tiles, a batch whose mean-field product takes 128-column tiles, and
+    value rows in grids large enough for 128-column tiles.  The default (direct
     copy) path is the one the oracle tests in this file check."""
-    cases = (("LiH", 301, True), ("LiF", 37, True), ("H20", 13, True), ("H20", 8192, False), ("LiH", 16381, False))
+    cases = (("LiH", 301, True), ("LiH", 1501, True), ("LiF", 37, True), ("H20", 13, True), ("H20", 8192, False),
+             ("LiH", 16381, False))
     try:
         for name, walkers, fl in cases:
             s = SYSTEMS[name]()
