@@ -23,8 +23,6 @@
 
 namespace fn {
 
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
-typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr int BM = 128, BK = 32;
 constexpr int LDH = BK;       // LDS row stride of BF16 tiles (64 bytes, chunk-swizzled by lds_chunk)
@@ -198,25 +196,20 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
             const float *base = kb < a.K1 ? A1 + kb : A2 + (kb - a.K1);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                __builtin_amdgcn_global_load_lds((const void *)(base + (kb < a.K1 ? da1[j] : da2[j])),
-                                                 (__attribute__((address_space(3))) void *)(stg + (4 * wave + j) * 1024),
-                                                 16, 0, 0);
+                copy16_to_lds(base + (kb < a.K1 ? da1[j] : da2[j]), stg + (4 * wave + j) * 1024);
             const uint16_t *W = (const uint16_t *)a.W + kb;
 #pragma unroll
             for (int q = 0; q < NP; ++q)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    __builtin_amdgcn_global_load_lds(
-                        (const void *)(W + (int64_t)q * a.wpart + dw[j]),
-                        (__attribute__((address_space(3))) void *)(stg + AST + q * BNT * BK * 2 + (2 * wave + j) * 1024),
-                        16, 0, 0);
+                    copy16_to_lds(W + (int64_t)q * a.wpart + dw[j], stg + AST + q * BNT * BK * 2 + (2 * wave + j) * 1024);
         };
         if (ktiles > 0) dma(0, 0);
         const int ar = wm * 16 * WI + (lane & 15), br = wn * 16 * WJ + (lane & 15);
         const int ko = 8 * lds_chunk(lane & 15, lane >> 4);
         const int h = lane >> 4, sw = lane & 7;
         for (int kt = 0; kt < ktiles; ++kt) {
-            __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0): this lane's copies of step kt have landed
+            wait_copies();                           // this lane's copies of step kt have landed
             __syncthreads();                         // everyone's have; step kt - 1's stage is free
             const unsigned char *stg = sR + (kt & 1) * STG;
             const float *sA = (const float *)stg;
@@ -236,13 +229,10 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
             if (kt + 1 < ktiles) dma(kt + 1, (kt + 1) & 1);
 #pragma unroll
             for (int i = 0; i < WI; ++i) {
-                uint32_t p0[NP], p1[NP], p2[NP], p3[NP];
-                split_bf16_pair<NP>(xa[i][0].x, xa[i][0].y, p0);
-                split_bf16_pair<NP>(xa[i][0].z, xa[i][0].w, p1);
-                split_bf16_pair<NP>(xa[i][1].x, xa[i][1].y, p2);
-                split_bf16_pair<NP>(xa[i][1].z, xa[i][1].w, p3);
+                bf16x8 hp[NP];
+                split_fragment<NP>(xa[i][0], xa[i][1], hp);
 #pragma unroll
-                for (int q = 0; q < NP; ++q) ha[q][i] = __builtin_bit_cast(bf16x8, make_uint4(p0[q], p1[q], p2[q], p3[q]));
+                for (int q = 0; q < NP; ++q) ha[q][i] = hp[q];
             }
 #pragma unroll
             for (int sum = NP - 1; sum >= 0; --sum)
@@ -254,21 +244,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
                         for (int j = 0; j < WJ; ++j)
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j], acc[i][j],
                                                                                 0, 0, 0);
-            // the first parts' conversions, then each matrix instruction of
-            // the first NP - 1 product groups with a share of the next parts'
-            // conversions, then the rest
-            {
-                constexpr int G = WI * WJ, VM = (20 * WI + G - 1) / G;
-                __builtin_amdgcn_sched_group_barrier(0x002, 4 * WI, 0);
-#pragma unroll
-                for (int g = 0; g < NP - 1; ++g)
-#pragma unroll
-                    for (int m = 0; m < G; ++m) {
-                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                        __builtin_amdgcn_sched_group_barrier(0x002, VM, 0);
-                    }
-                __builtin_amdgcn_sched_group_barrier(0x008, G * (NP * (NP + 1) / 2 - (NP - 1)), 0);
-            }
+            sched_split_products<NP, WI, WJ>();
         }
     } else {
     if (ktiles > 0) load_tile(0);

@@ -79,6 +79,7 @@ __host__ __device__ inline int lds_chunk(int r, int c) { return c ^ (((r >> 1) ^
 typedef __attribute__((__vector_size__(2 * sizeof(float)))) float f32x2_t;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;     // one 16 x 16 MFMA accumulator per lane
 typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_t;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;     // one BF16 MFMA operand fragment
 
 // Split two FP32 values a, b into NP BF16 parts, x = p0 + p1 + ..., each part
 // the round-to-nearest-even of what the earlier parts leave (NaN stays NaN).
@@ -97,6 +98,52 @@ __device__ inline void split_bf16_pair(float a, float b, uint32_t (&h)[NP])
             b -= __uint_as_float(w & 0xffff0000u);
         }
     }
+}
+
+// Direct global-to-LDS staging of operand tiles (split-BF16 products).
+// copy16_to_lds: each lane copies 16 bytes from its own global address g to
+// lds + 16 * lane (lds: the wave's 1 KB block, the same for all lanes).
+// wait_copies: until this lane's copies have landed (vmcnt(0) with the other
+// counters left alone; a barrier after it makes every lane's copies visible).
+__device__ inline void copy16_to_lds(const void *g, void *lds)
+{
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+}
+__device__ inline void wait_copies() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// The NP BF16 parts of one MFMA A fragment: eight consecutive FP32 values
+// (x0 then x1) of one row, split with split_bf16_pair.
+template <int NP>
+__device__ inline void split_fragment(float4 x0, float4 x1, bf16x8 (&h)[NP])
+{
+    uint32_t p0[NP], p1[NP], p2[NP], p3[NP];
+    split_bf16_pair<NP>(x0.x, x0.y, p0);
+    split_bf16_pair<NP>(x0.z, x0.w, p1);
+    split_bf16_pair<NP>(x1.x, x1.y, p2);
+    split_bf16_pair<NP>(x1.z, x1.w, p3);
+#pragma unroll
+    for (int q = 0; q < NP; ++q) h[q] = __builtin_bit_cast(bf16x8, make_uint4(p0[q], p1[q], p2[q], p3[q]));
+}
+
+// Scheduling hint for a reduction step of NB x NJ accumulator blocks and NP
+// operand parts: the first parts' conversions (4 per row block), then each
+// matrix instruction of the first NP - 1 product groups followed by a share
+// of the next parts' conversions (about 20 vector instructions per row
+// block and part), then the remaining matrix instructions.
+constexpr int SCHED_VALU = 0x002, SCHED_MFMA = 0x008;
+template <int NP, int NB, int NJ>
+__device__ inline void sched_split_products()
+{
+    constexpr int G = NB * NJ, VM = (20 * NB + G - 1) / G;
+    __builtin_amdgcn_sched_group_barrier(SCHED_VALU, 4 * NB, 0);
+#pragma unroll
+    for (int g = 0; g < NP - 1; ++g)
+#pragma unroll
+        for (int m = 0; m < G; ++m) {
+            __builtin_amdgcn_sched_group_barrier(SCHED_MFMA, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(SCHED_VALU, VM, 0);
+        }
+    __builtin_amdgcn_sched_group_barrier(SCHED_MFMA, G * (NP * (NP + 1) / 2 - (NP - 1)), 0);
 }
 
 inline __host__ __device__ int gemm_parts(int mode) { return mode == GEMM_BF16 ? 1 : (mode == GEMM_BF16X3 ? 2 : (mode == GEMM_BF16X6 ? 3 : 1)); }

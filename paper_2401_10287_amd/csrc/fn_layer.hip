@@ -25,8 +25,6 @@
 
 namespace fn {
 
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
-typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 namespace {
 
@@ -234,25 +232,20 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
             const float *base = kb < a.K1 ? A1 + kb : A2 + (kb - a.K1);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                __builtin_amdgcn_global_load_lds((const void *)(base + (kb < a.K1 ? da1[j] : da2[j])),
-                                                 (__attribute__((address_space(3))) void *)(stg + (4 * wave + j) * 1024),
-                                                 16, 0, 0);
+                copy16_to_lds(base + (kb < a.K1 ? da1[j] : da2[j]), stg + (4 * wave + j) * 1024);
             const uint16_t *W = (const uint16_t *)a.W + kb;
 #pragma unroll
             for (int q = 0; q < NP; ++q)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    __builtin_amdgcn_global_load_lds(
-                        (const void *)(W + (int64_t)q * a.wpart + dw[j]),
-                        (__attribute__((address_space(3))) void *)(stg + AST + q * LBN * LBK * 2 + (2 * wave + j) * 1024),
-                        16, 0, 0);
+                    copy16_to_lds(W + (int64_t)q * a.wpart + dw[j], stg + AST + q * LBN * LBK * 2 + (2 * wave + j) * 1024);
         };
         if (ktiles > 0) dma(0, 0);
         const int ar = wm * 16 * WI + (lane & 15), br = wn * 16 * WJ + (lane & 15);
         const int ko = 8 * lds_chunk(lane & 15, lane >> 4);
         const int h = lane >> 4, sw = lane & 7;          // rows ar + 16 i share bits 0-2 with lane
         for (int kt = 0; kt < ktiles; ++kt) {
-            __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0): this lane's copies of step kt have landed
+            wait_copies();                           // this lane's copies of step kt have landed
             __syncthreads();                         // everyone's have; step kt - 1's stage is free
             // every fragment of step kt is read into registers before the
             // copies of step kt + 1 are issued, so no read of this stage
@@ -277,17 +270,10 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 #pragma unroll
             for (int i = 0; i < WI; ++i)
                 if (i < LIVE || TP != 64) {
-                    const float4 x0 = xa[i][0], x1 = xa[i][1];
-                    uint32_t p0[NP], p1[NP], p2[NP], p3[NP];
-                    split_bf16_pair<NP>(x0.x, x0.y, p0);
-                    split_bf16_pair<NP>(x0.z, x0.w, p1);
-                    split_bf16_pair<NP>(x1.x, x1.y, p2);
-                    split_bf16_pair<NP>(x1.z, x1.w, p3);
+                    bf16x8 hp[NP];
+                    split_fragment<NP>(xa[i][0], xa[i][1], hp);
 #pragma unroll
-                    for (int q = 0; q < NP; ++q) {
-                        const uint4 u = make_uint4(p0[q], p1[q], p2[q], p3[q]);
-                        ha[q][i] = __builtin_bit_cast(bf16x8, u);
-                    }
+                    for (int q = 0; q < NP; ++q) ha[q][i] = hp[q];
                 }
 #pragma unroll
             for (int sum = NP - 1; sum >= 0; --sum)
@@ -300,22 +286,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
                             if (i < LIVE || TP != 64)
                                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j],
                                                                                     acc[i][j], 0, 0, 0);
-            // schedule: the first parts' conversions, then each matrix
-            // instruction of the first NP - 1 product groups followed by a
-            // share of the next parts' conversions (about 20 vector
-            // instructions per row block and part), then the rest
-            {
-                constexpr int NB = TP == 64 ? LIVE : WI, G = NB * WJ, VM = (20 * NB + G - 1) / G;
-                __builtin_amdgcn_sched_group_barrier(0x002, 4 * NB, 0);
-#pragma unroll
-                for (int g = 0; g < NP - 1; ++g)
-#pragma unroll
-                    for (int m = 0; m < G; ++m) {
-                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                        __builtin_amdgcn_sched_group_barrier(0x002, VM, 0);
-                    }
-                __builtin_amdgcn_sched_group_barrier(0x008, G * (NP * (NP + 1) / 2 - (NP - 1)), 0);
-            }
+            sched_split_products<NP, TP == 64 ? LIVE : WI, WJ>();
         }
     } else {
     if (ktiles > 0) load_tile(0);
