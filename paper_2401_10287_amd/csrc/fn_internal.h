@@ -225,7 +225,8 @@ struct LayerArgs {
     int64_t rows; int N; int n3; int w1; int W1p; int resid;
     // when a 128-row tile holds whole walkers (N * TR divides 128): also
     // write the next layer's spin means [g_up | g_dn] of h^{l+1}, rows
-    // walker * TR + t, ld 2 * W1p (Gout = nullptr: skip)
+    // walker * TR + t for t up to the Laplacian row (padding rows are not
+    // written), ld 2 * W1p (Gout = nullptr: skip)
     float *Gout; int nu;
 };
 

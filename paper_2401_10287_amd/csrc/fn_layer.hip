@@ -457,13 +457,18 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
                 }
             }
         }
-        srcp[q] = src;
-        __syncthreads();
+        // with one item per (electron, column quad) the item's own partial
+        // source is the whole source: no exchange through LDS
+        if constexpr (QPR > 1) {
+            srcp[q] = src;
+            __syncthreads();
+        }
         float y0[4], dd[4], lap[4];
         if (live) {
-            float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
+            float4 s4 = QPR > 1 ? make_float4(0.f, 0.f, 0.f, 0.f) : src;
 #pragma unroll
-            for (int k = 0; k < QPR; ++k) s4 = f4add(s4, srcp[el * 32 * QPR + cq * QPR + k]);
+            for (int k = 0; k < QPR; ++k)
+                if constexpr (QPR > 1) s4 = f4add(s4, srcp[el * 32 * QPR + cq * QPR + k]);
             const float *z0 = xc, *zl = xc + tl * XS;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -509,6 +514,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
             const int wl = wt / TP, t = wt % TP;
             const int64_t wg = m0 / ((int64_t)a.N * TP) + wl;
             if ((int64_t)(wl + 1) * a.N * TP > rows_here || n0 + 4 * c4 >= a.W1p) continue;
+            if (t > a.n3 + 1) continue;                   // padding rows: never read
             const int j0 = sp ? a.nu : 0, j1 = sp ? a.N : a.nu;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
             for (int j = j0; j < j1; ++j) v = f4add(v, *(const float4 *)(sX + ((wl * a.N + j) * TP + t) * XS + 4 * c4));
