@@ -642,7 +642,14 @@ __global__ __launch_bounds__(256) void k_spin_mean(const T *__restrict__ H, int6
         T v = T(0);
         if (k < dh) {
             const int j0 = sp ? nu : 0, j1 = sp ? N : nu;
-            for (int j = j0; j < j1; ++j) v += h0[j * jstride + k];
+            // four rows requested at once, added in electron order
+            int j = j0;
+            for (; j + 4 <= j1; j += 4) {
+                const T a0 = h0[j * jstride + k], a1 = h0[(j + 1) * jstride + k];
+                const T a2 = h0[(j + 2) * jstride + k], a3 = h0[(j + 3) * jstride + k];
+                v += a0; v += a1; v += a2; v += a3;
+            }
+            for (; j < j1; ++j) v += h0[j * jstride + k];
             v *= sp ? id : iu;
         }
         G[wt * 2 * HWl + col] = v;
@@ -671,9 +678,15 @@ __global__ __launch_bounds__(256) void k_spin_mean<float>(const float *__restric
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (k < dh) {
             const int j0 = sp ? nu : 0, j1 = sp ? N : nu;
-            for (int j = j0; j < j1; ++j) {
-                const float4 h = *(const float4 *)(h0 + j * jstride + k);
-                v.x += h.x; v.y += h.y; v.z += h.z; v.w += h.w;
+            // up to four rows requested at once, added in electron order
+            for (int jb = j0; jb < j1; jb += 4) {
+                float4 h[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    h[u] = jb + u < j1 ? *(const float4 *)(h0 + (jb + u) * jstride + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (jb + u < j1) { v.x += h[u].x; v.y += h[u].y; v.z += h[u].z; v.w += h[u].w; }
             }
             const float sc = sp ? id : iu;
             v.x *= sc; v.y *= sc; v.z *= sc; v.w *= sc;
