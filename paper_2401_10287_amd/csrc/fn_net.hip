@@ -507,7 +507,6 @@ __global__ __launch_bounds__(256) void k_pair_mfma(Sys s, const double *x, const
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, li = lane & 15;
     const int64_t wi0 = (int64_t)blockIdx.x * WB;
     const int nwi = B * s.N - wi0 < WB ? (int)(B * s.N - wi0) : WB;
-    const int rows = FL ? TR : 1;
     const int nrow = nwi * s.N * R;                       // pair rows held here
     const int nblk = (nrow + 15) / 16;
     const int rows_alloc = round_up(WB * s.N * R, 16);
@@ -933,6 +932,7 @@ __global__ __launch_bounds__(64) void k_det(const T *Phi, int64_t B, int K, int 
 // Envelope, entries, LU and traces in FP64 for every precision.
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int orbdet_cd(int n) { return n >= 64 ? 1 : 64 / n; }
+constexpr int ORB_PF = 12;   // spins up to this size prefetch a direction's head values
 
 size_t orbdet_lds(int n, bool fl)
 {
@@ -1054,17 +1054,47 @@ __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *
             const int mt = t0 + d, j = j0 + jj;
             const T *Oj = O + ((w * n + jj) * TR) * ldo + k * n;
             double *v = Mc + d * nn;
-            for (int r = 0; r < n; ++r) {
-                const int io = perm[r], e = io * n + jj;
-                double dv;
-                if (mt < n3) {
-                    dv = EV[e] * (double)Oj[(1 + mt) * ldo + io];
-                    if (mt / 3 == j) dv += A0[e] * GE[3 * e + mt % 3];
-                } else {
-                    dv = EV[e] * (double)Oj[(n3 + 1) * ldo + io] + A0[e] * LE[e];
-                    for (int a = 0; a < 3; ++a) dv += 2.0 * (double)Oj[(1 + 3 * j + a) * ldo + io] * GE[3 * e + a];
+            if (n <= ORB_PF) {
+                // every row's head value is requested before the first is used
+                // (the stores below would otherwise order each load after the
+                // previous row's store)
+                const int orow = mt < n3 ? 1 + mt : n3 + 1;
+                int pv[ORB_PF];
+                double ov[ORB_PF];
+                // rows past n repeat row n - 1: unconditional loads, no branches
+#pragma unroll
+                for (int r = 0; r < ORB_PF; ++r) pv[r] = perm[r < n ? r : n - 1];
+#pragma unroll
+                for (int r = 0; r < ORB_PF; ++r) ov[r] = (double)Oj[orow * ldo + pv[r]];
+#pragma unroll
+                for (int r = 0; r < ORB_PF; ++r) {
+                    if (r < n) {
+                        const int io = pv[r], e = io * n + jj;
+                        double dv;
+                        if (mt < n3) {
+                            dv = EV[e] * ov[r];
+                            if (mt / 3 == j) dv += A0[e] * GE[3 * e + mt % 3];
+                        } else {
+                            dv = EV[e] * ov[r] + A0[e] * LE[e];
+                            for (int a = 0; a < 3; ++a)
+                                dv += 2.0 * (double)Oj[(1 + 3 * j + a) * ldo + io] * GE[3 * e + a];
+                        }
+                        v[r * n + jj] = dv;
+                    }
                 }
-                v[r * n + jj] = dv;
+            } else {
+                for (int r = 0; r < n; ++r) {
+                    const int io = perm[r], e = io * n + jj;
+                    double dv;
+                    if (mt < n3) {
+                        dv = EV[e] * (double)Oj[(1 + mt) * ldo + io];
+                        if (mt / 3 == j) dv += A0[e] * GE[3 * e + mt % 3];
+                    } else {
+                        dv = EV[e] * (double)Oj[(n3 + 1) * ldo + io] + A0[e] * LE[e];
+                        for (int a = 0; a < 3; ++a) dv += 2.0 * (double)Oj[(1 + 3 * j + a) * ldo + io] * GE[3 * e + a];
+                    }
+                    v[r * n + jj] = dv;
+                }
             }
             for (int r = 1; r < n; ++r) {
                 double acc = v[r * n + jj];
