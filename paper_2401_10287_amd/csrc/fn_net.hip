@@ -940,8 +940,10 @@ size_t orbdet_lds(int n, bool fl)
     return ((fl ? 7 * nn + (size_t)orbdet_cd(n) * nn : nn)) * sizeof(double) + (size_t)n * sizeof(int) + 16;
 }
 
-// FL = false: value only (envelope, LU, sign and log|det|), LDS holds the matrix only
-template <typename T, bool FL>
+// FL = false: value only (envelope, LU, sign and log|det|), LDS holds the matrix only.
+// REG: triangular solves of the directions in registers (spins of 7 ..
+// ORB_PF electrons, where LDS, not registers, bounds the resident waves)
+template <typename T, bool FL, bool REG>
 __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *theta, int64_t gof, int64_t piof,
                                                int64_t sigof, int sp, const T *O, int64_t ldo, int64_t B, int TR,
                                                double *DR, int rec)
@@ -1066,8 +1068,13 @@ __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *
                 for (int r = 0; r < ORB_PF; ++r) pv[r] = perm[r < n ? r : n - 1];
 #pragma unroll
                 for (int r = 0; r < ORB_PF; ++r) ov[r] = (double)Oj[orow * ldo + pv[r]];
+                // REG: right-hand side and both triangular solves in registers
+                // (static indices), the solved column stored once; otherwise
+                // the right-hand side goes to LDS for the solves below
+                double vv[ORB_PF];
 #pragma unroll
                 for (int r = 0; r < ORB_PF; ++r) {
+                    vv[r] = 0.0;
                     if (r < n) {
                         const int io = pv[r], e = io * n + jj;
                         double dv;
@@ -1079,8 +1086,33 @@ __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *
                             for (int a = 0; a < 3; ++a)
                                 dv += 2.0 * (double)Oj[(1 + 3 * j + a) * ldo + io] * GE[3 * e + a];
                         }
-                        v[r * n + jj] = dv;
+                        if constexpr (REG) vv[r] = dv;
+                        else v[r * n + jj] = dv;
                     }
+                }
+                if constexpr (REG) {
+#pragma unroll
+                for (int r = 1; r < ORB_PF; ++r) {
+                    if (r < n) {
+                        double acc = vv[r];
+#pragma unroll
+                        for (int c = 0; c < r; ++c) acc -= LU[r * n + c] * vv[c];
+                        vv[r] = acc;
+                    }
+                }
+#pragma unroll
+                for (int r = ORB_PF - 1; r >= 0; --r) {
+                    if (r < n) {
+                        double acc = vv[r];
+#pragma unroll
+                        for (int c = r + 1; c < ORB_PF; ++c)
+                            if (c < n) acc -= LU[r * n + c] * vv[c];
+                        vv[r] = acc / LU[r * n + r];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < ORB_PF; ++r)
+                    if (r < n) v[r * n + jj] = vv[r];
                 }
             } else {
                 for (int r = 0; r < n; ++r) {
@@ -1096,15 +1128,17 @@ __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *
                     v[r * n + jj] = dv;
                 }
             }
-            for (int r = 1; r < n; ++r) {
-                double acc = v[r * n + jj];
-                for (int c = 0; c < r; ++c) acc -= LU[r * n + c] * v[c * n + jj];
-                v[r * n + jj] = acc;
-            }
-            for (int r = n - 1; r >= 0; --r) {
-                double acc = v[r * n + jj];
-                for (int c = r + 1; c < n; ++c) acc -= LU[r * n + c] * v[c * n + jj];
-                v[r * n + jj] = acc / LU[r * n + r];
+            if (!REG || n > ORB_PF) {
+                for (int r = 1; r < n; ++r) {
+                    double acc = v[r * n + jj];
+                    for (int c = 0; c < r; ++c) acc -= LU[r * n + c] * v[c * n + jj];
+                    v[r * n + jj] = acc;
+                }
+                for (int r = n - 1; r >= 0; --r) {
+                    double acc = v[r * n + jj];
+                    for (int c = r + 1; c < n; ++c) acc -= LU[r * n + c] * v[c * n + jj];
+                    v[r * n + jj] = acc / LU[r * n + r];
+                }
             }
         }
         __syncthreads();
@@ -1605,8 +1639,15 @@ static void launch_orbdet_fl(const Sys &s, const double *x, const T *theta, int6
         }
     }
 #undef FN_SMALL
-    hipLaunchKernelGGL((k_orbdet<T, FL>), dim3((unsigned)(B * s.K)), dim3(64), orbdet_lds(n, FL), st, s, x, theta, gof,
-                       piof, sigof, sp, O, ldo, B, TR, DR, rec);
+    if constexpr (FL) {
+        if (n >= 7 && n <= ORB_PF) {
+            hipLaunchKernelGGL((k_orbdet<T, true, true>), dim3((unsigned)(B * s.K)), dim3(64), orbdet_lds(n, FL), st, s,
+                               x, theta, gof, piof, sigof, sp, O, ldo, B, TR, DR, rec);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_orbdet<T, FL, false>), dim3((unsigned)(B * s.K)), dim3(64), orbdet_lds(n, FL), st, s, x, theta,
+                       gof, piof, sigof, sp, O, ldo, B, TR, DR, rec);
 }
 
 template <typename T>
