@@ -78,8 +78,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
         int f = tid + 256 * v;
         int64_t r = m0 + (f >> 3);
         aval[v] = r < a.rows;
-        int64_t g = r / a.rows_per_group, q = r - g * a.rows_per_group;
-        arow[v] = g * a.group_stride + a.row_offset + q;
+        arow[v] = gemm_a_row(a, r);
     }
     const float *A1 = (const float *)a.A1;
     const float *A2 = (const float *)a.A2;
@@ -179,8 +178,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
             const int r = 8 * (4 * wave + j) + (lane >> 3);
             const int c = (lane & 7) ^ (r & 7);
             const int64_t rr = m0 + r < a.rows ? m0 + r : m0;
-            const int64_t g = rr / a.rows_per_group, q = rr - g * a.rows_per_group;
-            const int64_t ar = g * a.group_stride + a.row_offset + q;
+            const int64_t ar = gemm_a_row(a, rr);
             da1[j] = ar * a.lda1 + 4 * c;
             da2[j] = ar * a.lda2 + 4 * c;
         }
@@ -329,8 +327,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs a)
         int f = tid + 256 * v;
         int64_t r = m0 + (f >> 4);
         aval[v] = r < a.rows;
-        int64_t g = r / a.rows_per_group, q = r - g * a.rows_per_group;
-        arow[v] = g * a.group_stride + a.row_offset + q;
+        arow[v] = gemm_a_row(a, r);
     }
     double acc[4][4] = {};
     const int K = a.K1 + a.K2;

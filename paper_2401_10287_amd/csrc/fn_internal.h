@@ -177,8 +177,10 @@ inline Widths make_widths(const Sys &s)
 // the row-wise concatenation [A1 | A2] (A2 may be empty) and W is stored
 // transposed (o major, k contiguous) in the product's operand type.  Row r of
 // A: group g = r / rows_per_group, q = r % rows_per_group, A's row is
-// g * group_stride + row_offset + q.  C's row is r, or, when
-// c_rows_per_group > 0, the same mapping with the c_ fields.
+// g * group_stride + row_offset + q, where, when rows_per_inner > 0, q itself
+// is mapped to (q / rows_per_inner) * inner_stride + q % rows_per_inner (the
+// live rows of each electron of one spin, say).  C's row is r, or, when
+// c_rows_per_group > 0, the one-level mapping with the c_ fields.
 struct GemmArgs {
     const void *A1; int64_t lda1; int K1;
     const void *A2; int64_t lda2; int K2;
@@ -187,7 +189,20 @@ struct GemmArgs {
     int64_t rows; int nout;
     int64_t rows_per_group, group_stride, row_offset;
     int64_t c_rows_per_group, c_group_stride, c_row_offset;
+    int64_t rows_per_inner, inner_stride;
 };
+
+// A's row for product row r (see GemmArgs)
+__host__ __device__ inline int64_t gemm_a_row(const GemmArgs &a, int64_t r)
+{
+    const int64_t g = r / a.rows_per_group;
+    int64_t q = r - g * a.rows_per_group;
+    if (a.rows_per_inner > 0) {
+        const int64_t e = q / a.rows_per_inner;
+        q = e * a.inner_stride + (q - e * a.rows_per_inner);
+    }
+    return g * a.group_stride + a.row_offset + q;
+}
 
 // Block order for a grid of row blocks x ncb column blocks (ncb = 1 or 2):
 // workgroups are dealt to the eight XCDs in turn, so the two column halves of

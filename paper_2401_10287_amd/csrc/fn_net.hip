@@ -251,11 +251,13 @@ __device__ void write_pair_means_wg(const Sys &s, const float *S, int per, int w
                                     int nwi, int TR, int GWl, int64_t ldg, float *gi0)
 {
     constexpr int R = FL ? 8 : 1;
-    const int n3 = 3 * s.N, rows = FL ? TR : 1, cqn = GWl / 4;
-    const int items = nwi * rows * cqn;
+    // rows value .. Laplacian only: the padding rows of TR are never read
+    // (every product over these rows reads its live rows only)
+    const int n3 = 3 * s.N, rows = FL ? TR : 1, live_rows = FL ? n3 + 2 : 1, cqn = GWl / 4;
+    const int items = nwi * live_rows * cqn;
     for (int it = threadIdx.x; it < items; it += blockDim.x) {
         const int col = 4 * (it % cqn), rt = it / cqn;
-        const int t = rt % rows, bb = rt / rows;
+        const int t = rt % live_rows, bb = rt / live_rows;
         const int64_t wi = wi0 + bb;
         const int i = (int)(wi % s.N);
         const float *Sb = S + (int64_t)bb * per;
