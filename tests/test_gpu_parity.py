@@ -325,10 +325,12 @@ def test_layer_operand_staging_bitwise(prec):
     value rows in grids large enough for 128-column tiles.  The default (direct
     copy) path is the one the oracle tests in this file check."""
     cases = (("LiH", 301, True), ("LiH", 1501, True), ("LiF", 37, True), ("H20", 13, True), ("H20", 8192, False),
-             ("LiH", 16381, False))
+             ("LiH", 16381, False),
+             # atoms: 3 electrons (16 rows, walkers straddle tiles), 5 and 9 (32 rows), tiny batches
+             ((3, 0), 1, True), ((3, 0), 130, True), ((5, 0), 2, True), ((9, 0), 7, True), ((8, 1), 3, True))
     try:
         for name, walkers, fl in cases:
-            s = SYSTEMS[name]()
+            s = SYSTEMS[name]() if isinstance(name, str) else I.atom_ion(*name, walkers=walkers)
             torch, fnvmc, cfg, tt, xt, th, x = _setup(s, prec, walkers)
             got = {}
             for dma in (1, 0):
