@@ -225,7 +225,9 @@ const char *fn_server_last_error(void);
    electron stream-layer product), "walker_gemm" (per-walker mean-field
    product), "head_gemm", "features", "pair_stream", "spin_mean",
    "layer_epilogue", "envelope", "det", "combine", "pack", "propose",
-   "accept", "backward".  Not thread-safe with concurrent library calls.
+   "accept" (counts no launches: the acceptance runs in the "combine"
+   kernel of the proposal), "backward".  Not thread-safe with concurrent
+   library calls.
    fn_timing_select(name) restricts the brackets to that one class (each
    pair of event records adds a few microseconds to the stream), NULL
    brackets every class again; FN_EINVAL for an unknown name. */

@@ -356,7 +356,8 @@ void pack_weights(const Ctx &c, const Plan &p, const T *theta, char *ws, hipStre
 // for the backward pass.
 template <typename T>
 void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw, int64_t b, double *log_abs,
-                   int8_t *sign, double *e_loc, double *parts, char *ws, hipStream_t st)
+                   int8_t *sign, double *e_loc, double *parts, char *ws, hipStream_t st,
+                   const AcceptArgs &acc = AcceptArgs{})
 {
     const Sys &s = c.s;
     const int TR = p.TR, n3 = 3 * s.N;
@@ -477,18 +478,24 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
         { Timed t_(K_DET, st); launch_det(Phi, b, s.K, n, TR, n3, sp, fl, DR, p.rec, st); }
     }
     Timed t_(K_COMBINE, st);
-    launch_combine(s, xw, DR, p.rec, b, c.vnn, log_abs, sign, e_loc, parts, fl, st);
+    launch_combine(s, xw, DR, p.rec, b, c.vnn, log_abs, sign, e_loc, parts, fl, acc, st);
 }
 
+// acc (value form only): Metropolis acceptance of the proposal x against
+// acc's current walkers, folded into the combine kernel
 template <typename T>
 void forward(const Ctx &c, const Plan &p, const T *theta, const double *x, int64_t B, double *log_abs, int8_t *sign,
-             double *e_loc, double *parts, char *ws, hipStream_t st)
+             double *e_loc, double *parts, char *ws, hipStream_t st, const AcceptArgs &acc = AcceptArgs{})
 {
     const int n3 = 3 * c.s.N;
     for (int64_t w0 = 0; w0 < B; w0 += p.Bc) {
         const int64_t b = std::min(p.Bc, B - w0);
+        AcceptArgs ac{};
+        if (acc.x)
+            ac = AcceptArgs{acc.x + w0 * n3, acc.xp + w0 * n3, acc.u + w0, acc.log_abs + w0,
+                            acc.n_accept ? acc.n_accept + w0 : nullptr};
         forward_chunk<T>(c, p, theta, x + w0 * n3, b, log_abs ? log_abs + w0 : nullptr, sign ? sign + w0 : nullptr,
-                         e_loc ? e_loc + w0 : nullptr, parts ? parts + 4 * w0 : nullptr, ws, st);
+                         e_loc ? e_loc + w0 : nullptr, parts ? parts + 4 * w0 : nullptr, ws, st, ac);
     }
 }
 
@@ -625,8 +632,9 @@ fn_status run_metropolis(const Ctx &c, const Plan &p, const void *theta, double 
             launch_propose(x, B, n3, sigma, seed, step0 + (uint64_t)k, stream_id,
                            z ? z + (int64_t)k * B * n3 : nullptr, u ? u + (int64_t)k * B : nullptr, xp, uu, st);
         }
-        forward<T>(c, p, (const T *)theta, xp, B, lpn, nullptr, nullptr, nullptr, w, st);
-        { Timed t_(K_ACCEPT, st); launch_accept(x, log_abs, xp, lpn, uu, B, n3, n_accept, st); }
+        // the acceptance runs in the combine kernel of the proposal's value pass
+        forward<T>(c, p, (const T *)theta, xp, B, lpn, nullptr, nullptr, nullptr, w, st,
+                   AcceptArgs{x, xp, uu, log_abs, n_accept});
     }
     return hip_status();
 }

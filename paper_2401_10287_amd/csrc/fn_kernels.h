@@ -59,8 +59,18 @@ void launch_orbdet(const Sys &s, const double *x, const T *theta, int64_t gof, i
                    const T *O, int64_t ldo, int64_t B, int TR, bool fl, double *DR, int rec, hipStream_t st);
 void launch_det(const double *Phi, int64_t B, int K, int n, int TR, int n3, int sp, bool fl, double *DR, int rec,
                 hipStream_t st);
+// Metropolis acceptance folded into the value-only combine of the proposal:
+// walker w keeps x'[w] (and log|psi'|) iff log|psi'| is finite and
+// log u[w] <= 2 (log|psi'| - log_abs[w]); x == nullptr: no acceptance.
+struct AcceptArgs {
+    double *x;               // current positions [B][3N], updated in place
+    const double *xp;        // proposed positions [B][3N]
+    const double *u;         // uniforms [B]
+    double *log_abs;         // current log|psi| [B], updated in place
+    int32_t *n_accept;       // per-walker acceptance counters [B] or nullptr
+};
 void launch_combine(const Sys &s, const double *x, const double *DR, int rec, int64_t B, double vnn, double *log_abs,
-                    int8_t *sign, double *e_loc, double *parts, bool fl, hipStream_t st);
+                    int8_t *sign, double *e_loc, double *parts, bool fl, const AcceptArgs &acc, hipStream_t st);
 
 // backward (fn_backward.hip)
 size_t det_backward_lds(int n);
@@ -101,8 +111,6 @@ void launch_pack_head_bwd(const T *theta, int64_t woff, int w1, int kn, int KNp,
 // Monte Carlo
 void launch_propose(const double *x, int64_t B, int n3, double sigma, uint64_t seed, uint64_t step, uint32_t stream_id,
                     const double *z_ext, const double *u_ext, double *xp, double *u, hipStream_t st);
-void launch_accept(double *x, double *log_abs, const double *xp, const double *lp_new, const double *u, int64_t B,
-                   int n3, int32_t *n_accept, hipStream_t st);
 void launch_energy_stats(const double *e_loc, int64_t B, double *stats, double *coeff, hipStream_t st);
 
 }  // namespace fn

@@ -2,7 +2,8 @@
 // of the paper) and the batch energy statistics of Eq. 1 and Eq. 6.
 //
 // Proposal: every electron of a walker moves by sigma z, z ~ N(0, 1); the
-// move is kept iff log|psi'| is finite and log u <= 2 (log|psi'| - log|psi|).
+// move is kept iff log|psi'| is finite and log u <= 2 (log|psi'| - log|psi|)
+// (decided in the combine kernel of the proposal's value pass, fn_net.hip).
 // Random numbers come from Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)
 // with key (seed low, seed high) and counter (d, walker, step, stream_id);
 // normal deviates by the Box-Muller transform (1958).
@@ -75,20 +76,6 @@ __global__ void k_propose(const double *x, int64_t B, int n3, double sigma, uint
     }
 }
 
-__global__ void k_accept(double *x, double *log_abs, const double *xp, const double *lp_new, const double *u, int64_t B,
-                         int n3, int32_t *n_accept)
-{
-    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < B; w += (int64_t)gridDim.x * blockDim.x) {
-        const double ln = lp_new[w];
-        const double A = 2.0 * (ln - log_abs[w]);
-        if (isfinite(ln) && log(u[w]) <= A) {
-            for (int q = 0; q < n3; ++q) x[w * n3 + q] = xp[w * n3 + q];
-            log_abs[w] = ln;
-            if (n_accept) n_accept[w] += 1;
-        }
-    }
-}
-
 // FP64 batch statistics of the local energy (Eq. 1): mean, variance (1/B),
 // standard error; optional Eq. 6 coefficients c_p = 2 (E_p - mean) / B.
 __global__ __launch_bounds__(1024) void k_energy_stats(const double *e, int64_t B, double *stats, double *coeff)
@@ -141,12 +128,6 @@ void launch_propose(const double *x, int64_t B, int n3, double sigma, uint64_t s
     const int64_t total = B * ((n3 + 1) / 2 + 1);
     hipLaunchKernelGGL(k_propose, dim3(grid_of(total)), dim3(256), 0, st, x, B, n3, sigma, (uint32_t)seed,
                        (uint32_t)(seed >> 32), (uint32_t)step, stream_id, z_ext, u_ext, xp, u);
-}
-
-void launch_accept(double *x, double *log_abs, const double *xp, const double *lp_new, const double *u, int64_t B,
-                   int n3, int32_t *n_accept, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_accept, dim3(grid_of(B)), dim3(256), 0, st, x, log_abs, xp, lp_new, u, B, n3, n_accept);
 }
 
 void launch_energy_stats(const double *e_loc, int64_t B, double *stats, double *coeff, hipStream_t st)

@@ -1343,7 +1343,7 @@ __device__ inline double wave_max(double v)
 template <bool FL>
 __global__ __launch_bounds__(64) void k_combine(Sys s, const double *x, const double *DR, int rec, int64_t B,
                                                 double vnn, double *log_abs, int8_t *sign, double *e_loc,
-                                                double *parts)
+                                                double *parts, AcceptArgs acc)
 {
     __shared__ double s_w[FN_MAX_DET];
     const int lane = threadIdx.x;
@@ -1368,7 +1368,20 @@ __global__ __launch_bounds__(64) void k_combine(Sys s, const double *x, const do
         if (log_abs) log_abs[w] = lpsi;
         if (sign) sign[w] = node ? 0 : (S > 0 ? 1 : -1);
     }
-    if (!FL) return;
+    if constexpr (!FL) {
+        if (acc.x) {
+            // the acceptance rule of the Metropolis step for this walker's proposal
+            const bool take = isfinite(lpsi) && log(acc.u[w]) <= 2.0 * (lpsi - acc.log_abs[w]);
+            if (take) {
+                for (int q = lane; q < n3; q += 64) acc.x[w * n3 + q] = acc.xp[w * n3 + q];
+                if (lane == 0) {
+                    acc.log_abs[w] = lpsi;
+                    if (acc.n_accept) acc.n_accept[w] += 1;
+                }
+            }
+        }
+        return;
+    }
     if (lane < K) s_w[lane] = node ? 0.0 : ek / S;
     __syncthreads();
     // sum_k w_k |grad l_k|^2 over coordinates, and sum_k w_k lap l_k
@@ -1661,14 +1674,14 @@ void launch_orbdet(const Sys &s, const double *x, const T *theta, int64_t gof, i
 }
 
 void launch_combine(const Sys &s, const double *x, const double *DR, int rec, int64_t B, double vnn, double *log_abs,
-                    int8_t *sign, double *e_loc, double *parts, bool fl, hipStream_t st)
+                    int8_t *sign, double *e_loc, double *parts, bool fl, const AcceptArgs &acc, hipStream_t st)
 {
     if (fl)
         hipLaunchKernelGGL(k_combine<true>, dim3((unsigned)B), dim3(64), 0, st, s, x, DR, rec, B, vnn, log_abs, sign,
-                           e_loc, parts);
+                           e_loc, parts, AcceptArgs{});
     else
         hipLaunchKernelGGL(k_combine<false>, dim3((unsigned)B), dim3(64), 0, st, s, x, DR, rec, B, vnn, log_abs, sign,
-                           e_loc, parts);
+                           e_loc, parts, acc);
 }
 
 #define FN_INST(T)                                                                                                  \
