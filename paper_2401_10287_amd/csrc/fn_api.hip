@@ -438,6 +438,7 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
         }
     }
     T *HL = Hbuf(s.L);
+    OrbSpins<T> orb{};
     for (int sp = 0; sp < 2; ++sp) {
         const int n = sp == 0 ? s.nu : s.nd, j0 = sp == 0 ? 0 : s.nu;
         if (n == 0) continue;
@@ -462,11 +463,13 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
         }
         { Timed t_(K_HEAD_GEMM, st); (void)launch_gemm(c.hmode, gh, st); }
         if (fl || !p.save) {
-            // orbital matrices formed and factorised in LDS or registers; only
-            // the backward needs them stored
-            Timed t_(K_DET, st);
-            launch_orbdet<T>(s, xw, theta, c.P.g[sp], c.P.pi[sp], c.P.sig[sp], sp, O, c.W.KNp[sp], b, TR, fl, DR,
-                             p.rec, st);
+            // orbital matrices formed and factorised in LDS or registers (both
+            // spins in one launch below); only the backward needs them stored
+            (sp ? orb.gof1 : orb.gof0) = c.P.g[sp];
+            (sp ? orb.piof1 : orb.piof0) = c.P.pi[sp];
+            (sp ? orb.sigof1 : orb.sigof0) = c.P.sig[sp];
+            (sp ? orb.ldo1 : orb.ldo0) = c.W.KNp[sp];
+            (sp ? orb.O1 : orb.O0) = O;
             continue;
         }
         double *Phi = (double *)(ws + p.Phi[sp]);
@@ -476,6 +479,10 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
                                st);
         }
         { Timed t_(K_DET, st); launch_det(Phi, b, s.K, n, TR, n3, sp, fl, DR, p.rec, st); }
+    }
+    if (fl || !p.save) {
+        Timed t_(K_DET, st);
+        launch_orbdet<T>(s, xw, theta, orb, b, TR, fl, DR, p.rec, st);
     }
     Timed t_(K_COMBINE, st);
     launch_combine(s, xw, DR, p.rec, b, c.vnn, log_abs, sign, e_loc, parts, fl, acc, st);

@@ -54,9 +54,18 @@ void launch_envelope(const Sys &s, const double *x, const T *theta, int64_t gof,
                      const T *O, int64_t ldo, int64_t B, int TR, bool fl, double *Phi, hipStream_t st);
 size_t det_lds(int n, int n3, bool fl, size_t elem);
 size_t orbdet_lds(int n, bool fl);
+// Per-spin operands of the fused orbital / envelope / determinant stage:
+// parameter offsets of g, pi and Sigma, and the head output O with its
+// leading dimension.  One launch covers both spins when they have the same
+// size (the kernels take the spin from the block index).
 template <typename T>
-void launch_orbdet(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof, int sp,
-                   const T *O, int64_t ldo, int64_t B, int TR, bool fl, double *DR, int rec, hipStream_t st);
+struct OrbSpins {
+    int64_t gof0, gof1, piof0, piof1, sigof0, sigof1, ldo0, ldo1;
+    const T *O0, *O1;
+};
+template <typename T>
+void launch_orbdet(const Sys &s, const double *x, const T *theta, const OrbSpins<T> &S, int64_t B, int TR, bool fl,
+                   double *DR, int rec, hipStream_t st);
 void launch_det(const double *Phi, int64_t B, int K, int n, int TR, int n3, int sp, bool fl, double *DR, int rec,
                 hipStream_t st);
 // Metropolis acceptance folded into the value-only combine of the proposal:

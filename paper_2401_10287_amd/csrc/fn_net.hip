@@ -945,12 +945,17 @@ size_t orbdet_lds(int n, bool fl)
 // FL = false: value only (envelope, LU, sign and log|det|), LDS holds the matrix only.
 // REG: triangular solves of the directions in registers (spins of 7 ..
 // ORB_PF electrons, where LDS, not registers, bounds the resident waves)
+// Spins sp0 .. sp0 + nsp - 1 of equal size, B * K workgroups each.
 template <typename T, bool FL, bool REG>
-__global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *theta, int64_t gof, int64_t piof,
-                                               int64_t sigof, int sp, const T *O, int64_t ldo, int64_t B, int TR,
-                                               double *DR, int rec)
+__global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *theta, OrbSpins<T> S, int sp0,
+                                               int64_t B, int TR, double *DR, int rec)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    const int64_t per = B * s.K;
+    const int sp = sp0 + (int)(blockIdx.x / per);
+    const int64_t gof = sp ? S.gof1 : S.gof0, piof = sp ? S.piof1 : S.piof0, sigof = sp ? S.sigof1 : S.sigof0;
+    const int64_t ldo = sp ? S.ldo1 : S.ldo0;
+    const T *O = sp ? S.O1 : S.O0;
     const int n = sp == 0 ? s.nu : s.nd, j0 = sp == 0 ? 0 : s.nu;
     const int n3 = 3 * s.N, nn = n * n, CD = orbdet_cd(n);
     double *LU = (double *)smem_raw;      // [n][n] orbitals x electrons, then its LU factors
@@ -963,7 +968,7 @@ __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *
     __shared__ int s_sign, s_sing;
     __shared__ double s_log;
     const int lane = threadIdx.x;
-    const int64_t wk = blockIdx.x;
+    const int64_t wk = blockIdx.x % per;
     const int64_t w = wk / s.K;
     const int k = (int)(wk % s.K);
     if (w >= B) return;
@@ -1168,14 +1173,19 @@ __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *
 // matrices in registers.  Same quantities as k_orbdet; here the directions
 // use the explicit inverse from the pivoted LU, M_c = A^-1 d_c A.
 template <typename T, int NS, bool FL>
-__global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, const T *theta, int64_t gof,
-                                                      int64_t piof, int64_t sigof, int sp, const T *O, int64_t ldo,
+__global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, const T *theta, OrbSpins<T> S, int sp0,
                                                       int64_t B, int TR, double *DR, int rec)
 {
+    // spins sp0 .. of NS electrons each, ceil(B K / 256) workgroups per spin
+    const int64_t per = B * s.K, gsp = (per + 255) / 256;
+    const int sp = sp0 + (int)(blockIdx.x / gsp);
+    const int64_t gof = sp ? S.gof1 : S.gof0, piof = sp ? S.piof1 : S.piof0, sigof = sp ? S.sigof1 : S.sigof0;
+    const int64_t ldo = sp ? S.ldo1 : S.ldo0;
+    const T *O = sp ? S.O1 : S.O0;
     const int j0 = sp == 0 ? 0 : s.nu;
     const int n3 = 3 * s.N;
-    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (id >= B * s.K) return;
+    const int64_t id = (blockIdx.x % gsp) * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= per) return;
     const int64_t w = id / s.K;
     const int k = (int)(id % s.K);
     double ev[NS][NS], ge[NS][NS][3], le[NS][NS], a0[NS][NS], A[NS][NS];
@@ -1620,23 +1630,22 @@ void launch_det(const double *Phi, int64_t B, int K, int n, int TR, int n3, int 
 }
 
 template <typename T, int NS, bool FL>
-static void launch_small(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof, int sp,
-                         const T *O, int64_t ldo, int64_t B, int TR, double *DR, int rec, hipStream_t st)
+static void launch_small(const Sys &s, const double *x, const T *theta, const OrbSpins<T> &S, int sp0, int nsp,
+                         int64_t B, int TR, double *DR, int rec, hipStream_t st)
 {
-    const dim3 gs((unsigned)((B * s.K + 255) / 256));
-    hipLaunchKernelGGL((k_orbdet_small<T, NS, FL>), gs, dim3(256), 0, st, s, x, theta, gof, piof, sigof, sp, O, ldo, B,
-                       TR, DR, rec);
+    const dim3 gs((unsigned)(nsp * ((B * s.K + 255) / 256)));
+    hipLaunchKernelGGL((k_orbdet_small<T, NS, FL>), gs, dim3(256), 0, st, s, x, theta, S, sp0, B, TR, DR, rec);
 }
 
-// one thread per determinant where its matrices fit in registers: n <= 2 in
-// forward-Laplacian form, n <= 8 for the value alone; one wave otherwise
+// spins sp0 .. sp0 + nsp - 1 (of n electrons each) in one launch: one thread
+// per determinant where its matrices fit in registers (n <= 2 in
+// forward-Laplacian form, n <= 8 for the value alone), one wave otherwise
 template <typename T, bool FL>
-static void launch_orbdet_fl(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof,
-                             int sp, const T *O, int64_t ldo, int64_t B, int TR, double *DR, int rec, hipStream_t st)
+static void launch_orbdet_spins(const Sys &s, const double *x, const T *theta, const OrbSpins<T> &S, int sp0, int nsp,
+                                int n, int64_t B, int TR, double *DR, int rec, hipStream_t st)
 {
-    const int n = sp == 0 ? s.nu : s.nd;
 #define FN_SMALL(NS)                                                                                        \
-    case NS: launch_small<T, NS, FL>(s, x, theta, gof, piof, sigof, sp, O, ldo, B, TR, DR, rec, st); return;
+    case NS: launch_small<T, NS, FL>(s, x, theta, S, sp0, nsp, B, TR, DR, rec, st); return;
     switch (n) {
         FN_SMALL(1)
         FN_SMALL(2)
@@ -1654,23 +1663,32 @@ static void launch_orbdet_fl(const Sys &s, const double *x, const T *theta, int6
         }
     }
 #undef FN_SMALL
+    const dim3 g((unsigned)(nsp * B * s.K));
     if constexpr (FL) {
         if (n >= 7 && n <= ORB_PF) {
-            hipLaunchKernelGGL((k_orbdet<T, true, true>), dim3((unsigned)(B * s.K)), dim3(64), orbdet_lds(n, FL), st, s,
-                               x, theta, gof, piof, sigof, sp, O, ldo, B, TR, DR, rec);
+            hipLaunchKernelGGL((k_orbdet<T, true, true>), g, dim3(64), orbdet_lds(n, FL), st, s, x, theta, S, sp0, B, TR,
+                               DR, rec);
             return;
         }
     }
-    hipLaunchKernelGGL((k_orbdet<T, FL, false>), dim3((unsigned)(B * s.K)), dim3(64), orbdet_lds(n, FL), st, s, x, theta,
-                       gof, piof, sigof, sp, O, ldo, B, TR, DR, rec);
+    hipLaunchKernelGGL((k_orbdet<T, FL, false>), g, dim3(64), orbdet_lds(n, FL), st, s, x, theta, S, sp0, B, TR, DR,
+                       rec);
 }
 
 template <typename T>
-void launch_orbdet(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof, int sp,
-                   const T *O, int64_t ldo, int64_t B, int TR, bool fl, double *DR, int rec, hipStream_t st)
+void launch_orbdet(const Sys &s, const double *x, const T *theta, const OrbSpins<T> &S, int64_t B, int TR, bool fl,
+                   double *DR, int rec, hipStream_t st)
 {
-    if (fl) launch_orbdet_fl<T, true>(s, x, theta, gof, piof, sigof, sp, O, ldo, B, TR, DR, rec, st);
-    else launch_orbdet_fl<T, false>(s, x, theta, gof, piof, sigof, sp, O, ldo, B, TR, DR, rec, st);
+    auto run = [&](int sp0, int nsp, int n) {
+        if (fl) launch_orbdet_spins<T, true>(s, x, theta, S, sp0, nsp, n, B, TR, DR, rec, st);
+        else launch_orbdet_spins<T, false>(s, x, theta, S, sp0, nsp, n, B, TR, DR, rec, st);
+    };
+    if (s.nu > 0 && s.nu == s.nd) {
+        run(0, 2, s.nu);
+        return;
+    }
+    if (s.nu > 0) run(0, 1, s.nu);
+    if (s.nd > 0) run(1, 1, s.nd);
 }
 
 void launch_combine(const Sys &s, const double *x, const double *DR, int rec, int64_t B, double vnn, double *log_abs,
@@ -1694,8 +1712,8 @@ void launch_combine(const Sys &s, const double *x, const double *DR, int rec, in
                                       int, int, int, int, bool, T *, hipStream_t);                                  \
     template void launch_envelope<T>(const Sys &, const double *, const T *, int64_t, int64_t, int64_t, int,        \
                                      const T *, int64_t, int64_t, int, bool, double *, hipStream_t);                \
-    template void launch_orbdet<T>(const Sys &, const double *, const T *, int64_t, int64_t, int64_t, int,          \
-                                   const T *, int64_t, int64_t, int, bool, double *, int, hipStream_t);
+    template void launch_orbdet<T>(const Sys &, const double *, const T *, const OrbSpins<T> &, int64_t, int, bool,  \
+                                   double *, int, hipStream_t);
 
 FN_INST(float)
 FN_INST(double)
