@@ -439,11 +439,13 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
     }
     T *HL = Hbuf(s.L);
     OrbSpins<T> orb{};
+    // the orbital head of both spins (one launch when their tiles match)
+    GemmArgs ghs[2]{};
     for (int sp = 0; sp < 2; ++sp) {
         const int n = sp == 0 ? s.nu : s.nd, j0 = sp == 0 ? 0 : s.nu;
         if (n == 0) continue;
         T *O = (T *)(ws + p.O[sp]);
-        GemmArgs gh{};
+        GemmArgs &gh = ghs[sp];
         gh.A1 = HL; gh.lda1 = ldh; gh.K1 = c.W.W1p;
         gh.W = ws + p.wh[sp]; gh.ldw = c.W.W1p; gh.wpart = (int64_t)s.K * n * c.W.W1p;
         gh.C = O; gh.ldc = c.W.KNp[sp];
@@ -461,7 +463,15 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
         } else {
             gh.rows = b * n * TR; gh.rows_per_group = (int64_t)n * TR;
         }
-        { Timed t_(K_HEAD_GEMM, st); (void)launch_gemm(c.hmode, gh, st); }
+    }
+    {
+        Timed t_(K_HEAD_GEMM, st);
+        (void)launch_gemm2(c.hmode, ghs[0], ghs[1], st);
+    }
+    for (int sp = 0; sp < 2; ++sp) {
+        const int n = sp == 0 ? s.nu : s.nd;
+        if (n == 0) continue;
+        T *O = (T *)(ws + p.O[sp]);
         if (fl || !p.save) {
             // orbital matrices formed and factorised in LDS or registers (both
             // spins in one launch below); only the backward needs them stored

@@ -39,7 +39,7 @@ struct ModeInfo {
 // activations split by each wave as it reads its fragments (the layout of
 // the fused layer kernel's staged path); bitwise equal to the register path.
 template <int MODE, int BNT, bool DMA>
-__global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
+__device__ __forceinline__ void gemm_tile(const GemmArgs &a, int64_t bid)
 {
     constexpr bool F32 = ModeInfo<MODE>::F32;
     constexpr int NP = ModeInfo<MODE>::NP;
@@ -60,10 +60,10 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
     int64_t rb;
     int cb;
     if (ncb <= 2) {
-        xcd_tile(blockIdx.x, ncb, rb, cb);
+        xcd_tile(bid, ncb, rb, cb);
     } else {
-        rb = blockIdx.x % ((a.rows + BM - 1) / BM);
-        cb = (int)(blockIdx.x / ((a.rows + BM - 1) / BM));
+        rb = bid % ((a.rows + BM - 1) / BM);
+        cb = (int)(bid / ((a.rows + BM - 1) / BM));
     }
     const int64_t m0 = rb * BM;
     const int n0 = cb * BNT;
@@ -310,6 +310,21 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
         }
 }
 
+template <int MODE, int BNT, bool DMA>
+__global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs a)
+{
+    gemm_tile<MODE, BNT, DMA>(a, blockIdx.x);
+}
+
+// two products of one tile shape in one launch: workgroups [0, nb0) take a0,
+// the rest a1 (the two spins of the orbital head)
+template <int MODE, int BNT, bool DMA>
+__global__ __launch_bounds__(256) void k_gemm_mfma2(GemmArgs a0, GemmArgs a1, int64_t nb0)
+{
+    if ((int64_t)blockIdx.x < nb0) gemm_tile<MODE, BNT, DMA>(a0, blockIdx.x);
+    else gemm_tile<MODE, BNT, DMA>(a1, (int64_t)blockIdx.x - nb0);
+}
+
 // FP64 on the vector ALUs: 64 x 64 tiles, 16-step reduction tiles, 4 x 4
 // outputs per thread.
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs a)
@@ -372,23 +387,61 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs a)
 }
 
 template <int BNT>
-static void launch_bn(int mode, const GemmArgs &a, hipStream_t st)
+static int64_t bn_grid(const GemmArgs &a)
 {
     const int64_t nrb = (a.rows + BM - 1) / BM;
     const int ncb = (a.nout + BNT - 1) / BNT;
-    dim3 grid((unsigned)(ncb <= 2 ? xcd_grid(nrb, ncb) : nrb * ncb));
+    return ncb <= 2 ? xcd_grid(nrb, ncb) : nrb * ncb;
+}
+
+template <int MODE, int BNT, bool DMA>
+static void launch_kernel(const GemmArgs &a, const GemmArgs *a1, hipStream_t st)
+{
+    const int64_t g0 = bn_grid<BNT>(a);
+    if (a1) {
+        const dim3 grid((unsigned)(g0 + bn_grid<BNT>(*a1)));
+        hipLaunchKernelGGL((k_gemm_mfma2<MODE, BNT, DMA>), grid, dim3(256), 0, st, a, *a1, g0);
+    } else {
+        hipLaunchKernelGGL((k_gemm_mfma<MODE, BNT, DMA>), dim3((unsigned)g0), dim3(256), 0, st, a);
+    }
+}
+
+// a1: a second product of the same tile shape in the same launch, or nullptr
+template <int BNT>
+static void launch_bn(int mode, const GemmArgs &a, const GemmArgs *a1, hipStream_t st)
+{
     if constexpr (BNT == 128) {
-        if (g_layer_dma && mode != GEMM_F32 && a.K1 % BK == 0) {
-            if (mode == GEMM_BF16) hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16, 128, true>), grid, dim3(256), 0, st, a);
-            else if (mode == GEMM_BF16X3) hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16X3, 128, true>), grid, dim3(256), 0, st, a);
-            else hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16X6, 128, true>), grid, dim3(256), 0, st, a);
+        if (g_layer_dma && mode != GEMM_F32 && a.K1 % BK == 0 && (!a1 || a1->K1 % BK == 0)) {
+            if (mode == GEMM_BF16) launch_kernel<GEMM_BF16, 128, true>(a, a1, st);
+            else if (mode == GEMM_BF16X3) launch_kernel<GEMM_BF16X3, 128, true>(a, a1, st);
+            else launch_kernel<GEMM_BF16X6, 128, true>(a, a1, st);
             return;
         }
     }
-    if (mode == GEMM_F32) hipLaunchKernelGGL((k_gemm_mfma<GEMM_F32, BNT, false>), grid, dim3(256), 0, st, a);
-    else if (mode == GEMM_BF16) hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16, BNT, false>), grid, dim3(256), 0, st, a);
-    else if (mode == GEMM_BF16X3) hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16X3, BNT, false>), grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_gemm_mfma<GEMM_BF16X6, BNT, false>), grid, dim3(256), 0, st, a);
+    if (mode == GEMM_F32) launch_kernel<GEMM_F32, BNT, false>(a, a1, st);
+    else if (mode == GEMM_BF16) launch_kernel<GEMM_BF16, BNT, false>(a, a1, st);
+    else if (mode == GEMM_BF16X3) launch_kernel<GEMM_BF16X3, BNT, false>(a, a1, st);
+    else launch_kernel<GEMM_BF16X6, BNT, false>(a, a1, st);
+}
+
+// narrowest column tile that covers the output, and narrower still when
+// 128-column tiles would leave CUs idle (latency-bound small grids)
+static int pick_bn(const GemmArgs &a)
+{
+    const int64_t nrb = (a.rows + BM - 1) / BM;
+    const int bn = a.nout <= 32 ? 32 : (a.nout <= 64 ? 64 : 128);
+    const int64_t blocks = nrb * ((a.nout + bn - 1) / bn);
+    if (bn == 32 || (blocks < 256 && nrb * ((a.nout + 31) / 32) <= 1024)) return 32;
+    return bn;
+}
+
+static void launch_mfma(int mode, const GemmArgs &a, const GemmArgs *a1, hipStream_t st)
+{
+    switch (pick_bn(a)) {
+    case 32: launch_bn<32>(mode, a, a1, st); break;
+    case 64: launch_bn<64>(mode, a, a1, st); break;
+    default: launch_bn<128>(mode, a, a1, st); break;
+    }
 }
 
 hipError_t launch_gemm(int mode, const GemmArgs &a, hipStream_t st)
@@ -398,16 +451,21 @@ hipError_t launch_gemm(int mode, const GemmArgs &a, hipStream_t st)
         dim3 grid((unsigned)((a.rows + 63) / 64), (unsigned)((a.nout + 63) / 64));
         hipLaunchKernelGGL(k_gemm_f64, grid, dim3(256), 0, st, a);
     } else {
-        // narrowest column tile that covers the output, and narrower still
-        // when 128-column tiles would leave CUs idle (latency-bound small grids)
-        const int64_t nrb = (a.rows + BM - 1) / BM;
-        const int bn = a.nout <= 32 ? 32 : (a.nout <= 64 ? 64 : 128);
-        const int64_t blocks = nrb * ((a.nout + bn - 1) / bn);
-        if (bn == 32 || (blocks < 256 && nrb * ((a.nout + 31) / 32) <= 1024)) launch_bn<32>(mode, a, st);
-        else if (bn == 64) launch_bn<64>(mode, a, st);
-        else launch_bn<128>(mode, a, st);
+        launch_mfma(mode, a, nullptr, st);
     }
     // peek, so that an earlier launch's error is still there for the caller's final check
+    return hipPeekAtLastError();
+}
+
+hipError_t launch_gemm2(int mode, const GemmArgs &a0, const GemmArgs &a1, hipStream_t st)
+{
+    const bool e0 = a0.rows <= 0 || a0.nout <= 0, e1 = a1.rows <= 0 || a1.nout <= 0;
+    if (mode == GEMM_F64 || e0 || e1 || pick_bn(a0) != pick_bn(a1)) {
+        if (!e0) (void)launch_gemm(mode, a0, st);
+        if (!e1) (void)launch_gemm(mode, a1, st);
+        return hipPeekAtLastError();
+    }
+    launch_mfma(mode, a0, &a1, st);
     return hipPeekAtLastError();
 }
 

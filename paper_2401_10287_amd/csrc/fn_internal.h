@@ -226,6 +226,9 @@ __host__ __device__ inline int64_t remap_row(int64_t r, int64_t per, int64_t str
 }
 
 hipError_t launch_gemm(int mode, const GemmArgs &a, hipStream_t st);
+// two products in one launch when they take the same tile shape (else two
+// launches); each product's results are those of launch_gemm
+hipError_t launch_gemm2(int mode, const GemmArgs &a0, const GemmArgs &a1, hipStream_t st);
 
 // One fused one-electron stream layer (product + forward-Laplacian tanh
 // epilogue + residual).  A1 = h^l (rows of TR per electron, also the residual
