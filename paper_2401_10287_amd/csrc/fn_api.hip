@@ -369,14 +369,15 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
     T *X = (T *)(ws + p.X);
     double *DR = (double *)(ws + p.DR);
     const int64_t ldh = c.W.HWmax, ldg = c.W.GWmax;
-    { Timed t_(K_FEATURES, st); launch_features<T>(s, xw, b, TR, c.W.HWl[0], ldh, Hbuf(0), st); }
+    // the features and, in the same launch, the first layer's spin means
+    { Timed t_(K_FEATURES, st); launch_features<T>(s, xw, b, TR, c.W.HWl[0], ldh, Hbuf(0), G, st); }
     {
         Timed t_(K_PAIR, st);
         launch_pair_stream<T>(s, xw, theta, c.P, b, TR, fl, ldg, p.gi_layer_stride, c.W.GWl[0],
                               s.L > 1 ? c.W.GWl[1] : c.W.GWl[0],
                               sizeof(T) == sizeof(float) ? (const float *)(ws + p.wpair) : nullptr, GI, st);
     }
-    bool g_ready = false;            // spin means of h^l already written by the previous layer
+    bool g_ready = true;             // spin means of h^l already written (features, previous layer)
     for (int l = 0; l < s.L; ++l) {
         const int dh = layer_dh(s, l), HWl = c.W.HWl[l], GWl = c.W.GWl[l];
         T *Hin = Hbuf(l), *Hout = Hbuf(l + 1);

@@ -23,8 +23,11 @@ struct PackList {
 };
 template <typename T>
 void launch_pack(const T *theta, const PackList &pl, hipStream_t st);
+// G (or nullptr): also the first layer's spin means of the features, in the
+// layout and arithmetic of launch_spin_mean
 template <typename T>
-void launch_features(const Sys &s, const double *x, int64_t B, int TR, int HW0, int64_t ldh, T *H, hipStream_t st);
+void launch_features(const Sys &s, const double *x, int64_t B, int TR, int HW0, int64_t ldh, T *H, T *G,
+                     hipStream_t st);
 size_t pair_stream_lds(const Sys &s, bool fl, size_t elem);
 // Matrix-core pair kernel layout of the pair weights: per pair layer l the
 // transposed weights Wt[wc][KP_l + 4] (wc = w2 rounded up to 16, KP_l = d_p

@@ -116,13 +116,53 @@ __device__ inline void store4(double *p, double a, double b, double c, double d)
 // Columns of m >= M (padding up to HW0) are zero.
 template <typename T>
 __global__ __launch_bounds__(256) void k_features(Sys s, const double *x, int64_t B, int TR, int HW0, int64_t ldh,
-                                                  T *H)
+                                                  T *H, T *G)
 {
     const int mq = HW0 / 4;
     const int n3 = 3 * s.N;
     const int64_t total = B * s.N * TR * mq;
-    for (int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; it < total;
+    // then the spin means of these rows for the first layer: G[w TR + t] =
+    // [g_up | g_dn] (row width 2 HW0) for t up to the Laplacian row, each
+    // the FP rounding of the features summed over the spin's electrons in
+    // order and scaled by 1 / n, as the spin-mean kernel forms them
+    const int live = TR == 1 ? 1 : n3 + 2;
+    const int64_t gtotal = G ? B * live * 2 * mq : 0;
+    for (int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; it < total + gtotal;
          it += (int64_t)gridDim.x * blockDim.x) {
+        if (it >= total) {
+            const int64_t ig = it - total;
+            const int q = (int)(ig % (2 * mq));
+            const int64_t wt = ig / (2 * mq);             // walker * live + t
+            const int64_t w = wt / live;
+            const int t = (int)(wt - w * live);
+            const int sp = q >= mq, m = q - sp * mq;
+            const int n = sp ? s.N - s.nu : s.nu, j0 = sp ? s.nu : 0;
+            const T inv = n > 0 ? T(1) / T(n) : T(0);
+            T v[4] = {T(0), T(0), T(0), T(0)};
+            if (m < s.M && n > 0) {
+                int e = -1, a = -1;                       // tangent row of electron e's coordinate a
+                if (t >= 1 && t <= n3) { e = (t - 1) / 3; a = t - 1 - 3 * e; }
+                for (int j = j0; j < j0 + n; ++j) {
+                    if (e >= 0 && j != e) continue;       // other electrons' tangent rows are zero
+                    const double *xj = x + (w * s.N + j) * 3;
+                    const double d0 = xj[0] - s.R[m][0], d1 = xj[1] - s.R[m][1], d2 = xj[2] - s.R[m][2];
+                    const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                    if (t == 0) {
+                        v[0] += (T)d0; v[1] += (T)d1; v[2] += (T)d2; v[3] += (T)r;
+                    } else if (t == n3 + 1) {
+                        v[3] += (T)(2.0 / r);
+                    } else {
+                        const double da = a == 0 ? d0 : (a == 1 ? d1 : d2);
+                        v[a] += T(1);
+                        v[3] += (T)(da / r);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) v[c] *= inv;
+            }
+            store4(G + (w * TR + t) * (2 * (int64_t)HW0) + sp * HW0 + 4 * m, v[0], v[1], v[2], v[3]);
+            continue;
+        }
         const int m = (int)(it % mq);
         const int64_t row = it / mq;                  // (walker * N + electron) * TR + t
         const int t = (int)(row % TR);
@@ -1457,10 +1497,12 @@ void launch_pack(const T *theta, const PackList &pl, hipStream_t st)
 }
 
 template <typename T>
-void launch_features(const Sys &s, const double *x, int64_t B, int TR, int HW0, int64_t ldh, T *H, hipStream_t st)
+void launch_features(const Sys &s, const double *x, int64_t B, int TR, int HW0, int64_t ldh, T *H, T *G,
+                     hipStream_t st)
 {
-    hipLaunchKernelGGL(k_features<T>, dim3(grid_for(B * s.N * TR * (HW0 / 4))), dim3(256), 0, st, s, x, B, TR, HW0,
-                       ldh, H);
+    const int64_t live = TR == 1 ? 1 : 3 * s.N + 2;
+    const int64_t items = B * s.N * TR * (HW0 / 4) + (G ? B * live * 2 * (HW0 / 4) : 0);
+    hipLaunchKernelGGL(k_features<T>, dim3(grid_for(items)), dim3(256), 0, st, s, x, B, TR, HW0, ldh, H, G);
 }
 
 // LDS of a pair-stream workgroup holding WB (walker, electron) rows
@@ -1704,7 +1746,8 @@ void launch_combine(const Sys &s, const double *x, const double *DR, int rec, in
 
 #define FN_INST(T)                                                                                                  \
     template void launch_pack<T>(const T *, const PackList &, hipStream_t);                                          \
-    template void launch_features<T>(const Sys &, const double *, int64_t, int, int, int64_t, T *, hipStream_t);    \
+    template void launch_features<T>(const Sys &, const double *, int64_t, int, int, int64_t, T *, T *,             \
+                                     hipStream_t);                                                                  \
     template void launch_pair_stream<T>(const Sys &, const double *, const T *, const ParamLayout &, int64_t, int,   \
                                         bool, int64_t, int64_t, int, int, const float *, T *, hipStream_t);         \
     template void launch_spin_mean<T>(const T *, int64_t, int64_t, int, int, int, int, int, T *, hipStream_t);      \
