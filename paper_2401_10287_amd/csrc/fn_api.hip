@@ -491,6 +491,11 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
         }
         { Timed t_(K_DET, st); launch_det(Phi, b, s.K, n, TR, n3, sp, fl, DR, p.rec, st); }
     }
+    if (!fl && !p.save) {
+        // value form with equal small spins: determinants and combine in one launch
+        Timed t_(K_DET, st);
+        if (launch_orbdet_combine<T>(s, xw, theta, orb, b, TR, log_abs, sign, acc, st)) return;
+    }
     if (fl || !p.save) {
         Timed t_(K_DET, st);
         launch_orbdet<T>(s, xw, theta, orb, b, TR, fl, DR, p.rec, st);

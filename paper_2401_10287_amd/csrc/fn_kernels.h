@@ -83,6 +83,13 @@ struct AcceptArgs {
 };
 void launch_combine(const Sys &s, const double *x, const double *DR, int rec, int64_t B, double vnn, double *log_abs,
                     int8_t *sign, double *e_loc, double *parts, bool fl, const AcceptArgs &acc, hipStream_t st);
+// Value form with both spins of 1..8 electrons and K <= 32: the orbital /
+// determinant stage and the combine (with the acceptance) in one launch;
+// results equal to launch_orbdet followed by launch_combine.  false (nothing
+// launched) for other shapes.
+template <typename T>
+bool launch_orbdet_combine(const Sys &s, const double *x, const T *theta, const OrbSpins<T> &S, int64_t B, int TR,
+                           double *log_abs, int8_t *sign, const AcceptArgs &acc, hipStream_t st);
 
 // backward (fn_backward.hip)
 size_t det_backward_lds(int n);

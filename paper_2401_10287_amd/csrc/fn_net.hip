@@ -1209,26 +1209,16 @@ __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *
     if (lane == 0) out[2 + n3] = trl - sq;
 }
 
-// Small spins: one thread per (walker, determinant k) with the
-// matrices in registers.  Same quantities as k_orbdet; here the directions
-// use the explicit inverse from the pivoted LU, M_c = A^-1 d_c A.
+// Entries of one small determinant (NS x NS; rows = orbitals io, columns =
+// electrons j0 + jj of one spin) for walker w, determinant k: envelope e
+// (Eq. 4) and, with FL, its electron-j gradient and Laplacian, the orbital
+// value a (head output plus bias) and A = a e; all FP64.
 template <typename T, int NS, bool FL>
-__global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, const T *theta, OrbSpins<T> S, int sp0,
-                                                      int64_t B, int TR, double *DR, int rec)
+__device__ __forceinline__ void small_entries(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof,
+                                              int64_t sigof, const T *O, int64_t ldo, int TR, int j0, int64_t w, int k,
+                                              double (&ev)[NS][NS], double (&ge)[NS][NS][3], double (&le)[NS][NS],
+                                              double (&a0)[NS][NS], double (&A)[NS][NS])
 {
-    // spins sp0 .. of NS electrons each, ceil(B K / 256) workgroups per spin
-    const int64_t per = B * s.K, gsp = (per + 255) / 256;
-    const int sp = sp0 + (int)(blockIdx.x / gsp);
-    const int64_t gof = sp ? S.gof1 : S.gof0, piof = sp ? S.piof1 : S.piof0, sigof = sp ? S.sigof1 : S.sigof0;
-    const int64_t ldo = sp ? S.ldo1 : S.ldo0;
-    const T *O = sp ? S.O1 : S.O0;
-    const int j0 = sp == 0 ? 0 : s.nu;
-    const int n3 = 3 * s.N;
-    const int64_t id = (blockIdx.x % gsp) * (int64_t)blockDim.x + threadIdx.x;
-    if (id >= per) return;
-    const int64_t w = id / s.K;
-    const int k = (int)(id % s.K);
-    double ev[NS][NS], ge[NS][NS][3], le[NS][NS], a0[NS][NS], A[NS][NS];
 #pragma unroll
     for (int io = 0; io < NS; ++io)
 #pragma unroll
@@ -1263,13 +1253,18 @@ __global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, co
             a0[io][jj] = (double)O[((w * NS + jj) * TR) * ldo + col] + (double)theta[gof + col];
             A[io][jj] = a0[io][jj] * env;
         }
-    // LU with partial pivoting (rows = orbitals), then the inverse
-    int perm[NS];
+}
+
+// LU with partial pivoting of A in place (rows = orbitals): row permutation,
+// sign and log|det A|; sing when a pivot column is zero.
+template <int NS>
+__device__ __forceinline__ void small_lu(double (&A)[NS][NS], int (&perm)[NS], int &sgn, double &lg, bool &sing)
+{
 #pragma unroll
     for (int r = 0; r < NS; ++r) perm[r] = r;
-    int sgn = 1;
-    double lg = 0.0;
-    bool sing = false;
+    sgn = 1;
+    lg = 0.0;
+    sing = false;
 #pragma unroll
     for (int c = 0; c < NS; ++c) {
         int p = c;
@@ -1299,6 +1294,34 @@ __global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, co
             for (int q = c + 1; q < NS; ++q) A[r][q] -= A[r][c] * A[c][q];
         }
     }
+}
+
+// Small spins: one thread per (walker, determinant k) with the
+// matrices in registers.  Same quantities as k_orbdet; here the directions
+// use the explicit inverse from the pivoted LU, M_c = A^-1 d_c A.
+template <typename T, int NS, bool FL>
+__global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, const T *theta, OrbSpins<T> S, int sp0,
+                                                      int64_t B, int TR, double *DR, int rec)
+{
+    // spins sp0 .. of NS electrons each, ceil(B K / 256) workgroups per spin
+    const int64_t per = B * s.K, gsp = (per + 255) / 256;
+    const int sp = sp0 + (int)(blockIdx.x / gsp);
+    const int64_t gof = sp ? S.gof1 : S.gof0, piof = sp ? S.piof1 : S.piof0, sigof = sp ? S.sigof1 : S.sigof0;
+    const int64_t ldo = sp ? S.ldo1 : S.ldo0;
+    const T *O = sp ? S.O1 : S.O0;
+    const int j0 = sp == 0 ? 0 : s.nu;
+    const int n3 = 3 * s.N;
+    const int64_t id = (blockIdx.x % gsp) * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= per) return;
+    const int64_t w = id / s.K;
+    const int k = (int)(id % s.K);
+    double ev[NS][NS], ge[NS][NS][3], le[NS][NS], a0[NS][NS], A[NS][NS];
+    small_entries<T, NS, FL>(s, x, theta, gof, piof, sigof, O, ldo, TR, j0, w, k, ev, ge, le, a0, A);
+    // LU with partial pivoting (rows = orbitals), then the inverse
+    int perm[NS], sgn;
+    double lg;
+    bool sing;
+    small_lu<NS>(A, perm, sgn, lg, sing);
     double *out = DR + (w * 2 + sp) * (int64_t)s.K * rec + (int64_t)k * rec;
     if (sing) {
         out[0] = 0.0;
@@ -1473,6 +1496,71 @@ __global__ __launch_bounds__(64) void k_combine(Sys s, const double *x, const do
         e_loc[w] = kin + vee + ven + vnn;
         if (parts) {
             parts[4 * w] = kin; parts[4 * w + 1] = vee; parts[4 * w + 2] = ven; parts[4 * w + 3] = vnn;
+        }
+    }
+}
+
+// Value form, both spins of NS electrons, K <= 32 determinants: the orbital
+// / determinant stage and the combine in one launch.  A group of G lanes
+// (G = 32 when 2K <= 32, else 64) takes one walker; lane sp K + k forms
+// determinant k of spin sp as k_orbdet_small does.  Lanes k < K then pair
+// the spins and reduce over k with the butterflies of k_combine in the same
+// order (that kernel's first step only adds lanes without a determinant), so
+// log|psi|, its sign and the Metropolis decision are those of the two
+// separate kernels.
+template <typename T, int NS, int G>
+__global__ __launch_bounds__(256) void k_orbdet_combine(Sys s, const double *x, const T *theta, OrbSpins<T> S,
+                                                        int64_t B, int TR, double *log_abs, int8_t *sign,
+                                                        AcceptArgs acc)
+{
+    const int lane = threadIdx.x & 63, gl = lane & (G - 1);
+    const int64_t w = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
+    const int K = s.K, n3 = 3 * s.N;
+    const bool wok = w < B;
+    double sg = 0.0, lg = -INFINITY;              // lanes without a determinant
+    if (wok && gl < 2 * K) {
+        const int sp = gl < K ? 0 : 1, k = gl < K ? gl : gl - K;
+        const int64_t gof = sp ? S.gof1 : S.gof0, piof = sp ? S.piof1 : S.piof0, sigof = sp ? S.sigof1 : S.sigof0;
+        const int64_t ldo = sp ? S.ldo1 : S.ldo0;
+        const T *O = sp ? S.O1 : S.O0;
+        double ev[NS][NS], ge[NS][NS][3], le[NS][NS], a0[NS][NS], A[NS][NS];
+        small_entries<T, NS, false>(s, x, theta, gof, piof, sigof, O, ldo, TR, sp ? s.nu : 0, w, k, ev, ge, le, a0, A);
+        int perm[NS], sgn;
+        double l;
+        bool sing;
+        small_lu<NS>(A, perm, sgn, l, sing);
+        sg = sing ? 0.0 : (double)sgn;
+        lg = sing ? -INFINITY : l;
+    }
+    // spin-down determinant k from lane K + k of the group
+    const int src = gl < K ? lane + K : lane;
+    const double sd = __shfl(sg, src, 64), ld = __shfl(lg, src, 64);
+    double sk = 0.0, lk = -INFINITY;
+    if (gl < K) {
+        sk = sg * sd;
+        lk = sk != 0.0 ? lg + ld : -INFINITY;
+    }
+    double lmax = lk;
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, off, 64));
+    double sum = (gl < K && sk != 0.0) ? sk * exp(lk - lmax) : 0.0;
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    const bool node = !(lmax > -INFINITY) || sum == 0.0 || !(sum == sum);
+    const double lpsi = node ? -INFINITY : lmax + log(fabs(sum));
+    if (!wok) return;
+    if (gl == 0) {
+        if (log_abs) log_abs[w] = lpsi;
+        if (sign) sign[w] = node ? 0 : (sum > 0 ? 1 : -1);
+    }
+    if (acc.x) {
+        const bool take = isfinite(lpsi) && log(acc.u[w]) <= 2.0 * (lpsi - acc.log_abs[w]);
+        if (take) {
+            for (int q = gl; q < n3; q += G) acc.x[w * n3 + q] = acc.xp[w * n3 + q];
+            if (gl == 0) {
+                acc.log_abs[w] = lpsi;
+                if (acc.n_accept) acc.n_accept[w] += 1;
+            }
         }
     }
 }
@@ -1733,6 +1821,27 @@ void launch_orbdet(const Sys &s, const double *x, const T *theta, const OrbSpins
     if (s.nd > 0) run(1, 1, s.nd);
 }
 
+template <typename T>
+bool launch_orbdet_combine(const Sys &s, const double *x, const T *theta, const OrbSpins<T> &S, int64_t B, int TR,
+                           double *log_abs, int8_t *sign, const AcceptArgs &acc, hipStream_t st)
+{
+    if (s.nu != s.nd || s.nu < 1 || s.nu > 8 || s.K > 32 || B <= 0) return false;
+    const bool g32 = 2 * s.K <= 32;
+    const dim3 g((unsigned)((B + (g32 ? 8 : 4) - 1) / (g32 ? 8 : 4)));
+#define FN_OC(NS)                                                                                                  \
+    case NS:                                                                                                       \
+        if (g32) hipLaunchKernelGGL((k_orbdet_combine<T, NS, 32>), g, dim3(256), 0, st, s, x, theta, S, B, TR,     \
+                                    log_abs, sign, acc);                                                           \
+        else hipLaunchKernelGGL((k_orbdet_combine<T, NS, 64>), g, dim3(256), 0, st, s, x, theta, S, B, TR,         \
+                                log_abs, sign, acc);                                                               \
+        return true;
+    switch (s.nu) {
+        FN_OC(1) FN_OC(2) FN_OC(3) FN_OC(4) FN_OC(5) FN_OC(6) FN_OC(7) FN_OC(8)
+    default: return false;
+    }
+#undef FN_OC
+}
+
 void launch_combine(const Sys &s, const double *x, const double *DR, int rec, int64_t B, double vnn, double *log_abs,
                     int8_t *sign, double *e_loc, double *parts, bool fl, const AcceptArgs &acc, hipStream_t st)
 {
@@ -1756,7 +1865,9 @@ void launch_combine(const Sys &s, const double *x, const double *DR, int rec, in
     template void launch_envelope<T>(const Sys &, const double *, const T *, int64_t, int64_t, int64_t, int,        \
                                      const T *, int64_t, int64_t, int, bool, double *, hipStream_t);                \
     template void launch_orbdet<T>(const Sys &, const double *, const T *, const OrbSpins<T> &, int64_t, int, bool,  \
-                                   double *, int, hipStream_t);
+                                   double *, int, hipStream_t);                                                     \
+    template bool launch_orbdet_combine<T>(const Sys &, const double *, const T *, const OrbSpins<T> &, int64_t,    \
+                                           int, double *, int8_t *, const AcceptArgs &, hipStream_t);
 
 FN_INST(float)
 FN_INST(double)
