@@ -834,6 +834,10 @@ fn_status fn_tuning_set(const char *name, int64_t value)
         fn::g_use_fused_layer = value != 0;
         return FN_OK;
     }
+    if (strcmp(name, "gemm_splitk") == 0) {
+        fn::g_gemm_splitk = value != 0;
+        return FN_OK;
+    }
     if (strcmp(name, "layer_dma") == 0) {
         fn::g_layer_dma = value != 0;
         return FN_OK;

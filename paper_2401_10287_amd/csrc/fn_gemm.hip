@@ -23,8 +23,17 @@
 
 namespace fn {
 
+bool g_gemm_splitk = true;
+
 
 constexpr int BM = 128, BK = 32;
+
+// bitwise select (m all ones or zero) of a float4
+__device__ inline float4 mask4f(float4 x, uint32_t m)
+{
+    return make_float4(__uint_as_float(__float_as_uint(x.x) & m), __uint_as_float(__float_as_uint(x.y) & m),
+                       __uint_as_float(__float_as_uint(x.z) & m), __uint_as_float(__float_as_uint(x.w) & m));
+}
 constexpr int LDH = BK;       // LDS row stride of BF16 tiles (64 bytes, chunk-swizzled by lds_chunk)
 constexpr int LDF = BK + 4;   // LDS row stride of FP32 tiles (144 bytes)
 
@@ -325,6 +334,136 @@ __global__ __launch_bounds__(256) void k_gemm_mfma2(GemmArgs a0, GemmArgs a1, in
     else gemm_tile<MODE, BNT, DMA>(a1, (int64_t)blockIdx.x - nb0);
 }
 
+// Small products (split-BF16 modes, grids that would leave most CUs idle):
+// one 32 x 32 output tile per 256-thread workgroup with the reduction
+// dimension split over its four waves.  Each wave takes a contiguous quarter
+// of the 32-wide reduction steps with its operand fragments loaded straight
+// from global memory into registers (the next step's loads issued before the
+// current step's matrix instructions; products of parts in the order of the
+// tiled kernel), and the four partial tiles are summed through LDS in wave
+// order.  The chain of dependent reduction steps is a quarter as long.
+template <int MODE>
+__device__ __forceinline__ void gemm_splitk_tile(const GemmArgs &a, int64_t bid)
+{
+    constexpr int NP = ModeInfo<MODE>::NP;
+    static_assert(MODE != GEMM_F32, "split-BF16 modes");
+    __shared__ float red[4][32][33];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t nrb = (a.rows + 31) / 32;
+    const int64_t m0 = (bid % nrb) * 32;
+    const int n0 = (int)(bid / nrb) * 32;
+    const int ksteps = (a.K1 + a.K2) / BK;
+    const int per = (ksteps + 3) / 4;
+    const int k0 = wave * per, k1 = min(ksteps, k0 + per);
+    const int li = lane & 15, kq = lane >> 4;          // row / column li of a block, reduction offset 8 kq
+    const float *A1 = (const float *)a.A1, *A2 = (const float *)a.A2;
+    const uint16_t *W = (const uint16_t *)a.W;
+    // rows past the end and columns past nout load row m0 / column n0 and are zeroed
+    int64_t ar[2], wr[2];
+    uint32_t am[2], wm[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int64_t r = m0 + 16 * i + li;
+        am[i] = r < a.rows ? 0xffffffffu : 0u;
+        ar[i] = gemm_a_row(a, r < a.rows ? r : m0);
+        const int o = n0 + 16 * i + li;
+        wm[i] = o < a.nout ? 0xffffffffu : 0u;
+        wr[i] = (int64_t)(o < a.nout ? o : n0) * a.ldw;
+    }
+    float4 xa[2][2], na[2][2];
+    uint4 xb[2][NP], nb[2][NP];
+    auto load = [&](int kt, float4 (&A)[2][2], uint4 (&Bv)[2][NP]) {
+        const int kb = kt * BK;
+        const bool first = kb < a.K1;
+        const float *base = first ? A1 : A2;
+        const int64_t lda = first ? a.lda1 : a.lda2;
+        const int kk = (first ? kb : kb - a.K1) + 8 * kq;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const float *pa = base + ar[i] * lda + kk;
+            A[i][0] = *(const float4 *)pa;
+            A[i][1] = *(const float4 *)(pa + 4);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < NP; ++q) Bv[j][q] = *(const uint4 *)(W + (int64_t)q * a.wpart + wr[j] + kb + 8 * kq);
+    };
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (k0 < k1) load(k0, xa, xb);
+    for (int kt = k0; kt < k1; ++kt) {
+        if (kt + 1 < k1) load(kt + 1, na, nb);
+        bf16x8 ha[NP][2], hb[NP][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const float4 x0 = mask4f(xa[i][0], am[i]), x1 = mask4f(xa[i][1], am[i]);
+            bf16x8 hp[NP];
+            split_fragment<NP>(x0, x1, hp);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) ha[q][i] = hp[q];
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const uint4 u = xb[j][q];
+                hb[q][j] = __builtin_bit_cast(bf16x8, make_uint4(u.x & wm[j], u.y & wm[j], u.z & wm[j], u.w & wm[j]));
+            }
+#pragma unroll
+        for (int sum = NP - 1; sum >= 0; --sum)
+#pragma unroll
+            for (int pa = 0; pa <= sum; ++pa)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j], acc[i][j], 0, 0, 0);
+        if (kt + 1 < k1) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) { xa[i][0] = na[i][0]; xa[i][1] = na[i][1]; }
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int q = 0; q < NP; ++q) xb[j][q] = nb[j][q];
+        }
+    }
+    // accumulator (i, j) element e: row 16 i + 4 kq + e, column 16 j + li
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) red[wave][16 * i + 4 * kq + e][16 * j + li] = acc[i][j][e];
+    __syncthreads();
+    float *C = (float *)a.C;
+    for (int q = tid; q < 32 * 32; q += 256) {
+        const int r = q >> 5, cc = q & 31;
+        int64_t row = m0 + r;
+        const int col = n0 + cc;
+        if (row >= a.rows || col >= a.nout) continue;
+        const float v = ((red[0][r][cc] + red[1][r][cc]) + red[2][r][cc]) + red[3][r][cc];
+        if (a.c_rows_per_group > 0) row = remap_row(row, a.c_rows_per_group, a.c_group_stride, a.c_row_offset);
+        C[row * a.ldc + col] = v;
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gemm_splitk(GemmArgs a)
+{
+    gemm_splitk_tile<MODE>(a, blockIdx.x);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gemm_splitk2(GemmArgs a0, GemmArgs a1, int64_t nb0)
+{
+    if ((int64_t)blockIdx.x < nb0) gemm_splitk_tile<MODE>(a0, blockIdx.x);
+    else gemm_splitk_tile<MODE>(a1, (int64_t)blockIdx.x - nb0);
+}
+
 // FP64 on the vector ALUs: 64 x 64 tiles, 16-step reduction tiles, 4 x 4
 // outputs per thread.
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs a)
@@ -435,8 +574,38 @@ static int pick_bn(const GemmArgs &a)
     return bn;
 }
 
+// split-K tiles for grids of 128-row tiles that would not fill the CUs
+static bool use_splitk(int mode, const GemmArgs &a)
+{
+    if (!g_gemm_splitk || mode == GEMM_F32 || mode == GEMM_F64 || a.K1 % BK != 0 || a.K2 % BK != 0) return false;
+    const int64_t nrb = (a.rows + BM - 1) / BM;
+    return nrb * ((a.nout + 31) / 32) < 256;
+}
+
+static int64_t splitk_grid(const GemmArgs &a) { return ((a.rows + 31) / 32) * ((a.nout + 31) / 32); }
+
+template <int MODE>
+static void launch_splitk_mode(const GemmArgs &a, const GemmArgs *a1, hipStream_t st)
+{
+    const int64_t g0 = splitk_grid(a);
+    if (a1) hipLaunchKernelGGL((k_gemm_splitk2<MODE>), dim3((unsigned)(g0 + splitk_grid(*a1))), dim3(256), 0, st, a,
+                               *a1, g0);
+    else hipLaunchKernelGGL((k_gemm_splitk<MODE>), dim3((unsigned)g0), dim3(256), 0, st, a);
+}
+
+static void launch_splitk(int mode, const GemmArgs &a, const GemmArgs *a1, hipStream_t st)
+{
+    if (mode == GEMM_BF16) launch_splitk_mode<GEMM_BF16>(a, a1, st);
+    else if (mode == GEMM_BF16X3) launch_splitk_mode<GEMM_BF16X3>(a, a1, st);
+    else launch_splitk_mode<GEMM_BF16X6>(a, a1, st);
+}
+
 static void launch_mfma(int mode, const GemmArgs &a, const GemmArgs *a1, hipStream_t st)
 {
+    if (use_splitk(mode, a) && (!a1 || use_splitk(mode, *a1))) {
+        launch_splitk(mode, a, a1, st);
+        return;
+    }
     switch (pick_bn(a)) {
     case 32: launch_bn<32>(mode, a, a1, st); break;
     case 64: launch_bn<64>(mode, a, a1, st); break;
@@ -460,7 +629,7 @@ hipError_t launch_gemm(int mode, const GemmArgs &a, hipStream_t st)
 hipError_t launch_gemm2(int mode, const GemmArgs &a0, const GemmArgs &a1, hipStream_t st)
 {
     const bool e0 = a0.rows <= 0 || a0.nout <= 0, e1 = a1.rows <= 0 || a1.nout <= 0;
-    if (mode == GEMM_F64 || e0 || e1 || pick_bn(a0) != pick_bn(a1)) {
+    if (mode == GEMM_F64 || e0 || e1 || pick_bn(a0) != pick_bn(a1) || use_splitk(mode, a0) != use_splitk(mode, a1)) {
         if (!e0) (void)launch_gemm(mode, a0, st);
         if (!e1) (void)launch_gemm(mode, a1, st);
         return hipPeekAtLastError();

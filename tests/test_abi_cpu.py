@@ -96,3 +96,17 @@ def test_timing_class_names_checked_on_host():
     for k in fnvmc.KERNEL_CLASSES:
         assert fnvmc.LIB.fn_timing_select(k.encode()) == fnvmc.FN_OK
     assert fnvmc.LIB.fn_timing_select(None) == fnvmc.FN_OK
+
+
+def test_tuning_switches_checked_on_host():
+    """Every documented tuning switch is accepted (and restored to its
+    default), unknown names and out-of-range values are rejected; setting a
+    switch touches no device."""
+    fnvmc = _fnvmc()
+    defaults = {"fused_layer": 1, "layer_dma": 1, "gemm_splitk": 1, "pair_mfma": 1, "pair_oc": 0, "pair_items": 0}
+    for name, default in defaults.items():
+        for v in (0, default):
+            assert fnvmc.LIB.fn_tuning_set(name.encode(), v) == fnvmc.FN_OK, name
+    assert fnvmc.LIB.fn_tuning_set(b"no_such_switch", 1) == fnvmc.FN_EINVAL
+    assert fnvmc.LIB.fn_tuning_set(b"pair_oc", 3) == fnvmc.FN_EINVAL
+    assert fnvmc.LIB.fn_tuning_set(b"pair_items", 5000) == fnvmc.FN_EINVAL

@@ -315,6 +315,29 @@ def test_pair_kernels_and_launch_shapes(name, walkers):
         fnvmc.fn_tuning_set("pair_items", 0)
 
 
+@pytest.mark.parametrize("name,walkers", [("LiH", 256), ("LiF", 37), ("LiH", 1024)])
+def test_small_grid_products_both_kernels(name, walkers):
+    """Small walker batches in the value form: products whose 128-row tiles
+    would not fill the CUs run as split-reduction 32 x 32 tiles (default) or
+    on the tiled kernel; both are held to the oracle's log|psi| bounds, and
+    the sign agrees."""
+    s = SYSTEMS[name]()
+    torch, fnvmc, cfg, tt, xt, th, x = _setup(s, "bf16x6", walkers)
+    o = O.Oracle(s)
+    ref = o.log_psi(th, x)
+    C = _conditioning(o, s, th, x)
+    well = _kappa_sum(o, th, x) <= 1e3          # the sign is fixed where the determinant sum does not cancel
+    try:
+        for v in (1, 0):
+            fnvmc.fn_tuning_set("gemm_splitk", v)
+            lp, sg = fnvmc.fn_log_psi(cfg, tt, xt)
+            torch.cuda.synchronize()
+            _check_logpsi(lp.cpu().numpy(), ref, 1e-5, f"{name} B={walkers} gemm_splitk={v}", C, False)
+            np.testing.assert_array_equal(sg.cpu().numpy()[well], ref["sign"][well])
+    finally:
+        fnvmc.fn_tuning_set("gemm_splitk", 1)
+
+
 @pytest.mark.parametrize("prec", ["bf16x6", "bf16x3", "bf16"])
 def test_layer_operand_staging_bitwise(prec):
     """The two ways of staging operand tiles of the fused layer and the
