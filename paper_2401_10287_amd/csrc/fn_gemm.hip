@@ -28,12 +28,6 @@ bool g_gemm_splitk = true;
 
 constexpr int BM = 128, BK = 32;
 
-// bitwise select (m all ones or zero) of a float4
-__device__ inline float4 mask4f(float4 x, uint32_t m)
-{
-    return make_float4(__uint_as_float(__float_as_uint(x.x) & m), __uint_as_float(__float_as_uint(x.y) & m),
-                       __uint_as_float(__float_as_uint(x.z) & m), __uint_as_float(__float_as_uint(x.w) & m));
-}
 constexpr int LDH = BK;       // LDS row stride of BF16 tiles (64 bytes, chunk-swizzled by lds_chunk)
 constexpr int LDF = BK + 4;   // LDS row stride of FP32 tiles (144 bytes)
 
@@ -348,97 +342,15 @@ __device__ __forceinline__ void gemm_splitk_tile(const GemmArgs &a, int64_t bid)
     constexpr int NP = ModeInfo<MODE>::NP;
     static_assert(MODE != GEMM_F32, "split-BF16 modes");
     __shared__ float red[4][32][33];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     const int64_t nrb = (a.rows + 31) / 32;
     const int64_t m0 = (bid % nrb) * 32;
     const int n0 = (int)(bid / nrb) * 32;
-    const int ksteps = (a.K1 + a.K2) / BK;
-    const int per = (ksteps + 3) / 4;
-    const int k0 = wave * per, k1 = min(ksteps, k0 + per);
-    const int li = lane & 15, kq = lane >> 4;          // row / column li of a block, reduction offset 8 kq
-    const float *A1 = (const float *)a.A1, *A2 = (const float *)a.A2;
-    const uint16_t *W = (const uint16_t *)a.W;
-    // rows past the end and columns past nout load row m0 / column n0 and are zeroed
-    int64_t ar[2], wr[2];
-    uint32_t am[2], wm[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int64_t r = m0 + 16 * i + li;
-        am[i] = r < a.rows ? 0xffffffffu : 0u;
-        ar[i] = gemm_a_row(a, r < a.rows ? r : m0);
-        const int o = n0 + 16 * i + li;
-        wm[i] = o < a.nout ? 0xffffffffu : 0u;
-        wr[i] = (int64_t)(o < a.nout ? o : n0) * a.ldw;
-    }
-    float4 xa[2][2], na[2][2];
-    uint4 xb[2][NP], nb[2][NP];
-    auto load = [&](int kt, float4 (&A)[2][2], uint4 (&Bv)[2][NP]) {
-        const int kb = kt * BK;
-        const bool first = kb < a.K1;
-        const float *base = first ? A1 : A2;
-        const int64_t lda = first ? a.lda1 : a.lda2;
-        const int kk = (first ? kb : kb - a.K1) + 8 * kq;
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const float *pa = base + ar[i] * lda + kk;
-            A[i][0] = *(const float4 *)pa;
-            A[i][1] = *(const float4 *)(pa + 4);
-        }
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int q = 0; q < NP; ++q) Bv[j][q] = *(const uint4 *)(W + (int64_t)q * a.wpart + wr[j] + kb + 8 * kq);
-    };
     f32x4 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (k0 < k1) load(k0, xa, xb);
-    for (int kt = k0; kt < k1; ++kt) {
-        if (kt + 1 < k1) load(kt + 1, na, nb);
-        bf16x8 ha[NP][2], hb[NP][2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const float4 x0 = mask4f(xa[i][0], am[i]), x1 = mask4f(xa[i][1], am[i]);
-            bf16x8 hp[NP];
-            split_fragment<NP>(x0, x1, hp);
-#pragma unroll
-            for (int q = 0; q < NP; ++q) ha[q][i] = hp[q];
-        }
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int q = 0; q < NP; ++q) {
-                const uint4 u = xb[j][q];
-                hb[q][j] = __builtin_bit_cast(bf16x8, make_uint4(u.x & wm[j], u.y & wm[j], u.z & wm[j], u.w & wm[j]));
-            }
-#pragma unroll
-        for (int sum = NP - 1; sum >= 0; --sum)
-#pragma unroll
-            for (int pa = 0; pa <= sum; ++pa)
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j], acc[i][j], 0, 0, 0);
-        if (kt + 1 < k1) {
-#pragma unroll
-            for (int i = 0; i < 2; ++i) { xa[i][0] = na[i][0]; xa[i][1] = na[i][1]; }
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int q = 0; q < NP; ++q) xb[j][q] = nb[j][q];
-        }
-    }
-    // accumulator (i, j) element e: row 16 i + 4 kq + e, column 16 j + li
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) red[wave][16 * i + 4 * kq + e][16 * j + li] = acc[i][j][e];
-    __syncthreads();
+    splitk_accumulate<NP>((const float *)a.A1, a.lda1, a.K1, (const float *)a.A2, a.lda2, a.K2,
+                          (const uint16_t *)a.W, a.wpart, a.ldw, a.nout, a.rows, m0, n0,
+                          [&](int64_t r) { return gemm_a_row(a, r); }, acc);
+    splitk_park(acc, red);
     float *C = (float *)a.C;
     for (int q = tid; q < 32 * 32; q += 256) {
         const int r = q >> 5, cc = q & 31;

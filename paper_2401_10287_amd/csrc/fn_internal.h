@@ -146,6 +146,119 @@ __device__ inline void sched_split_products()
     __builtin_amdgcn_sched_group_barrier(SCHED_MFMA, G * (NP * (NP + 1) / 2 - (NP - 1)), 0);
 }
 
+// bitwise select (m all ones or zero) of a float4
+__device__ inline float4 mask4f(float4 x, uint32_t m)
+{
+    return make_float4(__uint_as_float(__float_as_uint(x.x) & m), __uint_as_float(__float_as_uint(x.y) & m),
+                       __uint_as_float(__float_as_uint(x.z) & m), __uint_as_float(__float_as_uint(x.w) & m));
+}
+
+// Split-reduction tile of the small-grid products (NP split-BF16 parts): the
+// 32 x 32 output tile at (m0, n0) of [A1 | A2] W^T, the 32-wide reduction
+// steps split over the workgroup's four waves in contiguous quarters.  Each
+// wave loads its operand fragments straight from global memory into
+// registers (the next step's loads issued before the current step's matrix
+// instructions) and multiplies the parts in the order of the tiled kernels;
+// acc is this wave's partial tile, accumulator (i, j) element e at row
+// 16 i + 4 (lane / 16) + e, column 16 j + lane % 16.  arow(r): A's row of
+// product row r.  Rows past `rows` and columns past nout load row m0 /
+// column n0 and are zeroed.  A1 / A2 FP32 row-major; W NP parts of BF16
+// rows of ldw (part stride wpart); K1, K2 multiples of 32.
+template <int NP, typename ARow>
+__device__ __forceinline__ void splitk_accumulate(const float *A1, int64_t lda1, int K1, const float *A2, int64_t lda2,
+                                                  int K2, const uint16_t *W, int64_t wpart, int64_t ldw, int nout,
+                                                  int64_t rows, int64_t m0, int n0, ARow arow, f32x4 (&acc)[2][2])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ksteps = (K1 + K2) / 32;
+    const int per = (ksteps + 3) / 4;
+    const int k0 = wave * per, k1 = min(ksteps, k0 + per);
+    const int li = lane & 15, kq = lane >> 4;          // row / column li of a block, reduction offset 8 kq
+    int64_t ar[2], wr[2];
+    uint32_t am[2], wm[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int64_t r = m0 + 16 * i + li;
+        am[i] = r < rows ? 0xffffffffu : 0u;
+        ar[i] = arow(r < rows ? r : m0);
+        const int o = n0 + 16 * i + li;
+        wm[i] = o < nout ? 0xffffffffu : 0u;
+        wr[i] = (int64_t)(o < nout ? o : n0) * ldw;
+    }
+    float4 xa[2][2], na[2][2];
+    uint4 xb[2][NP], nb[2][NP];
+    auto load = [&](int kt, float4 (&A)[2][2], uint4 (&Bv)[2][NP]) {
+        const int kb = kt * 32;
+        const bool first = kb < K1;
+        const float *base = first ? A1 : A2;
+        const int64_t lda = first ? lda1 : lda2;
+        const int kk = (first ? kb : kb - K1) + 8 * kq;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const float *pa = base + ar[i] * lda + kk;
+            A[i][0] = *(const float4 *)pa;
+            A[i][1] = *(const float4 *)(pa + 4);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < NP; ++q) Bv[j][q] = *(const uint4 *)(W + (int64_t)q * wpart + wr[j] + kb + 8 * kq);
+    };
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (k0 < k1) load(k0, xa, xb);
+    for (int kt = k0; kt < k1; ++kt) {
+        if (kt + 1 < k1) load(kt + 1, na, nb);
+        bf16x8 ha[NP][2], hb[NP][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            bf16x8 hp[NP];
+            split_fragment<NP>(mask4f(xa[i][0], am[i]), mask4f(xa[i][1], am[i]), hp);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) ha[q][i] = hp[q];
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const uint4 u = xb[j][q];
+                hb[q][j] = __builtin_bit_cast(bf16x8, make_uint4(u.x & wm[j], u.y & wm[j], u.z & wm[j], u.w & wm[j]));
+            }
+#pragma unroll
+        for (int sum = NP - 1; sum >= 0; --sum)
+#pragma unroll
+            for (int pa = 0; pa <= sum; ++pa)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j], acc[i][j], 0, 0, 0);
+        if (kt + 1 < k1) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) { xa[i][0] = na[i][0]; xa[i][1] = na[i][1]; }
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int q = 0; q < NP; ++q) xb[j][q] = nb[j][q];
+        }
+    }
+}
+
+// each wave's partial tile into red[wave]; returns after a workgroup barrier
+__device__ __forceinline__ void splitk_park(const f32x4 (&acc)[2][2], float (&red)[4][32][33])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) red[wave][16 * i + 4 * kq + e][16 * j + li] = acc[i][j][e];
+    __syncthreads();
+}
+
 inline __host__ __device__ int gemm_parts(int mode) { return mode == GEMM_BF16 ? 1 : (mode == GEMM_BF16X3 ? 2 : (mode == GEMM_BF16X6 ? 3 : 1)); }
 
 // Padded widths.  Every product's reduction dimension is a multiple of 32.

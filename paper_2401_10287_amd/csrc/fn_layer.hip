@@ -525,6 +525,69 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
     }
 }
 
+// Value rows (TP = 1) in a grid too small to fill the CUs, split-BF16 modes:
+// 32 x 32 output tiles whose reduction steps are split over the four waves
+// (in contiguous quarters, partial tiles summed in LDS in wave order), then
+// the value epilogue of k_stream_layer: y = tanh((x + P_walker) + b)
+// (+ h^l), zero past w1, and the next layer's spin means when a 32-row tile
+// holds whole walkers (N divides 32).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_stream_value_splitk(LayerArgs a)
+{
+    constexpr int NP = MODE == GEMM_BF16 ? 1 : (MODE == GEMM_BF16X3 ? 2 : 3);
+    static_assert(MODE != GEMM_F32, "split-BF16 modes");
+    __shared__ float red[4][32][33];
+    __shared__ __attribute__((aligned(16))) float sy[32][36];
+    auto f4add = [](float4 u, float4 v) { return make_float4(u.x + v.x, u.y + v.y, u.z + v.z, u.w + v.w); };
+    const int tid = threadIdx.x;
+    const int64_t nrb = (a.rows + 31) / 32;
+    const int64_t m0 = (blockIdx.x % nrb) * 32;
+    const int n0 = (int)(blockIdx.x / nrb) * 32;
+    if (n0 >= a.W1p) return;
+    const int64_t rows_here = a.rows - m0 < 32 ? a.rows - m0 : 32;
+    // epilogue item: row r, column quad cq; its per-walker row, bias and
+    // residual are requested before the reduction
+    const int r = tid >> 3, cq = tid & 7;
+    const int col = n0 + 4 * cq;
+    const bool colreal = col < a.w1;
+    const int colc = colreal ? col : 0;
+    const uint32_t cm = colreal ? 0xffffffffu : 0u;
+    const int64_t R = m0 + (r < rows_here ? r : 0);
+    const float4 bb = mask4(*(const float4 *)(a.bias + colc), cm);
+    const float4 p4 = *(const float4 *)(a.Pw + (R / a.N) * a.w1 + colc);
+    const float4 rv = a.resid ? *(const float4 *)(a.A1 + R * a.lda1 + colc) : make_float4(0.f, 0.f, 0.f, 0.f);
+    f32x4 acc[2][2];
+    splitk_accumulate<NP>(a.A1, a.lda1, a.K1, a.A2, a.lda2, a.K2, (const uint16_t *)a.W, a.wpart, a.ldw, a.nout,
+                          a.rows, m0, n0, [](int64_t row) { return row; }, acc);
+    splitk_park(acc, red);
+    float x[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        x[e] = ((red[0][r][4 * cq + e] + red[1][r][4 * cq + e]) + red[2][r][4 * cq + e]) + red[3][r][4 * cq + e];
+    float4 y = make_float4(tanhf((x[0] + p4.x) + bb.x), tanhf((x[1] + p4.y) + bb.y), tanhf((x[2] + p4.z) + bb.z),
+                           tanhf((x[3] + p4.w) + bb.w));
+    y = mask4(f4add(y, rv), cm);
+    if (r < rows_here && col < a.W1p) *(float4 *)(a.Hout + (m0 + r) * a.ldh_out + col) = y;
+    if (a.Gout) {
+        *(float4 *)&sy[r][4 * cq] = y;
+        __syncthreads();
+        const int wpt = 32 / a.N;
+        const int nd = a.N - a.nu;
+        const float iu = a.nu > 0 ? 1.f / a.nu : 0.f, id = nd > 0 ? 1.f / nd : 0.f;
+        const int64_t ldg = 2 * (int64_t)a.W1p;
+        for (int q = tid; q < wpt * 2 * 8; q += 256) {
+            const int c4 = q & 7, sp = (q >> 3) & 1, wl = q >> 4;
+            if ((int64_t)(wl + 1) * a.N > rows_here || n0 + 4 * c4 >= a.W1p) continue;
+            const int j0 = sp ? a.nu : 0, j1 = sp ? a.N : a.nu;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int j = j0; j < j1; ++j) v = f4add(v, *(const float4 *)&sy[wl * a.N + j][4 * c4]);
+            const float sc = sp ? id : iu;
+            *(float4 *)(a.Gout + (m0 / a.N + wl) * ldg + sp * a.W1p + n0 + 4 * c4) =
+                make_float4(v.x * sc, v.y * sc, v.z * sc, v.w * sc);
+        }
+    }
+}
+
 // Default path for the stream layers in every MFMA mode whose row layout it
 // supports; the separate product + epilogue kernels remain for the others
 // (and for the backward pass, which keeps the tanh outputs).
@@ -562,8 +625,18 @@ static void launch_mode(const LayerArgs &a, int TR, hipStream_t st)
 {
     const int64_t nrb = (a.rows + LBM - 1) / LBM;
     const int64_t blocks = xcd_grid(nrb, (a.W1p + 127) / 128);
-    // value rows in a grid too small to fill the CUs: 32-column tiles, so
-    // each workgroup's reduction steps carry a quarter of the matrix work
+    // value rows in a grid too small to fill the CUs: in the split-BF16 modes
+    // 32 x 32 tiles with the reduction split over the waves while there are
+    // fewer 128 x 32 tiles than CUs, else 32-column tiles, so each
+    // workgroup's reduction steps carry a quarter of the matrix work
+    if constexpr (MODE != GEMM_F32) {
+        if (TR == 1 && g_gemm_splitk && a.K1 % 32 == 0 && a.K2 % 32 == 0 && (!a.Gout || 32 % a.N == 0) &&
+            nrb * ((a.W1p + 31) / 32) < 256) {
+            dim3 grid((unsigned)(((a.rows + 31) / 32) * ((a.W1p + 31) / 32)));
+            hipLaunchKernelGGL((k_stream_value_splitk<MODE>), grid, dim3(256), 0, st, a);
+            return;
+        }
+    }
     if (TR == 1 && blocks <= 512) {
         dim3 grid((unsigned)(nrb * ((a.W1p + 31) / 32)));
         hipLaunchKernelGGL((k_stream_layer<MODE, 1, 32, 1, false>), grid, dim3(256), 0, st, a);

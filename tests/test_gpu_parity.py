@@ -317,10 +317,12 @@ def test_pair_kernels_and_launch_shapes(name, walkers):
 
 @pytest.mark.parametrize("name,walkers", [("LiH", 256), ("LiF", 37), ("LiH", 1024)])
 def test_small_grid_products_both_kernels(name, walkers):
-    """Small walker batches in the value form: products whose 128-row tiles
-    would not fill the CUs run as split-reduction 32 x 32 tiles (default) or
-    on the tiled kernel; both are held to the oracle's log|psi| bounds, and
-    the sign agrees."""
+    """Small walker batches in the value form: products and stream layers
+    whose 128-row tiles would not fill the CUs run as split-reduction 32 x 32
+    tiles (default; the stream layer with its spin means where N divides 32,
+    LiH, and without where the next layer's means come from a separate
+    kernel, LiF) or on the tiled kernels; both are held to the oracle's
+    log|psi| bounds, and the sign agrees."""
     s = SYSTEMS[name]()
     torch, fnvmc, cfg, tt, xt, th, x = _setup(s, "bf16x6", walkers)
     o = O.Oracle(s)
