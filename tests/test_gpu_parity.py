@@ -315,15 +315,18 @@ def test_pair_kernels_and_launch_shapes(name, walkers):
         fnvmc.fn_tuning_set("pair_items", 0)
 
 
-@pytest.mark.parametrize("name,walkers", [("LiH", 256), ("LiF", 37), ("LiH", 1024)])
+@pytest.mark.parametrize("name,walkers", [("LiH", 256), ("LiF", 37), ("LiH", 1024), ("LiH", 37), ((8, 0), 13),
+                                          ((16, 0), 5)])
 def test_small_grid_products_both_kernels(name, walkers):
     """Small walker batches in the value form: products and stream layers
     whose 128-row tiles would not fill the CUs run as split-reduction 32 x 32
     tiles (default; the stream layer with its spin means where N divides 32,
     LiH, and without where the next layer's means come from a separate
     kernel, LiF) or on the tiled kernels; both are held to the oracle's
-    log|psi| bounds, and the sign agrees."""
-    s = SYSTEMS[name]()
+    log|psi| bounds, and the sign agrees.  Ragged last tiles: LiH 37 walkers
+    (5 walkers in the last 32-row tile), the O atom (8 electrons, 13 walkers:
+    one) and the S atom (16 electrons, 5 walkers: a tile is two walkers)."""
+    s = SYSTEMS[name]() if isinstance(name, str) else I.atom_ion(*name, walkers=walkers)
     torch, fnvmc, cfg, tt, xt, th, x = _setup(s, "bf16x6", walkers)
     o = O.Oracle(s)
     ref = o.log_psi(th, x)
