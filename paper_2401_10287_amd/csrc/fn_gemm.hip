@@ -480,7 +480,7 @@ static void launch_bn(int mode, const GemmArgs &a, const GemmArgs *a1, hipStream
 static int pick_bn(const GemmArgs &a)
 {
     const int64_t nrb = (a.rows + BM - 1) / BM;
-    const int bn = a.nout <= 32 ? 32 : (a.nout <= 64 ? 64 : 128);
+    const int bn = a.nout <= 32 ? 32 : (a.nout <= 64 ? 64 : (a.nout <= 96 ? 96 : 128));
     const int64_t blocks = nrb * ((a.nout + bn - 1) / bn);
     if (bn == 32 || (blocks < 256 && nrb * ((a.nout + 31) / 32) <= 1024)) return 32;
     return bn;
@@ -521,6 +521,7 @@ static void launch_mfma(int mode, const GemmArgs &a, const GemmArgs *a1, hipStre
     switch (pick_bn(a)) {
     case 32: launch_bn<32>(mode, a, a1, st); break;
     case 64: launch_bn<64>(mode, a, a1, st); break;
+    case 96: launch_bn<96>(mode, a, a1, st); break;
     default: launch_bn<128>(mode, a, a1, st); break;
     }
 }
