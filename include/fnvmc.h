@@ -245,11 +245,14 @@ fn_status fn_timing_read(const char *name, double *total_ms, int64_t *launches);
    the fused layer and of the 128-column products by direct global-to-LDS
    copies into a two-stage ring (default 1) or through registers; results
    are bitwise equal.
-   "gemm_splitk" 0/1: in the split-BF16 modes, products whose 128-row
-   tiles would not fill the CUs (small walker batches in the value form)
-   run as 32 x 32 tiles with the reduction split over the workgroup's four
-   waves and summed in wave order (default 1), or as the tiled kernel; the
-   two differ in summation order only.
+   "gemm_splitk" 0/1: in the split-BF16 modes, products and value-form
+   stream layers whose 128-row tiles would not fill the CUs (small walker
+   batches in the value form) run as 32 x 32 tiles with the reduction split
+   over the workgroup's four waves and summed in wave order (default 1), or
+   as the tiled kernels; the two differ in summation order only.
+   "gemm_wide" 0/1: products of 65..96 output columns (the orbital head of
+   spins with 5 or 6 electrons) take 96-column tiles (default 1) or
+   128-column tiles; results are bitwise equal.
    "pair_mfma" 0/1: FP32 pair layers, and their adjoint in the parameter
    gradient, as matrix-core products (default 1) or on the vector ALUs; the
    two differ in summation order only.  Unknown names and out-of-range

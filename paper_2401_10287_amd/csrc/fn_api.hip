@@ -838,6 +838,10 @@ fn_status fn_tuning_set(const char *name, int64_t value)
         fn::g_gemm_splitk = value != 0;
         return FN_OK;
     }
+    if (strcmp(name, "gemm_wide") == 0) {
+        fn::g_gemm_wide = value != 0;
+        return FN_OK;
+    }
     if (strcmp(name, "layer_dma") == 0) {
         fn::g_layer_dma = value != 0;
         return FN_OK;

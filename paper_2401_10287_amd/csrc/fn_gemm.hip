@@ -24,6 +24,12 @@
 namespace fn {
 
 bool g_gemm_splitk = true;
+// 96-column tiles for outputs of 65..96 columns (tuning switch "gemm_wide";
+// otherwise 128-column tiles); each output element takes the same
+// arithmetic whatever the tile width.  (160-column tiles for 129..160, one
+// workgroup per CU in the split-BF16 modes, measured slower than two
+// 128-column tiles.)
+bool g_gemm_wide = true;
 
 
 constexpr int BM = 128, BK = 32;
@@ -480,7 +486,8 @@ static void launch_bn(int mode, const GemmArgs &a, const GemmArgs *a1, hipStream
 static int pick_bn(const GemmArgs &a)
 {
     const int64_t nrb = (a.rows + BM - 1) / BM;
-    const int bn = a.nout <= 32 ? 32 : (a.nout <= 64 ? 64 : (a.nout <= 96 ? 96 : 128));
+    int bn = a.nout <= 32 ? 32 : (a.nout <= 64 ? 64 : 128);
+    if (g_gemm_wide && a.nout > 64 && a.nout <= 96) bn = 96;
     const int64_t blocks = nrb * ((a.nout + bn - 1) / bn);
     if (bn == 32 || (blocks < 256 && nrb * ((a.nout + 31) / 32) <= 1024)) return 32;
     return bn;

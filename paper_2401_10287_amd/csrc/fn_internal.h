@@ -364,6 +364,7 @@ struct LayerArgs {
 bool stream_layer_supported(int mode, int TR, int w1, int W1p);
 extern bool g_use_fused_layer;
 extern bool g_layer_dma;
+extern bool g_gemm_wide;     // 96-column product tiles (tuning switch "gemm_wide")
 extern bool g_gemm_splitk;   // split-K kernel for small-grid products (tuning switch "gemm_splitk")
 // pair-stream launch shape: output columns per thread (0: by size) and
 // (pair, column group) items per workgroup (0: by form)

@@ -103,7 +103,7 @@ def test_tuning_switches_checked_on_host():
     default), unknown names and out-of-range values are rejected; setting a
     switch touches no device."""
     fnvmc = _fnvmc()
-    defaults = {"fused_layer": 1, "layer_dma": 1, "gemm_splitk": 1, "pair_mfma": 1, "pair_oc": 0, "pair_items": 0}
+    defaults = {"fused_layer": 1, "layer_dma": 1, "gemm_splitk": 1, "gemm_wide": 1, "pair_mfma": 1, "pair_oc": 0, "pair_items": 0}
     for name, default in defaults.items():
         for v in (0, default):
             assert fnvmc.LIB.fn_tuning_set(name.encode(), v) == fnvmc.FN_OK, name

@@ -343,6 +343,46 @@ def test_small_grid_products_both_kernels(name, walkers):
         fnvmc.fn_tuning_set("gemm_splitk", 1)
 
 
+@pytest.mark.parametrize("name,walkers,fl,stride", [("LiF", 160, True, 16), ((10, 0), 256, True, 32),
+                                                    ((11, 0), 6600, False, 600)])
+def test_wide_head_tiles_sampled(name, walkers, fl, stride):
+    """Batches large enough that the orbital head takes 96-column tiles (LiF
+    and the Na atom: 6 orbitals x 16 determinants per spin; the Ne atom: 5 x
+    16 = 80 columns; forward-Laplacian form, and the value form for Na):
+    bitwise equal to 128-column tiles, and within the oracle's bounds on
+    every stride-th walker.  The E_L bound takes 2e-4 of |E_kin| here: LiF's
+    kinetic energies reach 90 Ha, and on such a walker the plain FP32 path is
+    itself 5e-3 Ha off."""
+    s = SYSTEMS[name]() if isinstance(name, str) else I.atom_ion(*name, walkers=walkers)
+    torch, fnvmc, cfg, tt, xt, th, x = _setup(s, "bf16x6", walkers)
+    got = {}
+    try:
+        for wide in (1, 0):
+            fnvmc.fn_tuning_set("gemm_wide", wide)
+            e = fnvmc.fn_local_energy(cfg, tt, xt)[::2] if fl else None
+            lv, sg = fnvmc.fn_log_psi(cfg, tt, xt)
+            torch.cuda.synchronize()
+            got[wide] = (None if e is None else (e[0].cpu().numpy(), e[1].cpu().numpy()), lv.cpu().numpy(),
+                         sg.cpu().numpy())
+    finally:
+        fnvmc.fn_tuning_set("gemm_wide", 1)
+    if fl:
+        np.testing.assert_array_equal(got[1][0][0], got[0][0][0])
+    np.testing.assert_array_equal(got[1][1], got[0][1])
+    o = O.Oracle(s)
+    idx = np.arange(0, walkers, stride)
+    xs = x[idx]
+    kap = _kappa_sum(o, th, xs)
+    if fl:
+        e, parts = got[1][0]
+        _check_energy(e[idx], parts[idx], o.local_energy(th, xs), 1e-3, f"{name} B={walkers} sampled", kap,
+                      rel=2e-4, mean_tol=None)
+    ref = o.log_psi(th, xs)
+    _check_logpsi(got[1][1][idx], ref, 1e-5, f"{name} B={walkers} sampled", _conditioning(o, s, th, xs), False)
+    well = kap <= 1e3
+    np.testing.assert_array_equal(got[1][2][idx][well], ref["sign"][well])
+
+
 @pytest.mark.parametrize("prec", ["bf16x6", "bf16x3", "bf16"])
 def test_layer_operand_staging_bitwise(prec):
     """The two ways of staging operand tiles of the fused layer and the
