@@ -234,6 +234,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, int64_t bid)
 #pragma unroll
                 for (int j = 0; j < WJ; ++j) hb[q][j] = *(const bf16x8 *)&sB[q * BNT * LDH + (br + 16 * j) * LDH + ko];
             if (kt + 1 < ktiles) dma(kt + 1, (kt + 1) & 1);
+            // split and multiply at raised wave priority: this wave's matrix
+            // instructions issue ahead of the other workgroup's on the SIMD,
+            // whose fragment reads and copies then fill the gaps
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int i = 0; i < WI; ++i) {
                 bf16x8 hp[NP];
@@ -252,6 +256,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, int64_t bid)
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j], acc[i][j],
                                                                                 0, 0, 0);
             sched_split_products<NP, WI, WJ>();
+            __builtin_amdgcn_s_setprio(0);
         }
     } else {
     if (ktiles > 0) load_tile(0);

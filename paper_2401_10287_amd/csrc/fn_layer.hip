@@ -267,6 +267,10 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 #pragma unroll
                 for (int j = 0; j < WJ; ++j) hb[q][j] = *(const bf16x8 *)&sB[q * LBN * LDH + (br + 16 * j) * LDH + ko];
             if (kt + 1 < ktiles) dma(kt + 1, (kt + 1) & 1);
+            // split and multiply at raised wave priority: this wave's matrix
+            // instructions issue ahead of the other workgroup's on the SIMD,
+            // whose fragment reads and copies then fill the gaps
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int i = 0; i < WI; ++i)
                 if (i < LIVE || TP != 64) {
@@ -287,6 +291,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
                                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j],
                                                                                     acc[i][j], 0, 0, 0);
             sched_split_products<NP, TP == 64 ? LIVE : WI, WJ>();
+            __builtin_amdgcn_s_setprio(0);
         }
     } else {
     if (ktiles > 0) load_tile(0);
