@@ -1297,22 +1297,29 @@ __device__ __forceinline__ void small_lu(double (&A)[NS][NS], int (&perm)[NS], i
 }
 
 // Small spins: one thread per (walker, determinant k) with the
-// matrices in registers.  Same quantities as k_orbdet; here the directions
-// use the explicit inverse from the pivoted LU, M_c = A^-1 d_c A.
+// matrices in registers (two adjacent threads in the forward-Laplacian form,
+// each taking half of the directions; four measured slower).  Same quantities as k_orbdet; here
+// the directions use the explicit inverse from the pivoted LU,
+// M_c = A^-1 d_c A.
 template <typename T, int NS, bool FL>
 __global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, const T *theta, OrbSpins<T> S, int sp0,
                                                       int64_t B, int TR, double *DR, int rec)
 {
-    // spins sp0 .. of NS electrons each, ceil(B K / 256) workgroups per spin
-    const int64_t per = B * s.K, gsp = (per + 255) / 256;
+    // spins sp0 .. of NS electrons each, ceil(H B K / 256) workgroups per spin
+    constexpr int H = FL ? 2 : 1;                         // threads per determinant
+    const int64_t per = B * s.K * H, gsp = (per + 255) / 256;
     const int sp = sp0 + (int)(blockIdx.x / gsp);
     const int64_t gof = sp ? S.gof1 : S.gof0, piof = sp ? S.piof1 : S.piof0, sigof = sp ? S.sigof1 : S.sigof0;
     const int64_t ldo = sp ? S.ldo1 : S.ldo0;
     const T *O = sp ? S.O1 : S.O0;
     const int j0 = sp == 0 ? 0 : s.nu;
     const int n3 = 3 * s.N;
-    const int64_t id = (blockIdx.x % gsp) * (int64_t)blockDim.x + threadIdx.x;
-    if (id >= per) return;
+    const int64_t tid = (blockIdx.x % gsp) * (int64_t)blockDim.x + threadIdx.x;
+    // the H threads of a determinant are adjacent lanes (per is a multiple of
+    // H, so either all of them return here or none)
+    if (tid >= per) return;
+    const int hh = (int)(tid % H);
+    const int64_t id = tid / H;
     const int64_t w = id / s.K;
     const int k = (int)(id % s.K);
     double ev[NS][NS], ge[NS][NS][3], le[NS][NS], a0[NS][NS], A[NS][NS];
@@ -1324,13 +1331,17 @@ __global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, co
     small_lu<NS>(A, perm, sgn, lg, sing);
     double *out = DR + (w * 2 + sp) * (int64_t)s.K * rec + (int64_t)k * rec;
     if (sing) {
-        out[0] = 0.0;
-        out[1] = -INFINITY;
-        for (int q = 2; q < rec; ++q) out[q] = NAN;
+        if (hh == 0) {
+            out[0] = 0.0;
+            out[1] = -INFINITY;
+            for (int q = 2; q < rec; ++q) out[q] = NAN;
+        }
         return;
     }
-    out[0] = (double)sgn;
-    out[1] = lg;
+    if (hh == 0) {
+        out[0] = (double)sgn;
+        out[1] = lg;
+    }
     if constexpr (!FL) return;
     // inverse: column e of A^-1 solves (LU) y = P e_e
     double Ai[NS][NS];
@@ -1354,8 +1365,10 @@ __global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, co
     }
     // directions: D = d_c A (tangents) or lap A; M = A^-1 D
     const T *Ob = O + (w * NS * TR) * ldo + k * NS;      // row (jj, t) at (jj TR + t) ldo
+    // directions mt0 .. mt1 - 1 of the 3N tangents and the Laplacian (mt = 3N)
+    const int mt0 = hh * ((n3 + 1) / H), mt1 = hh + 1 == H ? n3 + 1 : (hh + 1) * ((n3 + 1) / H);
     double sq = 0.0, trl = 0.0;
-    for (int mt = 0; mt <= n3; ++mt) {
+    for (int mt = mt0; mt < mt1; ++mt) {
         double D[NS][NS];
 #pragma unroll
         for (int io = 0; io < NS; ++io)
@@ -1396,7 +1409,13 @@ __global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, co
             trl = tr;
         }
     }
-    out[2 + n3] = trl - sq;
+    // the H threads' sums of tr(M_c^2) added in thread order; the Laplacian
+    // direction is the last thread's
+    const int l0 = (int)(threadIdx.x & 63) - hh;
+    double sqt = __shfl(sq, l0, 64);
+#pragma unroll
+    for (int q = 1; q < H; ++q) sqt += __shfl(sq, l0 + q, 64);
+    if (hh == H - 1) out[2 + n3] = trl - sqt;
 }
 
 // ---------------------------------------------------------------------------
@@ -1763,7 +1782,8 @@ template <typename T, int NS, bool FL>
 static void launch_small(const Sys &s, const double *x, const T *theta, const OrbSpins<T> &S, int sp0, int nsp,
                          int64_t B, int TR, double *DR, int rec, hipStream_t st)
 {
-    const dim3 gs((unsigned)(nsp * ((B * s.K + 255) / 256)));
+    const int H = FL ? 2 : 1;                             // threads per determinant (as in the kernel)
+    const dim3 gs((unsigned)(nsp * ((H * B * s.K + 255) / 256)));
     hipLaunchKernelGGL((k_orbdet_small<T, NS, FL>), gs, dim3(256), 0, st, s, x, theta, S, sp0, B, TR, DR, rec);
 }
 
