@@ -620,6 +620,14 @@ void orc_draws(uint64_t seed, uint32_t stream_id, int64_t B, int32_t n3, uint64_
     for (int64_t w = 0; w < B; ++w) draws(seed, stream_id, w, step, n3, z + w * n3, u + w);
 }
 
+/* the draws of one walker index (any 64-bit value; the counter takes its low
+   32 bits), for checking the word-to-deviate map against known answers */
+void orc_draw_one(uint64_t seed, uint32_t stream_id, int64_t walker, int32_t n3, uint64_t step, double *z /*[n3]*/,
+                  double *u)
+{
+    draws(seed, stream_id, walker, step, n3, z, u);
+}
+
 /*
  * n_steps Metropolis-Hastings moves (Electron Sampler section): all
  * electrons of a walker move together, x' = x + sigma z; the move is kept

@@ -53,6 +53,7 @@ def lib():
                                         ctypes.c_uint64, ctypes.c_uint32, vp, vp, vp]
         _lib.orc_philox4x32_10.argtypes = [vp, vp, vp]
         _lib.orc_draws.argtypes = [ctypes.c_uint64, ctypes.c_uint32, i64, ctypes.c_int32, ctypes.c_uint64, vp, vp]
+        _lib.orc_draw_one.argtypes = [ctypes.c_uint64, ctypes.c_uint32, i64, ctypes.c_int32, ctypes.c_uint64, vp, vp]
         _lib.orc_slogdet.argtypes = [ctypes.c_int32, i64, vp, vp, vp]
         _lib.orc_coulomb.argtypes = [vp, vp, i64, vp]
         _lib.orc_orbital_matrices.argtypes = [vp, vp, vp, i64, vp]
@@ -160,6 +161,14 @@ def draws(seed, stream_id, walkers, n3, step):
     u = np.empty(walkers)
     lib().orc_draws(seed, stream_id, walkers, n3, step, _p(z), _p(u))
     return z, u
+
+
+def draw_one(seed, stream_id, walker, n3, step):
+    """Normal deviates [n3] and the accept uniform of one walker index."""
+    z = np.empty(n3)
+    u = np.empty(1)
+    lib().orc_draw_one(seed, stream_id, walker, n3, step, _p(z), _p(u))
+    return z, float(u[0])
 
 
 def slogdet(a):

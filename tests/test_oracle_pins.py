@@ -505,3 +505,167 @@ def test_orbital_matrices_reproduce_log_psi():
     ref = o.log_psi(th, x)
     np.testing.assert_allclose(np.log(np.abs(psi)), ref["log_abs"], atol=1e-11)
     np.testing.assert_array_equal(np.sign(psi), ref["sign"])
+
+
+# --------------------------------------------------------------------------
+# residual connections of both streams, the envelope's matrix orientation,
+# the sum over nuclei and the per-(orbital, nucleus) envelope parameters
+# --------------------------------------------------------------------------
+def _log_tanh_chain(s, a):
+    """G(s) = tanh(tanh(a tanh s) + tanh s) and d^k log G / ds^k, k = 0, 1, 2,
+    by the chain rule written out step by step."""
+    t = np.tanh(s)
+    t1, t2 = 1 - t ** 2, -2 * t * (1 - t ** 2)
+    u = np.tanh(a * t)
+    u1 = a * (1 - u ** 2) * t1
+    u2 = a * (1 - u ** 2) * t2 - 2 * a * a * u * (1 - u ** 2) * t1 ** 2
+    v, v1, v2 = u + t, u1 + t1, u2 + t2
+    g = np.tanh(v)
+    g1 = (1 - g ** 2) * v1
+    g2 = (1 - g ** 2) * v2 - 2 * g * (1 - g ** 2) * v1 ** 2
+    return np.log(g), g1 / g, g2 / g - (g1 / g) ** 2
+
+
+def test_residuals_of_both_streams_closed_form():
+    """Three layers, one up and one down electron.  Pair stream: layer 0 maps
+    |r_ij| to unit 0, layer 1 adds tanh(a h_ij) to its own input (the pair
+    residual), so h_ij^2 = tanh(a tanh r_ij) + tanh r_ij.  One-electron
+    stream: layer 0 puts tanh|r_i| in unit 1, layers 1 and 2 carry it on by
+    their residual only (their own products are zero there), and layer 2 reads
+    the down-spin pair mean into unit 0.  Up orbital = unit 0, down orbital =
+    unit 1:  psi = G(r12) tanh(r2) exp(-Z (r1 + r2)) with G as in
+    _log_tanh_chain.  Dropping the pair residual changes G; dropping the
+    one-electron residual zeroes the down orbital."""
+    z, a = 0.8, 1.7
+    s = small(1, 1, [0, 0, 0], [z], L=3, w1=3, w2=2, K=1)
+    th, v = zero_theta(s)
+    v["V0"][3, 1] = 1.0                   # layer 0: |r_i - R| -> unit 1
+    v["W2_0"][3, 0] = 1.0                 # pair layer 0: |r_ij| -> pair unit 0
+    v["W2_1"][0, 0] = a                   # pair layer 1: tanh(a h) (+ h)
+    v["V2"][3 * s.w1 + s.w2, 0] = 1.0     # layer 2: g_i_dn, pair unit 0 -> unit 0
+    v["w_up"][0, 0] = 1.0
+    v["w_dn"][1, 0] = 1.0
+    v["sig_up"][...] = z * np.eye(3)
+    v["sig_dn"][...] = z * np.eye(3)
+    x = np.random.default_rng(7).standard_normal((10, 2, 3))
+    d = x[:, 0] - x[:, 1]
+    r12 = np.linalg.norm(d, axis=1)
+    r1, r2 = np.linalg.norm(x[:, 0], axis=1), np.linalg.norm(x[:, 1], axis=1)
+    G0, G1, G2 = _log_tanh_chain(r12, a)
+    h0, h1, h2 = _glt(r2)
+    e12 = d / r12[:, None]
+    gr1 = G1[:, None] * e12 - z * x[:, 0] / r1[:, None]
+    gr2 = -G1[:, None] * e12 + (h1 - z)[:, None] * x[:, 1] / r2[:, None]
+    lap = 2 * (G2 + 2 * G1 / r12) - 2 * z / r1 + h2 + 2 * (h1 - z) / r2
+    kin = -0.5 * (lap + (gr1 ** 2).sum(1) + (gr2 ** 2).sum(1))
+    out = O.Oracle(s).local_energy(th, x)
+    np.testing.assert_allclose(out["log_abs"], G0 + h0 - z * (r1 + r2), atol=1e-12)
+    np.testing.assert_allclose(out["parts"][:, 0], kin, rtol=1e-8, atol=1e-8)
+
+
+def test_anisotropic_envelope_orientation_closed_form():
+    """One electron, orbital weights 0, bias 1, a non-symmetric Sigma S and a
+    nucleus off the origin: psi = exp(-|S (r - R)|).  With d = r - R,
+    q = |S d| and M = S^T S: grad log psi = -M d / q, lap log psi =
+    -(tr M - |M d|^2 / q^2) / q.  S^T d in place of S d changes q (Eq. 4
+    reading: Sigma acts on the electron-nucleus vector)."""
+    S = np.array([[1.3, 0.4, -0.2], [0.1, 0.9, 0.5], [-0.6, 0.3, 1.1]])
+    R = np.array([0.4, -0.3, 0.7])
+    s = small(1, 0, R, [2.0], L=1, K=1)
+    th, v = zero_theta(s)
+    v["g_up"][...] = 1.0
+    v["sig_up"][...] = S
+    x = np.random.default_rng(8).standard_normal((12, 1, 3))
+    dv = x[:, 0] - R
+    Sd = dv @ S.T
+    q = np.linalg.norm(Sd, axis=1)
+    Md = Sd @ S                            # rows of (S^T S d)^T
+    trM = np.trace(S.T @ S)
+    lapq = (trM - (Md ** 2).sum(1) / q ** 2) / q
+    kin = 0.5 * lapq - 0.5 * (Md ** 2).sum(1) / q ** 2
+    out = O.Oracle(s).local_energy(th, x)
+    np.testing.assert_allclose(out["log_abs"], -q, atol=1e-12)
+    np.testing.assert_allclose(out["parts"][:, 0], kin, rtol=1e-10, atol=1e-10)
+
+
+def test_two_centre_envelope_closed_form():
+    """One electron, two nuclei, K = 2 determinants of which only the first
+    has a non-zero orbital (bias [1, 0]): psi = p0 exp(-s0 |r - R0|) + p1
+    exp(-s1 |r - R1|), the envelope of Eq. 4 summed over nuclei with the
+    first orbital's pi and Sigma = s_m I per nucleus (the second orbital's
+    entries differ, so a transposed [K n][M] index would pick them up).
+    E_kin = -1/2 lap psi / psi with lap exp(-s rho) = (s^2 - 2 s / rho)
+    exp(-s rho).  A max over nuclei, or one nucleus only, fails."""
+    R = np.array([[0.0, 0.0, -0.6], [0.2, 0.1, 0.9]])
+    s = small(1, 0, R, [3.0, 1.0], L=1, K=2)
+    th, v = zero_theta(s)
+    v["g_up"][:] = [1.0, 0.0]
+    p = np.array([[0.7, 1.9], [5.0, 11.0]])
+    sg = np.array([[2.1, 0.8], [0.3, 4.0]])
+    v["pi_up"][...] = p
+    for k in range(2):
+        for m in range(2):
+            v["sig_up"][k, m] = sg[k, m] * np.eye(3)
+    x = np.random.default_rng(9).standard_normal((12, 1, 3))
+    rho = np.linalg.norm(x[:, 0][:, None, :] - R[None], axis=2)       # [B][M]
+    e = p[0][None] * np.exp(-sg[0][None] * rho)
+    psi = e.sum(1)
+    lap = (e * (sg[0] ** 2 - 2 * sg[0] / rho)).sum(1)
+    out = O.Oracle(s).local_energy(th, x)
+    np.testing.assert_allclose(out["log_abs"], np.log(psi), atol=1e-12)
+    np.testing.assert_allclose(out["parts"][:, 0], -0.5 * lap / psi, rtol=1e-10, atol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# the word -> deviate map of the proposal and accept draws
+# --------------------------------------------------------------------------
+def _u01(a, b):
+    """Uniform in (0, 1] from two 32-bit words: ((a << 21 | b >> 11) + 1) 2^-53."""
+    return float(((int(a) << 21) | (int(b) >> 11)) + 1) / 2.0 ** 53
+
+
+def _kat():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) if l.strip() and l[0] != "#"]
+    return [[int(t, 16) for t in r] for r in rows]
+
+
+def test_box_muller_deviates_from_known_answer_words():
+    """Deviates computed by hand from the published Philox4x32-10 outputs:
+    counter (0, 0, 0, 0) with key (0, 0) is call d = 0 of walker 0, step 0,
+    stream 0, seed 0, so z_0 = sqrt(-2 ln u1) cos(2 pi u2) and z_1 the sine,
+    u1 from words 0-1 and u2 from words 2-3; counter (ffffffff x 4) with key
+    (ffffffff, ffffffff) is the accept call (d = 0xFFFFFFFF) of walker, step
+    and stream 0xFFFFFFFF with the all-ones seed, u from words 0-1.  Swapping
+    cos and sin, or the two word pairs, fails."""
+    k = _kat()
+    w = k[0][6:10]
+    u1, u2 = _u01(w[0], w[1]), _u01(w[2], w[3])
+    z, _ = O.draw_one(seed=0, stream_id=0, walker=0, n3=2, step=0)
+    rad = np.sqrt(-2.0 * np.log(u1))
+    np.testing.assert_allclose(z, [rad * np.cos(2 * np.pi * u2), rad * np.sin(2 * np.pi * u2)], rtol=1e-15, atol=1e-15)
+    w = k[1][6:10]
+    _, u = O.draw_one(seed=(1 << 64) - 1, stream_id=0xFFFFFFFF, walker=0xFFFFFFFF, n3=2, step=0xFFFFFFFF)
+    assert u == _u01(w[0], w[1])
+
+
+def test_draw_counter_layout():
+    """Each proposal deviate pair q = 2d, 2d + 1 and the accept uniform come
+    from the (KAT-pinned) generator at counter (d, walker, step, stream) and
+    key (seed low word, seed high word); checked for arbitrary values of each
+    field, so swapped counter fields or key words fail."""
+    rng = np.random.default_rng(10)
+    for _ in range(6):
+        seed = int(rng.integers(0, 1 << 63)) * 2 + 1
+        stream, walker, step = (int(v) for v in rng.integers(0, 1 << 32, 3))
+        n3 = 7
+        z, u = O.draw_one(seed=seed, stream_id=stream, walker=walker, n3=n3, step=step)
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        for d in range((n3 + 1) // 2):
+            o = O.philox4x32_10([d, walker, step, stream], key)
+            u1, u2 = _u01(o[0], o[1]), _u01(o[2], o[3])
+            rad = np.sqrt(-2.0 * np.log(u1))
+            assert z[2 * d] == pytest.approx(rad * np.cos(2 * np.pi * u2), rel=1e-14, abs=1e-15)
+            if 2 * d + 1 < n3:
+                assert z[2 * d + 1] == pytest.approx(rad * np.sin(2 * np.pi * u2), rel=1e-14, abs=1e-15)
+        o = O.philox4x32_10([0xFFFFFFFF, walker, step, stream], key)
+        assert u == _u01(o[0], o[1])
