@@ -166,6 +166,40 @@ fn_status fn_param_grad(const fn_config *cfg, const void *theta, const double *x
 fn_status fn_log_psi_vjp(const fn_config *cfg, const void *theta, const double *x, int64_t B, const double *coeff,
                          void *grad, void *ws, size_t ws_bytes, void *stream);
 
+/* Batch statistics of the local energy and the weights of the Eq. 6
+   gradient, in FP64: with E the batch mean of e_loc (the estimate of
+   Eq. 1 over the B walkers), stats = (E, variance with 1/B, standard error
+   sqrt(variance / B)) and coeff_p = 2 (e_loc_p - E) / B, so that
+   fn_log_psi_vjp with these weights is the gradient of Eq. 6.
+   e_loc: device [B].  stats: device [3] out or NULL.  coeff: device [B]
+   out or NULL (not both NULL).  B >= 1.  No local-energy clipping; a
+   non-finite e_loc makes every output non-finite. */
+fn_status fn_energy_stats(const double *e_loc, int64_t B, double *stats, double *coeff, void *stream);
+
+/* Electrons per nucleus of a molecular ion by the charge-initialisation
+   policy of Algorithm 1 (Ionic Charge Initialization section), on the host.
+   Starting from the neutral counts atomic_number[m] and t = ion_charge, while
+   t != 0: for t < 0 the nucleus of smallest partial charge gains an
+   electron, t and its partial charge grow by one; for t > 0 the nucleus of
+   largest partial charge loses one, t and its partial charge shrink by one.
+   Ties go to the lowest index.  partial_charge: host [n_nuc] (Mulliken
+   charges of the ion, supplied by the caller); atomic_number: host [n_nuc];
+   electrons: host [n_nuc] out.  FN_EINVAL if the policy would take an
+   electron from a nucleus that has none, or ion_charge exceeds the neutral
+   electron count; FN_EUNSUPPORTED beyond FN_MAX_ELEC electrons. */
+fn_status fn_ionic_electron_counts(int32_t n_nuc, const double *partial_charge, const int32_t *atomic_number,
+                                   int32_t ion_charge, int32_t *electrons);
+
+/* Initial walkers (Electron Sampler section): electron i of every walker at
+   the position of nucleus site[i] plus scale z, z ~ N(0, 1) from the
+   sampler's generator (Philox4x32-10 keyed by seed, counter (d, walker,
+   0xFFFFFFFF, stream_id), deviate q from call d = q/2 as in
+   vmc_metropolis_step).  site: host [N] nucleus index per electron (spin-up
+   electrons first).  x: device [B][N][3] out.  Only cfg's nuclei and
+   electron counts are read. */
+fn_status fn_init_walkers(const fn_config *cfg, const int32_t *site, double scale, uint64_t seed, uint32_t stream_id,
+                          int64_t B, double *x, void *stream);
+
 /* Message of the calling thread's last failed call ("" if none). */
 const char *fn_last_error(void);
 

@@ -37,7 +37,7 @@ def log_psi(cfg: "fnvmc.Config", theta: torch.Tensor, x: torch.Tensor, ws: "fnvm
 
 def vmc_loss(cfg: "fnvmc.Config", theta: torch.Tensor, x: torch.Tensor, e_loc: torch.Tensor,
              ws: "fnvmc.Workspace | None" = None):
-    """Surrogate whose gradient is Eq. 6: 2 E_p[(E_p - E_p(E_p)) d log|psi| / d theta]."""
-    e = e_loc.detach()
-    coeff = 2.0 * (e - e.mean()) / e.numel()
+    """Surrogate whose gradient is Eq. 6: 2 E_p[(E_p - E_p(E_p)) d log|psi| / d theta].
+    The weights 2 (E_p - mean) / B come from the library (fn_energy_stats)."""
+    _, coeff = fnvmc.fn_energy_stats(e_loc.detach().contiguous())
     return (coeff * log_psi(cfg, theta, x, ws)).sum()

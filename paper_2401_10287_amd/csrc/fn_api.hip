@@ -27,6 +27,7 @@ using namespace fn;
 namespace {
 
 thread_local std::string g_err;
+int g_fp32_products = 0;     // bit 0 stream layers, bit 1 mean-field, bit 2 orbital head
 
 fn_status fail(fn_status st, const std::string &msg)
 {
@@ -107,7 +108,8 @@ struct Ctx {
     int prec;
     bool f64;
     size_t esz;      // bytes of the stream scalar (float or double)
-    int smode;       // stream products
+    int smode;       // per-electron stream-layer products
+    int wmode;       // per-walker mean-field products
     int hmode;       // orbital head product
     double vnn;
 };
@@ -155,6 +157,14 @@ fn_status make_ctx(const fn_config *cfg, Ctx &c)
     // orbital head: FP32 operands; the six-product BF16 split carries them to
     // FP32 accuracy on the matrix cores, so that mode uses it here as well
     c.hmode = c.f64 ? GEMM_F64 : (c.smode == GEMM_BF16X6 ? GEMM_BF16X6 : GEMM_F32);
+    c.wmode = c.smode;
+    // diagnostic: selected product classes on the FP32 matrix cores in the
+    // split-BF16 modes (tuning switch "fp32_products")
+    if (c.smode == GEMM_BF16 || c.smode == GEMM_BF16X3 || c.smode == GEMM_BF16X6) {
+        if (g_fp32_products & 1) c.smode = GEMM_F32;
+        if (g_fp32_products & 2) c.wmode = GEMM_F32;
+        if (g_fp32_products & 4) c.hmode = GEMM_F32;
+    }
     double vnn = 0.0;
     for (int m = 0; m < s.M; ++m)
         for (int q = m + 1; q < s.M; ++q) {
@@ -208,14 +218,14 @@ fn_status make_plan(const Ctx &c, int64_t B, int op, Plan &p)
         if (det_backward_lds(nmax) > 64 * 1024) return fail(FN_EUNSUPPORTED, "determinant backward exceeds LDS");
     }
     size_t o = 0;
-    const size_t se = gemm_elem(c.smode), he = gemm_elem(c.hmode), e = c.esz;
-    const int np = gemm_parts(c.smode);
+    const size_t se = gemm_elem(c.smode), we = gemm_elem(c.wmode), he = gemm_elem(c.hmode), e = c.esz;
+    const int np = gemm_parts(c.smode), npw = gemm_parts(c.wmode);
     for (int l = 0; l < s.L; ++l) {
         size_t nx = (size_t)s.w1 * (c.W.HWl[l] + c.W.GWl[l]), ng = (size_t)s.w1 * 2 * c.W.HWl[l];
         p.wxpart[l] = (int64_t)nx;
         p.wgpart[l] = (int64_t)ng;
         p.wx[l] = o; o = al(o + nx * se * np);
-        p.wg[l] = o; o = al(o + ng * se * np);
+        p.wg[l] = o; o = al(o + ng * we * npw);
     }
     p.wpair = o;
     if (c.esz == sizeof(float)) o = al(o + (size_t)pair_mfma_woff(s, s.L > 1 ? s.L - 1 : 0) * sizeof(float));
@@ -316,7 +326,7 @@ void pack_weights(const Ctx &c, const Plan &p, const T *theta, char *ws, hipStre
     };
     for (int l = 0; l < s.L; ++l) {
         PackSeg g{};
-        g.kind = 0; g.mode = c.smode; g.off = c.P.V[l];
+        g.kind = 0; g.mode = c.smode; g.mode2 = c.wmode; g.off = c.P.V[l];
         g.dh = layer_dh(s, l); g.dp = layer_dp(s, l); g.w1 = s.w1; g.HWl = c.W.HWl[l]; g.GWl = c.W.GWl[l];
         g.count = (int64_t)s.w1 * (g.HWl + g.GWl) + (int64_t)s.w1 * 2 * g.HWl;
         g.d0 = ws + p.wx[l]; g.d1 = ws + p.wg[l];
@@ -393,7 +403,7 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
         ga.rows = b * tr_live; ga.nout = s.w1;
         ga.rows_per_group = tr_live; ga.group_stride = TR;
         ga.c_rows_per_group = tr_live; ga.c_group_stride = TR;
-        { Timed t_(K_WALKER_GEMM, st); (void)launch_gemm(c.smode, ga, st); }
+        { Timed t_(K_WALKER_GEMM, st); (void)launch_gemm(c.wmode, ga, st); }
         bool fused = false;
         if constexpr (std::is_same<T, float>::value) fused = !p.save && stream_layer_supported(c.smode, TR, s.w1, c.W.W1p);
         if constexpr (std::is_same<T, float>::value) if (fused) {
@@ -690,6 +700,8 @@ fn_status run_backward(const Ctx &c, const Plan &p, const void *theta, const dou
 
 }  // namespace
 
+fn_status fn::api_fail(fn_status st, const char *msg) { return fail(st, msg); }
+
 extern "C" {
 
 int64_t fn_param_count(const fn_config *cfg)
@@ -825,6 +837,15 @@ fn_status fn_log_psi_vjp(const fn_config *cfg, const void *theta, const double *
     return grad_common(cfg, theta, x, B, coeff, nullptr, nullptr, grad, ws, ws_bytes, stream);
 }
 
+fn_status fn_energy_stats(const double *e_loc, int64_t B, double *stats, double *coeff, void *stream)
+{
+    if (B < 1) return fail(FN_EINVAL, "B < 1");
+    if (!e_loc) return fail(FN_EINVAL, "e_loc is NULL");
+    if (!stats && !coeff) return fail(FN_EINVAL, "stats and coeff are both NULL");
+    launch_energy_stats(e_loc, B, stats, coeff, (hipStream_t)stream);
+    return hip_status();
+}
+
 const char *fn_last_error(void) { return g_err.c_str(); }
 
 fn_status fn_tuning_set(const char *name, int64_t value)
@@ -853,6 +874,11 @@ fn_status fn_tuning_set(const char *name, int64_t value)
     if (strcmp(name, "pair_oc") == 0) {
         if (value != 0 && value != 1 && value != 2 && value != 4) return fail(FN_EINVAL, "pair_oc: 0, 1, 2 or 4");
         fn::g_pair_oc = (int)value;
+        return FN_OK;
+    }
+    if (strcmp(name, "fp32_products") == 0) {
+        if (value < 0 || value > 7) return fail(FN_EINVAL, "fp32_products: 0..7");
+        g_fp32_products = (int)value;
         return FN_OK;
     }
     if (strcmp(name, "pair_items") == 0) {

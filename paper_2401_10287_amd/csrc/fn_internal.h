@@ -338,6 +338,31 @@ __host__ __device__ inline int64_t remap_row(int64_t r, int64_t per, int64_t str
     return g * stride + off + (r - g * per);
 }
 
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter c -> c, key
+// (k0, k1); the sampler's generator
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// 53 random bits from two words, mapped to (0, 1]
+__device__ inline double word_pair_to_unit(uint32_t a, uint32_t b)
+{
+    const uint64_t m = ((uint64_t)a << 21) | (uint64_t)(b >> 11);
+    return (double)(m + 1) * 0x1.0p-53;
+}
+
+// records msg as the calling thread's fn_last_error() message; returns st
+fn_status api_fail(fn_status st, const char *msg);
+
 hipError_t launch_gemm(int mode, const GemmArgs &a, hipStream_t st);
 // two products in one launch when they take the same tile shape (else two
 // launches); each product's results are those of launch_gemm

@@ -14,7 +14,7 @@ namespace fn {
 // [wc] from off2) into d0.
 struct PackSeg {
     int64_t begin, count, off, off2;
-    int kind, mode, dh, dp, w1, HWl, GWl, kn, W1p, w2, wc, ks;
+    int kind, mode, mode2, dh, dp, w1, HWl, GWl, kn, W1p, w2, wc, ks;   // mode2: Wg of a layer block
     void *d0, *d1;
 };
 struct PackList {

@@ -12,26 +12,6 @@
 
 namespace fn {
 
-__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
-        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
-        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
-
-// 53 random bits from two words, mapped to (0, 1]
-__device__ inline double word_pair_to_unit(uint32_t a, uint32_t b)
-{
-    const uint64_t m = ((uint64_t)a << 21) | (uint64_t)(b >> 11);
-    return (double)(m + 1) * 0x1.0p-53;
-}
-
 // one thread per (walker, d): d < ceil(3N/2) makes two normal deviates,
 // d == ceil(3N/2) makes the accept uniform.  x' = x + sigma z is rounded
 // as a product and then a sum (no fused multiply-add).

@@ -56,7 +56,7 @@ __device__ inline void pack_layer_elem(const T *theta, const PackSeg &g, int64_t
         if (k < g.dh) row = g.dh + k;
         else if (k >= g.HWl && k < g.HWl + g.dh) row = 2 * g.dh + (k - g.HWl);
         const T v = row >= 0 ? theta[g.off + (int64_t)row * g.w1 + o] : T(0);
-        put_w<T>(g.mode, g.d1, ng, u, v);
+        put_w<T>(g.mode2, g.d1, ng, u, v);
     }
 }
 

@@ -60,6 +60,12 @@ def _load():
     lib.fn_param_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]
     lib.fn_log_psi_vjp.restype = i32
     lib.fn_log_psi_vjp.argtypes = [vp, vp, vp, i64, vp, vp, vp, sz, vp]
+    lib.fn_ionic_electron_counts.restype = i32
+    lib.fn_ionic_electron_counts.argtypes = [i32, vp, vp, i32, vp]
+    lib.fn_init_walkers.restype = i32
+    lib.fn_init_walkers.argtypes = [vp, vp, ctypes.c_double, u64, u32, i64, vp, vp]
+    lib.fn_energy_stats.restype = i32
+    lib.fn_energy_stats.argtypes = [vp, i64, vp, vp, vp]
     lib.fn_last_error.restype = ctypes.c_char_p
     lib.fn_last_error.argtypes = []
     lib.fn_timing_enable.restype = i32
@@ -79,7 +85,8 @@ LIB = _load()
 LIB_PATH = _LIB_PATH
 
 EXPORTED = ["fn_param_count", "fn_workspace_bytes", "fn_log_psi", "fn_local_energy", "vmc_metropolis_step",
-            "vmc_metropolis_step_ext", "fn_param_grad", "fn_log_psi_vjp", "fn_last_error", "fn_timing_enable",
+            "vmc_metropolis_step_ext", "fn_param_grad", "fn_log_psi_vjp", "fn_energy_stats", "fn_ionic_electron_counts",
+            "fn_init_walkers", "fn_last_error", "fn_timing_enable",
             "fn_timing_select", "fn_timing_reset", "fn_timing_read", "fn_tuning_set", "fn_server_job_bytes", "fn_server_create", "fn_server_submit",
             "fn_server_step", "fn_server_result", "fn_server_destroy", "fn_server_last_error"]
 KERNEL_CLASSES = ["stream_gemm", "walker_gemm", "head_gemm", "features", "pair_stream", "spin_mean", "layer_epilogue",
@@ -244,6 +251,40 @@ def fn_log_psi_vjp(cfg: Config, theta: torch.Tensor, x: torch.Tensor, coeff: tor
     _check(LIB.fn_log_psi_vjp(cfg.ptr, theta.data_ptr(), x.data_ptr(), b, coeff.data_ptr(), grad.data_ptr(), p, n,
                               _stream(stream)))
     return grad
+
+
+def fn_energy_stats(e_loc: torch.Tensor, stream=None):
+    """(stats [3] = mean, variance, standard error; coeff [B] = 2 (E_p - mean) / B), FP64 on the device."""
+    b = e_loc.shape[0]
+    _need(e_loc, torch.float64, (b,), "e_loc")
+    stats = torch.empty(3, dtype=torch.float64, device=e_loc.device)
+    coeff = torch.empty(b, dtype=torch.float64, device=e_loc.device)
+    _check(LIB.fn_energy_stats(e_loc.data_ptr(), b, stats.data_ptr(), coeff.data_ptr(), _stream(stream)))
+    return stats, coeff
+
+
+def fn_ionic_electron_counts(partial_charge, atomic_number, ion_charge: int) -> np.ndarray:
+    """Electrons per nucleus of an ion by the charge-initialisation policy (host only)."""
+    q = np.ascontiguousarray(partial_charge, dtype=np.float64)
+    z = np.ascontiguousarray(atomic_number, dtype=np.int32)
+    if q.shape != z.shape or q.ndim != 1:
+        raise ValueError("partial_charge and atomic_number must be 1-D of the same length")
+    out = np.empty(q.size, dtype=np.int32)
+    _check(LIB.fn_ionic_electron_counts(q.size, q.ctypes.data, z.ctypes.data, int(ion_charge), out.ctypes.data))
+    return out
+
+
+def fn_init_walkers(cfg: Config, site, scale: float, seed: int, walkers: int, stream_id: int = 0,
+                    device: Optional[torch.device] = None, stream=None) -> torch.Tensor:
+    """[B][N][3] FP64 initial walkers on the device: electron i about nucleus site[i]."""
+    st = np.ascontiguousarray(site, dtype=np.int32)
+    if st.shape != (cfg.n_elec,):
+        raise ValueError(f"site: need {cfg.n_elec} nucleus indices")
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    x = torch.empty((walkers, cfg.n_elec, 3), dtype=torch.float64, device=dev)
+    _check(LIB.fn_init_walkers(cfg.ptr, st.ctypes.data, float(scale), int(seed), int(stream_id), walkers, x.data_ptr(),
+                               _stream(stream)))
+    return x
 
 
 def fn_timing_enable(on: bool) -> None:
