@@ -149,6 +149,30 @@ fn_status vmc_metropolis_step_ext(const fn_config *cfg, const void *theta, doubl
                                   int32_t n_steps, double sigma, const double *z, const double *u, int32_t *n_accept,
                                   void *ws, size_t ws_bytes, void *stream);
 
+/* Grouped Metropolis moves (Electron Sampler section) for several jobs of
+   one system and one parameter vector in one sequence of launches, for
+   small jobs that would leave the GPU idle alone.  Job q owns the walkers
+   walker0 .. walker0 + B - 1 of x, log_abs_psi and n_accept (the jobs must
+   tile 0 .. B_total - 1 in order, without gaps) and draws its random numbers
+   exactly as vmc_metropolis_step(seed, step0, stream_id) does for its own
+   walkers 0 .. B - 1.  The kernels take the same path at every batch size
+   (the small-batch split-reduction products are not used), so each job's
+   results are bitwise those it gets in a group of its own, and those of
+   vmc_metropolis_step with the "gemm_splitk" switch off.  jobs: host
+   [n_jobs], 1 <= n_jobs <= FN_MAX_GROUP_JOBS.  Workspace:
+   fn_workspace_bytes(cfg, B_total, FN_OP_METROPOLIS). */
+#define FN_MAX_GROUP_JOBS 64
+typedef struct {
+    int64_t walker0;        /* first walker of the job in the group           */
+    int64_t B;              /* walkers of the job, >= 1                      */
+    uint64_t seed;
+    uint64_t step0;         /* the job's step counter at this call's first move */
+    uint32_t stream_id;
+} fn_group_job;
+fn_status vmc_metropolis_step_group(const fn_config *cfg, const void *theta, const fn_group_job *jobs, int32_t n_jobs,
+                                    double *x, double *log_abs_psi, int32_t *n_accept, int64_t B_total,
+                                    int32_t n_steps, double sigma, void *ws, size_t ws_bytes, void *stream);
+
 /* Training gradient of Eq. 6 over the batch: with E the batch mean of e_loc,
    grad = sum_p (2/B)(e_loc_p - E) d log|psi_p| / d theta.
    e_loc: device [B] FP64.  grad: device [P] out (theta's type).
@@ -210,22 +234,26 @@ const char *fn_last_error(void);
    counter 0..n_steps-1, its own seed and stream_id) and then the batch
    mean, variance (1/B) and standard error of the local energy (Eq. 1, 2)
    plus the acceptance rate.
-   The server owns no device memory: every admitted job's walkers, log|psi|
-   and workspace live in the caller's device arena, whose size is the HBM
-   budget.  fn_server_step() retires finished jobs, admits queued jobs first
-   come first served while their footprint (fn_server_job_bytes) fits the
-   free arena and a stream is free, and enqueues the next quantum of
-   Metropolis steps of every running job on that job's stream, so the work
-   of different jobs overlaps on the device.  A job's results do not depend
-   on the other jobs.  theta and x0 of a job are read until it is done and
-   must stay valid until then.  The server creates one event and one pinned
-   4-double host buffer per stream.  Not safe against concurrent
-   fn_server_step calls on the same server from several threads.
+   The server allocates no memory on the device or pinned on the host: every
+   admitted job's walkers, log|psi| and workspace live in the caller's
+   device arena, whose size is the HBM budget, and results land in the
+   caller's pinned host buffer.  fn_server_step() retires finished jobs
+   (stream queries: each stream runs one job at a time and must carry no
+   other work), admits queued jobs in arrival order while their footprint
+   (fn_server_job_bytes) fits the free arena and a stream is free -- a job
+   that does not fit is passed by later jobs that do, at most 2 n_streams
+   times, after which admission waits until it fits -- and enqueues the next
+   quantum of Metropolis steps of every running job on that job's stream, so
+   the work of different jobs overlaps on the device.  A job's results do
+   not depend on the other jobs.  theta and x0 of a job are read until it is
+   done and must stay valid until then.  Not safe against concurrent calls on
+   the same server from several threads.
    ------------------------------------------------------------------------ */
 typedef struct fn_server fn_server;
 
 typedef struct {
-    int32_t state;          /* 0 queued, 1 running, 2 done, 3 failed          */
+    int32_t state;          /* 0 queued, 1 running, 2 done, 3 failed,
+                               4 cancelled                                   */
     double mean, variance, std_error, acceptance;
     double submit_s, admit_s, done_s;   /* host steady clock, seconds        */
     int64_t footprint_bytes;
@@ -236,9 +264,11 @@ size_t fn_server_job_bytes(const fn_config *cfg, int64_t B);
 
 /* arena: device, 256-byte aligned, arena_bytes long.  streams: host array of
    n_streams hipStream_t (one running job per stream).  quantum_steps:
-   Metropolis steps enqueued per job per fn_server_step. */
+   Metropolis steps enqueued per job per fn_server_step.  host_results:
+   pinned host memory (hipHostMalloc), [n_streams][4] doubles, owned by the
+   caller and valid until fn_server_destroy. */
 fn_status fn_server_create(void *arena, size_t arena_bytes, void *const *streams, int32_t n_streams,
-                           int32_t quantum_steps, fn_server **out);
+                           int32_t quantum_steps, double *host_results, fn_server **out);
 /* Queue a job; FN_ENOMEM if it could never fit the arena.  theta: device
    parameters (cfg's precision), x0: device [B][N][3] initial walkers. */
 fn_status fn_server_submit(fn_server *srv, const fn_config *cfg, const void *theta, const double *x0, int64_t B,
@@ -246,6 +276,12 @@ fn_status fn_server_submit(fn_server *srv, const fn_config *cfg, const void *the
 /* One scheduler step (non-blocking). */
 fn_status fn_server_step(fn_server *srv, int32_t *n_active, int32_t *n_queued);
 fn_status fn_server_result(fn_server *srv, int64_t job, fn_job_result *out);
+/* Cancel a job: a queued job leaves the queue; a running job's enqueued
+   quantum is waited for, then its stream and arena block are freed.  Its
+   state becomes 4.  Done, failed or cancelled jobs are left as they are. */
+fn_status fn_server_cancel(fn_server *srv, int64_t job);
+/* Free and total arena bytes. */
+fn_status fn_server_memory(fn_server *srv, size_t *free_bytes, size_t *arena_bytes);
 /* Waits for running jobs' streams, then frees the server. */
 fn_status fn_server_destroy(fn_server *srv);
 const char *fn_server_last_error(void);

@@ -672,6 +672,38 @@ fn_status run_metropolis(const Ctx &c, const Plan &p, const void *theta, double 
     return hip_status();
 }
 
+// grouped moves: every job advances n_steps together; job q's step counter
+// at move k is its step0 + k
+template <typename T>
+fn_status run_metropolis_group(const Ctx &c, const Plan &p, const void *theta, double *x, double *log_abs, int64_t B,
+                               int32_t n_steps, double sigma, const fn_group_job *jobs, int32_t n_jobs,
+                               int32_t *n_accept, void *ws, hipStream_t st)
+{
+    char *w = (char *)ws;
+    const int n3 = 3 * c.s.N;
+    pack_weights<T>(c, p, (const T *)theta, w, st);
+    double *xp = (double *)(w + p.xp), *lpn = (double *)(w + p.lpn), *uu = (double *)(w + p.u);
+    GroupTable g{};
+    g.n = n_jobs;
+    for (int q = 0; q < n_jobs; ++q) {
+        g.w0[q] = jobs[q].walker0;
+        g.k0[q] = (uint32_t)jobs[q].seed;
+        g.k1[q] = (uint32_t)(jobs[q].seed >> 32);
+        g.stream[q] = jobs[q].stream_id;
+    }
+    g.w0[n_jobs] = B;
+    for (int32_t k = 0; k < n_steps; ++k) {
+        for (int q = 0; q < n_jobs; ++q) g.step[q] = (uint32_t)(jobs[q].step0 + (uint64_t)k);
+        {
+            Timed t_(K_PROPOSE, st);
+            launch_propose_group(x, B, n3, sigma, g, xp, uu, st);
+        }
+        forward<T>(c, p, (const T *)theta, xp, B, lpn, nullptr, nullptr, nullptr, w, st,
+                   AcceptArgs{x, xp, uu, log_abs, n_accept});
+    }
+    return hip_status();
+}
+
 template <typename T>
 fn_status run_backward(const Ctx &c, const Plan &p, const void *theta, const double *x, int64_t B,
                        const double *coeff_in, const double *e_loc, double *stats, void *grad, void *ws, hipStream_t st)
@@ -796,6 +828,41 @@ fn_status vmc_metropolis_step_ext(const fn_config *cfg, const void *theta, doubl
     if (!z || !u) return fail(FN_EINVAL, "z or u is NULL");
     return metropolis_common(cfg, theta, x, log_abs_psi, B, n_steps, sigma, 0, 0, 0, z, u, n_accept, ws, ws_bytes,
                              stream);
+}
+
+fn_status vmc_metropolis_step_group(const fn_config *cfg, const void *theta, const fn_group_job *jobs, int32_t n_jobs,
+                                    double *x, double *log_abs_psi, int32_t *n_accept, int64_t B_total,
+                                    int32_t n_steps, double sigma, void *ws, size_t ws_bytes, void *stream)
+{
+    Ctx c;
+    fn_status r = make_ctx(cfg, c);
+    if (r) return r;
+    if (!jobs || n_jobs < 1 || n_jobs > FN_MAX_GROUP_JOBS) return fail(FN_EINVAL, "n_jobs out of range 1..64");
+    if (B_total < 1) return fail(FN_EINVAL, "B_total < 1");
+    int64_t next = 0;
+    for (int q = 0; q < n_jobs; ++q) {
+        if (jobs[q].B < 1) return fail(FN_EINVAL, "a job has no walkers");
+        if (jobs[q].walker0 != next) return fail(FN_EINVAL, "jobs must tile the walkers in order without gaps");
+        next += jobs[q].B;
+    }
+    if (next != B_total) return fail(FN_EINVAL, "the jobs' walkers do not add up to B_total");
+    if (n_steps < 0) return fail(FN_EINVAL, "n_steps < 0");
+    if (!(sigma >= 0.0) || !isfinite(sigma)) return fail(FN_EINVAL, "sigma must be finite and >= 0");
+    if (n_steps == 0) return FN_OK;
+    if (!theta || !x || !log_abs_psi) return fail(FN_EINVAL, "theta, x or log_abs_psi is NULL");
+    if (((uintptr_t)theta) % 16) return fail(FN_EINVAL, "theta must be 16-byte aligned");
+    Plan p;
+    if ((r = make_plan(c, B_total, FN_OP_METROPOLIS, p))) return r;
+    if ((r = check_ws(p, ws, ws_bytes))) return r;
+    struct Suppress {
+        Suppress() { g_splitk_suppressed = true; }
+        ~Suppress() { g_splitk_suppressed = false; }
+    } suppress_;
+    hipStream_t st = (hipStream_t)stream;
+    return c.f64 ? run_metropolis_group<double>(c, p, theta, x, log_abs_psi, B_total, n_steps, sigma, jobs, n_jobs,
+                                                n_accept, ws, st)
+                 : run_metropolis_group<float>(c, p, theta, x, log_abs_psi, B_total, n_steps, sigma, jobs, n_jobs,
+                                               n_accept, ws, st);
 }
 
 static fn_status grad_common(const fn_config *cfg, const void *theta, const double *x, int64_t B,

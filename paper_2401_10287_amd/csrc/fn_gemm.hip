@@ -24,6 +24,7 @@
 namespace fn {
 
 bool g_gemm_splitk = true;
+thread_local bool g_splitk_suppressed = false;
 // 96-column tiles for outputs of 65..96 columns (tuning switch "gemm_wide";
 // otherwise 128-column tiles); each output element takes the same
 // arithmetic whatever the tile width.  (160-column tiles for 129..160, one
@@ -501,7 +502,7 @@ static int pick_bn(const GemmArgs &a)
 // split-K tiles for grids of 128-row tiles that would not fill the CUs
 static bool use_splitk(int mode, const GemmArgs &a)
 {
-    if (!g_gemm_splitk || mode == GEMM_F32 || mode == GEMM_F64 || a.K1 % BK != 0 || a.K2 % BK != 0) return false;
+    if (!g_gemm_splitk || g_splitk_suppressed || mode == GEMM_F32 || mode == GEMM_F64 || a.K1 % BK != 0 || a.K2 % BK != 0) return false;
     const int64_t nrb = (a.rows + BM - 1) / BM;
     return nrb * ((a.nout + 31) / 32) < 256;
 }

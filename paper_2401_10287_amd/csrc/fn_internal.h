@@ -391,6 +391,10 @@ extern bool g_use_fused_layer;
 extern bool g_layer_dma;
 extern bool g_gemm_wide;     // 96-column product tiles (tuning switch "gemm_wide")
 extern bool g_gemm_splitk;   // split-K kernel for small-grid products (tuning switch "gemm_splitk")
+// set for the duration of a grouped call on the calling thread: the
+// split-reduction kernels are not chosen, so a walker's arithmetic does not
+// depend on the batch size
+extern thread_local bool g_splitk_suppressed;
 // pair-stream launch shape: output columns per thread (0: by size) and
 // (pair, column group) items per workgroup (0: by form)
 extern int g_pair_oc, g_pair_items;

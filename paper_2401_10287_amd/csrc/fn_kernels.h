@@ -130,6 +130,15 @@ void launch_pack_head_bwd(const T *theta, int64_t woff, int w1, int kn, int KNp,
 // Monte Carlo
 void launch_propose(const double *x, int64_t B, int n3, double sigma, uint64_t seed, uint64_t step, uint32_t stream_id,
                     const double *z_ext, const double *u_ext, double *xp, double *u, hipStream_t st);
+// per-job generator state of a grouped Metropolis call: job q owns walkers
+// [w0[q], w0[q + 1]) of the group, key (k0, k1), step counter, stream id
+struct GroupTable {
+    int n;
+    int64_t w0[FN_MAX_GROUP_JOBS + 1];
+    uint32_t k0[FN_MAX_GROUP_JOBS], k1[FN_MAX_GROUP_JOBS], step[FN_MAX_GROUP_JOBS], stream[FN_MAX_GROUP_JOBS];
+};
+void launch_propose_group(const double *x, int64_t B, int n3, double sigma, const GroupTable &g, double *xp,
+                          double *u, hipStream_t st);
 void launch_energy_stats(const double *e_loc, int64_t B, double *stats, double *coeff, hipStream_t st);
 
 }  // namespace fn

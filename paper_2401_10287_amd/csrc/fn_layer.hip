@@ -635,7 +635,7 @@ static void launch_mode(const LayerArgs &a, int TR, hipStream_t st)
     // fewer 128 x 32 tiles than CUs, else 32-column tiles, so each
     // workgroup's reduction steps carry a quarter of the matrix work
     if constexpr (MODE != GEMM_F32) {
-        if (TR == 1 && g_gemm_splitk && a.K1 % 32 == 0 && a.K2 % 32 == 0 && (!a.Gout || 32 % a.N == 0) &&
+        if (TR == 1 && g_gemm_splitk && !g_splitk_suppressed && a.K1 % 32 == 0 && a.K2 % 32 == 0 && (!a.Gout || 32 % a.N == 0) &&
             nrb * ((a.W1p + 31) / 32) < 256) {
             dim3 grid((unsigned)(((a.rows + 31) / 32) * ((a.W1p + 31) / 32)));
             hipLaunchKernelGGL((k_stream_value_splitk<MODE>), grid, dim3(256), 0, st, a);

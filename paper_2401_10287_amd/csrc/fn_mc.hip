@@ -12,47 +12,75 @@
 
 namespace fn {
 
-// one thread per (walker, d): d < ceil(3N/2) makes two normal deviates,
-// d == ceil(3N/2) makes the accept uniform.  x' = x + sigma z is rounded
-// as a product and then a sum (no fused multiply-add).
+// Deviate pair d of walker w (d < ceil(3N/2): coordinates 2 d and 2 d + 1,
+// x' = x + sigma z rounded as a product and then a sum, no fused
+// multiply-add), or its accept uniform (d == ceil(3N/2)).  The generator
+// counter takes the walker's index within its own job, wl.
+__device__ inline void propose_item(const double *x, int64_t w, int64_t wl, int d, int n3, double sigma, uint32_t k0,
+                                    uint32_t k1, uint32_t step, uint32_t stream_id, const double *z_ext,
+                                    const double *u_ext, double *xp, double *u)
+{
+#pragma clang fp contract(off)
+    const int D = (n3 + 1) / 2;
+    if (d == D) {
+        if (u_ext) {
+            u[w] = u_ext[w];
+        } else {
+            uint32_t c[4] = {0xFFFFFFFFu, (uint32_t)wl, step, stream_id};
+            philox4x32_10(c, k0, k1);
+            u[w] = word_pair_to_unit(c[0], c[1]);
+        }
+        return;
+    }
+    double z0, z1;
+    if (z_ext) {
+        z0 = z_ext[w * n3 + 2 * d];
+        z1 = 2 * d + 1 < n3 ? z_ext[w * n3 + 2 * d + 1] : 0.0;
+    } else {
+        uint32_t c[4] = {(uint32_t)d, (uint32_t)wl, step, stream_id};
+        philox4x32_10(c, k0, k1);
+        const double u1 = word_pair_to_unit(c[0], c[1]), u2 = word_pair_to_unit(c[2], c[3]);
+        const double rad = sqrt(-2.0 * log(u1));
+        const double ang = 2.0 * M_PI * u2;
+        z0 = rad * cos(ang);
+        z1 = rad * sin(ang);
+    }
+    const double s0 = sigma * z0;
+    xp[w * n3 + 2 * d] = x[w * n3 + 2 * d] + s0;
+    if (2 * d + 1 < n3) {
+        const double s1 = sigma * z1;
+        xp[w * n3 + 2 * d + 1] = x[w * n3 + 2 * d + 1] + s1;
+    }
+}
+
+// one thread per (walker, d), d = 0 .. ceil(3N/2)
 __global__ void k_propose(const double *x, int64_t B, int n3, double sigma, uint32_t k0, uint32_t k1, uint32_t step,
                           uint32_t stream_id, const double *z_ext, const double *u_ext, double *xp, double *u)
 {
-#pragma clang fp contract(off)
     const int D = (n3 + 1) / 2;
     const int64_t total = B * (D + 1);
     for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < total; id += (int64_t)gridDim.x * blockDim.x) {
         const int64_t w = id / (D + 1);
-        const int d = (int)(id % (D + 1));
-        if (d == D) {
-            if (u_ext) {
-                u[w] = u_ext[w];
-            } else {
-                uint32_t c[4] = {0xFFFFFFFFu, (uint32_t)w, step, stream_id};
-                philox4x32_10(c, k0, k1);
-                u[w] = word_pair_to_unit(c[0], c[1]);
-            }
-            continue;
+        propose_item(x, w, w, (int)(id % (D + 1)), n3, sigma, k0, k1, step, stream_id, z_ext, u_ext, xp, u);
+    }
+}
+
+// the same over the walkers of several jobs: job q owns walkers
+// [w0[q], w0[q + 1]) and its own key, step counter and stream id
+__global__ void k_propose_group(const double *x, int64_t B, int n3, double sigma, GroupTable g, double *xp, double *u)
+{
+    const int D = (n3 + 1) / 2;
+    const int64_t total = B * (D + 1);
+    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < total; id += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t w = id / (D + 1);
+        int lo = 0, hi = g.n - 1;                    // last job with w0 <= w
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (g.w0[mid] <= w) lo = mid;
+            else hi = mid - 1;
         }
-        double z0, z1;
-        if (z_ext) {
-            z0 = z_ext[w * n3 + 2 * d];
-            z1 = 2 * d + 1 < n3 ? z_ext[w * n3 + 2 * d + 1] : 0.0;
-        } else {
-            uint32_t c[4] = {(uint32_t)d, (uint32_t)w, step, stream_id};
-            philox4x32_10(c, k0, k1);
-            const double u1 = word_pair_to_unit(c[0], c[1]), u2 = word_pair_to_unit(c[2], c[3]);
-            const double rad = sqrt(-2.0 * log(u1));
-            const double ang = 2.0 * M_PI * u2;
-            z0 = rad * cos(ang);
-            z1 = rad * sin(ang);
-        }
-        const double s0 = sigma * z0;
-        xp[w * n3 + 2 * d] = x[w * n3 + 2 * d] + s0;
-        if (2 * d + 1 < n3) {
-            const double s1 = sigma * z1;
-            xp[w * n3 + 2 * d + 1] = x[w * n3 + 2 * d + 1] + s1;
-        }
+        propose_item(x, w, w - g.w0[lo], (int)(id % (D + 1)), n3, sigma, g.k0[lo], g.k1[lo], g.step[lo],
+                     g.stream[lo], nullptr, nullptr, xp, u);
     }
 }
 
@@ -108,6 +136,13 @@ void launch_propose(const double *x, int64_t B, int n3, double sigma, uint64_t s
     const int64_t total = B * ((n3 + 1) / 2 + 1);
     hipLaunchKernelGGL(k_propose, dim3(grid_of(total)), dim3(256), 0, st, x, B, n3, sigma, (uint32_t)seed,
                        (uint32_t)(seed >> 32), (uint32_t)step, stream_id, z_ext, u_ext, xp, u);
+}
+
+void launch_propose_group(const double *x, int64_t B, int n3, double sigma, const GroupTable &g, double *xp,
+                          double *u, hipStream_t st)
+{
+    const int64_t total = B * ((n3 + 1) / 2 + 1);
+    hipLaunchKernelGGL(k_propose_group, dim3(grid_of(total)), dim3(256), 0, st, x, B, n3, sigma, g, xp, u);
 }
 
 void launch_energy_stats(const double *e_loc, int64_t B, double *stats, double *coeff, hipStream_t st)

@@ -5,9 +5,14 @@
 // and the energy estimate of Eq. 1 over its walkers (local energies of Eq. 2).
 // The server keeps every admitted job's walkers, log|psi| and workspace in a
 // caller-provided device arena (the job's HBM footprint), admits queued jobs
-// first come first served as soon as their footprint fits and a slot (stream)
-// is free, and advances every running job by one quantum of Metropolis steps
-// per scheduler step, so the work of different jobs overlaps on the device.
+// in arrival order as soon as their footprint fits and a slot (stream) is
+// free -- a job that does not fit yet may be passed by later, smaller jobs a
+// bounded number of times, after which admission waits for it -- and
+// advances every running job by one quantum of Metropolis steps per
+// scheduler step, so the work of different jobs overlaps on the device.
+// The library allocates nothing: the arena, the streams and the pinned host
+// buffer the results land in are the caller's; completion is read with
+// stream queries (each stream runs one job at a time).
 // A job's arithmetic does not depend on what else runs: each job draws its
 // random numbers from its own (seed, stream_id) counter space and uses its own
 // workspace, so results are identical alone and in any mix.
@@ -107,6 +112,7 @@ struct Arena {
         }
     }
     size_t free_bytes() const { size_t t = 0; for (auto &kv : free_) t += kv.second; return t; }
+    size_t largest_free() const { size_t t = 0; for (auto &kv : free_) t = kv.second > t ? kv.second : t; return t; }
 };
 
 struct Job {
@@ -120,7 +126,8 @@ struct Job {
     double sigma;
     uint64_t seed;
     uint32_t stream_id;
-    int32_t state = 0;        // 0 queued, 1 running, 2 done, 3 failed
+    int32_t state = 0;        // 0 queued, 1 running, 2 done, 3 failed, 4 cancelled
+    int32_t bypassed = 0;     // times a later job was admitted ahead of it
     int slot = -1;
     size_t off = 0, bytes = 0, ws_bytes = 0;
     size_t o_x, o_lp, o_acc, o_e, o_stats, o_ws;
@@ -132,8 +139,7 @@ struct Job {
 
 struct Slot {
     hipStream_t stream;
-    hipEvent_t ev;
-    double *host_res;         // pinned [4]
+    double *host_res;         // the caller's pinned [4]
     int64_t job = -1;
 };
 
@@ -147,6 +153,7 @@ struct fn_server {
     int32_t quantum;
     std::map<int64_t, Job> jobs;
     std::deque<int64_t> queue;
+    int32_t max_bypass;
     int64_t next_id = 0;
     std::string err;
 };
@@ -210,7 +217,6 @@ fn_status advance(fn_server *s, Job &j)
         j.err = fn_last_error();
         return r;
     }
-    if (hipEventRecord(sl.ev, sl.stream) != hipSuccess) return sfail(FN_EHIP, "event record failed");
     return FN_OK;
 }
 
@@ -262,23 +268,20 @@ size_t fn_server_job_bytes(const fn_config *cfg, int64_t B)
 }
 
 fn_status fn_server_create(void *arena, size_t arena_bytes, void *const *streams, int32_t n_streams,
-                           int32_t quantum_steps, fn_server **out)
+                           int32_t quantum_steps, double *host_results, fn_server **out)
 {
-    if (!arena || !streams || n_streams < 1 || !out || quantum_steps < 1)
+    if (!arena || !streams || n_streams < 1 || !out || quantum_steps < 1 || !host_results)
         return sfail(FN_EINVAL, "invalid server arguments");
     if ((uintptr_t)arena % AL) return sfail(FN_EINVAL, "arena must be 256-byte aligned");
     fn_server *s = new fn_server();
     s->arena_base = (char *)arena;
     s->arena.init(arena_bytes);
     s->quantum = quantum_steps;
+    s->max_bypass = 2 * n_streams;
     for (int i = 0; i < n_streams; ++i) {
         Slot sl;
         sl.stream = (hipStream_t)streams[i];
-        if (hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess ||
-            hipHostMalloc((void **)&sl.host_res, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-            delete s;
-            return sfail(FN_EHIP, "event / pinned buffer creation failed");
-        }
+        sl.host_res = host_results + 4 * i;
         s->slots.push_back(sl);
     }
     *out = s;
@@ -322,23 +325,34 @@ fn_status fn_server_step(fn_server *s, int32_t *n_active, int32_t *n_queued)
     for (size_t i = 0; i < s->slots.size(); ++i) {
         Slot &sl = s->slots[i];
         if (sl.job < 0) continue;
-        hipError_t q = hipEventQuery(sl.ev);
+        hipError_t q = hipStreamQuery(sl.stream);
         if (q == hipErrorNotReady) continue;
         Job &j = s->jobs[sl.job];
         if (q != hipSuccess) { j.err = hipGetErrorString(q); retire(s, j, 3); continue; }
         if (j.finishing) { retire(s, j, 2); continue; }
         if (advance(s, j) != FN_OK) retire(s, j, 3);
     }
-    // 2. admission, first come first served, by HBM footprint and free slot
-    while (!s->queue.empty()) {
+    // 2. admission in arrival order by HBM footprint and free slot; a job
+    //    that does not fit is passed by later ones that do, until it has been
+    //    passed max_bypass times -- then admission waits for it
+    for (auto it = s->queue.begin(); it != s->queue.end();) {
         int slot = -1;
         for (size_t i = 0; i < s->slots.size(); ++i)
             if (s->slots[i].job < 0) { slot = (int)i; break; }
         if (slot < 0) break;
-        Job &j = s->jobs[s->queue.front()];
+        Job &j = s->jobs[*it];
         fn_status r = admit(s, j, slot);
-        if (r == FN_ENOMEM) break;          // wait for memory to free up
-        s->queue.pop_front();
+        if (r == FN_ENOMEM) {
+            if (j.bypassed >= s->max_bypass) break;
+            bool fits_later = false;          // count a pass only if someone behind is admitted
+            for (auto jt = std::next(it); jt != s->queue.end() && !fits_later; ++jt)
+                fits_later = s->jobs[*jt].bytes <= s->arena.largest_free();
+            if (!fits_later) break;
+            ++j.bypassed;
+            ++it;
+            continue;
+        }
+        it = s->queue.erase(it);
         if (r != FN_OK) retire(s, j, 3);
     }
     int32_t act = 0;
@@ -367,14 +381,38 @@ fn_status fn_server_result(fn_server *s, int64_t job, fn_job_result *out)
     return FN_OK;
 }
 
+fn_status fn_server_cancel(fn_server *s, int64_t job)
+{
+    if (!s) return sfail(FN_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(job);
+    if (it == s->jobs.end()) return sfail(FN_EINVAL, "unknown job");
+    Job &j = it->second;
+    if (j.state == 0) {
+        for (auto q = s->queue.begin(); q != s->queue.end(); ++q)
+            if (*q == job) { s->queue.erase(q); break; }
+        j.state = 4;
+        j.t_done = now_s();
+    } else if (j.state == 1) {
+        retire(s, j, 4);              // waits for the job's enqueued quantum, then frees its slot and memory
+    }
+    return FN_OK;
+}
+
+fn_status fn_server_memory(fn_server *s, size_t *free_bytes, size_t *arena_bytes)
+{
+    if (!s || !free_bytes || !arena_bytes) return sfail(FN_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *free_bytes = s->arena.free_bytes();
+    *arena_bytes = s->arena.size;
+    return FN_OK;
+}
+
 fn_status fn_server_destroy(fn_server *s)
 {
     if (!s) return FN_OK;
-    for (auto &sl : s->slots) {
+    for (auto &sl : s->slots)
         if (sl.job >= 0) (void)hipStreamSynchronize(sl.stream);
-        (void)hipEventDestroy(sl.ev);
-        (void)hipHostFree(sl.host_res);
-    }
     delete s;
     return FN_OK;
 }

@@ -36,7 +36,11 @@ _vp, _i32, _i64, _u64, _u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, c
 _L.fn_server_job_bytes.restype = ctypes.c_size_t
 _L.fn_server_job_bytes.argtypes = [_vp, _i64]
 _L.fn_server_create.restype = _i32
-_L.fn_server_create.argtypes = [_vp, ctypes.c_size_t, _vp, _i32, _i32, ctypes.POINTER(_vp)]
+_L.fn_server_create.argtypes = [_vp, ctypes.c_size_t, _vp, _i32, _i32, _vp, ctypes.POINTER(_vp)]
+_L.fn_server_cancel.restype = _i32
+_L.fn_server_cancel.argtypes = [_vp, _i64]
+_L.fn_server_memory.restype = _i32
+_L.fn_server_memory.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
 _L.fn_server_submit.restype = _i32
 _L.fn_server_submit.argtypes = [_vp, _vp, _vp, _vp, _i64, _i32, ctypes.c_double, _u64, _u32, ctypes.POINTER(_i64)]
 _L.fn_server_step.restype = _i32
@@ -48,7 +52,7 @@ _L.fn_server_destroy.argtypes = [_vp]
 _L.fn_server_last_error.restype = ctypes.c_char_p
 _L.fn_server_last_error.argtypes = []
 
-STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
+STATES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
 
 
 def _check(st: int):
@@ -70,8 +74,11 @@ class Server:
         self.base = base + (-base) % 256
         self.streams = [torch.cuda.Stream(self.device) for _ in range(n_streams)]
         arr = (_vp * n_streams)(*[s.cuda_stream for s in self.streams])
+        # pinned host buffer the per-job results are copied into (caller-owned)
+        self.host_results = torch.zeros((n_streams, 4), dtype=torch.float64, pin_memory=True)
         h = _vp()
-        _check(_L.fn_server_create(self.base, arena_bytes, arr, n_streams, quantum, ctypes.byref(h)))
+        _check(_L.fn_server_create(self.base, arena_bytes, arr, n_streams, quantum, self.host_results.data_ptr(),
+                                   ctypes.byref(h)))
         self.h = h
         self._keep: Dict[int, tuple] = {}
 
@@ -100,6 +107,15 @@ class Server:
         if r.state >= 2:
             self._keep.pop(job, None)
         return out
+
+    def cancel(self, job: int) -> None:
+        _check(_L.fn_server_cancel(self.h, job))
+
+    def memory(self) -> Tuple[int, int]:
+        """(free arena bytes, arena bytes)."""
+        f, t = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(_L.fn_server_memory(self.h, ctypes.byref(f), ctypes.byref(t)))
+        return f.value, t.value
 
     def drain(self, jobs: List[int], timeout_s: float = 600.0):
         t0 = time.perf_counter()

@@ -26,8 +26,10 @@ from paper_2401_10287_amd import inputs as I          # noqa: E402
 
 CHAIN_SEED = 2024
 SIGMA = 0.2
-# (system, walkers, steps)
-PLAN = (("LiH", I.lih, 4096, 300), ("LiF", I.lif, 512, 300), ("H20", I.h_chain, 128, 300))
+# (system, walkers, steps); the serving mix's atoms and ions (Z 2..10,
+# charge -1..+2) as "Z<z>q<charge>" with 6 walkers each
+PLAN = (("LiH", I.lih, 4096, 300), ("LiF", I.lif, 512, 300), ("H20", I.h_chain, 128, 300)) + tuple(
+    (f"Z{z}q{q:+d}", (lambda z=z, q=q: I.atom_ion(z, q, walkers=6)), 6, 200) for z, q in I.serving_job_types())
 
 
 def main():
@@ -43,7 +45,8 @@ def main():
         for k in range(0, steps, 50):
             x, la, a = o.metropolis(th, x, la, 50, SIGMA, seed=CHAIN_SEED, step0=k)
             acc += a
-            print(f"{name}: {k + 50} of {steps} steps, {time.time() - t:.0f} s", flush=True)
+            if walkers > 6:
+                print(f"{name}: {k + 50} of {steps} steps, {time.time() - t:.0f} s", flush=True)
         out[name] = x
         out[name + "_steps"] = np.array(steps)
         out[name + "_acceptance"] = np.array(acc.mean() / steps)

@@ -1,0 +1,108 @@
+"""Shared parity helpers of the GPU tests: walker sets, conditioning of a
+walker from the oracle's determinants, and the tolerance model.
+
+Tolerances (stated: log|psi| relative 1e-5 for FP32 and the FP32-accurate
+six-product split, 1e-3 for BF16 splits; per-walker E_L within 1e-3 Ha;
+batch mean within 1 mHa).
+
+A walker is well conditioned when its determinant sum does not cancel,
+kappa = sum_k |psi_k| / |psi| <= 10, and its orbital matrices are not close
+to singular: C = sum_k |psi_k / psi| sum_spin tr(|A_k^-1| |A_k|) <= 50 N
+(C >= N; C is the first-order amplification of a relative rounding of every
+orbital entry into log|psi|, the Skeel condition weighted by the
+determinants).
+  - well-conditioned walkers: |dE_L| <= 1e-3 Ha in every precision;
+  - every other walker, plain FP32: the same bound scaled by the
+    conditioning, 1e-3 max(1, kappa / 10)^2 max(1, C / (50 N)) (the kinetic
+    term divides by psi, once through kappa and once more through its
+    derivatives);
+  - every other walker, a reduced-precision (split-BF16) mode: within twice
+    the plain FP32 path's own error on that walker plus 1e-3, or within the
+    FP32 bound above, whichever is larger;
+  - the batch mean over all walkers within 1 mHa.
+Every walker is checked; the ill-conditioned ones are counted and printed.
+The walker sets are samples of |psi|^2 (tests/golden/equilibrated_walkers.npz,
+written by the oracle's own chain), the distribution Eq. 1 averages over.
+"""
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+KAPPA_WELL = 10.0
+C_WELL_PER_ELECTRON = 50.0
+
+
+def equilibrated(name, walkers):
+    """The first `walkers` equilibrated walkers of a system (the stored set
+    repeated in order when more are asked for)."""
+    d = np.load(os.path.join(GOLDEN, "equilibrated_walkers.npz"))
+    x = d[name]
+    reps = -(-walkers // x.shape[0])
+    return np.ascontiguousarray(np.tile(x, (reps, 1, 1))[:walkers])
+
+
+def kappa_and_c(o, s, th, x):
+    """(kappa, C) of every walker from the oracle's determinants and orbital matrices."""
+    d = o.log_psi(th, x, dets=True)["dets"]
+    sk = d[:, 0, :, 0] * d[:, 1, :, 0]
+    lk = d[:, 0, :, 1] + d[:, 1, :, 1]
+    with np.errstate(all="ignore"):
+        t = sk * np.exp(lk - lk.max(1, keepdims=True))
+        kappa = np.abs(t).sum(1) / np.abs(t.sum(1))
+        om = np.abs(t) / np.abs(t.sum(1, keepdims=True))
+        A = o.orbital_matrices(th, x)
+        C = np.zeros_like(om)
+        for sp, n in ((0, s.n_up), (1, s.n_dn)):
+            if n:
+                M = A[:, sp, :, :n, :n]
+                C += np.einsum("bkij,bkji->bk", np.abs(np.linalg.inv(M)), np.abs(M))
+        Cw = (om * C).sum(1)
+    return np.nan_to_num(kappa, nan=np.inf), np.nan_to_num(Cw, nan=np.inf)
+
+
+def energy_bound(kappa, C, n_elec, tol=1e-3, d32=None):
+    """Per-walker bound and the well-conditioned mask (see the module docstring)."""
+    c0 = C_WELL_PER_ELECTRON * n_elec
+    well = (kappa <= KAPPA_WELL) & (C <= c0)
+    cond = tol * np.maximum(1.0, kappa / KAPPA_WELL) ** 2 * np.maximum(1.0, C / c0)
+    ill = cond if d32 is None else np.maximum(2.0 * d32 + tol, cond)
+    return np.where(well, tol, ill), well
+
+
+def check_energy(e, ref, label, kappa=None, C=None, n_elec=None, tol=1e-3, d32=None, mean_tol=1e-3, parts=None):
+    """Per-walker and batch-mean check of local energies against the oracle.
+    kappa = None: a fixed bound tol on every walker (FP64)."""
+    r = ref["e_loc"]
+    fin = np.isfinite(r)
+    assert np.array_equal(np.isfinite(e), fin), f"{label}: non-finite pattern differs"
+    d = np.where(fin, np.abs(e - r), 0.0)
+    if parts is not None:
+        np.testing.assert_allclose(parts[fin, 1:], ref["parts"][fin, 1:], rtol=1e-12, atol=1e-12)
+    if kappa is None:
+        bound, well = np.full_like(d, tol), np.ones_like(fin)
+    else:
+        bound, well = energy_bound(kappa, C, n_elec, tol, d32)
+    dm = abs(e[fin].mean() - r[fin].mean()) if fin.any() else 0.0
+    worst = np.argsort(-(d / bound))[:3]
+    print(f"{label}: E_L max |d| {d.max():.2e} Ha (well-conditioned {d[well & fin].max(initial=0):.2e}, "
+          f"{int((~well).sum())} ill-conditioned walkers), median {np.median(d[fin]):.1e}, batch-mean |d| {dm:.2e} Ha; "
+          f"worst d/bound {(d / bound).max():.2f} at "
+          + ", ".join(f"w{i} (kappa {kappa[i]:.1f}, C {C[i]:.0f})" if kappa is not None else f"w{i}" for i in worst))
+    assert np.all(d <= bound), (label, (d / bound).max())
+    if mean_tol is not None:
+        assert dm <= mean_tol, (label, dm)
+    return d
+
+
+def check_logpsi(lp, ref, tol, label, C, fp64):
+    """|d log|psi|| <= tol max(1, |log|psi||) (+ 2e-7 C for FP32 arithmetic)."""
+    d = np.abs(lp - ref["log_abs"])
+    base = tol * np.maximum(1.0, np.abs(ref["log_abs"]))
+    bound = base if fp64 else base + 2e-7 * C
+    err = d / np.maximum(1.0, np.abs(ref["log_abs"]))
+    n_ill = int((bound > 2 * base).sum())
+    print(f"{label}: log|psi| max rel err {err.max():.2e} p99 {np.percentile(err, 99):.2e}; "
+          f"{n_ill} walkers where conditioning dominates the bound; worst d/bound {(d / bound).max():.2f}")
+    assert np.all(d <= bound), (d / bound).max()
+    return err

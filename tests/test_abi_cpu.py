@@ -110,3 +110,22 @@ def test_tuning_switches_checked_on_host():
     assert fnvmc.LIB.fn_tuning_set(b"no_such_switch", 1) == fnvmc.FN_EINVAL
     assert fnvmc.LIB.fn_tuning_set(b"pair_oc", 3) == fnvmc.FN_EINVAL
     assert fnvmc.LIB.fn_tuning_set(b"pair_items", 5000) == fnvmc.FN_EINVAL
+
+
+def test_group_call_rejects_bad_job_tables():
+    """The grouped Metropolis call checks its job table before touching any
+    pointer: gaps, overlaps, a wrong total and too many jobs are errors."""
+    import ctypes
+    from paper_2401_10287_amd import fnvmc
+    cfg = fnvmc.Config(I.lih(), "fp32")
+
+    def call(jobs, total):
+        tab = (fnvmc.GroupJob * max(1, len(jobs)))(*[fnvmc.GroupJob(*j) for j in jobs])
+        return fnvmc.LIB.vmc_metropolis_step_group(cfg.ptr, None, ctypes.addressof(tab), len(jobs), None, None, None,
+                                                   total, 1, 0.2, None, 0, None)
+    assert call([(0, 10, 1, 0, 0), (12, 5, 1, 0, 0)], 17) == fnvmc.FN_EINVAL        # gap
+    assert call([(0, 10, 1, 0, 0), (8, 5, 1, 0, 0)], 15) == fnvmc.FN_EINVAL         # overlap
+    assert call([(0, 10, 1, 0, 0)], 11) == fnvmc.FN_EINVAL                          # total
+    assert call([(0, 0, 1, 0, 0)], 0) == fnvmc.FN_EINVAL                            # empty job
+    assert call([(q, 1, 1, 0, 0) for q in range(65)], 65) == fnvmc.FN_EINVAL        # too many
+    assert b"job" in fnvmc.LIB.fn_last_error() or b"B_total" in fnvmc.LIB.fn_last_error()

@@ -156,20 +156,83 @@ def test_vjp_linear_and_deterministic_full_size():
     np.testing.assert_allclose(ab, a + b, rtol=1e-3, atol=1e-5 * np.abs(ab).max())
 
 
+@pytest.mark.parametrize("prec", ["bf16x6", "fp32"])
+def test_vjp_full_size_lif_sampled(prec):
+    """The LiF training configuration at full size (4096 walkers, 4 layers
+    256/32, 16 determinants): the backward with weights that are non-zero on
+    32 sampled walkers, against the oracle's exact derivative for one
+    parameter of every tensor group and against central finite differences
+    of the oracle's FP64 log|psi| for 8 parameters (one each from 8 groups);
+    bound 5e-4 of sum_p |c_p d log|psi_p||, as at reduced size."""
+    import parity_tools as T
+    torch, fnvmc = _dev()
+    s = I.lif()
+    cfg = fnvmc.Config(s, prec)
+    tt = torch.tensor(I.init_params(s), dtype=torch.float32, device="cuda")
+    th = tt.double().cpu().numpy()
+    x = T.equilibrated("LiF", 4096)
+    rng = np.random.default_rng(21)
+    idx = np.sort(rng.choice(512, 32, replace=False))        # distinct stored walkers
+    c = np.zeros(4096)
+    c[idx] = rng.standard_normal(32) / 32
+    g = fnvmc.fn_log_psi_vjp(cfg, tt, torch.tensor(x, device="cuda"), torch.tensor(c, device="cuda"))
+    torch.cuda.synchronize()
+    g = g.double().cpu().numpy()
+    print("LiF full size: oracle derivatives", flush=True)
+    o = O.Oracle(s)
+    gi = _group_indices(s)
+    d = o.dlogpsi_dtheta(th, x[idx], gi)
+    ref = c[idx] @ d
+    scale = np.abs(c[idx]) @ np.abs(d)
+    err = np.abs(g[gi] - ref)
+    print(prec, "full-size per-group max err / scale", (err / scale).max())
+    assert np.all(err <= 5e-4 * scale)
+    names = ["V0", "b1", "V2", "W2_0", "c2_2", "w_up", "pi_dn", "sig_up"]
+    off = I.param_offsets(s)
+    fd_idx = [off[n][0] + (5 * int(np.prod(off[n][1]))) // 9 for n in names]
+    dd = o.dlogpsi_dtheta(th, x[idx], fd_idx)
+    for t, i in enumerate(fd_idx):
+        h = 1e-6 * max(1.0, abs(th[i]))
+        tp, tm = th.copy(), th.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = c[idx] @ ((o.log_psi(tp, x[idx])["log_abs"] - o.log_psi(tm, x[idx])["log_abs"]) / (2 * h))
+        sc = np.abs(c[idx]) @ np.abs(dd[:, t])
+        print(f"  {names[t]}[{i}]: gpu {g[i]:.6e} finite difference {fd:.6e} scale {sc:.2e}")
+        assert abs(g[i] - fd) <= 5e-4 * sc + 1e-9, names[t]
+
+
 def test_training_step_lif_full_size():
-    """The LiF training step: 10 Metropolis moves + local energy + backward
-    on 4096 walkers (BF16x6 streams); everything finite, statistics sane."""
+    """The LiF training step on 4096 |psi|^2 samples: 10 Metropolis moves +
+    local energy + backward (BF16x6 streams).  The energy statistics are the
+    FP64 mean / variance / standard error of the returned local energies,
+    the local energies of sampled walkers after the moves match the oracle
+    (parity model of the E_L tests), log|psi| carried by the walk matches a
+    fresh evaluation, and the gradient is finite."""
+    import parity_tools as T
     torch, fnvmc = _dev()
     s = I.lif()
     cfg = fnvmc.Config(s, "bf16x6")
     tt = torch.tensor(I.init_params(s), dtype=torch.float32, device="cuda")
-    xt = torch.tensor(I.init_walkers(s), device="cuda")
+    xt = torch.tensor(T.equilibrated("LiF", 4096), device="cuda")
     lp, _ = fnvmc.fn_log_psi(cfg, tt, xt)
     acc = fnvmc.vmc_metropolis_step(cfg, tt, xt, lp, 10, 0.2, seed=I.METROPOLIS_SEED)
     e, lp2, _ = fnvmc.fn_local_energy(cfg, tt, xt)
     grad, stats = fnvmc.fn_param_grad(cfg, tt, xt, e)
     torch.cuda.synchronize()
-    print("LiF step: acceptance", acc.float().mean().item() / 10, "E", stats.cpu().numpy())
+    en, st = e.cpu().numpy(), stats.cpu().numpy()
+    print("LiF step: acceptance", acc.float().mean().item() / 10, "E", st)
     assert torch.isfinite(grad).all()
     assert 0.05 < acc.float().mean().item() / 10 < 0.99
+    np.testing.assert_allclose(st, [en.mean(), en.var(), np.sqrt(en.var() / en.size)], rtol=1e-12)
     np.testing.assert_allclose(lp.cpu().numpy(), lp2.cpu().numpy(), rtol=0, atol=1e-3)
+    idx = np.arange(0, 512, 32)                  # distinct stored walkers
+    x = xt.cpu().numpy()[idx]
+    th = tt.double().cpu().numpy()
+    o = O.Oracle(s)
+    ref = o.local_energy(th, x)
+    kap, C = T.kappa_and_c(o, s, th, x)
+    cfg32 = fnvmc.Config(s, "fp32")
+    e32, _, _ = fnvmc.fn_local_energy(cfg32, tt, xt[idx].contiguous())
+    d32 = np.abs(e32.cpu().numpy() - ref["e_loc"])
+    T.check_energy(en[idx], ref, "LiF after the moves", kap, C, s.n_elec, d32=d32)

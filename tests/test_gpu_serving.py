@@ -99,3 +99,108 @@ def test_served_job_matches_oracle_fp64():
     assert r["acceptance"] == pytest.approx(ao.sum() / (256 * 20), abs=0.5 / (256 * 20))
     assert abs(r["mean"] - eo.mean()) <= 1e-6
     assert r["variance"] == pytest.approx(eo.var(), rel=1e-6)
+
+
+def test_served_job_mixed_precision_matches_oracle():
+    """A mixed-precision job (the C atom, 6 electrons, the serving network 4
+    layers 256/32, 16 determinants, 256 walkers, 20 moves): its energy
+    estimate equals the same chain through the plain entry points bit for
+    bit; that chain's walkers equal the oracle's own chain (same counters,
+    FP64) wherever every decision agreed (at least 90% of the walkers;
+    decisions differ only within the log|psi| error), and there the local
+    energies match the oracle's within the parity model."""
+    import parity_tools as T
+    torch, fnvmc, serving = _mods()
+    s = I.atom_ion(6, 0, walkers=256)
+    th = I.init_params(s, seed=79)
+    x = I.init_walkers(s, 256, seed=80)
+    cfg = fnvmc.Config(s, "bf16x6")
+    tt = torch.tensor(th, dtype=torch.float32, device="cuda")
+    xt = torch.tensor(x, device="cuda")
+    srv = serving.Server(2 << 30, n_streams=2, quantum=7)
+    j = srv.submit(cfg, tt, xt, 20, 0.2, seed=3, stream_id=12)
+    srv.drain([j])
+    r = srv.result(j)
+    srv.close()
+    xg = xt.clone()
+    lp, _ = fnvmc.fn_log_psi(cfg, tt, xg)
+    acc = fnvmc.vmc_metropolis_step(cfg, tt, xg, lp, 20, 0.2, seed=3, step0=0, stream_id=12)
+    e, _, _ = fnvmc.fn_local_energy(cfg, tt, xg)
+    en = e.cpu().numpy()
+    assert r["state"] == "done"
+    assert r["mean"] == en.mean() or abs(r["mean"] - en.mean()) <= 1e-15 * abs(en.mean())
+    assert r["acceptance"] == acc.sum().item() / (256 * 20)
+    th32 = tt.double().cpu().numpy()
+    o = O.Oracle(s)
+    xo, lo, ao = o.metropolis(th32, x, o.log_psi(th32, x)["log_abs"], 20, 0.2, seed=3, step0=0, stream_id=12)
+    same = np.all(np.abs(xg.cpu().numpy() - xo) <= 1e-9, axis=(1, 2))
+    print(f"mixed served job: mean {r['mean']:.6f}, acceptance {r['acceptance']:.3f}; {int(same.sum())} of 256 "
+          f"walkers with the oracle's decisions")
+    assert same.mean() >= 0.9
+    ref = o.local_energy(th32, xo[same])
+    kap, C = T.kappa_and_c(o, s, th32, xo[same])
+    cfg32 = fnvmc.Config(s, "fp32")
+    e32, _, _ = fnvmc.fn_local_energy(cfg32, tt, torch.tensor(xo[same], device="cuda"))
+    d32 = np.abs(e32.cpu().numpy() - ref["e_loc"])
+    T.check_energy(en[same], ref, "served bf16x6 job", kap, C, s.n_elec, d32=d32)
+
+
+def test_cancel_frees_slot_and_memory():
+    """Cancelling a running job frees its stream and its arena block; a
+    cancelled queued job never runs; the remaining jobs finish with the
+    results they have alone."""
+    torch, fnvmc, serving = _mods()
+    fac = serving.JobFactory("bf16x6", seed=11, sizes=(1024,))
+    jobs = [fac.job(k) for k in range(3)]
+    need = max(serving.job_bytes(c, x.shape[0]) for c, _, x, _ in jobs)
+    srv = serving.Server(2 * need + 4096, n_streams=2, quantum=5)
+    ids = [srv.submit(c, t, x, 40, 0.2, seed=1, stream_id=k) for k, (c, t, x, _) in enumerate(jobs)]
+    active, queued = srv.step()
+    assert active == 2 and queued == 1
+    free0, total = srv.memory()
+    srv.cancel(ids[0])                       # running
+    free1, _ = srv.memory()
+    assert srv.result(ids[0])["state"] == "cancelled"
+    assert free1 - free0 >= need - 4096
+    active, queued = srv.step()              # the queued job takes the freed slot
+    assert active == 2 and queued == 0
+    srv.drain(ids[1:])
+    res = [srv.result(j) for j in ids]
+    assert [r["state"] for r in res] == ["cancelled", "done", "done"]
+    assert srv.memory()[0] == total
+    # a queued job cancelled before it runs
+    srv2 = serving.Server(need + 4096, n_streams=1, quantum=5)
+    a = srv2.submit(*jobs[1][:3], 40, 0.2, seed=1, stream_id=1)
+    b = srv2.submit(*jobs[2][:3], 40, 0.2, seed=1, stream_id=2)
+    srv2.step()
+    srv2.cancel(b)
+    srv2.drain([a])
+    assert srv2.result(b)["state"] == "cancelled" and srv2.result(b)["admit_s"] == 0.0
+    ra = srv2.result(a)
+    srv2.close()
+    srv.close()
+    assert ra["mean"] == res[1]["mean"] and ra["acceptance"] == res[1]["acceptance"]
+
+
+def test_small_jobs_pass_a_job_that_does_not_fit():
+    """A large job at the head of the queue that does not fit yet is passed
+    by later small jobs that do (bounded: at most 2 x streams passes), and
+    every job finishes."""
+    torch, fnvmc, serving = _mods()
+    big = serving.JobFactory("bf16x6", seed=12, sizes=(4096,)).job(0)
+    small = [serving.JobFactory("bf16x6", seed=13 + k, sizes=(256,)).job(k) for k in range(3)]
+    nb = serving.job_bytes(big[0], 4096)
+    ns = max(serving.job_bytes(c, x.shape[0]) for c, _, x, _ in small)
+    srv = serving.Server(nb + ns + 8192, n_streams=4, quantum=5)
+    first = srv.submit(*big[:3], 30, 0.2, seed=1, stream_id=0)          # fills most of the arena
+    srv.step()
+    head = srv.submit(*big[:3], 30, 0.2, seed=1, stream_id=1)           # cannot fit while the first runs
+    later = [srv.submit(c, t, x, 30, 0.2, seed=1, stream_id=2 + k) for k, (c, t, x, _) in enumerate(small)]
+    active, queued = srv.step()
+    assert srv.result(head)["state"] == "queued"
+    assert srv.result(later[0])["state"] in ("running", "done")          # passed the head
+    srv.drain([first, head] + later)
+    res = [srv.result(j) for j in [first, head] + later]
+    srv.close()
+    assert all(r["state"] == "done" for r in res)
+    assert res[2]["admit_s"] < res[1]["admit_s"]
