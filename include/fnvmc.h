@@ -185,6 +185,20 @@ fn_status vmc_metropolis_step_group(const fn_config *cfg, const void *theta, con
 fn_status fn_param_grad(const fn_config *cfg, const void *theta, const double *x, int64_t B, const double *e_loc,
                         void *grad, double *stats, void *ws, size_t ws_bytes, void *stream);
 
+/* Pretraining loss of Eq. 5 (FermiNet Training section) and its gradient:
+   loss = (1/B) sum_p sum_{spin, k, i, j} (Phi^{k,spin}_{ij}(x_p) - T^{k,spin}_{ij,p})^2
+   with Phi^{k,spin}_{ij} = orbital i of determinant k at electron j of that
+   spin (envelope of Eq. 4 times the orbital head) and T the caller's target
+   orbital values (Hartree-Fock in the paper; any values here).  Reading of
+   the equation's N: the number of walkers B.  target_up: device
+   [B][K][n_up][n_up] FP64 (row i = orbital, column j = electron; NULL if
+   n_up = 0), target_dn likewise.  loss: device [1] FP64 out or NULL.
+   grad: device [P] out (theta's type).  The orbital matrices come from a
+   value-form forward pass; the backward is the log|psi| one below the
+   determinants.  Workspace: fn_workspace_bytes(cfg, B, FN_OP_PARAM_GRAD). */
+fn_status fn_pretrain_grad(const fn_config *cfg, const void *theta, const double *x, int64_t B, const double *target_up,
+                           const double *target_dn, double *loss, void *grad, void *ws, size_t ws_bytes, void *stream);
+
 /* grad = sum_p coeff_p d log|psi_p| / d theta.  coeff: device [B] FP64.
    grad: device [P] out (theta's type). */
 fn_status fn_log_psi_vjp(const fn_config *cfg, const void *theta, const double *x, int64_t B, const double *coeff,

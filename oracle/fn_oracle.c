@@ -200,6 +200,7 @@ typedef struct {
     hd *h1, *h1n, *h2, *h2n, *f, *gu, *gd, *giu, *gid, *A;
     hd *hL_out;     /* optional copy of the final one-electron stream          */
     double *mats;   /* optional copy of the orbital matrices [2][K][nmax][nmax] */
+    double *mats_b; /* optional: their derivative along the parameter direction */
 } scratch;
 
 static scratch scratch_alloc(const orc_cfg *c)
@@ -222,6 +223,7 @@ static scratch scratch_alloc(const orc_cfg *c)
     s.A = (hd *)calloc((size_t)(nmax * nmax > 0 ? nmax * nmax : 1), sizeof(hd));
     s.hL_out = NULL;
     s.mats = NULL;
+    s.mats_b = NULL;
     return s;
 }
 
@@ -362,6 +364,11 @@ static void eval_walker(const orc_cfg *c, const orc_layout *Ly, const double *th
                 double *dst = S->mats + ((size_t)(s * K + k) * nmax * nmax);
                 for (int r = 0; r < ns; ++r)
                     for (int q = 0; q < ns; ++q) dst[r * nmax + q] = S->A[r * ns + q].a;
+                if (S->mats_b) {
+                    double *db = S->mats_b + ((size_t)(s * K + k) * nmax * nmax);
+                    for (int r = 0; r < ns; ++r)
+                        for (int q = 0; q < ns; ++q) db[r * nmax + q] = S->A[r * ns + q].b;
+                }
             }
             int sg; hd la;
             lu_slogdet(ns, S->A, &sg, &la);
@@ -529,6 +536,35 @@ void orc_orbital_matrices(const orc_cfg *c, const double *theta, const double *x
             S.mats = out + per * (size_t)w;
             hd lp; int sg;
             eval_walker(c, &Ly, theta, NULL, xh, &S, &lp, &sg, NULL);
+        }
+        free(xh);
+        scratch_free(&S);
+    }
+}
+
+/* the orbital matrices and their derivative along the parameter direction
+   dir (exact, dual numbers): out, out_dir [B][2][K][nmax][nmax] */
+void orc_orbital_matrices_dir(const orc_cfg *c, const double *theta, const double *dir, const double *x, int64_t B,
+                              double *out, double *out_dir)
+{
+    orc_layout Ly;
+    make_layout(c, &Ly);
+    const int N = c->n_up + c->n_dn;
+    const int nmax = c->n_up > c->n_dn ? c->n_up : c->n_dn;
+    const size_t per = (size_t)2 * c->n_det * nmax * nmax;
+    memset(out, 0, sizeof(double) * per * (size_t)B);
+    memset(out_dir, 0, sizeof(double) * per * (size_t)B);
+#pragma omp parallel
+    {
+        scratch S = scratch_alloc(c);
+        hd *xh = (hd *)malloc(sizeof(hd) * 3 * N);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t w = 0; w < B; ++w) {
+            load_real(xh, x + w * 3 * N, 3 * N);
+            S.mats = out + per * (size_t)w;
+            S.mats_b = out_dir + per * (size_t)w;
+            hd lp; int sg;
+            eval_walker(c, &Ly, theta, dir, xh, &S, &lp, &sg, NULL);
         }
         free(xh);
         scratch_free(&S);

@@ -57,6 +57,7 @@ def lib():
         _lib.orc_slogdet.argtypes = [ctypes.c_int32, i64, vp, vp, vp]
         _lib.orc_coulomb.argtypes = [vp, vp, i64, vp]
         _lib.orc_orbital_matrices.argtypes = [vp, vp, vp, i64, vp]
+        _lib.orc_orbital_matrices_dir.argtypes = [vp, vp, vp, vp, i64, vp, vp]
         _lib.orc_num_threads.restype = ctypes.c_int32
     return _lib
 
@@ -128,6 +129,33 @@ class Oracle:
         out = np.empty((x.shape[0], 2, self.s.n_det, nmax, nmax))
         lib().orc_orbital_matrices(self._cp, _p(theta), _p(x), x.shape[0], _p(out))
         return out
+
+    def orbital_matrices_dir(self, theta, theta_dir, x):
+        """(values, derivative along theta_dir) of the orbital matrices, [B][2][K][nmax][nmax] each."""
+        x = _f64(x)
+        theta = _f64(theta)
+        nmax = max(self.s.n_up, self.s.n_dn)
+        out = np.empty((x.shape[0], 2, self.s.n_det, nmax, nmax))
+        out_d = np.empty_like(out)
+        lib().orc_orbital_matrices_dir(self._cp, _p(theta), _p(_f64(theta_dir)), _p(x), x.shape[0], _p(out),
+                                       _p(out_d))
+        return out, out_d
+
+    def pretrain_loss(self, theta, x, targets, theta_dir=None):
+        """Eq. 5: (1/B) sum over walkers, spins, determinants, orbitals and
+        electrons of (Phi - target)^2, targets [B][2][K][nmax][nmax] (entries
+        outside a spin's n x n block ignored); with theta_dir also the exact
+        derivative of the loss along it."""
+        B = x.shape[0]
+        mask = np.zeros((2, self.s.n_det, max(self.s.n_up, self.s.n_dn), max(self.s.n_up, self.s.n_dn)))
+        mask[0, :, :self.s.n_up, :self.s.n_up] = 1.0
+        mask[1, :, :self.s.n_dn, :self.s.n_dn] = 1.0
+        if theta_dir is None:
+            phi = self.orbital_matrices(theta, x)
+            return float((((phi - targets) * mask) ** 2).sum() / B)
+        phi, dphi = self.orbital_matrices_dir(theta, theta_dir, x)
+        r = (phi - targets) * mask
+        return float((r ** 2).sum() / B), float(2.0 * (r * dphi).sum() / B)
 
     def coulomb(self, x):
         x = _f64(x)

@@ -190,7 +190,7 @@ struct Plan {
     int64_t wxpart[FN_MAX_LAYERS], wgpart[FN_MAX_LAYERS];   // elements per BF16 part
     size_t H[FN_MAX_LAYERS + 1], GI, G, Pw, X, O[2], Phi[2], DR, xp, lpn, u;
     // backward
-    size_t Tl, GA[2], Ga[2], EP[2], Gy[2], Gz, SGz, Gh, Gg, GGI, PP, part, gacc, coeff;
+    size_t Tl, GA[2], Ga[2], EP[2], Gy[2], Gz, SGz, Gh, Gg, GGI, PP, part, gacc, coeff, lsum;
     int64_t gi_layer_stride;   // elements
     int64_t npp, part_elems;
     size_t total;
@@ -251,6 +251,7 @@ fn_status make_plan(const Ctx &c, int64_t B, int op, Plan &p)
     const int64_t P = c.P.total;
     p.gacc = o; if (p.save) o = al(o + (size_t)P * 8);
     p.coeff = o; if (p.save) o = al(o + (size_t)B * 8);
+    p.lsum = o; if (p.save) o = al(o + (size_t)2 * B * 8);
     p.xp = o; o = al(o + (size_t)B * n3 * 8);
     p.lpn = o; o = al(o + (size_t)B * 8);
     p.u = o; o = al(o + (size_t)B * 8);
@@ -534,9 +535,18 @@ void forward(const Ctx &c, const Plan &p, const T *theta, const double *x, int64
 
 // Reverse pass for walkers [w0, w0 + b) after forward_chunk with p.save:
 // accumulates sum_p coeff_p d log|psi_p| / d theta into the FP64 buffer gacc.
+// With targets (Eq. 5 pretraining): the adjoint of the orbital matrices is
+// scale (Phi - target) instead of the determinants' adjoint, and each
+// walker's sum of squared differences goes to lsum[spin][walker].
+struct PretrainTargets {
+    const double *t[2];      // [B][K][n_s][n_s] of the whole batch, at this chunk's first walker
+    double scale;            // 2 / B_total
+    double *lsum[2];         // [B] of this chunk
+};
+
 template <typename T>
 void backward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw, const double *coeff, int64_t b,
-                    char *ws, hipStream_t st)
+                    char *ws, hipStream_t st, const PretrainTargets *pre = nullptr)
 {
     Timed t_(K_BACKWARD, st);
     const Sys &s = c.s;
@@ -555,8 +565,12 @@ void backward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *x
         double *GA = (double *)(ws + p.GA[sp]);
         T *Ga = (T *)(ws + p.Ga[sp]);
         T *EP = (T *)(ws + p.EP[sp]);
-        launch_det_backward((const double *)(ws + p.Phi[sp]), (const double *)(ws + p.DR), coeff, b, s.K, n, sp, s.nu,
-                            s.nd, p.rec, GA, st);
+        if (pre)
+            launch_pretrain_adjoint((const double *)(ws + p.Phi[sp]), pre->t[sp], b, s.K, n, pre->scale, GA,
+                                    pre->lsum[sp], st);
+        else
+            launch_det_backward((const double *)(ws + p.Phi[sp]), (const double *)(ws + p.DR), coeff, b, s.K, n, sp,
+                                s.nu, s.nd, p.rec, GA, st);
         launch_env_backward<T>(s, xw, theta, c.P.g[sp], c.P.pi[sp], c.P.sig[sp], sp, (const T *)(ws + p.O[sp]), KNp,
                                GA, b, KNp, Ga, EP, st);
         launch_colsum<T>(EP, (int64_t)kn * s.M * 10, kn * s.M * 10, b, part, gacc, c.P.pi[sp], 1, c.P.sig[sp], st);
@@ -701,6 +715,37 @@ fn_status run_metropolis_group(const Ctx &c, const Plan &p, const void *theta, d
         forward<T>(c, p, (const T *)theta, xp, B, lpn, nullptr, nullptr, nullptr, w, st,
                    AcceptArgs{x, xp, uu, log_abs, n_accept});
     }
+    return hip_status();
+}
+
+template <typename T>
+fn_status run_pretrain(const Ctx &c, const Plan &p, const void *theta, const double *x, int64_t B,
+                       const double *target_up, const double *target_dn, double *loss, void *grad, void *ws,
+                       hipStream_t st)
+{
+    char *w = (char *)ws;
+    const T *th = (const T *)theta;
+    const int n3 = 3 * c.s.N;
+    double *gacc = (double *)(w + p.gacc);
+    double *lsum = (double *)(w + p.lsum);
+    launch_zero_f64(gacc, c.P.total, st);
+    launch_zero_f64(lsum, 2 * B, st);
+    pack_weights<T>(c, p, th, w, st);
+    double *lp = (double *)(w + p.lpn);
+    const int64_t per[2] = {(int64_t)c.s.K * c.s.nu * c.s.nu, (int64_t)c.s.K * c.s.nd * c.s.nd};
+    for (int64_t w0 = 0; w0 < B; w0 += p.Bc) {
+        const int64_t b = std::min(p.Bc, B - w0);
+        forward_chunk<T>(c, p, th, x + w0 * n3, b, lp + w0, nullptr, nullptr, nullptr, w, st);
+        PretrainTargets pre{};
+        pre.t[0] = c.s.nu ? target_up + w0 * per[0] : nullptr;
+        pre.t[1] = c.s.nd ? target_dn + w0 * per[1] : nullptr;
+        pre.scale = 2.0 / (double)B;
+        pre.lsum[0] = lsum + w0;
+        pre.lsum[1] = lsum + B + w0;
+        backward_chunk<T>(c, p, th, x + w0 * n3, nullptr, b, w, st, &pre);
+    }
+    launch_grad_out<T>(gacc, c.P.total, (T *)grad, st);
+    if (loss) launch_pretrain_loss(lsum, B, loss, st);
     return hip_status();
 }
 
@@ -888,6 +933,24 @@ static fn_status grad_common(const fn_config *cfg, const void *theta, const doub
     }
     return c.f64 ? run_backward<double>(c, p, theta, x, B, coeff, e_loc, stats, grad, ws, st)
                  : run_backward<float>(c, p, theta, x, B, coeff, e_loc, stats, grad, ws, st);
+}
+
+fn_status fn_pretrain_grad(const fn_config *cfg, const void *theta, const double *x, int64_t B, const double *target_up,
+                           const double *target_dn, double *loss, void *grad, void *ws, size_t ws_bytes, void *stream)
+{
+    Ctx c;
+    fn_status r = make_ctx(cfg, c);
+    if (r) return r;
+    if (B < 1) return fail(FN_EINVAL, "B < 1");
+    if (!theta || !x || !grad) return fail(FN_EINVAL, "theta, x or grad is NULL");
+    if ((c.s.nu && !target_up) || (c.s.nd && !target_dn)) return fail(FN_EINVAL, "a spin's targets are NULL");
+    if (((uintptr_t)theta) % 16) return fail(FN_EINVAL, "theta must be 16-byte aligned");
+    Plan p;
+    if ((r = make_plan(c, B, FN_OP_PARAM_GRAD, p))) return r;
+    if ((r = check_ws(p, ws, ws_bytes))) return r;
+    hipStream_t st = (hipStream_t)stream;
+    return c.f64 ? run_pretrain<double>(c, p, theta, x, B, target_up, target_dn, loss, grad, ws, st)
+                 : run_pretrain<float>(c, p, theta, x, B, target_up, target_dn, loss, grad, ws, st);
 }
 
 fn_status fn_param_grad(const fn_config *cfg, const void *theta, const double *x, int64_t B, const double *e_loc,

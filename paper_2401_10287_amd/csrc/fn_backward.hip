@@ -858,6 +858,57 @@ __global__ void k_pack_head_bwd(const T *theta, int64_t woff, int w1, int kn, in
 // ---------------------------------------------------------------------------
 size_t det_backward_lds(int n) { return (size_t)2 * n * n * sizeof(double) + (size_t)n * sizeof(int) + 16; }
 
+// ---------------------------------------------------------------------------
+// pretraining loss of Eq. 5, (1/B) sum_w sum_{k,i,j} (Phi - Phi_target)^2
+// over both spins: the adjoint of the orbital matrices and each walker's sum
+// of squares, one thread per walker (entries in order, so the sums are
+// reproducible); the loss reduction in one workgroup in a fixed order
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pretrain_adjoint(const double *Phi, const double *target, int64_t B, int per,
+                                                          double scale, double *GA, double *lsum)
+{
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < B; w += (int64_t)gridDim.x * blockDim.x) {
+        const double *p = Phi + w * per, *t = target + w * per;
+        double *g = GA + w * per;
+        double acc = 0.0;
+        for (int q = 0; q < per; ++q) {
+            const double d = p[q] - t[q];
+            g[q] = scale * d;
+            acc += d * d;
+        }
+        lsum[w] = acc;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_pretrain_loss(const double *lsum, int64_t B, double *loss)
+{
+    __shared__ double red[16];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double acc = 0.0;
+    for (int64_t p = tid; p < B; p += blockDim.x) acc += lsum[p] + lsum[B + p];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) red[wv] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += red[q];
+        *loss = t / (double)B;
+    }
+}
+
+void launch_pretrain_adjoint(const double *Phi, const double *target, int64_t B, int K, int n, double scale, double *GA,
+                             double *lsum, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pretrain_adjoint, dim3(gridn(B)), dim3(256), 0, st, Phi, target, B, K * n * n, scale, GA,
+                       lsum);
+}
+
+void launch_pretrain_loss(const double *lsum, int64_t B, double *loss, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pretrain_loss, dim3(1), dim3(1024), 0, st, lsum, B, loss);
+}
+
 void launch_det_backward(const double *Phi, const double *DR, const double *coeff, int64_t B, int K, int n, int sp,
                          int nu, int nd, int rec, double *GA, hipStream_t st)
 {

@@ -95,6 +95,12 @@ bool launch_orbdet_combine(const Sys &s, const double *x, const T *theta, const 
 size_t det_backward_lds(int n);
 void launch_det_backward(const double *Phi, const double *DR, const double *coeff, int64_t B, int K, int n, int sp,
                          int nu, int nd, int rec, double *GA, hipStream_t st);
+// Eq. 5: GA = scale (Phi - target) per (walker, determinant, orbital, electron)
+// and lsum[w] += sum of squared differences of walker w
+void launch_pretrain_adjoint(const double *Phi, const double *target, int64_t B, int K, int n, double scale, double *GA,
+                             double *lsum, hipStream_t st);
+// loss = sum_w (lsum[w] + lsum[B + w]) / B
+void launch_pretrain_loss(const double *lsum, int64_t B, double *loss, hipStream_t st);
 template <typename T>
 void launch_env_backward(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof,
                          int sp, const T *O, int64_t ldo, const double *GA, int64_t B, int KNp, T *Ga, T *EP,

@@ -60,6 +60,8 @@ def _load():
     lib.vmc_metropolis_step_group.argtypes = [vp, vp, vp, i32, vp, vp, vp, i64, i32, ctypes.c_double, vp, sz, vp]
     lib.fn_param_grad.restype = i32
     lib.fn_param_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]
+    lib.fn_pretrain_grad.restype = i32
+    lib.fn_pretrain_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
     lib.fn_log_psi_vjp.restype = i32
     lib.fn_log_psi_vjp.argtypes = [vp, vp, vp, i64, vp, vp, vp, sz, vp]
     lib.fn_ionic_electron_counts.restype = i32
@@ -87,7 +89,7 @@ LIB = _load()
 LIB_PATH = _LIB_PATH
 
 EXPORTED = ["fn_param_count", "fn_workspace_bytes", "fn_log_psi", "fn_local_energy", "vmc_metropolis_step",
-            "vmc_metropolis_step_ext", "vmc_metropolis_step_group", "fn_param_grad", "fn_log_psi_vjp", "fn_energy_stats", "fn_ionic_electron_counts",
+            "vmc_metropolis_step_ext", "vmc_metropolis_step_group", "fn_param_grad", "fn_pretrain_grad", "fn_log_psi_vjp", "fn_energy_stats", "fn_ionic_electron_counts",
             "fn_init_walkers", "fn_last_error", "fn_timing_enable",
             "fn_timing_select", "fn_timing_reset", "fn_timing_read", "fn_tuning_set", "fn_server_job_bytes", "fn_server_create", "fn_server_submit",
             "fn_server_step", "fn_server_result", "fn_server_cancel", "fn_server_memory", "fn_server_destroy",
@@ -269,6 +271,26 @@ def fn_param_grad(cfg: Config, theta: torch.Tensor, x: torch.Tensor, e_loc: torc
     _check(LIB.fn_param_grad(cfg.ptr, theta.data_ptr(), x.data_ptr(), b, e_loc.data_ptr(), grad.data_ptr(),
                              stats.data_ptr(), p, n, _stream(stream)))
     return grad, stats
+
+
+def fn_pretrain_grad(cfg: Config, theta: torch.Tensor, x: torch.Tensor, target_up: Optional[torch.Tensor],
+                     target_dn: Optional[torch.Tensor], ws: Optional[Workspace] = None, stream=None):
+    """(loss [1] FP64, grad [P]) of the Eq. 5 pretraining loss against target
+    orbital values [B][K][n][n] per spin (None for an empty spin)."""
+    b = x.shape[0]
+    s = cfg.system
+    _need(theta, cfg.param_dtype, (cfg.param_count(),), "theta")
+    _need(x, torch.float64, (b, cfg.n_elec, 3), "x")
+    for t, n, nm in ((target_up, s.n_up, "target_up"), (target_dn, s.n_dn, "target_dn")):
+        if n:
+            _need(t, torch.float64, (b, s.n_det, n, n), nm)
+    loss = torch.empty(1, dtype=torch.float64, device=x.device)
+    grad = torch.empty_like(theta)
+    w = _ws(ws, x)
+    p, n = w.get(cfg.workspace_bytes(b, FN_OP_PARAM_GRAD))
+    _check(LIB.fn_pretrain_grad(cfg.ptr, theta.data_ptr(), x.data_ptr(), b, _ptr(target_up), _ptr(target_dn),
+                                loss.data_ptr(), grad.data_ptr(), p, n, _stream(stream)))
+    return loss, grad
 
 
 def fn_log_psi_vjp(cfg: Config, theta: torch.Tensor, x: torch.Tensor, coeff: torch.Tensor,

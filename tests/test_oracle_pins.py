@@ -669,3 +669,46 @@ def test_draw_counter_layout():
                 assert z[2 * d + 1] == pytest.approx(rad * np.sin(2 * np.pi * u2), rel=1e-14, abs=1e-15)
         o = O.philox4x32_10([0xFFFFFFFF, walker, step, stream], key)
         assert u == _u01(o[0], o[1])
+
+
+# --------------------------------------------------------------------------
+# the pretraining loss of Eq. 5
+# --------------------------------------------------------------------------
+def test_pretrain_loss_closed_form():
+    """One electron, one determinant, orbital weights 0: Phi = g exp(-s r),
+    so Eq. 5 is (1/B) sum_p (g e_p - T_p)^2 and d/dg = (2/B) sum_p (g e_p -
+    T_p) e_p.  Pins the 1/B normalisation (N read as the number of walkers),
+    the square and the derivative; targets equal to Phi give 0."""
+    z, g = 1.7, 0.8
+    s = small(1, 0, [0.1, 0.0, -0.2], [z], L=2, K=1)
+    th, v = zero_theta(s)
+    v["g_up"][...] = g
+    v["sig_up"][...] = z * np.eye(3)
+    rng = np.random.default_rng(41)
+    x = rng.standard_normal((9, 1, 3))
+    e = np.exp(-z * np.linalg.norm(x[:, 0] - s.nuc_xyz[0], axis=1))
+    T = np.zeros((9, 2, 1, 1, 1))
+    T[:, 0, 0, 0, 0] = rng.standard_normal(9)
+    o = O.Oracle(s)
+    d = np.zeros_like(th)
+    d[I.param_offsets(s)["g_up"][0]] = 1.0
+    loss, dloss = o.pretrain_loss(th, x, T, theta_dir=d)
+    r = g * e - T[:, 0, 0, 0, 0]
+    assert loss == pytest.approx((r ** 2).sum() / 9, rel=1e-13)
+    assert dloss == pytest.approx(2 * (r * e).sum() / 9, rel=1e-12)
+    assert o.pretrain_loss(th, x, o.orbital_matrices(th, x)) == 0.0
+
+
+def test_pretrain_loss_derivative_matches_finite_differences():
+    s = I.System("LiF-s", I.lif().nuc_xyz, I.lif().nuc_z, 3, 2, 2, 8, 4, 2, 4, (0, 1, 1, 0, 1), 0.5)
+    th = I.init_params(s, seed=43)
+    x = I.init_walkers(s, 5, seed=44)
+    o = O.Oracle(s)
+    rng = np.random.default_rng(45)
+    T = o.orbital_matrices(th, x) * (1 + 0.3 * rng.standard_normal((5, 2, 2, 3, 3)))
+    for _ in range(3):
+        d = rng.standard_normal(th.size)
+        _, dl = o.pretrain_loss(th, x, T, theta_dir=d)
+        h = 1e-6
+        fd = (o.pretrain_loss(th + h * d, x, T) - o.pretrain_loss(th - h * d, x, T)) / (2 * h)
+        assert dl == pytest.approx(fd, rel=1e-6, abs=1e-9)
