@@ -149,6 +149,20 @@ fn_status vmc_metropolis_step_ext(const fn_config *cfg, const void *theta, doubl
                                   int32_t n_steps, double sigma, const double *z, const double *u, int32_t *n_accept,
                                   void *ws, size_t ws_bytes, void *stream);
 
+/* vmc_metropolis_step for callers that cannot allocate memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid allocation):
+   the same moves and results, with the workspace in a fixed device array of
+   the library (64 MiB, one copy per GPU, held until the process ends)
+   instead of a caller workspace.  No allocating call is made (the timing
+   diagnostics skip this call).  FN_ENOMEM if fn_workspace_bytes(cfg, B,
+   FN_OP_METROPOLIS) exceeds 64 MiB (for example LiH with 4 layers 256/32
+   and 16 determinants up to about 2600 walkers).  Every call on one GPU
+   shares that GPU's array: calls that overlap on one GPU (other streams,
+   other threads) race and must be serialised by the caller. */
+fn_status vmc_metropolis_step_noalloc(const fn_config *cfg, const void *theta, double *x, double *log_abs_psi,
+                                      int64_t B, int32_t n_steps, double sigma, uint64_t seed, uint64_t step0,
+                                      uint32_t stream_id, int32_t *n_accept, void *stream);
+
 /* Grouped Metropolis moves (Electron Sampler section) for several jobs of
    one system and one parameter vector in one sequence of launches, for
    small jobs that would leave the GPU idle alone.  Job q owns the walkers

@@ -46,6 +46,7 @@ const char *const kclass_names[K_NCLASS] = {"stream_gemm", "walker_gemm", "head_
 struct TimeRec { int cls; hipEvent_t a, b; };
 std::mutex g_tmu;
 bool g_timing = false;
+thread_local bool g_no_alloc_call = false;   // the timing brackets create events: not inside such a call
 int g_timing_only = -1;            // record one class only (-1: every class)
 std::vector<TimeRec> g_recs;
 std::vector<hipEvent_t> g_free_events;
@@ -71,7 +72,7 @@ struct Timed {
     hipEvent_t a = nullptr;
     Timed(int c, hipStream_t s) : cls(c), st(s)
     {
-        if (!g_timing || (g_timing_only >= 0 && c != g_timing_only)) return;
+        if (!g_timing || g_no_alloc_call || (g_timing_only >= 0 && c != g_timing_only)) return;
         std::lock_guard<std::mutex> lk(g_tmu);
         a = take_event();
         if (a) (void)hipEventRecord(a, st);
@@ -873,6 +874,74 @@ fn_status vmc_metropolis_step_ext(const fn_config *cfg, const void *theta, doubl
     if (!z || !u) return fail(FN_EINVAL, "z or u is NULL");
     return metropolis_common(cfg, theta, x, log_abs_psi, B, n_steps, sigma, 0, 0, 0, z, u, n_accept, ws, ws_bytes,
                              stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Workspace of vmc_metropolis_step_noalloc: a fixed device array, one copy per
+// GPU, held until the process ends.  Host code uses the per-device address
+// from hipGetSymbolAddress, never the array's name.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// the address of the current device's copy (looked up once per device)
+fn_status scratch_for_current_device(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(FN_EHIP, "hipGetDevice failed");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(FN_EUNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(FN_EHIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fn_status vmc_metropolis_step_noalloc(const fn_config *cfg, const void *theta, double *x, double *log_abs_psi,
+                                      int64_t B, int32_t n_steps, double sigma, uint64_t seed, uint64_t step0,
+                                      uint32_t stream_id, int32_t *n_accept, void *stream)
+{
+    Ctx c;
+    fn_status r = make_ctx(cfg, c);
+    if (r) return r;
+    if (B < 0) return fail(FN_EINVAL, "B < 0");
+    if (n_steps < 0) return fail(FN_EINVAL, "n_steps < 0");
+    if (!(sigma >= 0.0) || !isfinite(sigma)) return fail(FN_EINVAL, "sigma must be finite and >= 0");
+    if (B == 0 || n_steps == 0) return FN_OK;
+    if (!theta || !x || !log_abs_psi) return fail(FN_EINVAL, "theta, x or log_abs_psi is NULL");
+    if (((uintptr_t)theta) % 16) return fail(FN_EINVAL, "theta must be 16-byte aligned");
+    Plan p;
+    if ((r = make_plan(c, B, FN_OP_METROPOLIS, p))) return r;
+    if (p.total > NOALLOC_SCRATCH_BYTES)
+        return fail(FN_ENOMEM, "needs " + std::to_string(p.total) + " bytes of scratch; the fixed scratch holds " +
+                                   std::to_string(NOALLOC_SCRATCH_BYTES) + " (use vmc_metropolis_step with a workspace)");
+    void *ws = nullptr;
+    if ((r = scratch_for_current_device(&ws))) return r;
+    struct NoAlloc {
+        NoAlloc() { g_no_alloc_call = true; }
+        ~NoAlloc() { g_no_alloc_call = false; }
+    } no_alloc_;
+    hipStream_t st = (hipStream_t)stream;
+    return c.f64 ? run_metropolis<double>(c, p, theta, x, log_abs_psi, B, n_steps, sigma, seed, step0, stream_id,
+                                          nullptr, nullptr, n_accept, ws, st)
+                 : run_metropolis<float>(c, p, theta, x, log_abs_psi, B, n_steps, sigma, seed, step0, stream_id,
+                                         nullptr, nullptr, n_accept, ws, st);
 }
 
 fn_status vmc_metropolis_step_group(const fn_config *cfg, const void *theta, const fn_group_job *jobs, int32_t n_jobs,

@@ -56,6 +56,8 @@ def _load():
     lib.vmc_metropolis_step.argtypes = [vp, vp, vp, vp, i64, i32, ctypes.c_double, u64, u64, u32, vp, vp, sz, vp]
     lib.vmc_metropolis_step_ext.restype = i32
     lib.vmc_metropolis_step_ext.argtypes = [vp, vp, vp, vp, i64, i32, ctypes.c_double, vp, vp, vp, vp, sz, vp]
+    lib.vmc_metropolis_step_noalloc.restype = i32
+    lib.vmc_metropolis_step_noalloc.argtypes = [vp, vp, vp, vp, i64, i32, ctypes.c_double, u64, u64, u32, vp, vp]
     lib.vmc_metropolis_step_group.restype = i32
     lib.vmc_metropolis_step_group.argtypes = [vp, vp, vp, i32, vp, vp, vp, i64, i32, ctypes.c_double, vp, sz, vp]
     lib.fn_param_grad.restype = i32
@@ -89,7 +91,7 @@ LIB = _load()
 LIB_PATH = _LIB_PATH
 
 EXPORTED = ["fn_param_count", "fn_workspace_bytes", "fn_log_psi", "fn_local_energy", "vmc_metropolis_step",
-            "vmc_metropolis_step_ext", "vmc_metropolis_step_group", "fn_param_grad", "fn_pretrain_grad", "fn_log_psi_vjp", "fn_energy_stats", "fn_ionic_electron_counts",
+            "vmc_metropolis_step_ext", "vmc_metropolis_step_noalloc", "vmc_metropolis_step_group", "fn_param_grad", "fn_pretrain_grad", "fn_log_psi_vjp", "fn_energy_stats", "fn_ionic_electron_counts",
             "fn_init_walkers", "fn_last_error", "fn_timing_enable",
             "fn_timing_select", "fn_timing_reset", "fn_timing_read", "fn_tuning_set", "fn_server_job_bytes", "fn_server_create", "fn_server_submit",
             "fn_server_step", "fn_server_result", "fn_server_cancel", "fn_server_memory", "fn_server_destroy",
@@ -226,6 +228,21 @@ def vmc_metropolis_step(cfg: Config, theta: torch.Tensor, x: torch.Tensor, log_a
     else:
         _check(LIB.vmc_metropolis_step(cfg.ptr, theta.data_ptr(), x.data_ptr(), log_abs.data_ptr(), b, n_steps, sigma,
                                        seed, step0, stream_id, n_accept.data_ptr(), p, n, _stream(stream)))
+    return n_accept
+
+
+def vmc_metropolis_step_noalloc(cfg: Config, theta: torch.Tensor, x: torch.Tensor, log_abs: torch.Tensor,
+                                n_steps: int, sigma: float, seed: int, step0: int = 0, stream_id: int = 0,
+                                n_accept: Optional[torch.Tensor] = None, stream=None):
+    """As vmc_metropolis_step with the library's fixed scratch as workspace."""
+    b = x.shape[0]
+    _need(theta, cfg.param_dtype, (cfg.param_count(),), "theta")
+    _need(x, torch.float64, (b, cfg.n_elec, 3), "x")
+    _need(log_abs, torch.float64, (b,), "log_abs")
+    if n_accept is None:
+        n_accept = torch.zeros(b, dtype=torch.int32, device=x.device)
+    _check(LIB.vmc_metropolis_step_noalloc(cfg.ptr, theta.data_ptr(), x.data_ptr(), log_abs.data_ptr(), b, n_steps,
+                                           sigma, seed, step0, stream_id, n_accept.data_ptr(), _stream(stream)))
     return n_accept
 
 
