@@ -355,6 +355,15 @@ fn_status fn_timing_read(const char *name, double *total_ms, int64_t *launches);
    gradient, as matrix-core products (default 1) or on the vector ALUs; the
    two differ in summation order only.  Unknown names and out-of-range
    values return FN_EINVAL.
+   "layer_stack" 0/1/2: every one-electron layer of a forward-Laplacian
+   pass in one kernel that keeps a workgroup's walkers in LDS (two to four
+   electrons, w1 = 256): 0 never, 1 (default) in the one-pass BF16 mode,
+   2 in every split-BF16 mode.  "stack_shape" 0/1/2: that kernel's
+   workgroup shape (64 rows, two workgroups per CU; 64 rows with the next
+   step's weights prefetched; 128 rows prefetched); bitwise the same results.
+   "fp32_products" 0..7 (diagnostic): in the split-BF16 modes, run the
+   stream-layer (bit 0), mean-field (bit 1) and orbital-head (bit 2)
+   products on the FP32 matrix cores instead.
    "pair_oc" 0/1/2/4: output columns per thread of the vector pair kernel
    (0: chosen by N and w2).  "pair_items" 0..4096: (pair, column group)
    items per workgroup of the vector kernel, pair rows per workgroup of the

@@ -390,7 +390,27 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
                               sizeof(T) == sizeof(float) ? (const float *)(ws + p.wpair) : nullptr, GI, st);
     }
     bool g_ready = true;             // spin means of h^l already written (features, previous layer)
-    for (int l = 0; l < s.L; ++l) {
+    bool stacked = false;
+    if constexpr (std::is_same<T, float>::value) {
+        // every one-electron layer in one kernel (activations stay in LDS)
+        if (fl && !p.save && c.wmode == c.smode && stack_supported(c.smode, s.N, TR, s.w1, s.L)) {
+            StackArgs sa{};
+            sa.H0 = Hbuf(0); sa.ldh = ldh;
+            sa.GI = GI; sa.ldgi = ldg; sa.gi_stride = p.gi_layer_stride;
+            for (int l = 0; l < s.L; ++l) {
+                sa.Wx[l] = (const uint16_t *)(ws + p.wx[l]); sa.wxpart[l] = p.wxpart[l];
+                sa.Wg[l] = (const uint16_t *)(ws + p.wg[l]); sa.wgpart[l] = p.wgpart[l];
+                sa.HW[l] = c.W.HWl[l]; sa.GW[l] = c.W.GWl[l];
+                sa.bias[l] = theta + c.P.b[l];
+            }
+            sa.Hout = Hbuf(s.L);
+            sa.B = b; sa.L = s.L; sa.nu = s.nu; sa.n3 = n3;
+            Timed t_(K_STREAM_GEMM, st);
+            launch_stack(c.smode, sa, s.N, st);
+            stacked = true;
+        }
+    }
+    for (int l = 0; l < s.L && !stacked; ++l) {
         const int dh = layer_dh(s, l), HWl = c.W.HWl[l], GWl = c.W.GWl[l];
         T *Hin = Hbuf(l), *Hout = Hbuf(l + 1);
         if (!g_ready) { Timed t_(K_SPIN_MEAN, st); launch_spin_mean<T>(Hin, ldh, b, s.N, s.nu, TR, dh, HWl, G, st); }
@@ -1073,6 +1093,16 @@ fn_status fn_tuning_set(const char *name, int64_t value)
     if (strcmp(name, "pair_oc") == 0) {
         if (value != 0 && value != 1 && value != 2 && value != 4) return fail(FN_EINVAL, "pair_oc: 0, 1, 2 or 4");
         fn::g_pair_oc = (int)value;
+        return FN_OK;
+    }
+    if (strcmp(name, "layer_stack") == 0) {
+        if (value < 0 || value > 2) return fail(FN_EINVAL, "layer_stack: 0, 1 or 2");
+        fn::g_use_stack = (int)value;
+        return FN_OK;
+    }
+    if (strcmp(name, "stack_shape") == 0) {
+        if (value < 0 || value > 2) return fail(FN_EINVAL, "stack_shape: 0, 1 or 2");
+        fn::g_stack_shape = (int)value;
         return FN_OK;
     }
     if (strcmp(name, "fp32_products") == 0) {

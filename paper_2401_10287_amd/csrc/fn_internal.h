@@ -401,6 +401,23 @@ extern int g_pair_oc, g_pair_items;
 // FP32 pair layers on the matrix cores (false: vector kernel)
 extern bool g_pair_mfma;
 void launch_stream_layer(int mode, const LayerArgs &a, int TR, hipStream_t st);
+
+// Every one-electron layer of a forward-Laplacian pass in one kernel
+// (fn_stack.hip), for two to four electrons (TR = 16) and w1 = 256.
+struct StackArgs {
+    const float *H0; int64_t ldh;             // features of layer 0 (rows walker * N * 16 + e * 16 + t)
+    const float *GI; int64_t ldgi; int64_t gi_stride;   // pair means of every layer (layer stride in floats)
+    const uint16_t *Wx[FN_MAX_LAYERS], *Wg[FN_MAX_LAYERS];   // packed split-BF16 V_h / V_g per layer
+    int64_t wxpart[FN_MAX_LAYERS], wgpart[FN_MAX_LAYERS];
+    int HW[FN_MAX_LAYERS], GW[FN_MAX_LAYERS];  // padded widths of h and of [g_i_up | g_i_dn]
+    const float *bias[FN_MAX_LAYERS];
+    float *Hout;                               // h^L, live rows, leading dimension ldh
+    int64_t B; int L; int nu; int n3;
+};
+extern int g_use_stack;                        // tuning switch "layer_stack": 0 never, 1 one-pass BF16, 2 every split mode
+extern int g_stack_shape;                      // tuning switch "stack_shape": workgroup shape 0, 1, 2
+bool stack_supported(int mode, int N, int TR, int w1, int L);
+void launch_stack(int mode, const StackArgs &a, int N, hipStream_t st);
 // 128-row tiles of the fused layer hold whole walkers
 inline bool stream_layer_whole_walkers(int N, int TR) { return N * TR <= 128 && 128 % (N * TR) == 0; }
 

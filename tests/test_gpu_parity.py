@@ -573,3 +573,42 @@ def test_serving_types_local_energy_bf16x6():
         worst_e = max(worst_e, float(d.max()))
         worst_l = max(worst_l, float(np.abs(lp.cpu().numpy() - ref_l["log_abs"]).max()))
     print(f"serving types: worst |d log psi| {worst_l:.2e}, worst |d E_L| {worst_e:.2e} Ha")
+
+
+@pytest.mark.parametrize("name,walkers", [("LiH", 63), ("He", 61), ((3, 0), 37), ((4, 0), 9)])
+def test_layer_stack_kernel(name, walkers):
+    # switch value 2: the stacked kernel in the split modes too (by default
+    # only the one-pass BF16 mode takes it)
+    """Every one-electron layer in one kernel (activations kept in LDS,
+    mean-field product and spin means inside; two to four electrons): in
+    every workgroup shape (64 rows, with and without weight prefetch, and
+    128 rows) and against the layer-by-layer kernels, the local energy
+    within the oracle bounds; the shapes give bitwise the same results (each
+    walker's arithmetic is the same).  Ragged last workgroups: 61 He walkers in
+    workgroups of 2 or 4, 37 Li atoms, 9 Be atoms."""
+    s = SYSTEMS[name]() if isinstance(name, str) else I.atom_ion(*name, walkers=walkers)
+    x = T.equilibrated("LiH", walkers) if name == "LiH" else (
+        T.equilibrated(f"Z{name[0]}q+0", 6).repeat(-(-walkers // 6), axis=0)[:walkers] if not isinstance(name, str)
+        else I.init_walkers(s, walkers))
+    torch, fnvmc, cfg, tt, xt, th, x = _setup(s, "bf16x6", walkers, x=x)
+    o = O.Oracle(s)
+    ref_e = o.local_energy(th, x)
+    kap, C = T.kappa_and_c(o, s, th, x)
+    d32 = np.abs(_energies(fnvmc, torch, s, "fp32", tt, xt) - ref_e["e_loc"])
+    got = {}
+    try:
+        for stack, rows in ((2, 0), (2, 1), (2, 2), (0, 0)):
+            fnvmc.fn_tuning_set("layer_stack", stack)
+            fnvmc.fn_tuning_set("stack_shape", rows)
+            e, lp, parts = fnvmc.fn_local_energy(cfg, tt, xt)
+            torch.cuda.synchronize()
+            label = f"{name} B={walkers} stack={stack} shape={rows}"
+            T.check_energy(e.cpu().numpy(), ref_e, label, kap, C, s.n_elec, d32=d32, parts=parts.cpu().numpy(),
+                           mean_tol=1e-3 if name == "LiH" else None)
+            got[(stack, rows)] = (e.cpu().numpy(), lp.cpu().numpy())
+    finally:
+        fnvmc.fn_tuning_set("layer_stack", 1)
+        fnvmc.fn_tuning_set("stack_shape", 0)
+    for shape in (1, 2):
+        for a, b in zip(got[(2, 0)], got[(2, shape)]):
+            np.testing.assert_array_equal(a, b)
