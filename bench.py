@@ -69,7 +69,7 @@ def time_steps(fn, steps, torch):
 
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2401_10287_amd", "csrc", "fn_layer.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lih_stream_layer_hbm_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_layer_hbm_traffic.md")
 
 
 def copy_calibration():
