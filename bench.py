@@ -374,21 +374,30 @@ def main():
     if args.serving_jobs > 0:
         from paper_2401_10287_amd import serving
         torch.cuda.synchronize()
-        sat = serving.run_load(max(40, args.serving_jobs // 4), None, args.precision)
+        # saturation: the same number of jobs, all queued at t = 0; once with
+        # gangs of one system sharing the grouped Metropolis call, once with
+        # every job alone
+        sat = serving.run_load(args.serving_jobs, None, args.precision)
+        solo = serving.run_load(args.serving_jobs, None, args.precision, max_gang=1)
+        print(f"[bench] serving saturation: {sat['jobs_per_s']:.1f} jobs/s in gangs (mean "
+              f"{sat['mean_gang_jobs']:.2f} jobs), {solo['jobs_per_s']:.1f} jobs/s alone", file=sys.stderr, flush=True)
         runs = {}
         for frac in (0.5, 0.9):
             load = serving.run_load(args.serving_jobs, frac * sat["jobs_per_s"], args.precision,
                                     seed=17 + int(10 * frac))
-            print(f"[bench] serving: saturation {sat['jobs_per_s']:.1f} jobs/s; Poisson at {frac}x: "
-                  f"{load['jobs_per_s']:.1f} jobs/s, p50 {load['p50_ms']:.1f} ms p99 {load['p99_ms']:.1f} ms",
-                  file=sys.stderr, flush=True)
+            print(f"[bench] serving: Poisson at {frac}x: "
+                  f"{load['jobs_per_s']:.1f} jobs/s, p50 {load['p50_ms']:.1f} ms p99 {load['p99_ms']:.1f} ms, "
+                  f"mean gang {load['mean_gang_jobs']:.2f} jobs", file=sys.stderr, flush=True)
             runs[f"{frac}x"] = {"jobs": load["jobs"], "arrival_rate_jobs_per_s": load["rate"],
                                 "jobs_per_s": load["jobs_per_s"], "p50_latency_ms": load["p50_ms"],
-                                "p99_latency_ms": load["p99_ms"], "failed": load["failed"]}
+                                "p99_latency_ms": load["p99_ms"], "failed": load["failed"],
+                                "mean_gang_jobs": load["mean_gang_jobs"]}
         line["config"]["serving"] = {
             "workload": "Poisson stream of VMC jobs, atoms and ions Z 2..10, charge -1..+2, walker batches "
                         "256/1024/4096, 50 Metropolis steps + energy estimate each, 4 layers 256/32, 16 dets",
-            "saturation_jobs_per_s": sat["jobs_per_s"], "poisson": runs}
+            "saturation_jobs_per_s": sat["jobs_per_s"], "saturation_mean_gang_jobs": sat["mean_gang_jobs"],
+            "saturation_alone_jobs_per_s": solo["jobs_per_s"], "max_gang": sat["max_gang"],
+            "gang_walkers": sat["gang_walkers"], "poisson": runs}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = {"value": samp / t_orc, "unit": "evals/s", "cores": O.num_threads(), "kind": "oracle",
                                 "cpu_model": cpu_model(),

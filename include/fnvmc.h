@@ -262,20 +262,29 @@ const char *fn_last_error(void);
    counter 0..n_steps-1, its own seed and stream_id) and then the batch
    mean, variance (1/B) and standard error of the local energy (Eq. 1, 2)
    plus the acceptance rate.
+   Jobs of one system (identical configuration and nuclei, the same theta
+   pointer, step size and step count) are admitted together as a gang: the
+   first queued job of a gang takes later queued jobs of its system, in queue
+   order, up to max_gang jobs and gang_walkers walkers in total.  A gang's
+   walkers, log|psi|, counters, energies and one shared workspace sit in one
+   block of the arena, and each quantum of its Metropolis steps is one
+   vmc_metropolis_step_group call over all its jobs on the gang's stream.
    The server allocates no memory on the device or pinned on the host: every
-   admitted job's walkers, log|psi| and workspace live in the caller's
-   device arena, whose size is the HBM budget, and results land in the
-   caller's pinned host buffer.  fn_server_step() retires finished jobs
-   (stream queries: each stream runs one job at a time and must carry no
-   other work), admits queued jobs in arrival order while their footprint
-   (fn_server_job_bytes) fits the free arena and a stream is free -- a job
-   that does not fit is passed by later jobs that do, at most 2 n_streams
-   times, after which admission waits until it fits -- and enqueues the next
-   quantum of Metropolis steps of every running job on that job's stream, so
-   the work of different jobs overlaps on the device.  A job's results do
-   not depend on the other jobs.  theta and x0 of a job are read until it is
-   done and must stay valid until then.  Not safe against concurrent calls on
-   the same server from several threads.
+   admitted gang's block lives in the caller's device arena, whose size is
+   the HBM budget, and results land in the caller's pinned host buffer.
+   fn_server_step() retires finished gangs (stream queries: each stream runs
+   one gang at a time and must carry no other work), admits gangs in the
+   arrival order of their first job while the block fits the free arena and
+   a stream is free -- a job that does not fit even alone is passed by later
+   jobs that do, at most 2 n_streams times, after which admission waits until
+   it fits -- and enqueues the next quantum of every running gang on its
+   stream, so the work of different gangs overlaps on the device.  A job's
+   results do not depend on the other jobs: every call takes the kernel path
+   that is the same at every batch size (no split-reduction products), and a
+   job's log|psi| and energy estimate are computed over its own walkers.
+   theta and x0 of a job are read until it is done and must stay valid until
+   then.  Not safe against concurrent calls on the same server from several
+   threads.
    ------------------------------------------------------------------------ */
 typedef struct fn_server fn_server;
 
@@ -284,19 +293,27 @@ typedef struct {
                                4 cancelled                                   */
     double mean, variance, std_error, acceptance;
     double submit_s, admit_s, done_s;   /* host steady clock, seconds        */
-    int64_t footprint_bytes;
+    int64_t footprint_bytes;            /* arena bytes of the job alone      */
+    int32_t gang_jobs;                  /* jobs in the gang it ran in, 0 if
+                                           never admitted                    */
 } fn_job_result;
 
-/* Arena bytes one job of B walkers needs; 0 if cfg or B is invalid. */
+/* Arena bytes one job of B walkers needs alone (a gang of one); 0 if cfg or
+   B is invalid.  A gang needs less than the sum of its jobs' footprints: its
+   jobs share one workspace. */
 size_t fn_server_job_bytes(const fn_config *cfg, int64_t B);
 
 /* arena: device, 256-byte aligned, arena_bytes long.  streams: host array of
-   n_streams hipStream_t (one running job per stream).  quantum_steps:
-   Metropolis steps enqueued per job per fn_server_step.  host_results:
-   pinned host memory (hipHostMalloc), [n_streams][4] doubles, owned by the
-   caller and valid until fn_server_destroy. */
+   n_streams hipStream_t (one running gang per stream).  quantum_steps:
+   Metropolis steps enqueued per gang per fn_server_step.  max_gang: jobs per
+   gang, 1..FN_MAX_GROUP_JOBS (1: every job runs alone).  gang_walkers: the
+   most walkers a gang of several jobs may hold (a job larger than that runs
+   alone).  host_results: pinned host memory (hipHostMalloc),
+   [n_streams][max_gang][4] doubles, owned by the caller and valid until
+   fn_server_destroy. */
 fn_status fn_server_create(void *arena, size_t arena_bytes, void *const *streams, int32_t n_streams,
-                           int32_t quantum_steps, double *host_results, fn_server **out);
+                           int32_t quantum_steps, int32_t max_gang, int64_t gang_walkers, double *host_results,
+                           fn_server **out);
 /* Queue a job; FN_ENOMEM if it could never fit the arena.  theta: device
    parameters (cfg's precision), x0: device [B][N][3] initial walkers. */
 fn_status fn_server_submit(fn_server *srv, const fn_config *cfg, const void *theta, const double *x0, int64_t B,
@@ -304,9 +321,11 @@ fn_status fn_server_submit(fn_server *srv, const fn_config *cfg, const void *the
 /* One scheduler step (non-blocking). */
 fn_status fn_server_step(fn_server *srv, int32_t *n_active, int32_t *n_queued);
 fn_status fn_server_result(fn_server *srv, int64_t job, fn_job_result *out);
-/* Cancel a job: a queued job leaves the queue; a running job's enqueued
-   quantum is waited for, then its stream and arena block are freed.  Its
-   state becomes 4.  Done, failed or cancelled jobs are left as they are. */
+/* Cancel a job: a queued job leaves the queue; a running job stops being
+   reported (state 4) while the rest of its gang runs on; once every job of a
+   gang is cancelled, its enqueued work is waited for and its stream and
+   arena block are freed.  Done, failed or cancelled jobs are left as they
+   are. */
 fn_status fn_server_cancel(fn_server *srv, int64_t job);
 /* Free and total arena bytes. */
 fn_status fn_server_memory(fn_server *srv, size_t *free_bytes, size_t *arena_bytes);

@@ -989,8 +989,9 @@ fn_status vmc_metropolis_step_group(const fn_config *cfg, const void *theta, con
     if ((r = make_plan(c, B_total, FN_OP_METROPOLIS, p))) return r;
     if ((r = check_ws(p, ws, ws_bytes))) return r;
     struct Suppress {
+        bool prev = g_splitk_suppressed;
         Suppress() { g_splitk_suppressed = true; }
-        ~Suppress() { g_splitk_suppressed = false; }
+        ~Suppress() { g_splitk_suppressed = prev; }
     } suppress_;
     hipStream_t st = (hipStream_t)stream;
     return c.f64 ? run_metropolis_group<double>(c, p, theta, x, log_abs_psi, B_total, n_steps, sigma, jobs, n_jobs,

@@ -28,7 +28,8 @@ from . import inputs as I
 class _JobResult(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int32), ("mean", ctypes.c_double), ("variance", ctypes.c_double),
                 ("std_error", ctypes.c_double), ("acceptance", ctypes.c_double), ("submit_s", ctypes.c_double),
-                ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double), ("footprint_bytes", ctypes.c_int64)]
+                ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double), ("footprint_bytes", ctypes.c_int64),
+                ("gang_jobs", ctypes.c_int32)]
 
 
 _L = fnvmc.LIB
@@ -36,7 +37,7 @@ _vp, _i32, _i64, _u64, _u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, c
 _L.fn_server_job_bytes.restype = ctypes.c_size_t
 _L.fn_server_job_bytes.argtypes = [_vp, _i64]
 _L.fn_server_create.restype = _i32
-_L.fn_server_create.argtypes = [_vp, ctypes.c_size_t, _vp, _i32, _i32, _vp, ctypes.POINTER(_vp)]
+_L.fn_server_create.argtypes = [_vp, ctypes.c_size_t, _vp, _i32, _i32, _i32, _i64, _vp, ctypes.POINTER(_vp)]
 _L.fn_server_cancel.restype = _i32
 _L.fn_server_cancel.argtypes = [_vp, _i64]
 _L.fn_server_memory.restype = _i32
@@ -65,9 +66,12 @@ def job_bytes(cfg: fnvmc.Config, walkers: int) -> int:
 
 
 class Server:
-    """fn_server over a device arena of `arena_bytes` and `n_streams` streams."""
+    """fn_server over a device arena of `arena_bytes` and `n_streams` streams;
+    jobs of one system are admitted in gangs of up to `max_gang` jobs and
+    `gang_walkers` walkers (max_gang=1: every job alone)."""
 
-    def __init__(self, arena_bytes: int, n_streams: int = 8, quantum: int = 5, device: str = "cuda:0"):
+    def __init__(self, arena_bytes: int, n_streams: int = 8, quantum: int = 5, max_gang: int = 16,
+                 gang_walkers: int = 4096, device: str = "cuda:0"):
         self.device = torch.device(device)
         self.arena = torch.empty(arena_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.arena.data_ptr()
@@ -75,10 +79,10 @@ class Server:
         self.streams = [torch.cuda.Stream(self.device) for _ in range(n_streams)]
         arr = (_vp * n_streams)(*[s.cuda_stream for s in self.streams])
         # pinned host buffer the per-job results are copied into (caller-owned)
-        self.host_results = torch.zeros((n_streams, 4), dtype=torch.float64, pin_memory=True)
+        self.host_results = torch.zeros((n_streams, max_gang, 4), dtype=torch.float64, pin_memory=True)
         h = _vp()
-        _check(_L.fn_server_create(self.base, arena_bytes, arr, n_streams, quantum, self.host_results.data_ptr(),
-                                   ctypes.byref(h)))
+        _check(_L.fn_server_create(self.base, arena_bytes, arr, n_streams, quantum, max_gang, gang_walkers,
+                                   self.host_results.data_ptr(), ctypes.byref(h)))
         self.h = h
         self._keep: Dict[int, tuple] = {}
 
@@ -173,7 +177,7 @@ class JobFactory:
 
 def run_load(n_jobs: int, rate: Optional[float], precision: str = "bf16x6", arena_gb: float = 64.0,
              n_streams: int = 8, quantum: int = 5, n_steps: int = 50, sigma: float = 0.2, seed: int = 2024,
-             sizes=(256, 1024, 4096)) -> dict:
+             sizes=(256, 1024, 4096), max_gang: int = 16, gang_walkers: int = 4096) -> dict:
     """Poisson arrivals at `rate` jobs/s (None: all jobs arrive at t = 0, the
     saturation throughput).  Returns latency percentiles and throughput."""
     fac = JobFactory(precision, seed, sizes=sizes)
@@ -181,7 +185,7 @@ def run_load(n_jobs: int, rate: Optional[float], precision: str = "bf16x6", aren
     torch.cuda.synchronize()
     rng = np.random.default_rng(seed + 1)
     arrivals = np.zeros(n_jobs) if rate is None else np.cumsum(rng.exponential(1.0 / rate, n_jobs))
-    srv = Server(int(arena_gb * (1 << 30)), n_streams, quantum)
+    srv = Server(int(arena_gb * (1 << 30)), n_streams, quantum, max_gang, gang_walkers)
     ids: List[int] = []
     t0 = time.perf_counter()
     nxt = 0
@@ -205,7 +209,8 @@ def run_load(n_jobs: int, rate: Optional[float], precision: str = "bf16x6", aren
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_ms": float(lat.mean() * 1e3), "failed": int(failed), "precision": precision,
             "walker_sizes": list(sizes), "n_streams": n_streams, "quantum": quantum, "arena_gb": arena_gb,
-            "results": res}
+            "max_gang": max_gang, "gang_walkers": gang_walkers,
+            "mean_gang_jobs": float(np.mean([r["gang_jobs"] for r in res])), "results": res}
 
 
 def main():
@@ -215,11 +220,14 @@ def main():
     ap.add_argument("--streams", type=int, default=8)
     ap.add_argument("--quantum", type=int, default=5)
     ap.add_argument("--arena-gb", type=float, default=64.0)
+    ap.add_argument("--max-gang", type=int, default=16)
     args = ap.parse_args()
-    sat = run_load(min(args.jobs, 200), None, args.precision, args.arena_gb, args.streams, args.quantum)
+    sat = run_load(args.jobs, None, args.precision, args.arena_gb, args.streams, args.quantum,
+                   max_gang=args.max_gang)
     out = {"saturation_jobs_per_s": sat["jobs_per_s"]}
     for frac in (0.5, 0.9):
-        r = run_load(args.jobs, frac * sat["jobs_per_s"], args.precision, args.arena_gb, args.streams, args.quantum)
+        r = run_load(args.jobs, frac * sat["jobs_per_s"], args.precision, args.arena_gb, args.streams, args.quantum,
+                     max_gang=args.max_gang)
         r.pop("results")
         out[f"load_{frac}"] = r
         print(f"[serving] load {frac}: {r['jobs_per_s']:.2f} jobs/s p50 {r['p50_ms']:.1f} ms p99 {r['p99_ms']:.1f} ms",

@@ -129,3 +129,21 @@ def test_group_call_rejects_bad_job_tables():
     assert call([(0, 0, 1, 0, 0)], 0) == fnvmc.FN_EINVAL                            # empty job
     assert call([(q, 1, 1, 0, 0) for q in range(65)], 65) == fnvmc.FN_EINVAL        # too many
     assert b"job" in fnvmc.LIB.fn_last_error() or b"B_total" in fnvmc.LIB.fn_last_error()
+
+
+def test_server_create_checks_gang_limits():
+    """fn_server_create validates its gang limits on the host (no device
+    work: the arena and stream are never touched without jobs)."""
+    import ctypes
+    import numpy as np
+    from paper_2401_10287_amd import serving  # noqa: F401  (declares the server signatures)
+    fnvmc = _fnvmc()
+    L = fnvmc.LIB
+    res = np.zeros(64 * 4 * 2)
+    streams = (ctypes.c_void_p * 2)(None, None)
+    h = ctypes.c_void_p()
+    for max_gang, walkers in ((0, 4096), (65, 4096), (4, 0)):
+        st = L.fn_server_create(1 << 20, 1 << 20, streams, 2, 5, max_gang, walkers, res.ctypes.data, ctypes.byref(h))
+        assert st == fnvmc.FN_EINVAL, (max_gang, walkers)
+    assert L.fn_server_create(1 << 20, 1 << 20, streams, 2, 5, 64, 4096, res.ctypes.data, ctypes.byref(h)) == 0
+    assert L.fn_server_destroy(h) == 0

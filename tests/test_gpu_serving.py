@@ -1,6 +1,6 @@
-"""Continuous batching (fn_server_*): results alone and in a mix are the
-same, admission follows the HBM footprint, and a served job equals the
-oracle's Metropolis chain and energy estimate."""
+"""Continuous batching (fn_server_*): results alone, in a gang of jobs of the
+same system and in a mix are the same, admission follows the HBM footprint,
+and a served job equals the oracle's Metropolis chain and energy estimate."""
 import numpy as np
 import pytest
 
@@ -45,11 +45,16 @@ def test_alone_equals_mix_and_plain_api():
     assert all(o["state"] == "done" for o in others)
     for key in ("mean", "variance", "std_error", "acceptance"):
         assert alone[key] == mix[key], key
-    # the same job through the plain entry points
+    # the same job through the plain entry points, on the kernel path the
+    # server takes at every batch size (no split-reduction products)
     x = x0.clone()
-    lp, _ = fnvmc.fn_log_psi(cfg, th, x)
-    acc = fnvmc.vmc_metropolis_step(cfg, th, x, lp, 50, 0.2, seed=1, step0=0, stream_id=target)
-    e, _, _ = fnvmc.fn_local_energy(cfg, th, x)
+    fnvmc.fn_tuning_set("gemm_splitk", 0)
+    try:
+        lp, _ = fnvmc.fn_log_psi(cfg, th, x)
+        acc = fnvmc.vmc_metropolis_step(cfg, th, x, lp, 50, 0.2, seed=1, step0=0, stream_id=target)
+        e, _, _ = fnvmc.fn_local_energy(cfg, th, x)
+    finally:
+        fnvmc.fn_tuning_set("gemm_splitk", 1)
     en = e.cpu().numpy()
     assert abs(en.mean() - alone["mean"]) <= 1e-12 * max(1.0, abs(en.mean()))
     assert acc.sum().item() / (x.shape[0] * 50) == pytest.approx(alone["acceptance"], abs=1e-15)
@@ -60,7 +65,7 @@ def test_admission_by_footprint():
     fac = serving.JobFactory("fp32", seed=7, sizes=(1024,))
     jobs = [fac.job(k) for k in range(3)]
     need = max(serving.job_bytes(c, x.shape[0]) for c, _, x, _ in jobs)
-    srv = serving.Server(need + 4096, n_streams=4, quantum=10)
+    srv = serving.Server(need + 4096, n_streams=4, quantum=10, max_gang=1)
     ids = [srv.submit(c, t, x, 20, 0.2, seed=1, stream_id=k) for k, (c, t, x, _) in enumerate(jobs)]
     active, queued = srv.step()
     assert active == 1 and queued == 2
@@ -123,9 +128,13 @@ def test_served_job_mixed_precision_matches_oracle():
     r = srv.result(j)
     srv.close()
     xg = xt.clone()
-    lp, _ = fnvmc.fn_log_psi(cfg, tt, xg)
-    acc = fnvmc.vmc_metropolis_step(cfg, tt, xg, lp, 20, 0.2, seed=3, step0=0, stream_id=12)
-    e, _, _ = fnvmc.fn_local_energy(cfg, tt, xg)
+    fnvmc.fn_tuning_set("gemm_splitk", 0)        # the server's batch-size-independent kernel path
+    try:
+        lp, _ = fnvmc.fn_log_psi(cfg, tt, xg)
+        acc = fnvmc.vmc_metropolis_step(cfg, tt, xg, lp, 20, 0.2, seed=3, step0=0, stream_id=12)
+        e, _, _ = fnvmc.fn_local_energy(cfg, tt, xg)
+    finally:
+        fnvmc.fn_tuning_set("gemm_splitk", 1)
     en = e.cpu().numpy()
     assert r["state"] == "done"
     assert r["mean"] == en.mean() or abs(r["mean"] - en.mean()) <= 1e-15 * abs(en.mean())
@@ -153,7 +162,7 @@ def test_cancel_frees_slot_and_memory():
     fac = serving.JobFactory("bf16x6", seed=11, sizes=(1024,))
     jobs = [fac.job(k) for k in range(3)]
     need = max(serving.job_bytes(c, x.shape[0]) for c, _, x, _ in jobs)
-    srv = serving.Server(2 * need + 4096, n_streams=2, quantum=5)
+    srv = serving.Server(2 * need + 4096, n_streams=2, quantum=5, max_gang=1)
     ids = [srv.submit(c, t, x, 40, 0.2, seed=1, stream_id=k) for k, (c, t, x, _) in enumerate(jobs)]
     active, queued = srv.step()
     assert active == 2 and queued == 1
@@ -170,7 +179,7 @@ def test_cancel_frees_slot_and_memory():
     assert [r["state"] for r in res] == ["cancelled", "done", "done"]
     assert srv.memory()[0] == total
     # a queued job cancelled before it runs
-    srv2 = serving.Server(need + 4096, n_streams=1, quantum=5)
+    srv2 = serving.Server(need + 4096, n_streams=1, quantum=5, max_gang=1)
     a = srv2.submit(*jobs[1][:3], 40, 0.2, seed=1, stream_id=1)
     b = srv2.submit(*jobs[2][:3], 40, 0.2, seed=1, stream_id=2)
     srv2.step()
@@ -192,7 +201,7 @@ def test_small_jobs_pass_a_job_that_does_not_fit():
     small = [serving.JobFactory("bf16x6", seed=13 + k, sizes=(256,)).job(k) for k in range(3)]
     nb = serving.job_bytes(big[0], 4096)
     ns = max(serving.job_bytes(c, x.shape[0]) for c, _, x, _ in small)
-    srv = serving.Server(nb + ns + 8192, n_streams=4, quantum=5)
+    srv = serving.Server(nb + ns + 8192, n_streams=4, quantum=5, max_gang=1)
     first = srv.submit(*big[:3], 30, 0.2, seed=1, stream_id=0)          # fills most of the arena
     srv.step()
     head = srv.submit(*big[:3], 30, 0.2, seed=1, stream_id=1)           # cannot fit while the first runs
@@ -205,3 +214,85 @@ def test_small_jobs_pass_a_job_that_does_not_fit():
     srv.close()
     assert all(r["state"] == "done" for r in res)
     assert res[2]["admit_s"] < res[1]["admit_s"]
+
+
+def _same_system_jobs(serving, fnvmc, torch, z, q, sizes, precision="bf16x6", seed=21):
+    fac = serving.JobFactory(precision, seed=seed)
+    cfg, th = fac.system(z, q)
+    return [(cfg, th, torch.tensor(I.init_walkers(cfg.system, b, seed=I.WALKER_SEED + 500 + k), device="cuda"))
+            for k, b in enumerate(sizes)]
+
+
+def test_gangs_equal_jobs_alone():
+    """Jobs of one system queued together run as one gang through the
+    grouped Metropolis call; every job's results equal those it gets alone,
+    bit for bit, and the gang respects max_gang and gang_walkers."""
+    torch, fnvmc, serving = _mods()
+    sizes = (256, 1024, 256, 512, 256, 2048)
+    jobs = _same_system_jobs(serving, fnvmc, torch, 7, 0, sizes)
+    other = serving.JobFactory("bf16x6", seed=22).system(5, -1)
+    xo = torch.tensor(I.init_walkers(other[0].system, 256, seed=9), device="cuda")
+    srv = serving.Server(8 << 30, n_streams=1, quantum=5, max_gang=1)
+    alone = []
+    for k, (c, t, x) in enumerate(jobs):
+        j = srv.submit(c, t, x, 20, 0.2, seed=1, stream_id=100 + k)
+        srv.drain([j])
+        alone.append(srv.result(j))
+    srv.close()
+    assert all(r["state"] == "done" and r["gang_jobs"] == 1 for r in alone)
+    srv = serving.Server(16 << 30, n_streams=2, quantum=5, max_gang=4, gang_walkers=2048)
+    ids = []
+    for k, (c, t, x) in enumerate(jobs):
+        ids.append(srv.submit(c, t, x, 20, 0.2, seed=1, stream_id=100 + k))
+        if k == 2:
+            ids.append(srv.submit(other[0], other[1], xo, 20, 0.2, seed=1, stream_id=99))
+    srv.drain(ids)
+    res = [srv.result(j) for j in ids]
+    srv.close()
+    oth = res.pop(3)
+    assert oth["state"] == "done" and oth["gang_jobs"] == 1      # another system never joins
+    gangs = [r["gang_jobs"] for r in res]
+    print("gang sizes", gangs)
+    assert max(gangs) > 1 and max(gangs) <= 4
+    # the first four jobs (256 + 1024 + 256 + 512 = 2048 walkers) form one gang
+    assert gangs[:4] == [4, 4, 4, 4]
+    for a, b in zip(alone, res):
+        assert b["state"] == "done"
+        for key in ("mean", "variance", "std_error", "acceptance"):
+            assert a[key] == b[key], key
+
+
+def test_cancel_inside_a_gang():
+    """Cancelling one job of a running gang leaves the others running with
+    their own results; cancelling every job frees the gang's block."""
+    torch, fnvmc, serving = _mods()
+    jobs = _same_system_jobs(serving, fnvmc, torch, 8, 1, (256, 256, 256), seed=23)
+    srv = serving.Server(8 << 30, n_streams=1, quantum=5, max_gang=1)
+    ref = []
+    for k, (c, t, x) in enumerate(jobs):
+        j = srv.submit(c, t, x, 30, 0.2, seed=1, stream_id=k)
+        srv.drain([j])
+        ref.append(srv.result(j))
+    srv.close()
+    srv = serving.Server(8 << 30, n_streams=1, quantum=5, max_gang=8)
+    ids = [srv.submit(c, t, x, 30, 0.2, seed=1, stream_id=k) for k, (c, t, x) in enumerate(jobs)]
+    active, queued = srv.step()
+    assert active == 3 and queued == 0
+    srv.cancel(ids[1])
+    assert srv.result(ids[1])["state"] == "cancelled"
+    srv.drain([ids[0], ids[2]])
+    res = [srv.result(j) for j in ids]
+    assert [r["state"] for r in res] == ["done", "cancelled", "done"]
+    for k in (0, 2):
+        assert res[k]["mean"] == ref[k]["mean"] and res[k]["acceptance"] == ref[k]["acceptance"]
+    free, total = srv.memory()
+    assert free == total
+    ids = [srv.submit(c, t, x, 30, 0.2, seed=1, stream_id=k) for k, (c, t, x) in enumerate(jobs)]
+    srv.step()
+    assert srv.memory()[0] < total
+    for j in ids:
+        srv.cancel(j)
+    assert srv.memory()[0] == total
+    assert all(srv.result(j)["state"] == "cancelled" for j in ids)
+    assert srv.step() == (0, 0)
+    srv.close()
