@@ -32,7 +32,9 @@
  * Network reading used where the paper is silent (tanh activations,
  * residuals when in-width equals out-width, L one-electron layers and L-1
  * two-electron layers, mean-field inputs [h_i, g_up, g_dn, g_i_up, g_i_dn],
- * anisotropic envelope exp(-|Sigma (r_j - R_m)|), psi = sum_k det A_k_up *
+ * anisotropic envelope exp(-|Sigma (r_j - R_m)|) with a 3x3 Sigma per
+ * orbital and nucleus, or the isotropic special case Sigma = sigma I with
+ * one scalar sigma per orbital and nucleus, psi = sum_k det A_k_up *
  * det A_k_dn, self pairs included with |r_ii| := 0).
  *
  * Parameter layout (flat, FP64 here):
@@ -42,6 +44,7 @@
  *   for spin s = up, dn with n_s > 0:
  *                    w_s [w1][K n_s] (column k n_s + i), g_s [K n_s],
  *                    pi_s [K n_s][M], Sig_s [K n_s][M][3][3]
+ *                    (isotropic envelope: sigma_s [K n_s][M])
  *   with d_h = 4M, d_p = 4 at layer 0 and d_h = w1, d_p = w2 after,
  *   d_in = 3 d_h + 2 d_p.
  */
@@ -93,6 +96,7 @@ typedef struct {
     const double *nuc_xyz; /* [M][3] */
     const double *nuc_z;   /* [M]    */
     int32_t n_up, n_dn, n_layers, w1, w2, n_det;
+    int32_t envelope;      /* 0: Sigma 3x3 per orbital and nucleus; 1: Sigma = sigma I */
 } orc_cfg;
 
 typedef struct {
@@ -123,7 +127,7 @@ static void make_layout(const orc_cfg *c, orc_layout *L)
         L->w[s] = o; o += (int64_t)c->w1 * kn;
         L->g[s] = o; o += kn;
         L->pi[s] = o; o += (int64_t)kn * c->n_nuc;
-        L->sig[s] = o; o += (int64_t)kn * c->n_nuc * 9;
+        L->sig[s] = o; o += (int64_t)kn * c->n_nuc * (c->envelope ? 1 : 9);
     }
     L->total = o;
 }
@@ -347,11 +351,16 @@ static void eval_walker(const orc_cfg *c, const orc_layout *Ly, const double *th
                     for (int m = 0; m < M; ++m) {
                         hd dv[3];
                         for (int q = 0; q < 3; ++q) dv[q] = hsub(x[3 * j + q], hconst(c->nuc_xyz[3 * m + q]));
-                        hd sd[3];
-                        for (int p = 0; p < 3; ++p) {
-                            int64_t base = Ly->sig[s] + (((int64_t)col * M + m) * 9) + 3 * p;
-                            sd[p] = hadd(hadd(hmul(P(th, dir, base + 0), dv[0]), hmul(P(th, dir, base + 1), dv[1])),
-                                         hmul(P(th, dir, base + 2), dv[2]));
+                        hd sd[3];   /* Sigma (r_j - R_m) */
+                        if (c->envelope) {
+                            const hd sg = P(th, dir, Ly->sig[s] + (int64_t)col * M + m);
+                            for (int p = 0; p < 3; ++p) sd[p] = hmul(sg, dv[p]);
+                        } else {
+                            for (int p = 0; p < 3; ++p) {
+                                int64_t base = Ly->sig[s] + (((int64_t)col * M + m) * 9) + 3 * p;
+                                sd[p] = hadd(hadd(hmul(P(th, dir, base + 0), dv[0]), hmul(P(th, dir, base + 1), dv[1])),
+                                             hmul(P(th, dir, base + 2), dv[2]));
+                            }
                         }
                         hd q = hnorm3(sd[0], sd[1], sd[2]);
                         env = hadd(env, hmul(P(th, dir, Ly->pi[s] + (int64_t)col * M + m), hexp(hscale(q, -1.0))));

@@ -31,7 +31,8 @@ def build(force: bool = True) -> str:
 class _Cfg(ctypes.Structure):
     _fields_ = [("n_nuc", ctypes.c_int32), ("nuc_xyz", ctypes.c_void_p), ("nuc_z", ctypes.c_void_p),
                 ("n_up", ctypes.c_int32), ("n_dn", ctypes.c_int32), ("n_layers", ctypes.c_int32),
-                ("w1", ctypes.c_int32), ("w2", ctypes.c_int32), ("n_det", ctypes.c_int32)]
+                ("w1", ctypes.c_int32), ("w2", ctypes.c_int32), ("n_det", ctypes.c_int32),
+                ("envelope", ctypes.c_int32)]
 
 
 _lib = None
@@ -78,7 +79,7 @@ class Oracle:
         self._xyz = _f64(system.nuc_xyz).reshape(-1)
         self._z = _f64(system.nuc_z)
         self.cfg = _Cfg(system.n_nuc, self._xyz.ctypes.data, self._z.ctypes.data, system.n_up, system.n_dn,
-                        system.n_layers, system.w1, system.w2, system.n_det)
+                        system.n_layers, system.w1, system.w2, system.n_det, int(system.envelope))
         self._cp = ctypes.byref(self.cfg)
         self.n = system.n_elec
 

@@ -12,9 +12,10 @@ Parameter layout (flat vector, one entry per scalar parameter):
   for l in 0..L-2 : W2_l [d_p][w2], c2_l [w2]
   for spin in (up, dn) with n_spin > 0:
                     w [w1][K n] (column k n + i), g [K n], pi [K n][M], Sigma [K n][M][3][3]
+                    (isotropic envelope: sigma [K n][M] in place of Sigma)
 with d_h = 4M, d_p = 4 at layer 0 and d_h = w1, d_p = w2 afterwards, d_in = 3 d_h + 2 d_p.
 Every matrix and bias is drawn N(0, 1/fan_in) with fan_in the matrix's input
-width; envelope weights pi start at 1 and Sigma at the identity.
+width; envelope weights pi start at 1 and Sigma at the identity (sigma at 1).
 """
 from __future__ import annotations
 
@@ -43,6 +44,10 @@ class System:
     # nucleus index of each electron slot, in electron order (up first)
     electron_site: Tuple[int, ...] = ()
     init_scale: float = 1.0
+    # 0: anisotropic envelope, a 3x3 Sigma per orbital and nucleus (Eq. 4);
+    # 1: its isotropic special case Sigma = sigma I, one scalar per orbital
+    # and nucleus
+    envelope: int = 0
 
     @property
     def n_nuc(self) -> int:
@@ -70,6 +75,11 @@ def _sites_from_counts(counts: Sequence[int], n_up: int, n_dn: int) -> Tuple[int
         extra = len(even) - n_up
         even, odd = even[: len(even) - extra], odd + even[len(even) - extra:]
     return tuple(even) + tuple(odd)
+
+
+def isotropic(s: System) -> System:
+    """The same system with the isotropic envelope Sigma = sigma I."""
+    return dataclasses.replace(s, envelope=1)
 
 
 def he(walkers: int = 256) -> System:
@@ -152,7 +162,7 @@ def param_tensors(s: System) -> List[Tuple[str, Tuple[int, ...], int]]:
         out.append((f"w_{tag}", (s.w1, kn), s.w1))
         out.append((f"g_{tag}", (kn,), s.w1))
         out.append((f"pi_{tag}", (kn, s.n_nuc), 0))
-        out.append((f"sig_{tag}", (kn, s.n_nuc, 3, 3), 0))
+        out.append((f"sig_{tag}", (kn, s.n_nuc) if s.envelope else (kn, s.n_nuc, 3, 3), 0))
     return out
 
 
@@ -178,7 +188,7 @@ def init_params(s: System, seed: int = THETA_SEED) -> np.ndarray:
         if name.startswith("pi_"):
             parts.append(np.ones(shape))
         elif name.startswith("sig_"):
-            parts.append(np.broadcast_to(np.eye(3), shape).copy())
+            parts.append(np.ones(shape) if s.envelope else np.broadcast_to(np.eye(3), shape).copy())
         else:
             parts.append(rng.standard_normal(shape) / np.sqrt(fan_in))
     return np.concatenate([p.reshape(-1) for p in parts]).astype(np.float64)

@@ -15,9 +15,9 @@ from paper_2401_10287_amd import inputs as I
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def small(n_up, n_dn, nuc_xyz, nuc_z, L=2, w1=6, w2=4, K=2, scale=1.0):
+def small(n_up, n_dn, nuc_xyz, nuc_z, L=2, w1=6, w2=4, K=2, scale=1.0, envelope=0):
     s = I.System("t", np.asarray(nuc_xyz, float).reshape(-1, 3), np.asarray(nuc_z, float), n_up, n_dn, L, w1, w2, K,
-                 8, tuple([0] * (n_up + n_dn)), scale)
+                 8, tuple([0] * (n_up + n_dn)), scale, envelope)
     return s
 
 
@@ -28,7 +28,7 @@ def zero_theta(s):
         if name.startswith("pi_"):
             t[...] = 1.0
         if name.startswith("sig_"):
-            t[...] = np.eye(3)
+            t[...] = 1.0 if s.envelope else np.eye(3)
     return th, v
 
 
@@ -712,3 +712,94 @@ def test_pretrain_loss_derivative_matches_finite_differences():
         h = 1e-6
         fd = (o.pretrain_loss(th + h * d, x, T) - o.pretrain_loss(th - h * d, x, T)) / (2 * h)
         assert dl == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+# --------------------------------------------------------------------------
+# the isotropic envelope Sigma = sigma I (Eq. 4, special case)
+# --------------------------------------------------------------------------
+def test_isotropic_two_centre_envelope_closed_form():
+    """The two-centre closed form with the isotropic layout: one scalar sigma
+    per (orbital, nucleus), psi = p0 exp(-|s0| rho0) + p1 exp(-|s1| rho1).
+    A negative sigma acts through |sigma| (the norm of sigma I d); the second
+    orbital's entries differ, so a transposed [K n][M] index fails, and so
+    does reading sigma from the anisotropic layout's stride."""
+    R = np.array([[0.0, 0.0, -0.6], [0.2, 0.1, 0.9]])
+    s = small(1, 0, R, [3.0, 1.0], L=1, K=2, envelope=1)
+    th, v = zero_theta(s)
+    assert v["sig_up"].shape == (2, 2)
+    v["g_up"][:] = [1.0, 0.0]
+    p = np.array([[0.7, 1.9], [5.0, 11.0]])
+    sg = np.array([[2.1, -0.8], [0.3, 4.0]])
+    v["pi_up"][...] = p
+    v["sig_up"][...] = sg
+    x = np.random.default_rng(19).standard_normal((12, 1, 3))
+    rho = np.linalg.norm(x[:, 0][:, None, :] - R[None], axis=2)
+    a = np.abs(sg[0])[None]
+    e = p[0][None] * np.exp(-a * rho)
+    psi = e.sum(1)
+    lap = (e * (a ** 2 - 2 * a / rho)).sum(1)
+    out = O.Oracle(s).local_energy(th, x)
+    np.testing.assert_allclose(out["log_abs"], np.log(psi), atol=1e-12)
+    np.testing.assert_allclose(out["parts"][:, 0], -0.5 * lap / psi, rtol=1e-10, atol=1e-10)
+
+
+def _iso_pair(seed=71):
+    """A LiH-like network with random weights in both layouts, the
+    anisotropic one carrying Sigma = sigma I for the isotropic one's sigma."""
+    base = I.System("LiH-s", I.lih().nuc_xyz, I.lih().nuc_z, 2, 2, 2, 8, 4, 3, 4, I.lih().electron_site, 1.0)
+    iso = I.isotropic(base)
+    rng = np.random.default_rng(seed)
+    th_a = I.init_params(base, seed=seed)
+    va = I.view_params(base, th_a)
+    th_i = np.zeros(I.param_count(iso))
+    vi = I.view_params(iso, th_i)
+    for name in vi:
+        if name.startswith("sig_"):
+            sg = rng.uniform(0.5, 2.0, vi[name].shape)
+            vi[name][...] = sg
+            va[name][...] = sg[..., None, None] * np.eye(3)
+        elif name.startswith("pi_"):
+            pv = rng.uniform(0.5, 1.5, vi[name].shape)
+            vi[name][...] = pv
+            va[name][...] = pv
+        else:
+            vi[name][...] = va[name]
+    return base, th_a, iso, th_i
+
+
+def test_isotropic_layout_is_the_anisotropic_special_case():
+    """log|psi|, E_L and its parts agree between the isotropic layout and the
+    anisotropic one with Sigma = sigma I; the derivative with respect to an
+    isotropic sigma equals the sum of the derivatives with respect to the
+    three diagonal entries of the corresponding Sigma (chain rule), for
+    every sigma of both spins."""
+    base, th_a, iso, th_i = _iso_pair()
+    x = I.init_walkers(base, 6, seed=72)
+    oa, oi = O.Oracle(base), O.Oracle(iso)
+    assert oi.param_count() == I.param_count(iso) == I.param_count(base) - 2 * (3 * 2) * 2 * 8
+    ra, ri = oa.local_energy(th_a, x), oi.local_energy(th_i, x)
+    np.testing.assert_allclose(ri["log_abs"], ra["log_abs"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(ri["e_loc"], ra["e_loc"], rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(ri["parts"], ra["parts"], rtol=1e-11, atol=1e-11)
+    offa, offi = I.param_offsets(base), I.param_offsets(iso)
+    for tag in ("up", "dn"):
+        oi0, shp = offi[f"sig_{tag}"]
+        oa0, _ = offa[f"sig_{tag}"]
+        n = int(np.prod(shp))
+        idx_i = oi0 + np.arange(n)
+        idx_a = (oa0 + 9 * np.arange(n))[:, None] + np.array([0, 4, 8])[None]
+        gi = oi.dlogpsi_dtheta(th_i, x, idx_i)
+        ga = oa.dlogpsi_dtheta(th_a, x, idx_a.reshape(-1)).reshape(x.shape[0], n, 3).sum(2)
+        np.testing.assert_allclose(gi, ga, rtol=1e-10, atol=1e-12)
+        assert np.abs(gi).max() > 1e-3
+
+
+def test_isotropic_hydrogenic_exact():
+    """Isotropic layout, sigma = Z: psi = exp(-Z r), E_L = -Z^2/2 everywhere."""
+    s = small(1, 0, [0.3, -0.2, 0.1], [3.0], L=1, K=1, envelope=1)
+    th, v = zero_theta(s)
+    v["g_up"][...] = 1.0
+    v["sig_up"][...] = 3.0
+    x = np.random.default_rng(73).standard_normal((16, 1, 3)) + s.nuc_xyz[0]
+    r = O.Oracle(s).local_energy(th, x)
+    np.testing.assert_allclose(r["e_loc"], -4.5, atol=1e-10)
