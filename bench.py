@@ -152,14 +152,16 @@ def lif_training_step(prec, steps=10, warmup=2):
             "energy": float(stats[0].item()), "finite_gradient": bool(torch.isfinite(grad).all().item())}
 
 
-def h20_local_energy(prec, steps=5, warmup=1):
-    """H20 chain (8192 walkers) forward + Laplacian local energy: evals/s and
-    the stream layer's algorithmic TFLOP/s over its event-timed launches."""
+def h20_local_energy(prec, steps=5, warmup=1, envelope=0):
+    """H20 chain (8192 walkers) forward + Laplacian local energy: evals/s,
+    the stream layer's algorithmic TFLOP/s over its event-timed launches and
+    the time of the envelope + determinant stage.  envelope=1: the isotropic
+    envelope (Sigma = sigma I) at sigma = 1, the same wavefunction."""
     import torch
     from paper_2401_10287_amd import fnvmc
     from paper_2401_10287_amd import inputs as I
     import parity_tools as T
-    s = I.h_chain()
+    s = I.h_chain() if envelope == 0 else I.isotropic(I.h_chain())
     B = 8192
     cfg = fnvmc.Config(s, prec)
     tt = torch.tensor(I.init_params(s), dtype=cfg.param_dtype, device="cuda:0")
@@ -172,16 +174,24 @@ def h20_local_energy(prec, steps=5, warmup=1):
     fnvmc.fn_timing_select("stream_gemm")
     fnvmc.fn_timing_enable(True)
     wall, lat = time_steps(lambda: fnvmc.fn_local_energy(cfg, tt, xt, ws=ws, want_parts=False), steps, torch)
-    fnvmc.fn_timing_enable(False)
     ms_g, n_g = fnvmc.fn_timing_read("stream_gemm")
+    fnvmc.fn_timing_reset()
+    fnvmc.fn_timing_select("det")
+    for _ in range(steps):
+        fnvmc.fn_local_energy(cfg, tt, xt, ws=ws, want_parts=False)
+    ms_d, _ = fnvmc.fn_timing_read("det")
+    fnvmc.fn_timing_enable(False)
     fnvmc.fn_timing_select(None)
     flops, _ = stream_gemm_flops(s, B)
     achieved = flops * steps / (ms_g * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec]
-    print(f"[bench] H20 {prec}: {B * steps / wall:.4g} evals/s, stream layer {achieved:.1f} TFLOP/s "
-          f"({achieved / peak:.3f} of peak)", file=sys.stderr, flush=True)
-    return {"workload": "H20 chain local energy, 8192 walkers, 4 layers 256/32, 16 determinants",
+    env = "isotropic" if envelope else "anisotropic"
+    print(f"[bench] H20 {prec} {env} envelope: {B * steps / wall:.4g} evals/s, stream layer {achieved:.1f} TFLOP/s "
+          f"({achieved / peak:.3f} of peak), envelope + determinants {ms_d / steps:.2f} ms per step",
+          file=sys.stderr, flush=True)
+    return {"workload": f"H20 chain local energy, 8192 walkers, 4 layers 256/32, 16 determinants, {env} envelope",
             "precision": prec, "evals_per_s": B * steps / wall, "ms_per_step": wall / steps * 1e3,
+            "envelope_and_determinants_ms_per_step": ms_d / steps,
             "stream_layer": {"achieved_TFLOPs": achieved, "peak_TFLOPs": peak, "frac": achieved / peak,
                              "launches": n_g}}
 
@@ -371,6 +381,7 @@ def main():
     if not args.no_extra:
         line["config"]["lif_training_step"] = lif_training_step(args.precision)
         line["config"]["h20_local_energy"] = h20_local_energy(args.precision)
+        line["config"]["h20_local_energy_isotropic"] = h20_local_energy(args.precision, envelope=1)
     if args.serving_jobs > 0:
         from paper_2401_10287_amd import serving
         torch.cuda.synchronize()

@@ -42,6 +42,7 @@
  *   for spin s = up, down with n_s > 0 :
  *                    w_s [w1][K n_s] (column k n_s + i), g_s [K n_s],
  *                    pi_s [K n_s][M], Sigma_s [K n_s][M][3][3]
+ *                    (FN_ENV_ISOTROPIC: sigma_s [K n_s][M] in place of Sigma_s)
  *   with d_h = 4M, d_p = 4 at layer 0, d_h = w1, d_p = w2 afterwards and
  *   d_in = 3 d_h + 2 d_p.
  */
@@ -79,6 +80,14 @@ typedef int32_t fn_status;
 #define FN_BF16X3_MIXED 3
 #define FN_BF16X6_MIXED 4
 
+/* Envelope of Eq. 4, sum_m pi_im exp(-|Sigma_im (r_j - R_m)|).
+   FN_ENV_ANISOTROPIC: Sigma_im is a 3x3 matrix (9 parameters).
+   FN_ENV_ISOTROPIC: the special case Sigma_im = sigma_im I, one parameter;
+   the envelope is pi exp(-|sigma| |r_j - R_m|), which skips the 3x3
+   products and reads one parameter per orbital and nucleus instead of nine. */
+#define FN_ENV_ANISOTROPIC 0
+#define FN_ENV_ISOTROPIC 1
+
 /* Operation selector for fn_workspace_bytes. */
 #define FN_OP_LOG_PSI 0
 #define FN_OP_LOCAL_ENERGY 1
@@ -103,6 +112,7 @@ typedef struct {
     int32_t w1, w2;         /* one- / two-electron stream widths              */
     int32_t n_det;          /* K determinants                                 */
     int32_t precision;      /* FN_FP64 .. FN_BF16X6_MIXED                    */
+    int32_t envelope;       /* FN_ENV_ANISOTROPIC or FN_ENV_ISOTROPIC         */
 } fn_config;
 
 /* Number of scalars in the flat parameter vector; -1 if cfg is invalid. */

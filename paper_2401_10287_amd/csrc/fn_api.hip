@@ -128,8 +128,11 @@ fn_status make_ctx(const fn_config *cfg, Ctx &c)
     if (cfg->w2 < 1 || cfg->w2 > FN_MAX_W2) return fail(FN_EINVAL, "w2 out of range 1..64");
     if (cfg->n_det < 1 || cfg->n_det > FN_MAX_DET) return fail(FN_EINVAL, "n_det out of range 1..32");
     if (cfg->precision < FN_FP64 || cfg->precision > FN_BF16X6_MIXED) return fail(FN_EINVAL, "unknown precision");
+    if (cfg->envelope != FN_ENV_ANISOTROPIC && cfg->envelope != FN_ENV_ISOTROPIC)
+        return fail(FN_EINVAL, "unknown envelope form");
     Sys &s = c.s;
     memset(&s, 0, sizeof(s));
+    s.iso = cfg->envelope == FN_ENV_ISOTROPIC;
     s.M = cfg->n_nuc;
     s.nu = cfg->n_up;
     s.nd = cfg->n_down;
@@ -242,7 +245,7 @@ fn_status make_plan(const Ctx &c, int64_t B, int op, Plan &p)
     if (p.save) {
         const int64_t kn_max = (int64_t)s.K * nmax;
         pe = std::max<int64_t>(pe, (int64_t)s.w1 * std::max<int64_t>(std::max(c.W.HWmax, 2 * c.W.GWmax), kn_max));
-        pe = std::max<int64_t>(pe, kn_max * s.M * 10);
+        pe = std::max<int64_t>(pe, kn_max * s.M * env_partials(s));
         pe = std::max<int64_t>(pe, p.npp);
         pe = std::max<int64_t>(pe, c.W.KNp[0] > c.W.KNp[1] ? c.W.KNp[0] : c.W.KNp[1]);
         pe *= max_splits();
@@ -277,8 +280,8 @@ fn_status make_plan(const Ctx &c, int64_t B, int op, Plan &p)
         {&p.GA[1], p.save ? (size_t)s.K * s.nd * s.nd * 8 : 0},
         {&p.Ga[0], p.save ? (size_t)s.nu * c.W.KNp[0] * e : 0},
         {&p.Ga[1], p.save ? (size_t)s.nd * c.W.KNp[1] * e : 0},
-        {&p.EP[0], p.save ? (size_t)s.K * s.nu * s.M * 10 * e : 0},
-        {&p.EP[1], p.save ? (size_t)s.K * s.nd * s.M * 10 * e : 0},
+        {&p.EP[0], p.save ? (size_t)s.K * s.nu * s.M * env_partials(s) * e : 0},
+        {&p.EP[1], p.save ? (size_t)s.K * s.nd * s.M * env_partials(s) * e : 0},
         {&p.Gy[0], p.save ? N * s.w1 * e : 0},
         {&p.Gy[1], p.save ? N * s.w1 * e : 0},
         {&p.Gz, p.save ? N * s.w1 * e : 0},
@@ -594,7 +597,8 @@ void backward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *x
                                 s.nu, s.nd, p.rec, GA, st);
         launch_env_backward<T>(s, xw, theta, c.P.g[sp], c.P.pi[sp], c.P.sig[sp], sp, (const T *)(ws + p.O[sp]), KNp,
                                GA, b, KNp, Ga, EP, st);
-        launch_colsum<T>(EP, (int64_t)kn * s.M * 10, kn * s.M * 10, b, part, gacc, c.P.pi[sp], 1, c.P.sig[sp], st);
+        launch_colsum<T>(EP, (int64_t)kn * s.M * env_partials(s), kn * s.M * env_partials(s), b, part, gacc, c.P.pi[sp],
+                         env_partials(s), c.P.sig[sp], st);
         launch_colsum<T>(Ga, KNp, kn, b * n, part, gacc, c.P.g[sp], 0, 0, st);
         launch_tn<T>((const T *)(ws + p.H[s.L]), ldh, w1, Ga, KNp, kn, b * n, n, N, j0, part, gacc, c.P.w[sp], kn, st);
         GemmArgs g{};

@@ -251,6 +251,8 @@ __global__ __launch_bounds__(256) void k_det_backward_small(const double *Phi, c
 //   Ga[w n + j][col] = G env                       (adjoint of a = w . h + g)
 //   EP[w][col][m][0]   = sum_j G a exp(-q_m)             (pi_m)
 //   EP[w][col][m][1+3p+q] = sum_j -G a pi_m exp(-q_m) (Sigma d)_p d_q / q
+// and for the isotropic envelope (q_m = |sigma_m| r_m, two partials):
+//   EP[w][col][m][1] = sum_j -G a pi_m exp(-q_m) sign(sigma_m) r_m
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_env_backward(Sys s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof, int sp,
@@ -273,19 +275,47 @@ __global__ void k_env_backward(Sys s, const double *x, const T *theta, int64_t g
             const double *xj = x + (w * s.N + j0 + jj) * 3;
             double env = 0.0;
             for (int m = 0; m < s.M; ++m) {
-                const T *Sg = theta + sigof + ((int64_t)col * s.M + m) * 9;
                 const double d0 = xj[0] - s.R[m][0], d1 = xj[1] - s.R[m][1], d2 = xj[2] - s.R[m][2];
-                double q2 = 0.0;
-                for (int p = 0; p < 3; ++p) {
-                    const double v = (double)Sg[3 * p] * d0 + (double)Sg[3 * p + 1] * d1 + (double)Sg[3 * p + 2] * d2;
-                    q2 += v * v;
+                double q;
+                if (s.iso) {
+                    q = fabs((double)theta[sigof + (int64_t)col * s.M + m]) * sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                } else {
+                    const T *Sg = theta + sigof + ((int64_t)col * s.M + m) * 9;
+                    double q2 = 0.0;
+                    for (int p = 0; p < 3; ++p) {
+                        const double v = (double)Sg[3 * p] * d0 + (double)Sg[3 * p + 1] * d1 + (double)Sg[3 * p + 2] * d2;
+                        q2 += v * v;
+                    }
+                    q = sqrt(q2);
                 }
-                env += (double)theta[piof + (int64_t)col * s.M + m] * exp(-sqrt(q2));
+                env += (double)theta[piof + (int64_t)col * s.M + m] * exp(-q);
             }
             const double G = GA[((w * s.K + k) * n + io) * n + jj];
             Ga[(w * n + jj) * KNp + col] = (T)(G * env);
         }
         // envelope parameters, summed over the electrons of this walker
+        if (s.iso) {
+            for (int m = 0; m < s.M; ++m) {
+                const double sraw = (double)theta[sigof + (int64_t)col * s.M + m];
+                const double sg = fabs(sraw), sgn = sraw < 0.0 ? -1.0 : 1.0;
+                const double pim = (double)theta[piof + (int64_t)col * s.M + m];
+                double gp = 0.0, gs = 0.0;
+                for (int jj = 0; jj < n; ++jj) {
+                    const double *xj = x + (w * s.N + j0 + jj) * 3;
+                    const double d0 = xj[0] - s.R[m][0], d1 = xj[1] - s.R[m][1], d2 = xj[2] - s.R[m][2];
+                    const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                    const double e = exp(-(sg * r));
+                    const double a0 = (double)O[(w * n + jj) * ldo + col] + gcol;
+                    const double ga = GA[((w * s.K + k) * n + io) * n + jj] * a0;
+                    gp += ga * e;
+                    gs -= ga * pim * e * sgn * r;
+                }
+                T *ep = EP + ((w * kn + col) * s.M + m) * 2;
+                ep[0] = (T)gp;
+                ep[1] = (T)gs;
+            }
+            continue;
+        }
         for (int m = 0; m < s.M; ++m) {
             const T *Sg = theta + sigof + ((int64_t)col * s.M + m) * 9;
             const double pim = (double)theta[piof + (int64_t)col * s.M + m];
@@ -813,8 +843,10 @@ __global__ __launch_bounds__(256) void k_colsum_partial(const T *in, int64_t ld,
     if (ty == 0 && c < C) part[(int64_t)blockIdx.y * C + c] = (T)(red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
-// acc[map(c)] += sum_s part[s][c]; map: envelope partials [col][m][10] go to
-// pi [col][m] and Sigma [col][m][9]; otherwise acc[off + c]
+// acc[map(c)] += sum_s part[s][c]; map (env_map = E > 0 partials per
+// (column, nucleus)): envelope partials [col][m][E] go to pi [col][m] and
+// Sigma [col][m][E - 1] (the nine entries, or the isotropic sigma);
+// env_map = 0: acc[off + c]
 template <typename T>
 __global__ void k_colsum_reduce(const T *part, int S, int C, double *acc, int64_t off, int env_map, int64_t off2)
 {
@@ -824,9 +856,9 @@ __global__ void k_colsum_reduce(const T *part, int S, int C, double *acc, int64_
         if (!env_map) {
             acc[off + c] += v;
         } else {
-            const int cm = c / 10, e = c % 10;      // cm = col * M + m
+            const int cm = c / env_map, e = c % env_map;      // cm = col * M + m
             if (e == 0) acc[off + cm] += v;
-            else acc[off2 + (int64_t)cm * 9 + (e - 1)] += v;
+            else acc[off2 + (int64_t)cm * (env_map - 1) + (e - 1)] += v;
         }
     }
 }

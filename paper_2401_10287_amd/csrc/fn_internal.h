@@ -23,6 +23,7 @@ namespace fn {
 // System and network sizes, passed to kernels by value.
 struct Sys {
     int M, N, nu, nd, L, w1, w2, K;
+    int iso;        // isotropic envelope: one sigma per orbital and nucleus (Sigma = sigma I)
     double R[FN_MAX_NUC][3];
     double Z[FN_MAX_NUC];
 };
@@ -40,6 +41,9 @@ struct ParamLayout {
 inline __host__ __device__ int layer_dh(const Sys &s, int l) { return l == 0 ? 4 * s.M : s.w1; }
 inline __host__ __device__ int layer_dp(const Sys &s, int l) { return l == 0 ? 4 : s.w2; }
 inline __host__ __device__ int layer_din(const Sys &s, int l) { return 3 * layer_dh(s, l) + 2 * layer_dp(s, l); }
+// envelope parameter partials per (orbital column, nucleus) in the backward:
+// pi and the nine entries of Sigma, or pi and sigma
+inline __host__ __device__ int env_partials(const Sys &s) { return s.iso ? 2 : 10; }
 
 inline ParamLayout make_layout(const Sys &s)
 {
@@ -60,7 +64,7 @@ inline ParamLayout make_layout(const Sys &s)
         p.w[sp] = o; o += (int64_t)s.w1 * kn;
         p.g[sp] = o; o += kn;
         p.pi[sp] = o; o += (int64_t)kn * s.M;
-        p.sig[sp] = o; o += (int64_t)kn * s.M * 9;
+        p.sig[sp] = o; o += (int64_t)kn * s.M * (s.iso ? 1 : 9);
     }
     p.total = o;
     return p;

@@ -786,6 +786,50 @@ __global__ __launch_bounds__(256) void k_layer_epi(const T *__restrict__ X, cons
 //   lap e = e (|grad q|^2 - lap q); lap(a e) = e lap a + a lap e + 2 grad a . grad e.
 // Output Phi[w][k][t][i][jj] (rows t = value, 3N tangents, Laplacian).
 // ---------------------------------------------------------------------------
+// One nucleus' term of orbital column col's envelope at electron position
+// xj: em = pi exp(-q) added to env, and with FL its contributions to the
+// electron's gradient and Laplacian of the envelope (all FP64).
+//   anisotropic: q = |Sigma d|, grad q = S d / q, S = Sigma^T Sigma,
+//                lap q = (tr S - |S d|^2 / q^2) / q;
+//   isotropic (Sigma = sigma I): q = |sigma| r with r = |d|,
+//                grad q = |sigma| d / r, |grad q|^2 = sigma^2, lap q = 2 |sigma| / r.
+template <typename T, bool FL>
+__device__ __forceinline__ void env_add(const Sys &s, const T *theta, int64_t piof, int64_t sigof, int col, int m,
+                                        const double *xj, double &env, double (&ge)[3], double &le)
+{
+    const double d[3] = {xj[0] - s.R[m][0], xj[1] - s.R[m][1], xj[2] - s.R[m][2]};
+    if (s.iso) {
+        const double sg = fabs((double)theta[sigof + (int64_t)col * s.M + m]);
+        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const double em = (double)theta[piof + (int64_t)col * s.M + m] * exp(-(sg * r));
+        env += em;
+        if constexpr (FL) {
+            const double gr = sg / r;
+            for (int a = 0; a < 3; ++a) ge[a] -= em * gr * d[a];
+            le += em * (sg * sg - 2.0 * gr);
+        }
+        return;
+    }
+    const T *Sgp = theta + sigof + ((int64_t)col * s.M + m) * 9;
+    double sd[3], ad[3], Sg[9];
+    for (int e = 0; e < 9; ++e) Sg[e] = (double)Sgp[e];
+    for (int p = 0; p < 3; ++p) sd[p] = Sg[3 * p] * d[0] + Sg[3 * p + 1] * d[1] + Sg[3 * p + 2] * d[2];
+    for (int a = 0; a < 3; ++a) ad[a] = Sg[a] * sd[0] + Sg[3 + a] * sd[1] + Sg[6 + a] * sd[2];
+    const double qd = sqrt(sd[0] * sd[0] + sd[1] * sd[1] + sd[2] * sd[2]);
+    const double em = (double)theta[piof + (int64_t)col * s.M + m] * exp(-qd);
+    env += em;
+    if constexpr (FL) {
+        double trS = 0.0;
+        for (int e = 0; e < 9; ++e) trS += Sg[e] * Sg[e];
+        const double iq = 1.0 / qd;
+        const double ad2 = ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2];
+        const double lq = (trS - ad2 * iq * iq) * iq;
+        const double gq2 = ad2 * iq * iq;
+        for (int a = 0; a < 3; ++a) ge[a] -= em * ad[a] * iq;
+        le += em * (gq2 - lq);
+    }
+}
+
 template <typename T, bool FL>
 __global__ void k_envelope(Sys s, const double *x, const T *theta, int64_t gof, int64_t piof, int64_t sigof, int sp,
                            const T *O, int64_t ldo, int64_t B, int TR, double *Phi)
@@ -804,27 +848,7 @@ __global__ void k_envelope(Sys s, const double *x, const T *theta, int64_t gof, 
         const int k = col / n, io = col % n;
         const double *xj = x + (w * s.N + j) * 3;
         E env = 0.0, ge[3] = {0.0, 0.0, 0.0}, le = 0.0;
-        for (int m = 0; m < s.M; ++m) {
-            const T *Sgp = theta + sigof + ((int64_t)col * s.M + m) * 9;
-            E d[3] = {xj[0] - s.R[m][0], xj[1] - s.R[m][1], xj[2] - s.R[m][2]};
-            E sd[3], ad[3], Sg[9];
-            for (int e = 0; e < 9; ++e) Sg[e] = (E)Sgp[e];
-            for (int p = 0; p < 3; ++p) sd[p] = Sg[3 * p] * d[0] + Sg[3 * p + 1] * d[1] + Sg[3 * p + 2] * d[2];
-            for (int a = 0; a < 3; ++a) ad[a] = Sg[a] * sd[0] + Sg[3 + a] * sd[1] + Sg[6 + a] * sd[2];
-            const E q = sqrt(sd[0] * sd[0] + sd[1] * sd[1] + sd[2] * sd[2]);
-            const E em = (E)theta[piof + (int64_t)col * s.M + m] * exp(-q);
-            env += em;
-            if (FL) {
-                E trS = 0.0;
-                for (int e = 0; e < 9; ++e) trS += Sg[e] * Sg[e];
-                const E iq = 1.0 / q;
-                const E ad2 = ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2];
-                const E lq = (trS - ad2 * iq * iq) * iq;
-                const E gq2 = ad2 * iq * iq;
-                for (int a = 0; a < 3; ++a) ge[a] -= em * ad[a] * iq;
-                le += em * (gq2 - lq);
-            }
-        }
+        for (int m = 0; m < s.M; ++m) env_add<T, FL>(s, theta, piof, sigof, col, m, xj, env, ge, le);
         const int64_t orow = (w * n + jj) * TR;
         const E a0 = (E)O[orow * ldo + col] + (E)theta[gof + col];
         const int64_t base = ((w * s.K + k) * TR) * n * n + io * n + jj;
@@ -1019,27 +1043,7 @@ __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *
         const int col = k * n + io, j = j0 + jj;
         const double *xj = x + (w * s.N + j) * 3;
         double env = 0.0, ge[3] = {0.0, 0.0, 0.0}, le = 0.0;
-        for (int m = 0; m < s.M; ++m) {
-            const T *Sgp = theta + sigof + ((int64_t)col * s.M + m) * 9;
-            double d[3] = {xj[0] - s.R[m][0], xj[1] - s.R[m][1], xj[2] - s.R[m][2]};
-            double sd[3], ad[3], Sg[9];
-            for (int e = 0; e < 9; ++e) Sg[e] = (double)Sgp[e];
-            for (int p = 0; p < 3; ++p) sd[p] = Sg[3 * p] * d[0] + Sg[3 * p + 1] * d[1] + Sg[3 * p + 2] * d[2];
-            for (int a = 0; a < 3; ++a) ad[a] = Sg[a] * sd[0] + Sg[3 + a] * sd[1] + Sg[6 + a] * sd[2];
-            const double qd = sqrt(sd[0] * sd[0] + sd[1] * sd[1] + sd[2] * sd[2]);
-            const double em = (double)theta[piof + (int64_t)col * s.M + m] * exp(-qd);
-            env += em;
-            if constexpr (FL) {
-                double trS = 0.0;
-                for (int e = 0; e < 9; ++e) trS += Sg[e] * Sg[e];
-                const double iq = 1.0 / qd;
-                const double ad2 = ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2];
-                const double lq = (trS - ad2 * iq * iq) * iq;
-                const double gq2 = ad2 * iq * iq;
-                for (int a = 0; a < 3; ++a) ge[a] -= em * ad[a] * iq;
-                le += em * (gq2 - lq);
-            }
-        }
+        for (int m = 0; m < s.M; ++m) env_add<T, FL>(s, theta, piof, sigof, col, m, xj, env, ge, le);
         const double a0 = (double)O[((w * n + jj) * TR) * ldo + col] + (double)theta[gof + col];
         if constexpr (FL) {
             EV[q] = env;
@@ -1226,27 +1230,7 @@ __device__ __forceinline__ void small_entries(const Sys &s, const double *x, con
             const int col = k * NS + io, j = j0 + jj;
             const double *xj = x + (w * s.N + j) * 3;
             double env = 0.0, g3[3] = {0.0, 0.0, 0.0}, lp = 0.0;
-            for (int m = 0; m < s.M; ++m) {
-                const T *Sgp = theta + sigof + ((int64_t)col * s.M + m) * 9;
-                double d[3] = {xj[0] - s.R[m][0], xj[1] - s.R[m][1], xj[2] - s.R[m][2]};
-                double sd[3], ad[3], Sg[9];
-                for (int e = 0; e < 9; ++e) Sg[e] = (double)Sgp[e];
-                for (int p = 0; p < 3; ++p) sd[p] = Sg[3 * p] * d[0] + Sg[3 * p + 1] * d[1] + Sg[3 * p + 2] * d[2];
-                for (int a = 0; a < 3; ++a) ad[a] = Sg[a] * sd[0] + Sg[3 + a] * sd[1] + Sg[6 + a] * sd[2];
-                const double qd = sqrt(sd[0] * sd[0] + sd[1] * sd[1] + sd[2] * sd[2]);
-                const double em = (double)theta[piof + (int64_t)col * s.M + m] * exp(-qd);
-                env += em;
-                if constexpr (FL) {
-                    double trS = 0.0;
-                    for (int e = 0; e < 9; ++e) trS += Sg[e] * Sg[e];
-                    const double iq = 1.0 / qd;
-                    const double ad2 = ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2];
-                    const double lq = (trS - ad2 * iq * iq) * iq;
-                    const double gq2 = ad2 * iq * iq;
-                    for (int a = 0; a < 3; ++a) g3[a] -= em * ad[a] * iq;
-                    lp += em * (gq2 - lq);
-                }
-            }
+            for (int m = 0; m < s.M; ++m) env_add<T, FL>(s, theta, piof, sigof, col, m, xj, env, g3, lp);
             ev[io][jj] = env;
             ge[io][jj][0] = g3[0]; ge[io][jj][1] = g3[1]; ge[io][jj][2] = g3[2];
             le[io][jj] = lp;

@@ -237,7 +237,7 @@ bool same_system(const Job &a, const Job &b)
     const fn_config &p = a.cfg, &q = b.cfg;
     if (a.theta != b.theta || a.sigma != b.sigma || a.n_steps != b.n_steps) return false;
     if (p.n_nuc != q.n_nuc || p.n_up != q.n_up || p.n_down != q.n_down || p.n_layers != q.n_layers || p.w1 != q.w1 ||
-        p.w2 != q.w2 || p.n_det != q.n_det || p.precision != q.precision)
+        p.w2 != q.w2 || p.n_det != q.n_det || p.precision != q.precision || p.envelope != q.envelope)
         return false;
     return a.nuc_xyz == b.nuc_xyz && a.nuc_z == b.nuc_z;
 }

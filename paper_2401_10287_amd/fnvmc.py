@@ -35,7 +35,7 @@ class _Config(ctypes.Structure):
     _fields_ = [("n_nuc", ctypes.c_int32), ("nuc_xyz", ctypes.c_void_p), ("nuc_z", ctypes.c_void_p),
                 ("n_up", ctypes.c_int32), ("n_down", ctypes.c_int32), ("n_layers", ctypes.c_int32),
                 ("w1", ctypes.c_int32), ("w2", ctypes.c_int32), ("n_det", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("envelope", ctypes.c_int32)]
 
 
 def _load():
@@ -114,7 +114,8 @@ class Config:
         self._xyz = np.ascontiguousarray(system.nuc_xyz, dtype=np.float64).reshape(-1)
         self._z = np.ascontiguousarray(system.nuc_z, dtype=np.float64)
         self.c = _Config(system.n_nuc, self._xyz.ctypes.data, self._z.ctypes.data, system.n_up, system.n_dn,
-                         system.n_layers, system.w1, system.w2, system.n_det, PRECISIONS[precision])
+                         system.n_layers, system.w1, system.w2, system.n_det, PRECISIONS[precision],
+                         int(system.envelope))
         self.ptr = ctypes.addressof(self.c)
         self.n_elec = system.n_elec
         self.param_dtype = torch.float64 if precision == "fp64" else torch.float32

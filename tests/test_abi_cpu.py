@@ -29,7 +29,8 @@ def test_header_symbols_exported():
         assert hasattr(lib, name), name
 
 
-@pytest.mark.parametrize("make", [I.he, I.lih, I.lif, I.h_chain])
+@pytest.mark.parametrize("make", [I.he, I.lih, I.lif, I.h_chain, lambda: I.isotropic(I.lih()),
+                                  lambda: I.isotropic(I.h_chain())])
 def test_param_count_agrees(make):
     fnvmc = _fnvmc()
     s = make()
@@ -147,3 +148,11 @@ def test_server_create_checks_gang_limits():
         assert st == fnvmc.FN_EINVAL, (max_gang, walkers)
     assert L.fn_server_create(1 << 20, 1 << 20, streams, 2, 5, 64, 4096, res.ctypes.data, ctypes.byref(h)) == 0
     assert L.fn_server_destroy(h) == 0
+
+
+def test_unknown_envelope_rejected():
+    fnvmc = _fnvmc()
+    cfg = fnvmc.Config(I.lih(), "fp32")
+    cfg.c.envelope = 2
+    assert fnvmc.LIB.fn_param_count(cfg.ptr) == -1
+    assert b"envelope" in fnvmc.LIB.fn_last_error()
