@@ -28,6 +28,17 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_sanitizer_driver(out: str) -> str:
+    """Compile sanitize_driver.c (the oracle in one translation unit) with
+    AddressSanitizer and UndefinedBehaviorSanitizer into the executable
+    `out`; raises CalledProcessError with the compiler's output on failure."""
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+           "-I", _HERE, "-o", out, os.path.join(_HERE, "sanitize_driver.c"), "-lm"]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    return out
+
+
 class _Cfg(ctypes.Structure):
     _fields_ = [("n_nuc", ctypes.c_int32), ("nuc_xyz", ctypes.c_void_p), ("nuc_z", ctypes.c_void_p),
                 ("n_up", ctypes.c_int32), ("n_dn", ctypes.c_int32), ("n_layers", ctypes.c_int32),

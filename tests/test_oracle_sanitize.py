@@ -13,8 +13,6 @@ import pytest
 from oracle import oracle as O
 from paper_2401_10287_amd import inputs as I
 
-HERE = os.path.dirname(os.path.abspath(__file__))
-ORACLE = os.path.join(os.path.dirname(HERE), "oracle")
 
 
 @pytest.fixture(scope="module")
@@ -22,13 +20,12 @@ def driver(tmp_path_factory):
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
     out = str(tmp_path_factory.mktemp("san") / "sanitize_driver")
-    cmd = ["gcc", "-O1", "-g", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
-           "-I", ORACLE, "-o", out, os.path.join(ORACLE, "sanitize_driver.c"), "-lm"]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0 and "asan" in (r.stderr or "").lower():
-        pytest.skip("sanitizer runtime not available: " + r.stderr[-300:])
-    assert r.returncode == 0, r.stderr
+    try:
+        O.build_sanitizer_driver(out)
+    except subprocess.CalledProcessError as e:
+        if "asan" in (e.stderr or "").lower() or "ubsan" in (e.stderr or "").lower():
+            pytest.skip("sanitizer runtime not available: " + e.stderr[-300:])
+        raise
     return out
 
 
