@@ -89,6 +89,14 @@ def he(walkers: int = 256) -> System:
                   (0, 0), 1.0)
 
 
+def h2(bond: float = 1.4, walkers: int = 256) -> System:
+    """H2 molecule: protons at (0, 0, -bond/2) and (0, 0, bond/2) bohr, 1 up
+    + 1 down electron, one starting about each proton with N(0, 1) offsets;
+    the He network (2 layers, widths 32/8, 2 determinants)."""
+    xyz = np.array([[0.0, 0.0, -0.5 * bond], [0.0, 0.0, 0.5 * bond]])
+    return System(f"H2-{bond:g}", xyz, np.ones(2), 1, 1, 2, 32, 8, 2, walkers, (0, 1), 1.0)
+
+
 def lih(walkers: int = 4096) -> System:
     """LiH: Li (Z=3) at the origin, H (Z=1) at (0,0,3.015) bohr; 2 up + 2 down;
     3 electrons start about Li and 1 about H with N(0, 1) offsets; 4 layers,
