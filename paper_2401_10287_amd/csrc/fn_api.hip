@@ -190,6 +190,8 @@ struct Plan {
     int TR, rec;
     int64_t Bc;
     size_t wx[FN_MAX_LAYERS], wg[FN_MAX_LAYERS], wh[2], wb[2];
+    size_t wx32[FN_MAX_LAYERS], wg32[FN_MAX_LAYERS];   // FP32 copies for the stacked kernel (0: none)
+    bool stack32;
     size_t wpair;        // FP32 pair weights in the matrix-core pair kernel's layout (FP32 parameters only)
     int64_t wxpart[FN_MAX_LAYERS], wgpart[FN_MAX_LAYERS];   // elements per BF16 part
     size_t H[FN_MAX_LAYERS + 1], GI, G, Pw, X, O[2], Phi[2], DR, xp, lpn, u;
@@ -231,6 +233,13 @@ fn_status make_plan(const Ctx &c, int64_t B, int op, Plan &p)
         p.wx[l] = o; o = al(o + nx * se * np);
         p.wg[l] = o; o = al(o + ng * we * npw);
     }
+    p.stack32 = p.fl && !p.save && c.wmode == c.smode && stack_fp32_weights(c.smode) &&
+                stack_supported(c.smode, s.N, p.TR, s.w1, s.L);
+    if (p.stack32)
+        for (int l = 0; l < s.L; ++l) {
+            p.wx32[l] = o; o = al(o + (size_t)p.wxpart[l] * sizeof(float));
+            p.wg32[l] = o; o = al(o + (size_t)p.wgpart[l] * sizeof(float));
+        }
     p.wpair = o;
     if (c.esz == sizeof(float)) o = al(o + (size_t)pair_mfma_woff(s, s.L > 1 ? s.L - 1 : 0) * sizeof(float));
     for (int sp = 0; sp < 2; ++sp) {
@@ -337,6 +346,15 @@ void pack_weights(const Ctx &c, const Plan &p, const T *theta, char *ws, hipStre
         g.d0 = ws + p.wx[l]; g.d1 = ws + p.wg[l];
         add(g);
     }
+    if (p.stack32)
+        for (int l = 0; l < s.L; ++l) {
+            PackSeg g{};
+            g.kind = 0; g.mode = GEMM_F32; g.mode2 = GEMM_F32; g.off = c.P.V[l];
+            g.dh = layer_dh(s, l); g.dp = layer_dp(s, l); g.w1 = s.w1; g.HWl = c.W.HWl[l]; g.GWl = c.W.GWl[l];
+            g.count = (int64_t)s.w1 * (g.HWl + g.GWl) + (int64_t)s.w1 * 2 * g.HWl;
+            g.d0 = ws + p.wx32[l]; g.d1 = ws + p.wg32[l];
+            add(g);
+        }
     for (int sp = 0; sp < 2; ++sp) {
         const int n = sp == 0 ? s.nu : s.nd;
         if (n == 0) continue;
@@ -403,6 +421,10 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
             for (int l = 0; l < s.L; ++l) {
                 sa.Wx[l] = (const uint16_t *)(ws + p.wx[l]); sa.wxpart[l] = p.wxpart[l];
                 sa.Wg[l] = (const uint16_t *)(ws + p.wg[l]); sa.wgpart[l] = p.wgpart[l];
+                if (p.stack32) {
+                    sa.Wx32[l] = (const float *)(ws + p.wx32[l]);
+                    sa.Wg32[l] = (const float *)(ws + p.wg32[l]);
+                }
                 sa.HW[l] = c.W.HWl[l]; sa.GW[l] = c.W.GWl[l];
                 sa.bias[l] = theta + c.P.b[l];
             }

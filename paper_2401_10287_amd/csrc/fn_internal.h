@@ -412,6 +412,7 @@ struct StackArgs {
     const float *H0; int64_t ldh;             // features of layer 0 (rows walker * N * 16 + e * 16 + t)
     const float *GI; int64_t ldgi; int64_t gi_stride;   // pair means of every layer (layer stride in floats)
     const uint16_t *Wx[FN_MAX_LAYERS], *Wg[FN_MAX_LAYERS];   // packed split-BF16 V_h / V_g per layer
+    const float *Wx32[FN_MAX_LAYERS], *Wg32[FN_MAX_LAYERS];  // the same transposed, FP32 (six-product split)
     int64_t wxpart[FN_MAX_LAYERS], wgpart[FN_MAX_LAYERS];
     int HW[FN_MAX_LAYERS], GW[FN_MAX_LAYERS];  // padded widths of h and of [g_i_up | g_i_dn]
     const float *bias[FN_MAX_LAYERS];
@@ -421,6 +422,9 @@ struct StackArgs {
 extern int g_use_stack;                        // tuning switch "layer_stack": 0 never, 1 one-pass BF16, 2 every split mode
 extern int g_stack_shape;                      // tuning switch "stack_shape": workgroup shape 0, 1, 2
 bool stack_supported(int mode, int N, int TR, int w1, int L);
+// the stacked kernel of the six-product split reads FP32 weights and splits
+// them in registers (one copy of every layer's weights fits in L2)
+inline bool stack_fp32_weights(int mode) { return mode == GEMM_BF16X6; }
 void launch_stack(int mode, const StackArgs &a, int N, hipStream_t st);
 // 128-row tiles of the fused layer hold whole walkers
 inline bool stream_layer_whole_walkers(int N, int TR) { return N * TR <= 128 && 128 % (N * TR) == 0; }

@@ -19,7 +19,7 @@ struct PackSeg {
 };
 struct PackList {
     int n;
-    PackSeg seg[2 * FN_MAX_LAYERS + 2];
+    PackSeg seg[3 * FN_MAX_LAYERS + 2];
 };
 template <typename T>
 void launch_pack(const T *theta, const PackList &pl, hipStream_t st);

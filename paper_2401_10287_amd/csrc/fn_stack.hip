@@ -39,10 +39,16 @@ __device__ inline float4 ld4(const float *s, int r, int k) { return *(const floa
 
 }  // namespace
 
+// Raw weight registers of one reduction step: the BF16 parts as packed, or
+// (WF) the FP32 values, split into parts in registers when used -- one FP32
+// copy of every layer's weights stays in L2 where three BF16 parts do not.
+template <int NP, bool WF> struct WRegs { uint4 v[NP][4]; };
+template <int NP> struct WRegs<NP, true> { float4 v[4][2]; };
+
 // W walkers per workgroup; PF: the next reduction step's weight fragments
 // are requested before the current step's matrix instructions (one wave
 // per SIMD), else two workgroups share each CU and hide each other's loads
-template <int NP, int NE, int W, bool PF>
+template <int NP, int NE, int W, bool PF, bool WF>
 __global__ __launch_bounds__(256, PF ? 1 : 2) void k_stack_fl(StackArgs a)
 {
     constexpr int RB = W * NE;                   // 16-row blocks, one per (walker, electron)
@@ -97,21 +103,45 @@ __global__ __launch_bounds__(256, PF ? 1 : 2) void k_stack_fl(StackArgs a)
         int64_t wrow[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) wrow[j] = (int64_t)(col0 + 16 * j + li);
-        uint4 hb[NP][4], nb[NP][PF ? 4 : 1];
-        auto load_wx = [&](int kt, uint4 (&B)[NP][4]) {
+        const float *__restrict__ Wx32 = a.Wx32[l];
+        const float *__restrict__ Wg32 = a.Wg32[l];
+        typedef WRegs<NP, WF> WR;
+        auto load_w = [&](const uint16_t *W16, const float *W32, int64_t part, int ld, int kt, WR &B) {
+            if constexpr (WF) {
 #pragma unroll
-            for (int q = 0; q < NP; ++q)
+                for (int j = 0; j < 4; ++j) {
+                    const float *src = W32 + wrow[j] * ld + 32 * kt + 8 * kq;
+                    B.v[j][0] = *(const float4 *)src;
+                    B.v[j][1] = *(const float4 *)(src + 4);
+                }
+            } else {
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    B[q][j] = *(const uint4 *)(Wx + q * px + wrow[j] * ldx + 32 * kt + 8 * kq);
+                for (int q = 0; q < NP; ++q)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        B.v[q][j] = *(const uint4 *)(W16 + q * part + wrow[j] * ld + 32 * kt + 8 * kq);
+            }
         };
-        auto load_wg = [&](int kt, uint4 (&B)[NP][4]) {
+        auto load_wx = [&](int kt, WR &B) { load_w(Wx, Wx32, px, ldx, kt, B); };
+        auto load_wg = [&](int kt, WR &B) { load_w(Wg, Wg32, pg, ldgw, kt, B); };
+        // the BF16 parts of a step's weight fragments
+        auto parts = [&](const WR &B, bf16x8 (&hb)[NP][4]) {
+            if constexpr (WF) {
 #pragma unroll
-            for (int q = 0; q < NP; ++q)
+                for (int j = 0; j < 4; ++j) {
+                    bf16x8 p[NP];
+                    split_fragment<NP>(B.v[j][0], B.v[j][1], p);
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    B[q][j] = *(const uint4 *)(Wg + q * pg + wrow[j] * ldgw + 32 * kt + 8 * kq);
+                    for (int q = 0; q < NP; ++q) hb[q][j] = p[q];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < NP; ++q)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) hb[q][j] = __builtin_bit_cast(bf16x8, B.v[q][j]);
+            }
         };
+        WR cur, nxt;
 
         // ---- P = [g_up | g_dn] V_g, one row block per walker (rows t = li)
 #pragma unroll
@@ -120,15 +150,14 @@ __global__ __launch_bounds__(256, PF ? 1 : 2) void k_stack_fl(StackArgs a)
             for (int j = 0; j < 4; ++j) pac[w][j] = f32x4{0.f, 0.f, 0.f, 0.f};
         // the mean-field steps carry a quarter of the matrix work per weight
         // fragment: the next step's fragments are always requested first
-        uint4 pb[NP][4];
-        load_wg(0, hb);
-        for (int kt = 0; kt < kg; ++kt) {
-            if (kt + 1 < kg) load_wg(kt + 1, pb);
+        auto p_step = [&](int kt, const WR &B) {
             const int kb = 32 * kt;
             const bool dn = kb >= HW;
             const int kc = (dn ? kb - HW : kb) + 8 * kq;
             const int e0 = dn ? nu : 0, e1 = dn ? NE : nu;
             const float sc = dn ? inv_d : inv_u;
+            bf16x8 hb[NP][4];
+            parts(B, hb);
 #pragma unroll
             for (int w = 0; w < W; ++w) {
                 float4 s0 = zero4, s1 = zero4;
@@ -148,15 +177,15 @@ __global__ __launch_bounds__(256, PF ? 1 : 2) void k_stack_fl(StackArgs a)
                     for (int pa = 0; pa <= sum; ++pa)
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
-                            pac[w][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                ha[pa], __builtin_bit_cast(bf16x8, hb[sum - pa][j]), pac[w][j], 0, 0, 0);
+                            pac[w][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa], hb[sum - pa][j], pac[w][j],
+                                                                                0, 0, 0);
             }
-            if (kt + 1 < kg) {
-#pragma unroll
-                for (int q = 0; q < NP; ++q)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) hb[q][j] = pb[q][j];
-            }
+        };
+        load_wg(0, cur);
+        for (int kt = 0; kt < kg; ++kt) {
+            if (kt + 1 < kg) load_wg(kt + 1, nxt);
+            p_step(kt, cur);
+            if (kt + 1 < kg) cur = nxt;
         }
 
         // ---- X = [h | g_i] V_h over all (walker, electron) row blocks
@@ -164,15 +193,17 @@ __global__ __launch_bounds__(256, PF ? 1 : 2) void k_stack_fl(StackArgs a)
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[rb][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-        if constexpr (PF) load_wx(0, hb);
+        if constexpr (PF) load_wx(0, cur);
         for (int kt = 0; kt < kx; ++kt) {
             if constexpr (PF) {
-                if (kt + 1 < kx) load_wx(kt + 1, nb);
+                if (kt + 1 < kx) load_wx(kt + 1, nxt);
             } else {
-                load_wx(kt, hb);
+                load_wx(kt, cur);
             }
             const int kb = 32 * kt;
             const int kc = kb < HW ? kb + 8 * kq : 256 + (kb - HW) + 8 * kq;   // LDS column of this lane's fragment
+            bf16x8 hb[NP][4];
+            parts(cur, hb);
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
                 const int r = 16 * rb + li;
@@ -185,16 +216,11 @@ __global__ __launch_bounds__(256, PF ? 1 : 2) void k_stack_fl(StackArgs a)
                     for (int pa = 0; pa <= sum; ++pa)
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
-                            acc[rb][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                ha[pa], __builtin_bit_cast(bf16x8, hb[sum - pa][j]), acc[rb][j], 0, 0, 0);
+                            acc[rb][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa], hb[sum - pa][j], acc[rb][j],
+                                                                                 0, 0, 0);
             }
             if constexpr (PF) {
-                if (kt + 1 < kx) {
-#pragma unroll
-                    for (int q = 0; q < NP; ++q)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) hb[q][j] = nb[q][j];
-                }
+                if (kt + 1 < kx) cur = nxt;
             }
         }
 
@@ -256,7 +282,9 @@ __global__ __launch_bounds__(256, PF ? 1 : 2) void k_stack_fl(StackArgs a)
 // 0: never; 1 (default): the one-pass BF16 mode, where the stacked kernel
 // is the faster one; 2: every split-BF16 mode (the split modes measure
 // slower stacked: each wave splits every activation fragment it reads, and
-// the register budget leaves no room to hide load latency)
+// the register budget leaves no room to hide load latency; the six-product
+// split reads FP32 weights, split in registers, so that every layer's
+// weights stay in L2 -- three BF16 parts of all four layers did not)
 int g_use_stack = 1;
 
 bool stack_supported(int mode, int N, int TR, int w1, int L)
@@ -271,26 +299,26 @@ bool stack_supported(int mode, int N, int TR, int w1, int L)
 // step's weights prefetched; 2 = 128 rows, prefetched
 int g_stack_shape = 0;
 
-template <int NP, int NE>
+template <int NP, int NE, bool WF>
 static void launch_ne(const StackArgs &a, hipStream_t st)
 {
     constexpr int W1 = 4 / NE, W2 = NE == 3 ? 2 : 8 / NE;
     const dim3 b(256);
     if (g_stack_shape == 2)
-        hipLaunchKernelGGL((k_stack_fl<NP, NE, W2, true>), dim3((unsigned)((a.B + W2 - 1) / W2)), b, 0, st, a);
+        hipLaunchKernelGGL((k_stack_fl<NP, NE, W2, true, WF>), dim3((unsigned)((a.B + W2 - 1) / W2)), b, 0, st, a);
     else if (g_stack_shape == 1)
-        hipLaunchKernelGGL((k_stack_fl<NP, NE, W1, true>), dim3((unsigned)((a.B + W1 - 1) / W1)), b, 0, st, a);
+        hipLaunchKernelGGL((k_stack_fl<NP, NE, W1, true, WF>), dim3((unsigned)((a.B + W1 - 1) / W1)), b, 0, st, a);
     else
-        hipLaunchKernelGGL((k_stack_fl<NP, NE, W1, false>), dim3((unsigned)((a.B + W1 - 1) / W1)), b, 0, st, a);
+        hipLaunchKernelGGL((k_stack_fl<NP, NE, W1, false, WF>), dim3((unsigned)((a.B + W1 - 1) / W1)), b, 0, st, a);
 }
 
-template <int NP>
+template <int NP, bool WF>
 static void launch_np(const StackArgs &a, int N, hipStream_t st)
 {
     switch (N) {
-    case 2: launch_ne<NP, 2>(a, st); break;
-    case 3: launch_ne<NP, 3>(a, st); break;
-    default: launch_ne<NP, 4>(a, st); break;
+    case 2: launch_ne<NP, 2, WF>(a, st); break;
+    case 3: launch_ne<NP, 3, WF>(a, st); break;
+    default: launch_ne<NP, 4, WF>(a, st); break;
     }
 }
 
@@ -298,9 +326,12 @@ void launch_stack(int mode, const StackArgs &a, int N, hipStream_t st)
 {
     if (a.B <= 0) return;
     switch (mode) {
-    case GEMM_BF16: launch_np<1>(a, N, st); break;
-    case GEMM_BF16X3: launch_np<2>(a, N, st); break;
-    default: launch_np<3>(a, N, st); break;
+    case GEMM_BF16: launch_np<1, false>(a, N, st); break;
+    case GEMM_BF16X3: launch_np<2, false>(a, N, st); break;
+    default:
+        if (a.Wx32[0]) launch_np<3, true>(a, N, st);
+        else launch_np<3, false>(a, N, st);
+        break;
     }
 }
 
