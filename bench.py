@@ -5,8 +5,11 @@ sums, Eq. 2-3 of the paper) of every walker of one batch: LiH (Li Z=3 at the
 origin, H Z=1 at 3.015 bohr, 2 up + 2 down electrons), FermiNet with 4
 layers, widths 256/32, 16 determinants, 4096 walkers, seeded synthetic
 parameters and walker positions resident on the GPU.  The mixed-precision
-path (six-product BF16 split, FP32 operand accuracy) is timed, then the plain
-FP32 path and the two-part BF16 split on the same inputs.  The walkers are
+path (BF16 layer weights, FP32 activations carried exactly as three BF16
+parts, FP32 accumulation) is timed, then the plain FP32 path, the six-product
+split and the two-part split on the same network and inputs.  In the
+BF16-weight modes the network's layer weights are the BF16 roundings of the
+seeded parameters, and every leg and the oracle use those parameters.  The walkers are
 samples of |psi|^2 (tests/golden/equilibrated_walkers.npz, written by the
 oracle's own Metropolis chain), the distribution Eq. 1 averages over; the
 mixed result counts only if its batch-mean energy over every walker is within
@@ -30,10 +33,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "local-energy evals/s on 1 GPU (mixed vs plain FP32 at dE<=1 mHa); p50/p99 latency"
-PEAK_TFLOPS = {"bf16": 2516.6, "bf16x3": 2516.6, "bf16x6": 2516.6, "fp32": 157.3, "fp64": 78.6}
-DTYPE = {"bf16": "bf16", "bf16x3": "bf16", "bf16x6": "bf16", "fp32": "f32", "fp64": "f64"}
+PEAK_TFLOPS = {"bf16": 2516.6, "bf16x3": 2516.6, "bf16x6": 2516.6, "bf16w": 2516.6, "bf16w2": 2516.6, "fp32": 157.3,
+               "fp64": 78.6}
+DTYPE = {"bf16": "bf16", "bf16x3": "bf16", "bf16x6": "bf16", "bf16w": "bf16", "bf16w2": "bf16", "fp32": "f32",
+         "fp64": "f64"}
 # matrix-core products executed per algorithmic product (operand splits)
-PRODUCTS = {"bf16": 1, "bf16x3": 3, "bf16x6": 6, "fp32": 1, "fp64": 1}
+PRODUCTS = {"bf16": 1, "bf16x3": 3, "bf16x6": 6, "bf16w": 3, "bf16w2": 2, "fp32": 1, "fp64": 1}
 HBM_PEAK_GBPS = 8000.0
 
 
@@ -53,6 +58,15 @@ def stream_gemm_flops(s, walkers):
     return tot, per_layer
 
 
+def mean_field_flops(s, walkers):
+    """Algorithmic FLOPs of the per-walker mean-field products of one
+    local-energy pass: 2 B T (2 d_h) w1 per layer ([g_up | g_dn] V_g over the
+    T = 3N + 2 rows of each walker)."""
+    from paper_2401_10287_amd import inputs as I
+    T = 3 * s.n_elec + 2
+    return sum(2 * walkers * T * 2 * I.layer_dims(s, l)[0] * s.w1 for l in range(s.n_layers))
+
+
 def time_steps(fn, steps, torch):
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
@@ -70,6 +84,8 @@ def time_steps(fn, steps, torch):
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2401_10287_amd", "csrc", "fn_layer.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_layer_hbm_traffic.md")
+STACK_SOURCE = os.path.join(ROOT, "paper_2401_10287_amd", "csrc", "fn_stackr.hip")
+STACK_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stacked_registers_hbm_traffic.md")
 
 
 def copy_calibration():
@@ -85,21 +101,21 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": 4 * n, "copies": 5}))
 
 
-def kernel_hash():
+def kernel_hash(path=KERNEL_SOURCE):
     import hashlib
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """Bytes per launch of the stream layer from the committed counter
-    summary, or None when the kernel source changed since it was taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(summary=TRAFFIC_FILE, source=KERNEL_SOURCE):
+    """Bytes per launch of a kernel from its committed counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    if not os.path.exists(summary):
         return None
     import re
-    txt = open(TRAFFIC_FILE).read()
+    txt = open(summary).read()
     m = re.search(r"kernel source sha256\[:16\]: `([0-9a-f]+)`", txt)
     t = re.search(r"traffic per launch \(bytes\): `([0-9.e+]+)`", txt)
-    if not m or not t or m.group(1) != kernel_hash():
+    if not m or not t or m.group(1) != kernel_hash(source):
         return None
     return float(t.group(1))
 
@@ -201,7 +217,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="bf16x6", choices=["bf16", "bf16x3", "bf16x6", "fp32"])
+    ap.add_argument("--precision", default="bf16w", choices=["bf16", "bf16x3", "bf16x6", "bf16w", "bf16w2", "fp32"])
     ap.add_argument("--walkers", type=int, default=4096)
     ap.add_argument("--sample", type=int, default=4096,
                     help="walkers checked against / timed on the CPU oracle (default: the whole batch, ~10 s)")
@@ -226,13 +242,15 @@ def main():
     import parity_tools as T
 
     s = I.lih(args.walkers)
-    theta = I.init_params(s)
+    theta = I.init_params(s).astype(np.float32).astype(np.float64)
+    if args.precision in fnvmc.BF16_WEIGHT_PRECISIONS:
+        theta = T.bf16_weights(s, theta)       # the BF16-weight network, in every leg
     x = T.equilibrated("LiH", args.walkers)
     dev = torch.device("cuda:0")
     xt = torch.tensor(x, device=dev)
     out = {}
     results = {}
-    precs = [args.precision, "fp32"] + (["bf16x3"] if args.precision != "bf16x3" else [])
+    precs = [args.precision, "fp32"] + [p for p in ("bf16x6", "bf16x3") if p != args.precision]
     for prec in precs:
         cfg = fnvmc.Config(s, prec)
         tt = torch.tensor(theta, dtype=cfg.param_dtype, device=dev)
@@ -308,23 +326,32 @@ def main():
     d_mixed = acc_mixed["batch_mean_err_mHa"]
     gate_ok = d_mixed <= 1.0 and acc_mixed["worst_err_over_bound"] <= 1.0
     x3 = results.get("bf16x3")
+    x6 = results.get("bf16x6") if args.precision != "bf16x6" else None
     print(f"[bench] oracle {samp} walkers in {t_orc:.2f}s; batch-mean |dE| mixed {d_mixed:.5f} mHa, fp32 "
           f"{acc_fp32['batch_mean_err_mHa']:.5f} mHa; worst |dE| / bound mixed "
           f"{acc_mixed['worst_err_over_bound']:.3f}, fp32 {acc_fp32['worst_err_over_bound']:.3f}",
           file=sys.stderr, flush=True)
 
-    # roofline of the dominant kernel (per-electron stream-layer product)
+    # roofline of the dominant kernel: the stacked one-electron stream (every
+    # layer's per-electron and mean-field products in one launch per step)
+    # or, layer by layer, the fused stream layer (per-electron product)
     kern = results["kernels"]
     ms_g, n_g = results["stream_gemm"]
     flops, _ = stream_gemm_flops(s, args.walkers)
-    launches_per_step = s.n_layers
+    stacked = n_g == args.steps
     avg_launch_s = ms_g / max(n_g, 1) * 1e-3
-    flops_per_launch = flops / launches_per_step
+    if stacked:
+        flops_per_launch = flops + mean_field_flops(s, args.walkers)
+        kernel_name = "k_stack_regs (every one-electron layer, per-electron and mean-field products)"
+        traffic = measured_traffic(STACK_TRAFFIC_FILE, STACK_SOURCE) if args.walkers == 4096 else None
+    else:
+        flops_per_launch = flops / s.n_layers
+        kernel_name = "k_stream_layer (one layer's per-electron product and epilogue)"
+        # the committed counter summary covers the six-product split at 4096 walkers
+        traffic = measured_traffic() if (args.precision == "bf16x6" and args.walkers == 4096) else None
     achieved = flops_per_launch / avg_launch_s / 1e12
     peak = PEAK_TFLOPS[args.precision]
     total_kernel_ms = sum(v[0] for v in kern.values())
-    # the committed counter summary covers the default workload (bf16x6, 4096 walkers)
-    traffic = measured_traffic() if (args.precision == "bf16x6" and args.walkers == 4096) else None
     nb = results["breakdown_steps"]
 
     line = {
@@ -351,6 +378,10 @@ def main():
                           "from the seeded start)",
             "accuracy": {"oracle_walkers": samp, "batch_mean_over": "all walkers", "mixed": acc_mixed,
                          "fp32": acc_fp32, "gate_passed": gate_ok},
+            "bf16x6": None if x6 is None else {
+                "evals_per_s": args.walkers / (x6["wall"] / args.steps),
+                "accuracy": acc(x6["e"], True),
+                "note": "six-product split of FP32 weights and activations (FP32 operand precision)"},
             "bf16x3": None if x3 is None else {
                 "evals_per_s": args.walkers / (x3["wall"] / args.steps),
                 "accuracy": acc(x3["e"], True),
@@ -362,7 +393,7 @@ def main():
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "stream_gemm",
+            "kernel": kernel_name,
             "achieved": achieved,
             "peak": peak,
             "unit": "TFLOP/s",

@@ -72,13 +72,28 @@ typedef int32_t fn_status;
    FN_BF16X6_MIXED: each operand split into three BF16 parts and the six
    products whose part indices sum to at most 2, accumulated in FP32 (FP32
    operand precision on the BF16 matrix cores); the orbital head uses the
-   same split.  In every mode the envelope, the determinants and their
-   derivative traces run in FP64. */
+   same split.
+   FN_BF16W_MIXED: BF16 stream weights with FP32 activations.  The weight
+   matrices V of the one-electron layers are taken as their BF16 values
+   (each FP32 parameter rounded to nearest even); the activations, tangent
+   and Laplacian rows stay FP32 and enter the products split exactly into
+   three BF16 parts, so each layer product is three BF16 matrix products
+   whose terms are exact, accumulated in FP32.  Every call in this mode
+   (values, local energies, Metropolis moves, gradients) is the network whose
+   V are so rounded; gradients are with respect to those rounded entries.
+   The orbital head keeps FP32 weights (six-product split), the pair layers
+   FP32.
+   FN_BF16W2_MIXED: as FN_BF16W_MIXED with the activations split into two
+   BF16 parts (16 significant bits), two products per layer product.
+   In every mode the envelope, the determinants and their derivative traces
+   run in FP64. */
 #define FN_FP64 0
 #define FN_FP32 1
 #define FN_BF16_MIXED 2
 #define FN_BF16X3_MIXED 3
 #define FN_BF16X6_MIXED 4
+#define FN_BF16W_MIXED 5
+#define FN_BF16W2_MIXED 6
 
 /* Envelope of Eq. 4, sum_m pi_im exp(-|Sigma_im (r_j - R_m)|).
    FN_ENV_ANISOTROPIC: Sigma_im is a 3x3 matrix (9 parameters).
@@ -390,6 +405,12 @@ fn_status fn_timing_read(const char *name, double *total_ms, int64_t *launches);
    2 in every split-BF16 mode.  "stack_shape" 0/1/2: that kernel's
    workgroup shape (64 rows, two workgroups per CU; 64 rows with the next
    step's weights prefetched; 128 rows prefetched); bitwise the same results.
+   "stack_regs" 0/1: for four electrons, two of each spin, w1 = 256, in the
+   modes with one BF16 weight part (FN_BF16_MIXED, FN_BF16W_MIXED,
+   FN_BF16W2_MIXED), every one-electron layer of a forward-Laplacian pass in
+   one kernel that keeps the activations in registers and streams the
+   weights through LDS (default 1; "layer_stack" 0 turns it off as well);
+   it differs from the layer-by-layer kernels in summation order only.
    "fp32_products" 0..7 (diagnostic): in the split-BF16 modes, run the
    stream-layer (bit 0), mean-field (bit 1) and orbital-head (bit 2)
    products on the FP32 matrix cores instead.

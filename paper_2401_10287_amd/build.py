@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfnvmc.so")
 OBJDIR = os.path.join(PKG, "_build")
-SOURCES = ["fn_api.hip", "fn_gemm.hip", "fn_layer.hip", "fn_net.hip", "fn_mc.hip", "fn_backward.hip", "fn_serve.hip", "fn_init.hip", "fn_stack.hip"]
+SOURCES = ["fn_api.hip", "fn_gemm.hip", "fn_layer.hip", "fn_net.hip", "fn_mc.hip", "fn_backward.hip", "fn_serve.hip", "fn_init.hip", "fn_stack.hip", "fn_stackr.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

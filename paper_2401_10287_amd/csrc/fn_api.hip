@@ -112,6 +112,7 @@ struct Ctx {
     int smode;       // per-electron stream-layer products
     int wmode;       // per-walker mean-field products
     int hmode;       // orbital head product
+    bool round_v;    // the layer weights V are their BF16 roundings (FN_BF16W*_MIXED)
     double vnn;
 };
 
@@ -127,7 +128,7 @@ fn_status make_ctx(const fn_config *cfg, Ctx &c)
     if (cfg->w1 < 1 || cfg->w1 > FN_MAX_W1) return fail(FN_EINVAL, "w1 out of range 1..1024");
     if (cfg->w2 < 1 || cfg->w2 > FN_MAX_W2) return fail(FN_EINVAL, "w2 out of range 1..64");
     if (cfg->n_det < 1 || cfg->n_det > FN_MAX_DET) return fail(FN_EINVAL, "n_det out of range 1..32");
-    if (cfg->precision < FN_FP64 || cfg->precision > FN_BF16X6_MIXED) return fail(FN_EINVAL, "unknown precision");
+    if (cfg->precision < FN_FP64 || cfg->precision > FN_BF16W2_MIXED) return fail(FN_EINVAL, "unknown precision");
     if (cfg->envelope != FN_ENV_ANISOTROPIC && cfg->envelope != FN_ENV_ISOTROPIC)
         return fail(FN_EINVAL, "unknown envelope form");
     Sys &s = c.s;
@@ -154,17 +155,26 @@ fn_status make_ctx(const fn_config *cfg, Ctx &c)
     c.prec = cfg->precision;
     c.f64 = c.prec == FN_FP64;
     c.esz = c.f64 ? 8 : 4;
-    c.smode = c.f64 ? GEMM_F64
-                    : (c.prec == FN_FP32 ? GEMM_F32
-                                         : (c.prec == FN_BF16_MIXED ? GEMM_BF16
-                                                                    : (c.prec == FN_BF16X3_MIXED ? GEMM_BF16X3 : GEMM_BF16X6)));
+    switch (c.prec) {
+    case FN_FP64: c.smode = GEMM_F64; break;
+    case FN_FP32: c.smode = GEMM_F32; break;
+    case FN_BF16_MIXED: c.smode = GEMM_BF16; break;
+    case FN_BF16X3_MIXED: c.smode = GEMM_BF16X3; break;
+    case FN_BF16W_MIXED: c.smode = GEMM_BF16W3; break;
+    case FN_BF16W2_MIXED: c.smode = GEMM_BF16W2; break;
+    default: c.smode = GEMM_BF16X6; break;
+    }
     // orbital head: FP32 operands; the six-product BF16 split carries them to
-    // FP32 accuracy on the matrix cores, so that mode uses it here as well
-    c.hmode = c.f64 ? GEMM_F64 : (c.smode == GEMM_BF16X6 ? GEMM_BF16X6 : GEMM_F32);
+    // FP32 accuracy on the matrix cores, so the modes with FP32-exact
+    // activation splits use it here as well (with FP32 weights)
+    c.hmode = c.f64 ? GEMM_F64
+                    : (c.smode == GEMM_BF16X6 || c.smode == GEMM_BF16W3 || c.smode == GEMM_BF16W2 ? GEMM_BF16X6
+                                                                                                 : GEMM_F32);
     c.wmode = c.smode;
+    c.round_v = bf16_weight_mode(c.smode);
     // diagnostic: selected product classes on the FP32 matrix cores in the
     // split-BF16 modes (tuning switch "fp32_products")
-    if (c.smode == GEMM_BF16 || c.smode == GEMM_BF16X3 || c.smode == GEMM_BF16X6) {
+    if (split_mode(c.smode)) {
         if (g_fp32_products & 1) c.smode = GEMM_F32;
         if (g_fp32_products & 2) c.wmode = GEMM_F32;
         if (g_fp32_products & 4) c.hmode = GEMM_F32;
@@ -191,6 +201,8 @@ struct Plan {
     int64_t Bc;
     size_t wx[FN_MAX_LAYERS], wg[FN_MAX_LAYERS], wh[2], wb[2];
     size_t wx32[FN_MAX_LAYERS], wg32[FN_MAX_LAYERS];   // FP32 copies for the stacked kernel (0: none)
+    size_t vr[FN_MAX_LAYERS];  // BF16-rounded layer weights V in the parameter layout (backward, BF16-weight modes)
+    bool vround;
     bool stack32;
     size_t wpair;        // FP32 pair weights in the matrix-core pair kernel's layout (FP32 parameters only)
     int64_t wxpart[FN_MAX_LAYERS], wgpart[FN_MAX_LAYERS];   // elements per BF16 part
@@ -225,7 +237,7 @@ fn_status make_plan(const Ctx &c, int64_t B, int op, Plan &p)
     }
     size_t o = 0;
     const size_t se = gemm_elem(c.smode), we = gemm_elem(c.wmode), he = gemm_elem(c.hmode), e = c.esz;
-    const int np = gemm_parts(c.smode), npw = gemm_parts(c.wmode);
+    const int np = weight_parts(c.smode), npw = weight_parts(c.wmode);
     for (int l = 0; l < s.L; ++l) {
         size_t nx = (size_t)s.w1 * (c.W.HWl[l] + c.W.GWl[l]), ng = (size_t)s.w1 * 2 * c.W.HWl[l];
         p.wxpart[l] = (int64_t)nx;
@@ -240,12 +252,17 @@ fn_status make_plan(const Ctx &c, int64_t B, int op, Plan &p)
             p.wx32[l] = o; o = al(o + (size_t)p.wxpart[l] * sizeof(float));
             p.wg32[l] = o; o = al(o + (size_t)p.wgpart[l] * sizeof(float));
         }
+    p.vround = p.save && c.round_v;
+    if (p.vround)
+        for (int l = 0; l < s.L; ++l) {
+            p.vr[l] = o; o = al(o + (size_t)layer_din(s, l) * s.w1 * e);
+        }
     p.wpair = o;
     if (c.esz == sizeof(float)) o = al(o + (size_t)pair_mfma_woff(s, s.L > 1 ? s.L - 1 : 0) * sizeof(float));
     for (int sp = 0; sp < 2; ++sp) {
         int n = sp == 0 ? s.nu : s.nd;
         size_t nh = (size_t)s.K * n * c.W.W1p;
-        p.wh[sp] = o; o = al(o + nh * he * gemm_parts(c.hmode));
+        p.wh[sp] = o; o = al(o + nh * he * weight_parts(c.hmode));
         p.wb[sp] = o; if (p.save) o = al(o + (size_t)s.w1 * c.W.KNp[sp] * e);
     }
     // sizes that do not scale with the walker chunk
@@ -340,16 +357,23 @@ void pack_weights(const Ctx &c, const Plan &p, const T *theta, char *ws, hipStre
     };
     for (int l = 0; l < s.L; ++l) {
         PackSeg g{};
-        g.kind = 0; g.mode = c.smode; g.mode2 = c.wmode; g.off = c.P.V[l];
+        g.kind = 0; g.mode = c.smode; g.mode2 = c.wmode; g.off = c.P.V[l]; g.round = c.round_v;
         g.dh = layer_dh(s, l); g.dp = layer_dp(s, l); g.w1 = s.w1; g.HWl = c.W.HWl[l]; g.GWl = c.W.GWl[l];
         g.count = (int64_t)s.w1 * (g.HWl + g.GWl) + (int64_t)s.w1 * 2 * g.HWl;
         g.d0 = ws + p.wx[l]; g.d1 = ws + p.wg[l];
         add(g);
     }
+    if (p.vround)
+        for (int l = 0; l < s.L; ++l) {
+            PackSeg g{};
+            g.kind = 3; g.off = c.P.V[l]; g.count = (int64_t)layer_din(s, l) * s.w1;
+            g.d0 = ws + p.vr[l];
+            add(g);
+        }
     if (p.stack32)
         for (int l = 0; l < s.L; ++l) {
             PackSeg g{};
-            g.kind = 0; g.mode = GEMM_F32; g.mode2 = GEMM_F32; g.off = c.P.V[l];
+            g.kind = 0; g.mode = GEMM_F32; g.mode2 = GEMM_F32; g.off = c.P.V[l]; g.round = c.round_v;
             g.dh = layer_dh(s, l); g.dp = layer_dp(s, l); g.w1 = s.w1; g.HWl = c.W.HWl[l]; g.GWl = c.W.GWl[l];
             g.count = (int64_t)s.w1 * (g.HWl + g.GWl) + (int64_t)s.w1 * 2 * g.HWl;
             g.d0 = ws + p.wx32[l]; g.d1 = ws + p.wg32[l];
@@ -414,7 +438,9 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
     bool stacked = false;
     if constexpr (std::is_same<T, float>::value) {
         // every one-electron layer in one kernel (activations stay in LDS)
-        if (fl && !p.save && c.wmode == c.smode && stack_supported(c.smode, s.N, TR, s.w1, s.L)) {
+        const bool regs = fl && !p.save && c.wmode == c.smode &&
+                          stack_regs_supported(c.smode, s.N, s.nu, TR, s.w1, s.L, c.W.HWl, c.W.GWl);
+        if (regs || (fl && !p.save && c.wmode == c.smode && stack_supported(c.smode, s.N, TR, s.w1, s.L))) {
             StackArgs sa{};
             sa.H0 = Hbuf(0); sa.ldh = ldh;
             sa.GI = GI; sa.ldgi = ldg; sa.gi_stride = p.gi_layer_stride;
@@ -431,7 +457,8 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
             sa.Hout = Hbuf(s.L);
             sa.B = b; sa.L = s.L; sa.nu = s.nu; sa.n3 = n3;
             Timed t_(K_STREAM_GEMM, st);
-            launch_stack(c.smode, sa, s.N, st);
+            if (regs) launch_stack_regs(c.smode, sa, st);
+            else launch_stack(c.smode, sa, s.N, st);
             stacked = true;
         }
     }
@@ -641,6 +668,8 @@ void backward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *x
         const T *Hl = (const T *)(ws + p.H[l]);
         const T *Tl = (const T *)(ws + p.Tl) + (int64_t)l * rows * w1;
         const int64_t voff = c.P.V[l];
+        // the layer's weights as the forward multiplied with them
+        const T *Vl = p.vround ? (const T *)(ws + p.vr[l]) : theta + voff;
         launch_bwd_gz<T>(Gy, Tl, b, N, w1, Gz, SGz, st);
         launch_colsum<T>(Gz, w1, w1, rows, part, gacc, c.P.b[l], 0, 0, st);
         launch_tn<T>(Hl, ldh, dh, Gz, w1, w1, rows, 0, 0, 0, part, gacc, voff, w1, st);
@@ -652,7 +681,7 @@ void backward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *x
         // adjoints of the pair means (to the pair stream) and of h^l
         GemmArgs gq{};
         gq.A1 = Gz; gq.lda1 = w1; gq.K1 = w1;
-        gq.W = theta + voff + (int64_t)3 * dh * w1; gq.ldw = w1;
+        gq.W = Vl + (int64_t)3 * dh * w1; gq.ldw = w1;
         gq.C = GGI + (int64_t)l * p.gi_layer_stride; gq.ldc = ldg;
         gq.rows = rows; gq.nout = 2 * dp;
         gq.rows_per_group = rows;
@@ -660,14 +689,14 @@ void backward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *x
         if (l == 0) break;
         GemmArgs gh{};
         gh.A1 = Gz; gh.lda1 = w1; gh.K1 = w1;
-        gh.W = theta + voff; gh.ldw = w1;
+        gh.W = Vl; gh.ldw = w1;
         gh.C = Gh; gh.ldc = dh;
         gh.rows = rows; gh.nout = dh;
         gh.rows_per_group = rows;
         (void)launch_gemm(gmode, gh, st);
         GemmArgs gg{};
         gg.A1 = SGz; gg.lda1 = w1; gg.K1 = w1;
-        gg.W = theta + voff + (int64_t)dh * w1; gg.ldw = w1;
+        gg.W = Vl + (int64_t)dh * w1; gg.ldw = w1;
         gg.C = Gg; gg.ldc = 2 * dh;
         gg.rows = b; gg.nout = 2 * dh;
         gg.rows_per_group = b;
@@ -1120,6 +1149,11 @@ fn_status fn_tuning_set(const char *name, int64_t value)
     if (strcmp(name, "pair_oc") == 0) {
         if (value != 0 && value != 1 && value != 2 && value != 4) return fail(FN_EINVAL, "pair_oc: 0, 1, 2 or 4");
         fn::g_pair_oc = (int)value;
+        return FN_OK;
+    }
+    if (strcmp(name, "stack_regs") == 0) {
+        if (value < 0 || value > 1) return fail(FN_EINVAL, "stack_regs: 0 or 1");
+        fn::g_stack_regs = value != 0;
         return FN_OK;
     }
     if (strcmp(name, "layer_stack") == 0) {

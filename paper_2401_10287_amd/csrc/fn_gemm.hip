@@ -18,6 +18,10 @@
 //   GEMM_BF16X3 x = hi + lo split of each FP32 operand, hi*hi + hi*lo + lo*hi
 //   GEMM_BF16X6 x = hi + mid + lo split, the six products whose part indices
 //               sum to at most 2 (FP32-level operand precision)
+//   GEMM_BF16W3 BF16 weights (the parameters rounded to nearest even) times
+//               the exact hi + mid + lo split of the FP32 activations: three
+//               products, each exact, accumulated in FP32
+//   GEMM_BF16W2 BF16 weights times the hi + lo split of the activations
 //   GEMM_F64    FP64 on the vector ALUs (64 x 64 tiles)
 #include "fn_internal.h"
 
@@ -41,7 +45,8 @@ constexpr int LDF = BK + 4;   // LDS row stride of FP32 tiles (144 bytes)
 template <int MODE>
 struct ModeInfo {
     static constexpr bool F32 = MODE == GEMM_F32;
-    static constexpr int NP = MODE == GEMM_BF16 ? 1 : (MODE == GEMM_BF16X3 ? 2 : (MODE == GEMM_BF16X6 ? 3 : 1));
+    static constexpr int NA = act_parts(MODE);      // BF16 parts of the activation operand
+    static constexpr int NW = weight_parts(MODE);   // BF16 parts of the weight operand
 };
 
 // DMA (split-BF16 modes, 128-column tiles, K1 a multiple of 32): operand
@@ -52,16 +57,16 @@ template <int MODE, int BNT, bool DMA>
 __device__ __forceinline__ void gemm_tile(const GemmArgs &a, int64_t bid)
 {
     constexpr bool F32 = ModeInfo<MODE>::F32;
-    constexpr int NP = ModeInfo<MODE>::NP;
+    constexpr int NA = ModeInfo<MODE>::NA, NW = ModeInfo<MODE>::NW;
     static_assert(!DMA || (BNT == 128 && !F32), "staged copies");
     // wave tiling: 2 x 2 waves of 64 x 64 for 128 columns, else 4 x 1 waves of 32 x BNT
     constexpr int WI = BNT == 128 ? 4 : 2;          // 16-row blocks per wave
     constexpr int WJ = BNT == 128 ? 4 : BNT / 16;   // 16-column blocks per wave
-    constexpr int AST = BM * BK * 4, STG = AST + NP * BNT * BK * 2;
+    constexpr int AST = BM * BK * 4, STG = AST + NW * BNT * BK * 2;
     __shared__ __attribute__((aligned(16))) float sAf[F32 ? BM * LDF : 1];
     __shared__ __attribute__((aligned(16))) float sBf[F32 ? BNT * LDF : 1];
-    __shared__ __attribute__((aligned(16))) uint16_t sAh[F32 || DMA ? 8 : NP * BM * LDH];
-    __shared__ __attribute__((aligned(16))) uint16_t sBh[F32 || DMA ? 8 : NP * BNT * LDH];
+    __shared__ __attribute__((aligned(16))) uint16_t sAh[F32 || DMA ? 8 : NA * BM * LDH];
+    __shared__ __attribute__((aligned(16))) uint16_t sBh[F32 || DMA ? 8 : NW * BNT * LDH];
     __shared__ __attribute__((aligned(16))) unsigned char sR[DMA ? 2 * STG : 16];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -96,7 +101,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, int64_t bid)
     constexpr int NWF = F32 ? (BNT * 8 + 255) / 256 : 1;      // float4 of B per thread
     constexpr int NWH = F32 ? 1 : (BNT * 4 + 255) / 256;      // uint4 of B per thread per part
     float4 ra[4];
-    uint4 rwh[F32 ? 1 : NWH * NP];
+    uint4 rwh[F32 ? 1 : NWH * NW];
     float4 rwf[NWF];
 
     auto load_tile = [&](int kt) {
@@ -122,10 +127,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, int64_t bid)
                                                      : make_float4(0.f, 0.f, 0.f, 0.f);
             }
         } else {
-            // the NP weight parts are stored one after another, part stride a.wpart elements
+            // the NW weight parts are stored one after another, part stride a.wpart elements
             const uint16_t *W = (const uint16_t *)a.W;
 #pragma unroll
-            for (int q = 0; q < NP; ++q)
+            for (int q = 0; q < NW; ++q)
 #pragma unroll
                 for (int v = 0; v < NWH; ++v) {
                     int f = tid + 256 * v;
@@ -145,11 +150,11 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, int64_t bid)
             if constexpr (F32) {
                 *(float4 *)&sAf[r * LDF + k] = x;
             } else {
-                uint32_t h01[NP], h23[NP];
-                split_bf16_pair<NP>(x.x, x.y, h01);
-                split_bf16_pair<NP>(x.z, x.w, h23);
+                uint32_t h01[NA], h23[NA];
+                split_bf16_pair<NA>(x.x, x.y, h01);
+                split_bf16_pair<NA>(x.z, x.w, h23);
 #pragma unroll
-                for (int q = 0; q < NP; ++q)
+                for (int q = 0; q < NA; ++q)
                     *(uint2 *)&sAh[q * BM * LDH + r * LDH + 8 * lds_chunk(r, k >> 3) + (k & 7)] = make_uint2(h01[q], h23[q]);
             }
         }
@@ -161,7 +166,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, int64_t bid)
             }
         } else {
 #pragma unroll
-            for (int q = 0; q < NP; ++q)
+            for (int q = 0; q < NW; ++q)
 #pragma unroll
                 for (int v = 0; v < NWH; ++v) {
                     int f = tid + 256 * v;
@@ -207,7 +212,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, int64_t bid)
                 copy16_to_lds(base + (kb < a.K1 ? da1[j] : da2[j]), stg + (4 * wave + j) * 1024);
             const uint16_t *W = (const uint16_t *)a.W + kb;
 #pragma unroll
-            for (int q = 0; q < NP; ++q)
+            for (int q = 0; q < NW; ++q)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
                     copy16_to_lds(W + (int64_t)q * a.wpart + dw[j], stg + AST + q * BNT * BK * 2 + (2 * wave + j) * 1024);
@@ -223,7 +228,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, int64_t bid)
             const float *sA = (const float *)stg;
             const uint16_t *sB = (const uint16_t *)(stg + AST);
             float4 xa[WI][2];
-            bf16x8 ha[NP][WI], hb[NP][WJ];
+            bf16x8 ha[NA][WI], hb[NW][WJ];
 #pragma unroll
             for (int i = 0; i < WI; ++i) {
                 const float *rowp = sA + (ar + 16 * i) * BK;
@@ -231,7 +236,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, int64_t bid)
                 xa[i][1] = *(const float4 *)(rowp + 4 * ((2 * h + 1) ^ sw));
             }
 #pragma unroll
-            for (int q = 0; q < NP; ++q)
+            for (int q = 0; q < NW; ++q)
 #pragma unroll
                 for (int j = 0; j < WJ; ++j) hb[q][j] = *(const bf16x8 *)&sB[q * BNT * LDH + (br + 16 * j) * LDH + ko];
             if (kt + 1 < ktiles) dma(kt + 1, (kt + 1) & 1);
@@ -241,22 +246,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, int64_t bid)
             __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int i = 0; i < WI; ++i) {
-                bf16x8 hp[NP];
-                split_fragment<NP>(xa[i][0], xa[i][1], hp);
+                bf16x8 hp[NA];
+                split_fragment<NA>(xa[i][0], xa[i][1], hp);
 #pragma unroll
-                for (int q = 0; q < NP; ++q) ha[q][i] = hp[q];
+                for (int q = 0; q < NA; ++q) ha[q][i] = hp[q];
             }
-#pragma unroll
-            for (int sum = NP - 1; sum >= 0; --sum)
-#pragma unroll
-                for (int pa = 0; pa <= sum; ++pa)
-#pragma unroll
-                    for (int i = 0; i < WI; ++i)
-#pragma unroll
-                        for (int j = 0; j < WJ; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j], acc[i][j],
-                                                                                0, 0, 0);
-            sched_split_products<NP, WI, WJ>();
+            split_products<NA, NW, WI, WI, WJ>(ha, hb, acc);
+            sched_split_products<NA, NW, WI, WJ>();
             __builtin_amdgcn_s_setprio(0);
         }
     } else {
@@ -283,25 +279,16 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, int64_t bid)
             }
         } else {
             const int ko = 8 * lds_chunk(lane & 15, lane >> 4);   // rows ar + 16 i, br + 16 j share bits 0-3 with lane
-            bf16x8 ha[NP][WI], hb[NP][WJ];
+            bf16x8 ha[NA][WI], hb[NW][WJ];
 #pragma unroll
-            for (int q = 0; q < NP; ++q) {
+            for (int q = 0; q < NA; ++q)
 #pragma unroll
                 for (int i = 0; i < WI; ++i) ha[q][i] = *(const bf16x8 *)&sAh[q * BM * LDH + (ar + 16 * i) * LDH + ko];
 #pragma unroll
+            for (int q = 0; q < NW; ++q)
+#pragma unroll
                 for (int j = 0; j < WJ; ++j) hb[q][j] = *(const bf16x8 *)&sBh[q * BNT * LDH + (br + 16 * j) * LDH + ko];
-            }
-            // products of parts (pa, pb) with pa + pb < NP, smallest first
-#pragma unroll
-            for (int sum = NP - 1; sum >= 0; --sum)
-#pragma unroll
-                for (int pa = 0; pa <= sum; ++pa)
-#pragma unroll
-                    for (int i = 0; i < WI; ++i)
-#pragma unroll
-                        for (int j = 0; j < WJ; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j], acc[i][j],
-                                                                                0, 0, 0);
+            split_products<NA, NW, WI, WI, WJ>(ha, hb, acc);
         }
     }
     }
@@ -351,7 +338,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma2(GemmArgs a0, GemmArgs a1, in
 template <int MODE>
 __device__ __forceinline__ void gemm_splitk_tile(const GemmArgs &a, int64_t bid)
 {
-    constexpr int NP = ModeInfo<MODE>::NP;
+    constexpr int NA = ModeInfo<MODE>::NA, NW = ModeInfo<MODE>::NW;
     static_assert(MODE != GEMM_F32, "split-BF16 modes");
     __shared__ float red[4][32][33];
     const int tid = threadIdx.x;
@@ -359,7 +346,7 @@ __device__ __forceinline__ void gemm_splitk_tile(const GemmArgs &a, int64_t bid)
     const int64_t m0 = (bid % nrb) * 32;
     const int n0 = (int)(bid / nrb) * 32;
     f32x4 acc[2][2];
-    splitk_accumulate<NP>((const float *)a.A1, a.lda1, a.K1, (const float *)a.A2, a.lda2, a.K2,
+    splitk_accumulate<NA, NW>((const float *)a.A1, a.lda1, a.K1, (const float *)a.A2, a.lda2, a.K2,
                           (const uint16_t *)a.W, a.wpart, a.ldw, a.nout, a.rows, m0, n0,
                           [&](int64_t r) { return gemm_a_row(a, r); }, acc);
     splitk_park(acc, red);
@@ -475,16 +462,12 @@ static void launch_bn(int mode, const GemmArgs &a, const GemmArgs *a1, hipStream
 {
     if constexpr (BNT == 128) {
         if (g_layer_dma && mode != GEMM_F32 && a.K1 % BK == 0 && (!a1 || a1->K1 % BK == 0)) {
-            if (mode == GEMM_BF16) launch_kernel<GEMM_BF16, 128, true>(a, a1, st);
-            else if (mode == GEMM_BF16X3) launch_kernel<GEMM_BF16X3, 128, true>(a, a1, st);
-            else launch_kernel<GEMM_BF16X6, 128, true>(a, a1, st);
+            with_split_mode(mode, [&](auto m) { launch_kernel<decltype(m)::value, 128, true>(a, a1, st); });
             return;
         }
     }
     if (mode == GEMM_F32) launch_kernel<GEMM_F32, BNT, false>(a, a1, st);
-    else if (mode == GEMM_BF16) launch_kernel<GEMM_BF16, BNT, false>(a, a1, st);
-    else if (mode == GEMM_BF16X3) launch_kernel<GEMM_BF16X3, BNT, false>(a, a1, st);
-    else launch_kernel<GEMM_BF16X6, BNT, false>(a, a1, st);
+    else with_split_mode(mode, [&](auto m) { launch_kernel<decltype(m)::value, BNT, false>(a, a1, st); });
 }
 
 // narrowest column tile that covers the output, and narrower still when
@@ -520,9 +503,7 @@ static void launch_splitk_mode(const GemmArgs &a, const GemmArgs *a1, hipStream_
 
 static void launch_splitk(int mode, const GemmArgs &a, const GemmArgs *a1, hipStream_t st)
 {
-    if (mode == GEMM_BF16) launch_splitk_mode<GEMM_BF16>(a, a1, st);
-    else if (mode == GEMM_BF16X3) launch_splitk_mode<GEMM_BF16X3>(a, a1, st);
-    else launch_splitk_mode<GEMM_BF16X6>(a, a1, st);
+    with_split_mode(mode, [&](auto m) { launch_splitk_mode<decltype(m)::value>(a, a1, st); });
 }
 
 static void launch_mfma(int mode, const GemmArgs &a, const GemmArgs *a1, hipStream_t st)

@@ -14,6 +14,7 @@
 // In value-only mode (Metropolis, gradient) TR = 1.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <stdint.h>
 
 #include "fnvmc.h"
@@ -71,7 +72,36 @@ inline ParamLayout make_layout(const Sys &s)
 }
 
 // Matrix-product arithmetic.
-enum GemmMode { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16 = 2, GEMM_BF16X3 = 3, GEMM_BF16X6 = 4 };
+//   GEMM_BF16W3 / GEMM_BF16W2: BF16 weights (the parameters rounded to
+//   nearest even when packed) times FP32 activations split into three (exact)
+//   or two BF16 parts: one product per activation part.
+enum GemmMode { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16 = 2, GEMM_BF16X3 = 3, GEMM_BF16X6 = 4, GEMM_BF16W3 = 5,
+                GEMM_BF16W2 = 6 };
+
+// BF16 parts of the activation operand and of the weight operand of a mode
+// (1 for the FP32 / FP64 modes)
+__host__ __device__ constexpr int act_parts(int m)
+{
+    return m == GEMM_BF16X3 || m == GEMM_BF16W2 ? 2 : (m == GEMM_BF16X6 || m == GEMM_BF16W3 ? 3 : 1);
+}
+__host__ __device__ constexpr int weight_parts(int m) { return m == GEMM_BF16X3 ? 2 : (m == GEMM_BF16X6 ? 3 : 1); }
+// modes whose products run on the BF16 matrix instructions
+__host__ __device__ constexpr bool split_mode(int m) { return m >= GEMM_BF16 && m <= GEMM_BF16W2; }
+// modes whose weights are the BF16 roundings of the parameters
+__host__ __device__ constexpr bool bf16_weight_mode(int m) { return m == GEMM_BF16W3 || m == GEMM_BF16W2; }
+
+// f(std::integral_constant<int, MODE>{}) for a split-BF16 mode known at run time
+template <typename F>
+inline void with_split_mode(int mode, F &&f)
+{
+    switch (mode) {
+    case GEMM_BF16: f(std::integral_constant<int, GEMM_BF16>{}); break;
+    case GEMM_BF16X3: f(std::integral_constant<int, GEMM_BF16X3>{}); break;
+    case GEMM_BF16W3: f(std::integral_constant<int, GEMM_BF16W3>{}); break;
+    case GEMM_BF16W2: f(std::integral_constant<int, GEMM_BF16W2>{}); break;
+    default: f(std::integral_constant<int, GEMM_BF16X6>{}); break;
+    }
+}
 
 // LDS layout of the BF16 operand tiles of the matrix-core kernels: rows of
 // 32 elements (four 16-byte chunks, no padding), chunk c of row r stored in
@@ -129,25 +159,59 @@ __device__ inline void split_fragment(float4 x0, float4 x1, bf16x8 (&h)[NP])
     for (int q = 0; q < NP; ++q) h[q] = __builtin_bit_cast(bf16x8, make_uint4(p0[q], p1[q], p2[q], p3[q]));
 }
 
-// Scheduling hint for a reduction step of NB x NJ accumulator blocks and NP
-// operand parts: the first parts' conversions (4 per row block), then each
-// matrix instruction of the first NP - 1 product groups followed by a share
-// of the next parts' conversions (about 20 vector instructions per row
-// block and part), then the remaining matrix instructions.
+// Products of one reduction step, activation fragments in NA BF16 parts and
+// weight fragments in NW parts, for the first NI of WI row blocks.  Equal
+// splits: the pairs (pa, pb) with pa + pb < NA, the smallest terms first
+// (pa + pb descending).  One weight part (BF16 weights): pa = 0 .. NA - 1, so
+// the first group needs only the leading activation part.
+template <int NA, int NW, int NI, int WI, int WJ>
+__device__ __forceinline__ void split_products(const bf16x8 (&ha)[NA][WI], const bf16x8 (&hb)[NW][WJ],
+                                               f32x4 (&acc)[WI][WJ])
+{
+    static_assert(NW == NA || NW == 1, "split pairing");
+    if constexpr (NW == 1) {
+#pragma unroll
+        for (int pa = 0; pa < NA; ++pa)
+#pragma unroll
+            for (int i = 0; i < NI; ++i)
+#pragma unroll
+                for (int j = 0; j < WJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[0][j], acc[i][j], 0, 0, 0);
+    } else {
+#pragma unroll
+        for (int sum = NA - 1; sum >= 0; --sum)
+#pragma unroll
+            for (int pa = 0; pa <= sum; ++pa)
+#pragma unroll
+                for (int i = 0; i < NI; ++i)
+#pragma unroll
+                    for (int j = 0; j < WJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j], acc[i][j],
+                                                                            0, 0, 0);
+    }
+}
+__host__ __device__ constexpr int split_product_count(int na, int nw) { return nw == 1 ? na : na * (na + 1) / 2; }
+
+// Scheduling hint for a reduction step of NB x NJ accumulator blocks with
+// activations in NA parts and weights in NW parts: the first part's
+// conversions (4 per row block), then each matrix instruction of the first
+// NA - 1 product groups followed by a share of the next parts' conversions
+// (about 20 vector instructions per row block and part), then the remaining
+// matrix instructions.
 constexpr int SCHED_VALU = 0x002, SCHED_MFMA = 0x008;
-template <int NP, int NB, int NJ>
+template <int NA, int NW, int NB, int NJ>
 __device__ inline void sched_split_products()
 {
     constexpr int G = NB * NJ, VM = (20 * NB + G - 1) / G;
     __builtin_amdgcn_sched_group_barrier(SCHED_VALU, 4 * NB, 0);
 #pragma unroll
-    for (int g = 0; g < NP - 1; ++g)
+    for (int g = 0; g < NA - 1; ++g)
 #pragma unroll
         for (int m = 0; m < G; ++m) {
             __builtin_amdgcn_sched_group_barrier(SCHED_MFMA, 1, 0);
             __builtin_amdgcn_sched_group_barrier(SCHED_VALU, VM, 0);
         }
-    __builtin_amdgcn_sched_group_barrier(SCHED_MFMA, G * (NP * (NP + 1) / 2 - (NP - 1)), 0);
+    __builtin_amdgcn_sched_group_barrier(SCHED_MFMA, G * (split_product_count(NA, NW) - (NA - 1)), 0);
 }
 
 // bitwise select (m all ones or zero) of a float4
@@ -157,7 +221,8 @@ __device__ inline float4 mask4f(float4 x, uint32_t m)
                        __uint_as_float(__float_as_uint(x.z) & m), __uint_as_float(__float_as_uint(x.w) & m));
 }
 
-// Split-reduction tile of the small-grid products (NP split-BF16 parts): the
+// Split-reduction tile of the small-grid products (activations in NA and
+// weights in NW BF16 parts): the
 // 32 x 32 output tile at (m0, n0) of [A1 | A2] W^T, the 32-wide reduction
 // steps split over the workgroup's four waves in contiguous quarters.  Each
 // wave loads its operand fragments straight from global memory into
@@ -166,9 +231,9 @@ __device__ inline float4 mask4f(float4 x, uint32_t m)
 // acc is this wave's partial tile, accumulator (i, j) element e at row
 // 16 i + 4 (lane / 16) + e, column 16 j + lane % 16.  arow(r): A's row of
 // product row r.  Rows past `rows` and columns past nout load row m0 /
-// column n0 and are zeroed.  A1 / A2 FP32 row-major; W NP parts of BF16
+// column n0 and are zeroed.  A1 / A2 FP32 row-major; W NW parts of BF16
 // rows of ldw (part stride wpart); K1, K2 multiples of 32.
-template <int NP, typename ARow>
+template <int NA, int NW, typename ARow>
 __device__ __forceinline__ void splitk_accumulate(const float *A1, int64_t lda1, int K1, const float *A2, int64_t lda2,
                                                   int K2, const uint16_t *W, int64_t wpart, int64_t ldw, int nout,
                                                   int64_t rows, int64_t m0, int n0, ARow arow, f32x4 (&acc)[2][2])
@@ -190,8 +255,8 @@ __device__ __forceinline__ void splitk_accumulate(const float *A1, int64_t lda1,
         wr[i] = (int64_t)(o < nout ? o : n0) * ldw;
     }
     float4 xa[2][2], na[2][2];
-    uint4 xb[2][NP], nb[2][NP];
-    auto load = [&](int kt, float4 (&A)[2][2], uint4 (&Bv)[2][NP]) {
+    uint4 xb[2][NW], nb[2][NW];
+    auto load = [&](int kt, float4 (&A)[2][2], uint4 (&Bv)[2][NW]) {
         const int kb = kt * 32;
         const bool first = kb < K1;
         const float *base = first ? A1 : A2;
@@ -206,7 +271,7 @@ __device__ __forceinline__ void splitk_accumulate(const float *A1, int64_t lda1,
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int q = 0; q < NP; ++q) Bv[j][q] = *(const uint4 *)(W + (int64_t)q * wpart + wr[j] + kb + 8 * kq);
+            for (int q = 0; q < NW; ++q) Bv[j][q] = *(const uint4 *)(W + (int64_t)q * wpart + wr[j] + kb + 8 * kq);
     };
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -215,37 +280,29 @@ __device__ __forceinline__ void splitk_accumulate(const float *A1, int64_t lda1,
     if (k0 < k1) load(k0, xa, xb);
     for (int kt = k0; kt < k1; ++kt) {
         if (kt + 1 < k1) load(kt + 1, na, nb);
-        bf16x8 ha[NP][2], hb[NP][2];
+        bf16x8 ha[NA][2], hb[NW][2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            bf16x8 hp[NP];
-            split_fragment<NP>(mask4f(xa[i][0], am[i]), mask4f(xa[i][1], am[i]), hp);
+            bf16x8 hp[NA];
+            split_fragment<NA>(mask4f(xa[i][0], am[i]), mask4f(xa[i][1], am[i]), hp);
 #pragma unroll
-            for (int q = 0; q < NP; ++q) ha[q][i] = hp[q];
+            for (int q = 0; q < NA; ++q) ha[q][i] = hp[q];
         }
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int q = 0; q < NP; ++q) {
+            for (int q = 0; q < NW; ++q) {
                 const uint4 u = xb[j][q];
                 hb[q][j] = __builtin_bit_cast(bf16x8, make_uint4(u.x & wm[j], u.y & wm[j], u.z & wm[j], u.w & wm[j]));
             }
-#pragma unroll
-        for (int sum = NP - 1; sum >= 0; --sum)
-#pragma unroll
-            for (int pa = 0; pa <= sum; ++pa)
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j], acc[i][j], 0, 0, 0);
+        split_products<NA, NW, 2, 2, 2>(ha, hb, acc);
         if (kt + 1 < k1) {
 #pragma unroll
             for (int i = 0; i < 2; ++i) { xa[i][0] = na[i][0]; xa[i][1] = na[i][1]; }
 #pragma unroll
             for (int j = 0; j < 2; ++j)
 #pragma unroll
-                for (int q = 0; q < NP; ++q) xb[j][q] = nb[j][q];
+                for (int q = 0; q < NW; ++q) xb[j][q] = nb[j][q];
         }
     }
 }
@@ -263,7 +320,6 @@ __device__ __forceinline__ void splitk_park(const f32x4 (&acc)[2][2], float (&re
     __syncthreads();
 }
 
-inline __host__ __device__ int gemm_parts(int mode) { return mode == GEMM_BF16 ? 1 : (mode == GEMM_BF16X3 ? 2 : (mode == GEMM_BF16X6 ? 3 : 1)); }
 
 // Padded widths.  Every product's reduction dimension is a multiple of 32.
 struct Widths {
@@ -426,6 +482,12 @@ bool stack_supported(int mode, int N, int TR, int w1, int L);
 // them in registers (one copy of every layer's weights fits in L2)
 inline bool stack_fp32_weights(int mode) { return mode == GEMM_BF16X6; }
 void launch_stack(int mode, const StackArgs &a, int N, hipStream_t st);
+// Every one-electron layer with the activations in registers (fn_stackr.hip):
+// four electrons, two per spin, w1 = 256, modes with one BF16 weight part
+// (tuning switch "stack_regs", on by default)
+extern bool g_stack_regs;
+bool stack_regs_supported(int mode, int N, int nu, int TR, int w1, int L, const int *HW, const int *GW);
+void launch_stack_regs(int mode, const StackArgs &a, hipStream_t st);
 // 128-row tiles of the fused layer hold whole walkers
 inline bool stream_layer_whole_walkers(int N, int TR) { return N * TR <= 128 && 128 % (N * TR) == 0; }
 

@@ -12,15 +12,21 @@ namespace fn {
 // Kind 2: FP32 pair block of one pair layer in the matrix-core pair
 // kernel's layout (transposed weights Wt[wc][ks] from off, then the bias
 // [wc] from off2) into d0.
+// kind 0: a layer's Wx / Wg operand blocks; 1: a head block; 2: a pair
+// block; 3: a plain copy of count parameters from off, rounded to BF16 (the
+// layer weights the backward of the BF16-weight modes multiplies with).
+// round: layer weights are taken as their BF16 roundings before packing.
 struct PackSeg {
     int64_t begin, count, off, off2;
     int kind, mode, mode2, dh, dp, w1, HWl, GWl, kn, W1p, w2, wc, ks;   // mode2: Wg of a layer block
+    int round;
     void *d0, *d1;
 };
 struct PackList {
     int n;
-    PackSeg seg[3 * FN_MAX_LAYERS + 2];
+    PackSeg seg[4 * FN_MAX_LAYERS + 2];
 };
+static_assert(sizeof(PackList) < 4000, "kernel argument");
 template <typename T>
 void launch_pack(const T *theta, const PackList &pl, hipStream_t st);
 // G (or nullptr): also the first layer's spin means of the features, in the

@@ -58,15 +58,15 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
     static_assert(LIVE == (TP + 15) / 16 || (TP == 64 && LBN == 128 && LIVE == 3), "live row blocks");
     constexpr int WI = LBN == 128 ? 4 : 2, WJ = LBN == 128 ? 4 : 2;   // 16 x 16 blocks per wave
     constexpr bool F32 = MODE == GEMM_F32;
-    constexpr int NP = MODE == GEMM_BF16 ? 1 : (MODE == GEMM_BF16X3 ? 2 : (MODE == GEMM_BF16X6 ? 3 : 1));
+    constexpr int NA = act_parts(MODE), NW = weight_parts(MODE);   // BF16 parts of activations / weights
     // one operand stage (A then B); the epilogue reuses it for a 128 x 64 tile
-    constexpr int ASZ = F32 ? LBM * LDF * 4 : NP * LBM * LDH * 2;
-    constexpr int BSZ = F32 ? LBN * LDF * 4 : NP * LBN * LDH * 2;
+    constexpr int ASZ = F32 ? LBM * LDF * 4 : NA * LBM * LDH * 2;
+    constexpr int BSZ = F32 ? LBN * LDF * 4 : NW * LBN * LDH * 2;
     constexpr int XS = LBN + 4;                      // float4-aligned rows of the pre-activation tile
     constexpr int XSZ = LBM * XS * 4;
     constexpr int ESZ = XSZ + 256 * 16;              // tile + partial Laplacian sources
-    constexpr int AST = LBM * LBK * 4;               // DMA stage: FP32 activations, then NP weight parts
-    constexpr int STG = AST + NP * LBN * LBK * 2;
+    constexpr int AST = LBM * LBK * 4;               // DMA stage: FP32 activations, then NW weight parts
+    constexpr int STG = AST + NW * LBN * LBK * 2;
     constexpr int MSZ = DMA ? 2 * STG : ASZ + BSZ;
     constexpr int SMEM = MSZ > ESZ ? MSZ : ESZ;
     __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
         offw[v] = (int64_t)(ok ? o : n0) * a.ldw + (F32 ? 4 * (f & 7) : 8 * (f & 3));
     }
     float4 ra[4];
-    uint4 rwh[F32 ? 1 : NBV * NP];
+    uint4 rwh[F32 ? 1 : NBV * NW];
     float4 rwf[F32 ? NBV : 1];
 
     auto load_tile = [&](int kt) {
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
         } else {
             const uint16_t *W = (const uint16_t *)a.W + kb;
 #pragma unroll
-            for (int q = 0; q < NP; ++q)
+            for (int q = 0; q < NW; ++q)
 #pragma unroll
                 for (int v = 0; v < NBV; ++v) rwh[q * NBV + v] = *(const uint4 *)(W + (int64_t)q * a.wpart + offw[v]);
         }
@@ -161,11 +161,11 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
             if constexpr (F32) {
                 *(float4 *)((float *)smem + r * LDF + k) = x;
             } else {
-                uint32_t h01[NP], h23[NP];
-                split_bf16_pair<NP>(x.x, x.y, h01);
-                split_bf16_pair<NP>(x.z, x.w, h23);
+                uint32_t h01[NA], h23[NA];
+                split_bf16_pair<NA>(x.x, x.y, h01);
+                split_bf16_pair<NA>(x.z, x.w, h23);
 #pragma unroll
-                for (int q = 0; q < NP; ++q)
+                for (int q = 0; q < NA; ++q)
                     *(uint2 *)((uint16_t *)smem + q * LBM * LDH + r * LDH + 8 * lds_chunk(r, k >> 3) + (k & 7)) =
                         make_uint2(h01[q], h23[q]);
             }
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
         } else {
             uint16_t *sB = (uint16_t *)(smem + ASZ);
 #pragma unroll
-            for (int q = 0; q < NP; ++q)
+            for (int q = 0; q < NW; ++q)
 #pragma unroll
                 for (int v = 0; v < NBV; ++v) {
                     const int f = tid + 256 * v;
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
                 copy16_to_lds(base + (kb < a.K1 ? da1[j] : da2[j]), stg + (4 * wave + j) * 1024);
             const uint16_t *W = (const uint16_t *)a.W + kb;
 #pragma unroll
-            for (int q = 0; q < NP; ++q)
+            for (int q = 0; q < NW; ++q)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
                     copy16_to_lds(W + (int64_t)q * a.wpart + dw[j], stg + AST + q * LBN * LBK * 2 + (2 * wave + j) * 1024);
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
             const float *sA = (const float *)stg;
             const uint16_t *sB = (const uint16_t *)(stg + AST);
             float4 xa[WI][2];
-            bf16x8 ha[NP][WI], hb[NP][WJ];
+            bf16x8 ha[NA][WI], hb[NW][WJ];
 #pragma unroll
             for (int i = 0; i < WI; ++i)
                 if (i < LIVE || TP != 64) {
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
                     xa[i][1] = *(const float4 *)(rowp + 4 * ((2 * h + 1) ^ sw));
                 }
 #pragma unroll
-            for (int q = 0; q < NP; ++q)
+            for (int q = 0; q < NW; ++q)
 #pragma unroll
                 for (int j = 0; j < WJ; ++j) hb[q][j] = *(const bf16x8 *)&sB[q * LBN * LDH + (br + 16 * j) * LDH + ko];
             if (kt + 1 < ktiles) dma(kt + 1, (kt + 1) & 1);
@@ -274,23 +274,13 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 #pragma unroll
             for (int i = 0; i < WI; ++i)
                 if (i < LIVE || TP != 64) {
-                    bf16x8 hp[NP];
-                    split_fragment<NP>(xa[i][0], xa[i][1], hp);
+                    bf16x8 hp[NA];
+                    split_fragment<NA>(xa[i][0], xa[i][1], hp);
 #pragma unroll
-                    for (int q = 0; q < NP; ++q) ha[q][i] = hp[q];
+                    for (int q = 0; q < NA; ++q) ha[q][i] = hp[q];
                 }
-#pragma unroll
-            for (int sum = NP - 1; sum >= 0; --sum)
-#pragma unroll
-                for (int pa = 0; pa <= sum; ++pa)
-#pragma unroll
-                    for (int i = 0; i < WI; ++i)
-#pragma unroll
-                        for (int j = 0; j < WJ; ++j)
-                            if (i < LIVE || TP != 64)
-                                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j],
-                                                                                    acc[i][j], 0, 0, 0);
-            sched_split_products<NP, TP == 64 ? LIVE : WI, WJ>();
+            split_products<NA, NW, TP == 64 ? LIVE : WI, WI, WJ>(ha, hb, acc);
+            sched_split_products<NA, NW, TP == 64 ? LIVE : WI, WJ>();
             __builtin_amdgcn_s_setprio(0);
         }
     } else {
@@ -321,27 +311,18 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
         } else {
             const uint16_t *sA = (const uint16_t *)smem, *sB = (const uint16_t *)(smem + ASZ);
             const int ko = 8 * lds_chunk(lane & 15, lane >> 4);   // rows ar + 16 i, br + 16 j share bits 0-3 with lane
-            bf16x8 ha[NP][WI], hb[NP][WJ];
+            bf16x8 ha[NA][WI], hb[NW][WJ];
 #pragma unroll
-            for (int q = 0; q < NP; ++q) {
+            for (int q = 0; q < NA; ++q)
 #pragma unroll
                 for (int i = 0; i < WI; ++i)
                     if (i < LIVE || TP != 64)
                         ha[q][i] = *(const bf16x8 *)&sA[q * LBM * LDH + (ar + 16 * i) * LDH + ko];
 #pragma unroll
+            for (int q = 0; q < NW; ++q)
+#pragma unroll
                 for (int j = 0; j < WJ; ++j) hb[q][j] = *(const bf16x8 *)&sB[q * LBN * LDH + (br + 16 * j) * LDH + ko];
-            }
-#pragma unroll
-            for (int sum = NP - 1; sum >= 0; --sum)
-#pragma unroll
-                for (int pa = 0; pa <= sum; ++pa)
-#pragma unroll
-                    for (int i = 0; i < WI; ++i)
-#pragma unroll
-                        for (int j = 0; j < WJ; ++j)
-                            if (i < LIVE || TP != 64)
-                                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[pa][i], hb[sum - pa][j],
-                                                                                    acc[i][j], 0, 0, 0);
+            split_products<NA, NW, TP == 64 ? LIVE : WI, WI, WJ>(ha, hb, acc);
         }
     }
     }
@@ -539,7 +520,7 @@ __global__ __launch_bounds__(256) void k_stream_layer(LayerArgs a)
 template <int MODE>
 __global__ __launch_bounds__(256) void k_stream_value_splitk(LayerArgs a)
 {
-    constexpr int NP = MODE == GEMM_BF16 ? 1 : (MODE == GEMM_BF16X3 ? 2 : 3);
+    constexpr int NA = act_parts(MODE), NW = weight_parts(MODE);
     static_assert(MODE != GEMM_F32, "split-BF16 modes");
     __shared__ float red[4][32][33];
     __shared__ __attribute__((aligned(16))) float sy[32][36];
@@ -562,7 +543,7 @@ __global__ __launch_bounds__(256) void k_stream_value_splitk(LayerArgs a)
     const float4 p4 = *(const float4 *)(a.Pw + (R / a.N) * a.w1 + colc);
     const float4 rv = a.resid ? *(const float4 *)(a.A1 + R * a.lda1 + colc) : make_float4(0.f, 0.f, 0.f, 0.f);
     f32x4 acc[2][2];
-    splitk_accumulate<NP>(a.A1, a.lda1, a.K1, a.A2, a.lda2, a.K2, (const uint16_t *)a.W, a.wpart, a.ldw, a.nout,
+    splitk_accumulate<NA, NW>(a.A1, a.lda1, a.K1, a.A2, a.lda2, a.K2, (const uint16_t *)a.W, a.wpart, a.ldw, a.nout,
                           a.rows, m0, n0, [](int64_t row) { return row; }, acc);
     splitk_park(acc, red);
     float x[4];
@@ -661,9 +642,7 @@ void launch_stream_layer(int mode, const LayerArgs &a, int TR, hipStream_t st)
     if (a.rows <= 0) return;
     switch (mode) {
     case GEMM_F32: launch_mode<GEMM_F32>(a, TR, st); break;
-    case GEMM_BF16: launch_mode<GEMM_BF16>(a, TR, st); break;
-    case GEMM_BF16X3: launch_mode<GEMM_BF16X3>(a, TR, st); break;
-    default: launch_mode<GEMM_BF16X6>(a, TR, st); break;
+    default: with_split_mode(mode, [&](auto m) { launch_mode<decltype(m)::value>(a, TR, st); }); break;
     }
 }
 

@@ -24,7 +24,7 @@ __device__ inline void put_w(int mode, void *base, int64_t part, int64_t idx, T 
         ((float *)base)[idx] = (float)v;
     } else {
         // BF16 parts, round to nearest even: v = p0 + p1 + ... (each rounds the rest)
-        const int np = gemm_parts(mode);
+        const int np = weight_parts(mode);
         float r = (float)v;
         for (int q = 0; q < np; ++q) {
             uint32_t u = __float_as_uint(r);
@@ -33,6 +33,14 @@ __device__ inline void put_w(int mode, void *base, int64_t part, int64_t idx, T 
             r = r - __uint_as_float(h << 16);
         }
     }
+}
+
+// v rounded to the nearest BF16 value, ties to even (NaN stays NaN)
+__device__ inline float bf16_round(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return v;
+    return __uint_as_float(((u + 0x7fffu + ((u >> 16) & 1u)) >> 16) << 16);
 }
 
 // Element t of a layer block.  Wx [w1][HWl + GWl]: per-electron inputs
@@ -47,7 +55,8 @@ __device__ inline void pack_layer_elem(const T *theta, const PackSeg &g, int64_t
         int row = -1;
         if (k < g.dh) row = k;
         else if (k >= g.HWl && k < g.HWl + 2 * g.dp) row = 3 * g.dh + (k - g.HWl);
-        const T v = row >= 0 ? theta[g.off + (int64_t)row * g.w1 + o] : T(0);
+        T v = row >= 0 ? theta[g.off + (int64_t)row * g.w1 + o] : T(0);
+        if (g.round) v = (T)bf16_round((float)v);
         put_w<T>(g.mode, g.d0, nx, t, v);
     } else {
         const int64_t u = t - nx;
@@ -55,7 +64,8 @@ __device__ inline void pack_layer_elem(const T *theta, const PackSeg &g, int64_t
         int row = -1;
         if (k < g.dh) row = g.dh + k;
         else if (k >= g.HWl && k < g.HWl + g.dh) row = 2 * g.dh + (k - g.HWl);
-        const T v = row >= 0 ? theta[g.off + (int64_t)row * g.w1 + o] : T(0);
+        T v = row >= 0 ? theta[g.off + (int64_t)row * g.w1 + o] : T(0);
+        if (g.round) v = (T)bf16_round((float)v);
         put_w<T>(g.mode2, g.d1, ng, u, v);
     }
 }
@@ -96,7 +106,8 @@ __global__ void k_pack(const T *theta, PackList pl, int64_t total)
         const PackSeg &g = pl.seg[q];
         if (g.kind == 0) pack_layer_elem<T>(theta, g, i - g.begin);
         else if (g.kind == 1) pack_head_elem<T>(theta, g, i - g.begin);
-        else pack_pair_elem<T>(theta, g, i - g.begin);
+        else if (g.kind == 2) pack_pair_elem<T>(theta, g, i - g.begin);
+        else ((T *)g.d0)[i - g.begin] = (T)bf16_round((float)theta[g.off + (i - g.begin)]);
     }
 }
 

@@ -20,9 +20,12 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfnvmc.s
 
 FN_OK, FN_EINVAL, FN_ENOMEM, FN_EUNSUPPORTED, FN_EHIP = 0, 1, 2, 3, 4
 FN_FP64, FN_FP32, FN_BF16_MIXED, FN_BF16X3_MIXED, FN_BF16X6_MIXED = 0, 1, 2, 3, 4
+FN_BF16W_MIXED, FN_BF16W2_MIXED = 5, 6
 FN_OP_LOG_PSI, FN_OP_LOCAL_ENERGY, FN_OP_METROPOLIS, FN_OP_PARAM_GRAD = 0, 1, 2, 3
 PRECISIONS = {"fp64": FN_FP64, "fp32": FN_FP32, "bf16": FN_BF16_MIXED, "bf16x3": FN_BF16X3_MIXED,
-              "bf16x6": FN_BF16X6_MIXED}
+              "bf16x6": FN_BF16X6_MIXED, "bf16w": FN_BF16W_MIXED, "bf16w2": FN_BF16W2_MIXED}
+# modes whose one-electron layer weights are the BF16 roundings of the parameters
+BF16_WEIGHT_PRECISIONS = ("bf16w", "bf16w2")
 
 
 class FnError(RuntimeError):

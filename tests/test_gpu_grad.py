@@ -28,6 +28,14 @@ def _group_indices(s):
     return np.array(idx, dtype=np.int64)
 
 
+def _model(s, prec, th):
+    """The parameters the GPU evaluates: in the BF16-weight modes the layer
+    weights rounded to BF16 (the gradient is with respect to those)."""
+    import parity_tools as T
+    from paper_2401_10287_amd import fnvmc
+    return T.bf16_weights(s, th) if prec in fnvmc.BF16_WEIGHT_PRECISIONS else th
+
+
 def _small_lif():
     return I.System("LiF-s", I.lif().nuc_xyz, I.lif().nuc_z, 3, 3, 3, 32, 8, 4, 16, (0, 1, 1, 0, 1, 1), 0.5)
 
@@ -72,7 +80,7 @@ def test_vjp_fp64_finite_differences():
         assert abs(g[i] - fd) <= 1e-6 * max(1.0, abs(fd)), (i, g[i], fd)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x6", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6", "fp64", "bf16w"])
 def test_vjp_against_oracle_lif(prec):
     """LiF training configuration at reduced width and 32 walkers: one
     parameter per tensor group and 4 random directions against the oracle."""
@@ -81,7 +89,7 @@ def test_vjp_against_oracle_lif(prec):
     cfg = fnvmc.Config(s, prec)
     th0 = I.init_params(s, seed=9)
     tt = torch.tensor(th0, dtype=cfg.param_dtype, device="cuda")
-    th = tt.double().cpu().numpy()
+    th = _model(s, prec, tt.double().cpu().numpy())
     x = I.init_walkers(s, 32, seed=10)
     c = np.random.default_rng(11).standard_normal(32) / 32
     g = fnvmc.fn_log_psi_vjp(cfg, tt, torch.tensor(x, device="cuda"), torch.tensor(c, device="cuda"))
@@ -156,7 +164,7 @@ def test_vjp_linear_and_deterministic_full_size():
     np.testing.assert_allclose(ab, a + b, rtol=1e-3, atol=1e-5 * np.abs(ab).max())
 
 
-@pytest.mark.parametrize("prec", ["bf16x6", "fp32"])
+@pytest.mark.parametrize("prec", ["bf16x6", "fp32", "bf16w"])
 def test_vjp_full_size_lif_sampled(prec):
     """The LiF training configuration at full size (4096 walkers, 4 layers
     256/32, 16 determinants): the backward with weights that are non-zero on
@@ -169,7 +177,7 @@ def test_vjp_full_size_lif_sampled(prec):
     s = I.lif()
     cfg = fnvmc.Config(s, prec)
     tt = torch.tensor(I.init_params(s), dtype=torch.float32, device="cuda")
-    th = tt.double().cpu().numpy()
+    th = _model(s, prec, tt.double().cpu().numpy())
     x = T.equilibrated("LiF", 4096)
     rng = np.random.default_rng(21)
     idx = np.sort(rng.choice(512, 32, replace=False))        # distinct stored walkers

@@ -38,6 +38,8 @@ def _setup(s, prec, walkers, seed=I.WALKER_SEED, theta=None, x=None):
     tt = torch.tensor(th, dtype=cfg.param_dtype, device="cuda")
     xt = torch.tensor(x, dtype=torch.float64, device="cuda")
     th_used = tt.double().cpu().numpy()      # the oracle sees exactly the GPU's parameters
+    if prec in fnvmc.BF16_WEIGHT_PRECISIONS:
+        th_used = T.bf16_weights(s, th_used)  # ... which in these modes have BF16 layer weights
     return torch, fnvmc, cfg, tt, xt, th_used, x
 
 
@@ -46,6 +48,15 @@ def _walkers(name, s, walkers):
     if name in ("LiH", "LiF", "H20"):
         return T.equilibrated(name, walkers)
     return I.init_walkers(s, walkers)
+
+
+def _model(torch, prec, tt, th_used):
+    """Parameters on the GPU that give another precision the same model: in
+    the BF16-weight modes the FP32 comparison runs on the rounded weights."""
+    from paper_2401_10287_amd import fnvmc
+    if prec in fnvmc.BF16_WEIGHT_PRECISIONS:
+        return torch.tensor(th_used, dtype=torch.float32, device="cuda")
+    return tt
 
 
 def _energies(fnvmc, torch, s, prec, tt32, xt):
@@ -60,6 +71,7 @@ def _energies(fnvmc, torch, s, prec, tt32, xt):
                                                    ("LiH", "fp32", 64, 1e-5), ("LiH", "fp64", 16, 1e-10),
                                                    ("LiF", "fp32", 16, 1e-5), ("H20", "fp32", 8, 1e-5),
                                                    ("LiH", "bf16x6", 64, 1e-5), ("H20", "bf16x6", 8, 1e-5),
+                                                   ("LiH", "bf16w", 64, 1e-5), ("H20", "bf16w", 8, 1e-5),
                                                    ("LiH", "bf16x3", 64, 1e-3), ("LiH", "bf16", 64, 2e-1)])
 def test_log_psi(name, prec, walkers, tol):
     """Seeded starting walkers (not |psi|^2 samples: some sit near nodes,
@@ -79,7 +91,8 @@ def test_log_psi(name, prec, walkers, tol):
 
 @pytest.mark.parametrize("name,prec,walkers", [("He", "fp64", 256), ("He", "fp32", 256), ("LiH", "fp64", 8),
                                                ("LiH", "fp32", 64), ("LiH", "bf16x6", 64), ("LiF", "fp32", 24),
-                                               ("LiF", "bf16x6", 24), ("H20", "fp32", 6), ("H20", "bf16x6", 6)])
+                                               ("LiF", "bf16x6", 24), ("H20", "fp32", 6), ("H20", "bf16x6", 6),
+                                               ("LiH", "bf16w", 64), ("LiF", "bf16w", 24), ("H20", "bf16w", 6)])
 def test_local_energy(name, prec, walkers):
     """Local energy (Eq. 2, 3) on |psi|^2 samples: per walker and the batch
     mean over every walker (He: seeded walkers, FP64 and FP32)."""
@@ -96,7 +109,7 @@ def test_local_energy(name, prec, walkers):
     kap, C = T.kappa_and_c(o, s, th, x)
     d32 = None
     if prec != "fp32":
-        d32 = np.abs(_energies(fnvmc, torch, s, "fp32", tt, xt) - ref["e_loc"])
+        d32 = np.abs(_energies(fnvmc, torch, s, "fp32", _model(torch, prec, tt, th), xt) - ref["e_loc"])
     T.check_energy(e.cpu().numpy(), ref, f"{name} {prec}", kap, C, s.n_elec, d32=d32, parts=parts.cpu().numpy())
 
 
@@ -130,10 +143,11 @@ def test_local_energy_seeded_walkers(name, walkers):
         assert np.percentile(d6, q) <= 1.5 * np.percentile(d32, q) + 1e-7, q
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16", "bf16w2"])
 def test_local_energy_reduced_splits_reported(prec):
     """The two- and one-part BF16 splits carry 16 and 8 significant bits of
-    each operand: their local-energy errors are measured and printed (they
+    each operand (bf16w2: 16 bits of the activations, BF16 weights taken as
+    the parameters): their local-energy errors are measured and printed (they
     are not claimed against the stated tolerances); results stay finite."""
     s = I.lih()
     x = T.equilibrated("LiH", 64)
@@ -195,6 +209,19 @@ def test_full_size_sampled(name, walkers, n_sample):
     # the whole batch: the two precisions' batch means agree within 1 mHa
     print(f"{name} {walkers}: batch means fp32 {e32.mean():.6f} bf16x6 {e6.mean():.6f}")
     assert abs(e32.mean() - e6.mean()) <= 1e-3
+    # BF16 layer weights: the oracle and FP32 on the rounded parameters
+    thw = T.bf16_weights(s, th)
+    ttw = torch.tensor(thw, dtype=torch.float32, device="cuda")
+    print(f"{name} {walkers}: oracle on {n_sample} walkers, BF16 weights", flush=True)
+    refw = o.local_energy(thw, x[idx])
+    kapw, Cw = T.kappa_and_c(o, s, thw, x[idx])
+    ew32 = _energies(fnvmc, torch, s, "fp32", ttw, xt)
+    ew = _energies(fnvmc, torch, s, "bf16w", tt, xt)
+    assert np.all(np.isfinite(ew))
+    dw32 = T.check_energy(ew32[idx], refw, f"{name} {walkers} fp32 (BF16 weights) sampled", kapw, Cw, s.n_elec)
+    T.check_energy(ew[idx], refw, f"{name} {walkers} bf16w sampled", kapw, Cw, s.n_elec, d32=dw32)
+    print(f"{name} {walkers}: batch means fp32 {ew32.mean():.6f} bf16w {ew.mean():.6f} (BF16 weights)")
+    assert abs(ew32.mean() - ew.mean()) <= 1e-3
 
 
 def test_metropolis_ext_bit_exact_fp64():
@@ -234,7 +261,8 @@ def test_metropolis_generator_matches_oracle_fp64():
     print("He fp64 10 steps acceptance", ao.mean() / 10)
 
 
-@pytest.mark.parametrize("name,prec", [("LiH", "fp32"), ("LiH", "bf16x6"), ("LiF", "bf16x6")])
+@pytest.mark.parametrize("name,prec", [("LiH", "fp32"), ("LiH", "bf16x6"), ("LiF", "bf16x6"), ("LiH", "bf16w"),
+                                       ("LiF", "bf16w")])
 def test_metropolis_decisions_reduced_precision(name, prec):
     """One Metropolis step with the generator, FP32 or mixed, against the
     FP64 oracle's step on the same walkers (each side with its own log|psi|):
@@ -612,3 +640,69 @@ def test_layer_stack_kernel(name, walkers):
     for shape in (1, 2):
         for a, b in zip(got[(2, 0)], got[(2, shape)]):
             np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("name,walkers", [("LiH", 256), ("LiF", 64)])
+def test_bf16_weight_rounding_agrees(name, walkers):
+    """The BF16-weight mode rounds the layer weights itself: parameters passed
+    unrounded and passed already rounded on the host (the oracle's rounding)
+    give bitwise the same log|psi|, local energies and Metropolis walk, and
+    parameters outside the layer weights are used as given."""
+    s = SYSTEMS[name]()
+    x = _walkers(name, s, walkers)
+    torch, fnvmc, cfg, tt, xt, th, x = _setup(s, "bf16w", walkers, x=x)
+    ttr = torch.tensor(th, dtype=torch.float32, device="cuda")
+    assert not torch.equal(tt, ttr)
+    e1, l1, _ = fnvmc.fn_local_energy(cfg, tt, xt)
+    e2, l2, _ = fnvmc.fn_local_energy(cfg, ttr, xt)
+    a1, a2 = fnvmc.fn_log_psi(cfg, tt, xt)[0], fnvmc.fn_log_psi(cfg, ttr, xt)[0]
+    x1, x2 = xt.clone(), xt.clone()
+    m1 = fnvmc.vmc_metropolis_step(cfg, tt, x1, a1.clone(), 3, 0.2, seed=3)
+    m2 = fnvmc.vmc_metropolis_step(cfg, ttr, x2, a2.clone(), 3, 0.2, seed=3)
+    torch.cuda.synchronize()
+    assert torch.equal(e1, e2) and torch.equal(l1, l2) and torch.equal(a1, a2)
+    assert torch.equal(x1, x2) and torch.equal(m1, m2)
+    # the rounded model differs from the unrounded one (a different network)
+    e32 = _energies(fnvmc, torch, s, "fp32", tt, xt)
+    print(f"{name}: BF16 rounding of the layer weights moves E_L by up to {np.abs(e32 - e1.cpu().numpy()).max():.2e} Ha "
+          f"(batch mean {abs(e32.mean() - e1.cpu().numpy().mean()):.2e} Ha)")
+
+
+@pytest.mark.parametrize("name,walkers", [("LiH", 63), ((4, 0), 9), ((5, 1), 5), ((3, -1), 4)])
+def test_stack_regs_kernel(name, walkers):
+    """Every one-electron layer in one kernel with the activations held in
+    registers (four electrons, two of each spin, one BF16 weight part),
+    against the layer-by-layer kernels (switch "stack_regs" 0) and the
+    oracle on the rounded parameters: in bf16w the local energy and log|psi|
+    within the FP32-level bounds; bf16w2 and the one-pass mode are reported
+    and must agree with the layer path to the size of their own errors.
+    Odd batches leave the last workgroup one walker short."""
+    s = SYSTEMS[name]() if isinstance(name, str) else I.atom_ion(*name, walkers=walkers)
+    x = T.equilibrated("LiH", walkers) if name == "LiH" else (
+        T.equilibrated(f"Z{name[0]}q{name[1]:+d}", 6).repeat(-(-walkers // 6), axis=0)[:walkers])
+    o = O.Oracle(s)
+    for prec in ("bf16w", "bf16w2", "bf16"):
+        torch, fnvmc, cfg, tt, xt, th, x = _setup(s, prec, walkers, x=x)
+        got = {}
+        try:
+            for regs in (1, 0):
+                fnvmc.fn_tuning_set("stack_regs", regs)
+                e, lp, parts = fnvmc.fn_local_energy(cfg, tt, xt)
+                torch.cuda.synchronize()
+                got[regs] = (e.cpu().numpy(), lp.cpu().numpy(), parts.cpu().numpy())
+        finally:
+            fnvmc.fn_tuning_set("stack_regs", 1)
+        ref = o.local_energy(th, x)
+        d1, d0 = np.abs(got[1][0] - ref["e_loc"]), np.abs(got[0][0] - ref["e_loc"])
+        print(f"{s.name} B={walkers} {prec}: E_L max |d| registers {d1.max():.2e} layer path {d0.max():.2e}; "
+              f"log|psi| max |d| {np.abs(got[1][1] - ref['log_abs']).max():.2e} / "
+              f"{np.abs(got[0][1] - ref['log_abs']).max():.2e}")
+        assert np.all(np.isfinite(got[1][0]))
+        if prec == "bf16w":
+            kap, C = T.kappa_and_c(o, s, th, x)
+            d32 = np.abs(_energies(fnvmc, torch, s, "fp32", _model(torch, prec, tt, th), xt) - ref["e_loc"])
+            T.check_energy(got[1][0], ref, f"{s.name} B={walkers} bf16w registers", kap, C, s.n_elec, d32=d32,
+                           parts=got[1][2], mean_tol=1e-3 if name == "LiH" else None)
+            T.check_logpsi(got[1][1], ref, 1e-5, f"{s.name} bf16w registers", C, False)
+        else:
+            assert np.all(d1 <= 3.0 * d0 + 1e-3), (prec, (d1 - 3.0 * d0).max())
