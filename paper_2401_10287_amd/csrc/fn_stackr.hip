@@ -43,6 +43,7 @@ namespace {
 constexpr int RT = 6;                 // ring tiles of 16 KB
 constexpr int TILE = 16384;
 constexpr int CPT = 2;                // 16-byte copies per lane per tile (eight waves)
+constexpr int N3 = 12;                // tangent rows: three coordinates of four electrons
 
 // until at most CPT * n vector-memory operations of this wave are
 // outstanding (n tiles still in flight; waiting for fewer is always safe)
@@ -95,16 +96,6 @@ __device__ inline void d_to_b(const f32x4 &x0, const f32x4 &x1, float4 &lo, floa
     hi = make_float4(h[0], h[1], h[2], h[3]);
 }
 
-// sum over the 16 lanes of a row group, the same bits in every lane
-__device__ inline float sum16(float v)
-{
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));  // row_half_mirror
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));  // row_mirror
-    return v;
-}
-
 __device__ inline float4 mask4r(float4 x, bool keep) { return keep ? x : make_float4(0.f, 0.f, 0.f, 0.f); }
 
 }  // namespace
@@ -114,13 +105,9 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
 {
     __shared__ __attribute__((aligned(16))) unsigned char ring[RT * TILE];
     __shared__ __attribute__((aligned(16))) f32x4 pex[2][16][64];       // P of each walker, D layout
-    // spin-mean operand slices [step parity][wave][lo, hi] (A phase), and in
-    // the same bytes the per-wave epilogue scratch [wave][z_0 -> tanh,
-    // Laplacian source term][column] (the epilogue writes the next layer's
-    // first slice only after its last read of the scratch)
+    // operand slices for the partner wave [step parity][wave][lo, hi]; the
+    // two slices of a wave are also its epilogue scratch
     __shared__ __attribute__((aligned(16))) float4 slc[2][8][2][64];
-    float (*vsc)[2][256] = reinterpret_cast<float (*)[2][256]>(&slc[0][0][0][0]);
-    static_assert(sizeof(float) * 8 * 2 * 256 <= sizeof(float4) * 2 * 8 * 2 * 64, "epilogue scratch");
 
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int t = lane & 15, og = lane >> 4;
@@ -129,12 +116,7 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
     const int64_t w = 2 * (int64_t)blockIdx.x + wl;
     const bool live = w < a.B;
     const int64_t wc = live ? w : a.B - 1;           // loads of an absent walker read a valid one
-    const int n3 = a.n3, tl = n3 + 1;
-    const bool trow = t <= tl;                        // rows past the Laplacian row are padding
-    const float ftan = t >= 1 && t <= n3 ? 1.f : 0.f; // tangent rows
-    const float flap = t == tl ? 1.f : 0.f;           // Laplacian row
-    const float fval = t == 0 ? 1.f : 0.f;            // value row
-    const uint32_t vmask = t == 0 ? 0xffffffffu : 0u;
+    const bool trow = t <= N3 + 1;                    // rows past the Laplacian row are padding
     const int64_t row0 = (wc * 4 + el) * 16;         // this wave's electron
     const int64_t row = row0 + t;
     const int64_t rowp0 = (wc * 4 + 2 * sig) * 16;   // the spin's first electron
@@ -143,51 +125,64 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
     //      of h the V_g tiles of both spins and the V_h tile; for each
     //      pair-mean step the V_h tile and then the pair means of every
     //      wave's rows (2 KB per wave, rows chunk-swizzled)
-    auto layer_tiles = [&](int l) { return 3 * (a.HW[l] >> 5) + 2 * (a.GW[l] >> 5); };
     int NT = 0;
-    for (int l = 0; l < a.L; ++l) NT += layer_tiles(l);
-    int il = 0, iu = 0;                              // layer and in-layer index of the next tile to issue
+    for (int l = 0; l < a.L; ++l) NT += 3 * (a.HW[l] >> 5) + 2 * (a.GW[l] >> 5);
     // lane parts of the copy offsets (the same for every tile): weight tiles
     // row (lane / 4) of a 16-row block, its chunk (lane & 3) swizzled; pair
     // means row (lane / 8) of an 8-row block, chunk (lane & 7) swizzled
     const uint32_t wrow2 = 2u * (uint32_t)(lane >> 2);
     const uint32_t wchunk = 16u * (uint32_t)lds_chunk(lane >> 2, lane & 3);
     const uint32_t glane = (uint32_t)((lane >> 3) * a.ldgi * 4 + 16 * ((lane & 7) ^ ((lane >> 3) & 7)));
-    auto issue = [&](int T) {
-        const int l = il, u = iu, nH = a.HW[l] >> 5;
-        if (++iu == layer_tiles(il)) {
-            iu = 0;
-            ++il;
-        }
-        unsigned char *slot = ring + (T % RT) * TILE;
-        if (u >= 3 * nH && ((u - 3 * nH) & 1)) {
-            // pair means, step g: rows 8 j + lane / 8 of this wave's 16,
+    // position of the next tile to issue: layer il, phase iph (0: input
+    // steps of h, 1: pair-mean steps), step is, tile ir of the step; the
+    // layer's weights and widths are read once per layer
+    int il = 0, iph = 0, is = 0, ir = 0, islot = 0;
+    const uint16_t *iWg = a.Wg[0], *iWx = a.Wx[0];
+    int iHW = a.HW[0], iGW = a.GW[0];
+    const float *igi = a.GI + row0 * a.ldgi;
+    auto issue = [&]() {
+        unsigned char *slot = ring + islot * TILE;
+        if (++islot == RT) islot = 0;
+        if (iph == 1 && ir == 1) {
+            // pair means, step is: rows 8 j + lane / 8 of this wave's 16,
             // 16-byte chunk c of the row stored at slot c ^ (row & 7)
-            const int g = (u - 3 * nH) >> 1;
-            const float *base = a.GI + (int64_t)l * a.gi_stride + row0 * a.ldgi + 32 * g;
-            const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(base, (uint32_t)(16 * a.ldgi * 4));
+            const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(igi + 32 * is, (uint32_t)(16 * a.ldgi * 4));
 #pragma unroll
             for (int j = 0; j < CPT; ++j)
                 copy16_buf(rs, glane, (uint32_t)(8 * j * a.ldgi * 4), slot + wave * 2048 + j * 1024);
+        } else {
+            const uint16_t *W;
+            int ld;
+            if (iph == 0 && ir < 2) {
+                W = iWg + ir * iHW + 32 * is;
+                ld = 2 * iHW;
+            } else {
+                W = iWx + (iph ? iHW : 0) + 32 * is;
+                ld = iHW + iGW;
+            }
+            const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(W, (uint32_t)(256 * ld * 2));
+            const uint32_t voff = wrow2 * (uint32_t)ld + wchunk;
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const int b = CPT * wave + j;
+                copy16_buf(rs, voff, (uint32_t)(16 * b * ld * 2), slot + b * 1024);
+            }
+        }
+        if (++ir < 3 - iph) return;
+        ir = 0;
+        if (++is < (iph ? iGW : iHW) >> 5) return;
+        is = 0;
+        if (iph == 0) {
+            iph = 1;
             return;
         }
-        const uint16_t *W;
-        int ld, k0;
-        if (u < 3 * nH && u % 3 < 2) {
-            W = a.Wg[l];
-            ld = 2 * a.HW[l];
-            k0 = (u % 3) * a.HW[l] + 32 * (u / 3);
-        } else {
-            W = a.Wx[l];
-            ld = a.HW[l] + a.GW[l];
-            k0 = u < 3 * nH ? 32 * (u / 3) : a.HW[l] + 32 * ((u - 3 * nH) >> 1);
-        }
-        const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(W + k0, (uint32_t)(256 * ld * 2));
-        const uint32_t voff = wrow2 * (uint32_t)ld + wchunk;
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) {
-            const int b = CPT * wave + j;
-            copy16_buf(rs, voff, (uint32_t)(16 * b * ld * 2), slot + b * 1024);
+        iph = 0;
+        if (++il < a.L) {
+            iWg = a.Wg[il];
+            iWx = a.Wx[il];
+            iHW = a.HW[il];
+            iGW = a.GW[il];
+            igi += a.gi_stride;
         }
     };
     int issued = 0, first = 0;
@@ -196,9 +191,16 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
     auto step_sync = [&](int need) {
         wait_tiles(issued - need);
         ring_barrier();
-        while (issued < NT && issued < first + RT) issue(issued++);
+        for (; issued < NT && issued < first + RT; ++issued) issue();
     };
-    while (issued < NT && issued < RT) issue(issued++);
+    for (; issued < NT && issued < RT; ++issued) issue();
+    // ring slot of tile first + k (k < RT)
+    int fslot = 0;
+    auto slot_of = [&](int k) { return fslot + k < RT ? fslot + k : fslot + k - RT; };
+    auto advance = [&](int k) {
+        first += k;
+        fslot = slot_of(k);
+    };
 
     // A fragment of output block c in a ring tile: row 16 c + t, chunk og
     // (formed again at each use from the lane id: cheaper than keeping it)
@@ -207,6 +209,14 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
         asm volatile("" : "+v"(ln));
         const int tt = ln & 15;
         return tt * 64 + 16 * lds_chunk(tt, ln >> 4);
+    };
+
+    // this lane's 16-byte slot in a 1 KB row of LDS, formed at each use (the
+    // compiler would otherwise keep one such offset per array and wave)
+    auto lane_slot = [&](void *base) {
+        int ln = __lane_id();
+        asm volatile("" : "+v"(ln));
+        return reinterpret_cast<f32x4 *>(reinterpret_cast<unsigned char *>(base) + 16 * ln);
     };
 
     f32x4 hp[16];                                     // h of this layer's input (then output), D layout
@@ -235,7 +245,7 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
         split_fragment<NA>(own_lo, own_hi, hb);
         const int af = afrag_now();
         {
-            const unsigned char *tile = ring + ((first + sig) % RT) * TILE + af + 8 * half * 1024;
+            const unsigned char *tile = ring + slot_of(sig) * TILE + af + 8 * half * 1024;
             bf16x8 wa[2], wn[2];
 #pragma unroll
             for (int j = 0; j < 2; ++j) wa[j] = *(const bf16x8 *)(tile + j * 1024);
@@ -258,7 +268,7 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
             }
         }
         {
-            const unsigned char *tile = ring + ((first + 2) % RT) * TILE + af;
+            const unsigned char *tile = ring + slot_of(2) * TILE + af;
             bf16x8 wa[2], wn[2];
 #pragma unroll
             for (int j = 0; j < 2; ++j) wa[j] = *(const bf16x8 *)(tile + j * 1024);
@@ -301,7 +311,7 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
                 feat_operand(row, s, own_lo, own_hi);
                 feat_operand(((wc * 4) + (el ^ 1)) * 16 + t, s, plo, phi);
                 step_products(plo, phi);
-                first += 3;
+                advance(3);
             }
         } else {
             // (unrolled: static register indices for the next step's operand)
@@ -309,17 +319,19 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
             for (int s = 0; s < 8; ++s) {
                 if (s >= nH) break;
                 step_sync(first + 3);
-                const float4 plo = slc[s & 1][wave ^ 1][0][lane], phi = slc[s & 1][wave ^ 1][1][lane];
+                const f32x4 *const ps = lane_slot(&slc[s & 1][wave ^ 1][0][0]);
+                const float4 plo = *(const float4 *)ps, phi = *(const float4 *)(ps + 64);
                 float4 nlo = own_lo, nhi = own_hi;
                 if (s + 1 < nH) {
                     d_to_b(hp[2 * s + 2], hp[2 * s + 3], nlo, nhi);
-                    slc[(s + 1) & 1][wave][0][lane] = nlo;
-                    slc[(s + 1) & 1][wave][1][lane] = nhi;
+                    f32x4 *const ns = lane_slot(&slc[(s + 1) & 1][wave][0][0]);
+                    *(float4 *)ns = nlo;
+                    *(float4 *)(ns + 64) = nhi;
                 }
                 step_products(plo, phi);
                 own_lo = nlo;
                 own_hi = nhi;
-                first += 3;
+                advance(3);
             }
         }
         // P = P_up + P_dn: the spin-up waves store their blocks, the spin-down
@@ -327,15 +339,14 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
         // the first pair-mean step)
         if (sig == 0) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) pex[wl][8 * half + j][lane] = pm[j];
+            for (int j = 0; j < 8; ++j) lane_slot(&pex[wl][8 * half][0])[64 * j] = pm[j];
         }
         ring_barrier();
         if (sig == 1) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                f32x4 v = pex[wl][8 * half + j][lane];
-                v += pm[j];
-                pex[wl][8 * half + j][lane] = v;
+                f32x4 *const pp = lane_slot(&pex[wl][8 * half][0]) + 64 * j;
+                *pp = *pp + pm[j];
             }
         }
 
@@ -343,12 +354,12 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
 #pragma unroll 1
         for (int g = 0; g < nG; ++g) {
             step_sync(first + 2);
-            const unsigned char *gt = ring + ((first + 1) % RT) * TILE + wave * 2048 + t * 128;
+            const unsigned char *gt = ring + slot_of(1) * TILE + wave * 2048 + t * 128;
             const float4 lo = mask4r(*(const float4 *)(gt + 16 * ((2 * og) ^ (t & 7))), trow);
             const float4 hi = mask4r(*(const float4 *)(gt + 16 * ((2 * og + 1) ^ (t & 7))), trow);
             bf16x8 hb[NA];
             split_fragment<NA>(lo, hi, hb);
-            const unsigned char *tile = ring + (first % RT) * TILE + afrag_now();
+            const unsigned char *tile = ring + fslot * TILE + afrag_now();
             bf16x8 wa[2], wn[2];
 #pragma unroll
             for (int j = 0; j < 2; ++j) wa[j] = *(const bf16x8 *)(tile + j * 1024);
@@ -369,68 +380,98 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
                     for (int j = 0; j < 2; ++j) wa[j] = wn[j];
                 }
             }
-            first += 2;
+            advance(2);
         }
 
-        // ---- epilogue, branch-free: row roles as multipliers and selects;
-        //      padding rows come out zero (their z is exactly zero).
-        //      Pass 1: z = (X + P) + b; per column the value row z_0 and the
-        //      sum over the tangent rows of z_c^2 to the wave's scratch.
-        //      Pass 2 (four columns per lane): y_0 = tanh(z_0) and the
-        //      Laplacian row's source term 2 y_0 (1 - y_0^2) sum_c z_c^2.
-        //      Pass 3: every row of the new h, plus the residual.
-        float *z0s = vsc[wave][0], *lts = vsc[wave][1];
-        const float *bl = a.bias[l];
+        // ---- epilogue.  Scratch of this wave: its two operand slices
+        //      (sA, sB: 2 KB each, free until it writes the next layer's
+        //      first slice at the end).
+        //      Pass 1, four chunks of 64 columns: z = X + P; rows 0-12
+        //      staged (rows 0-6 in sA, 7-12 in sB, 68 floats apart), then
+        //      lane j reads column j: the value row z_0 and the sum over the
+        //      tangent rows of z_c^2.
+        //      Pass 2, the four columns 64 q + lane: y_0 = tanh(z_0 + b),
+        //      d = 1 - y_0^2 and the Laplacian source -2 y_0 d sum_c z_c^2,
+        //      into per-column tables.
+        //      Pass 3: every row as A z + C with (A, C) by row role: value
+        //      (0, y_0), tangent and padding (d, 0), Laplacian (d, source);
+        //      then the residual.
+        float *const sA = &slc[0][wave][0][0].x, *const sB = &slc[1][wave][0][0].x;
+        // (lane-dependent offsets formed here from the lane id, not kept
+        // across the layer loop)
+        int ln = __lane_id();
+        asm volatile("" : "+v"(ln));
+        const int lt = ln & 15, lg = ln >> 4;
+        float bq[4];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            asm volatile("" ::: "memory");
-            const f32x4 P = pex[wl][c][lane];
-            const float4 b4 = *(const float4 *)(bl + 16 * c + 4 * og);
-            const f32x4 bv = f32x4{b4.x * fval, b4.y * fval, b4.z * fval, b4.w * fval};
-            const f32x4 z = (acc[c] + P) + bv;                // (X + P) + b on the value row
-            acc[c] = z;
-            f32x4 sq;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) sq[e] = sum16((z[e] * z[e]) * ftan);
-            if (t == 0) *(f32x4 *)(z0s + 16 * c + 4 * og) = z;
-            if (t == tl) *(f32x4 *)(lts + 16 * c + 4 * og) = sq;
-            __builtin_amdgcn_sched_barrier(0);
-        }
+        for (int q = 0; q < 4; ++q) bq[q] = a.bias[l][64 * q + ln];
+        float z0[4], sq[4];
         {
-            const float4 u = *(const float4 *)(z0s + 4 * lane);
-            const float4 q = *(const float4 *)(lts + 4 * lane);
-            const float4 y = make_float4(tanhf(u.x), tanhf(u.y), tanhf(u.z), tanhf(u.w));
-            const float4 d = make_float4(1.f - y.x * y.x, 1.f - y.y * y.y, 1.f - y.z * y.z, 1.f - y.w * y.w);
-            *(float4 *)(z0s + 4 * lane) = y;
-            *(float4 *)(lts + 4 * lane) = make_float4(2.f * y.x * d.x * q.x, 2.f * y.y * d.y * q.y, 2.f * y.z * d.z * q.z,
-                                                      2.f * y.w * d.w * q.w);
-        }
+            constexpr int RS = 68;                               // staged row stride (floats)
+            constexpr int SB = (int)(sizeof(slc[0]) / sizeof(float));   // sB - sA
+            float *const srow = (lt < 7 ? sA + RS * lt : sB + RS * (lt - 7)) + 4 * lg;
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            asm volatile("" ::: "memory");                     // this block's reads stay in its iteration
-            const float4 y4 = *(const float4 *)(z0s + 16 * c + 4 * og);
-            const float4 l4 = *(const float4 *)(lts + 16 * c + 4 * og);
-            const float y0[4] = {y4.x, y4.y, y4.z, y4.w};
-            const float dd[4] = {1.f - y4.x * y4.x, 1.f - y4.y * y4.y, 1.f - y4.z * y4.z, 1.f - y4.w * y4.w};
-            const float lt[4] = {l4.x, l4.y, l4.z, l4.w};
-            const f32x4 z = acc[c];
-            f32x4 y;
+            for (int q = 0; q < 4; ++q) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float v = dd[e] * z[e] - flap * lt[e];         // tangent rows; Laplacian row with its source
-                // value row: y_0 (a bit select, so no branch), plus the residual (zero before layer 1)
-                y[e] = __uint_as_float((__float_as_uint(y0[e]) & vmask) | (__float_as_uint(v) & ~vmask)) + hp[c][e];
+                for (int cc = 0; cc < 4; ++cc) {
+                    const int c = 4 * q + cc;
+                    const f32x4 z = acc[c] + lane_slot(&pex[wl][0][0])[64 * c];
+                    acc[c] = z;
+                    if (lt <= N3) *(f32x4 *)(srow + 16 * cc) = z;
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                asm volatile("" ::: "memory");
+                const float *const col = sA + ln;
+                z0[q] = col[0];
+                float v = 0.f;
+#pragma unroll
+                for (int r = 1; r <= N3; ++r) {
+                    const float x = col[r < 7 ? RS * r : SB + RS * (r - 7)];
+                    v = r == 1 ? x * x : fmaf(x, x, v);
+                }
+                sq[q] = v;
+                asm volatile("" ::: "memory");
             }
-            hp[c] = y;
-            asm volatile("" : "+a"(hp[c]));                    // h lives in the accumulator registers
-            __builtin_amdgcn_sched_barrier(0);
         }
+        float *const y0T = sA, *const ddT = sA + 256, *const srcT = sB, *const zeroT = sB + 256;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float y = tanhf(z0[q] + bq[q]);
+            const float d = 1.f - y * y;
+            y0T[64 * q + ln] = y;
+            ddT[64 * q + ln] = d;
+            srcT[64 * q + ln] = -(2.f * y * d * sq[q]);
+        }
+        *(float4 *)(zeroT + 4 * ln) = make_float4(0.f, 0.f, 0.f, 0.f);
+        asm volatile("" ::: "memory");
+        {
+            const float *const tA = (lt == 0 ? zeroT : ddT) + 4 * lg;
+            const float *const tC = (lt == 0 ? y0T : (lt == N3 + 1 ? srcT : zeroT)) + 4 * lg;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const float4 A4 = *(const float4 *)(tA + 16 * c);
+                const float4 C4 = *(const float4 *)(tC + 16 * c);
+                const f32x4 z = acc[c];
+                f32x4 y;
+                y[0] = fmaf(A4.x, z[0], C4.x);
+                y[1] = fmaf(A4.y, z[1], C4.y);
+                y[2] = fmaf(A4.z, z[2], C4.z);
+                y[3] = fmaf(A4.w, z[3], C4.w);
+                hp[c] = y + hp[c];                               // residual (zero before layer 1)
+                asm volatile("" : "+a"(hp[c]));                  // h lives in the accumulator registers
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        asm volatile("" ::: "memory");
         // the next layer's first operand of this wave's electron, and its slice
         // for the partner
-        if (l + 1 < a.L) {
-            d_to_b(hp[0], hp[1], own_lo, own_hi);
-            slc[0][wave][0][lane] = own_lo;
-            slc[0][wave][1][lane] = own_hi;
+        // (also after the last layer: unconditional, so that the previous
+        // operand is dead through the epilogue)
+        d_to_b(hp[0], hp[1], own_lo, own_hi);
+        {
+            f32x4 *const ns = lane_slot(&slc[0][wave][0][0]);
+            *(float4 *)ns = own_lo;
+            *(float4 *)(ns + 64) = own_hi;
         }
     }
 
