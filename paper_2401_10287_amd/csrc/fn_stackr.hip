@@ -140,15 +140,15 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
     const uint16_t *iWg = a.Wg[0], *iWx = a.Wx[0];
     int iHW = a.HW[0], iGW = a.GW[0];
     const float *igi = a.GI + row0 * a.ldgi;
-    auto issue = [&]() {
+    // copies j0 .. j1 - 1 of the next tile; the position moves on after its last
+    auto issue = [&](int j0, int j1) {
         unsigned char *slot = ring + islot * TILE;
-        if (++islot == RT) islot = 0;
         if (iph == 1 && ir == 1) {
             // pair means, step is: rows 8 j + lane / 8 of this wave's 16,
             // 16-byte chunk c of the row stored at slot c ^ (row & 7)
             const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(igi + 32 * is, (uint32_t)(16 * a.ldgi * 4));
 #pragma unroll
-            for (int j = 0; j < CPT; ++j)
+            for (int j = j0; j < j1; ++j)
                 copy16_buf(rs, glane, (uint32_t)(8 * j * a.ldgi * 4), slot + wave * 2048 + j * 1024);
         } else {
             const uint16_t *W;
@@ -163,11 +163,13 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
             const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(W, (uint32_t)(256 * ld * 2));
             const uint32_t voff = wrow2 * (uint32_t)ld + wchunk;
 #pragma unroll
-            for (int j = 0; j < CPT; ++j) {
+            for (int j = j0; j < j1; ++j) {
                 const int b = CPT * wave + j;
                 copy16_buf(rs, voff, (uint32_t)(16 * b * ld * 2), slot + b * 1024);
             }
         }
+        if (j1 < CPT) return;
+        if (++islot == RT) islot = 0;
         if (++ir < 3 - iph) return;
         ir = 0;
         if (++is < (iph ? iGW : iHW) >> 5) return;
@@ -188,12 +190,23 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
     int issued = 0, first = 0;
     // every lane has landed the tiles before `need`, then the workgroup
     // agrees; tiles that no step before `first` still reads are refilled
+    // (the refills go out between the step's matrix instructions, a tile at
+    // a time, so that no wave waits for a queue of copies before its first
+    // products; any left over go out at the next step's start)
     auto step_sync = [&](int need) {
         wait_tiles(issued - need);
         ring_barrier();
-        for (; issued < NT && issued < first + RT; ++issued) issue();
+        for (; issued < NT && issued < first - 3 + RT; ++issued) issue(0, CPT);
     };
-    for (; issued < NT && issued < RT; ++issued) issue();
+    // refill position p of a step (p static): a whole tile at positions 0,
+    // 2, 4 and 5 (at most three go out in a step)
+    auto refill_at = [&](int p) {
+        if ((p == 0 || p == 2 || p == 4 || p == 5) && issued < NT && issued < first + RT) {
+            issue(0, CPT);
+            ++issued;
+        }
+    };
+    for (; issued < NT && issued < RT; ++issued) issue(0, CPT);
     // ring slot of tile first + k (k < RT)
     int fslot = 0;
     auto slot_of = [&](int k) { return fslot + k < RT ? fslot + k : fslot + k - RT; };
@@ -261,6 +274,7 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
                         pm[2 * g + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], ha[p], pm[2 * g + j], 0, 0, 0);
+                refill_at(g);
                 if (g < 3) {
 #pragma unroll
                     for (int j = 0; j < 2; ++j) wa[j] = wn[j];
@@ -284,6 +298,7 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
                         acc[2 * g + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], hb[p], acc[2 * g + j], 0, 0, 0);
+                refill_at(4 + g);
                 if (g < 7) {
 #pragma unroll
                     for (int j = 0; j < 2; ++j) wa[j] = wn[j];
@@ -296,6 +311,11 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
         const int nH = a.HW[l] >> 5, nG = a.GW[l] >> 5;
 #pragma unroll
         for (int j = 0; j < 8; ++j) pm[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // the bias of this wave's eight column blocks, block t in lane (t, og)
+        // (t < 8): the spin-up waves add it to the value row of P_up at the
+        // exchange, so that P + b comes out of it
+        f32x4 bias8 = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (sig == 0 && t < 8) bias8 = *(const f32x4 *)(a.bias[l] + 16 * (8 * half + t) + 4 * og);
 #pragma unroll
         for (int c = 0; c < 16; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
 
@@ -338,8 +358,21 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
         // waves add theirs after the barrier (complete before the barrier of
         // the first pair-mean step)
         if (sig == 0) {
+            int ln = __lane_id();
+            asm volatile("" : "+v"(ln));
+            const bool vrow = (ln & 15) == 0;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) lane_slot(&pex[wl][8 * half][0])[64 * j] = pm[j];
+            for (int j = 0; j < 8; ++j) {
+                // lane (0, og) takes block j's bias from lane (j, og)
+                const int src = 4 * (j + (ln & 48));
+                f32x4 b;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) b[e] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(bias8[e])));
+                f32x4 v = pm[j];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = vrow ? v[e] + b[e] : v[e];
+                lane_slot(&pex[wl][8 * half][0])[64 * j] = v;
+            }
         }
         ring_barrier();
         if (sig == 1) {
@@ -375,6 +408,7 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
                         acc[2 * q + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], hb[p], acc[2 * q + j], 0, 0, 0);
+                refill_at(q);
                 if (q < 7) {
 #pragma unroll
                     for (int j = 0; j < 2; ++j) wa[j] = wn[j];
@@ -402,20 +436,21 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
         int ln = __lane_id();
         asm volatile("" : "+v"(ln));
         const int lt = ln & 15, lg = ln >> 4;
-        float bq[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) bq[q] = a.bias[l][64 * q + ln];
         float z0[4], sq[4];
         {
             constexpr int RS = 68;                               // staged row stride (floats)
             constexpr int SB = (int)(sizeof(slc[0]) / sizeof(float));   // sB - sA
             float *const srow = (lt < 7 ? sA + RS * lt : sB + RS * (lt - 7)) + 4 * lg;
+            const f32x4 *const pl = lane_slot(&pex[wl][0][0]);
+            f32x4 pn = pl[0];                                   // P of the next block, read one ahead
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
 #pragma unroll
                 for (int cc = 0; cc < 4; ++cc) {
                     const int c = 4 * q + cc;
-                    const f32x4 z = acc[c] + lane_slot(&pex[wl][0][0])[64 * c];
+                    const f32x4 P = pn;
+                    if (c < 15) pn = pl[64 * (c + 1)];
+                    const f32x4 z = acc[c] + P;
                     acc[c] = z;
                     if (lt <= N3) *(f32x4 *)(srow + 16 * cc) = z;
                     __builtin_amdgcn_sched_barrier(0);
@@ -436,7 +471,7 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
         float *const y0T = sA, *const ddT = sA + 256, *const srcT = sB, *const zeroT = sB + 256;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const float y = tanhf(z0[q] + bq[q]);
+            const float y = tanhf(z0[q]);
             const float d = 1.f - y * y;
             y0T[64 * q + ln] = y;
             ddT[64 * q + ln] = d;
@@ -447,10 +482,14 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
         {
             const float *const tA = (lt == 0 ? zeroT : ddT) + 4 * lg;
             const float *const tC = (lt == 0 ? y0T : (lt == N3 + 1 ? srcT : zeroT)) + 4 * lg;
+            float4 An = *(const float4 *)tA, Cn = *(const float4 *)tC;   // read one block ahead
 #pragma unroll
             for (int c = 0; c < 16; ++c) {
-                const float4 A4 = *(const float4 *)(tA + 16 * c);
-                const float4 C4 = *(const float4 *)(tC + 16 * c);
+                const float4 A4 = An, C4 = Cn;
+                if (c < 15) {
+                    An = *(const float4 *)(tA + 16 * (c + 1));
+                    Cn = *(const float4 *)(tC + 16 * (c + 1));
+                }
                 const f32x4 z = acc[c];
                 f32x4 y;
                 y[0] = fmaf(A4.x, z[0], C4.x);
