@@ -19,7 +19,7 @@ LiF training step (10 Metropolis moves + local energy + Eq. 6 gradient, 4096
 walkers), the H20 local energy (8192 walkers) with the stream layer's
 roofline fraction, and Poisson serving runs at 0.5x and 0.9x saturation.
 
-    python bench.py [--steps K] [--warmup W] [--precision bf16x6]
+    python bench.py [--steps K] [--warmup W] [--precision bf16w|bf16w2|bf16x6|bf16x3|bf16|fp32]
 """
 import argparse
 import json

@@ -31,7 +31,10 @@ def main(argv=None) -> None:
     ap.add_argument("--passes", type=int, default=3)
     ap.add_argument("--layer-stack", type=int, default=None, help="tuning switch layer_stack (0, 1, 2)")
     ap.add_argument("--stack-shape", type=int, default=None, help="tuning switch stack_shape (0, 1, 2)")
+    ap.add_argument("--stack-regs", type=int, default=None, help="tuning switch stack_regs (0, 1)")
     args = ap.parse_args(argv)
+    if args.stack_regs is not None:
+        fnvmc.fn_tuning_set("stack_regs", args.stack_regs)
     if args.layer_stack is not None:
         fnvmc.fn_tuning_set("layer_stack", args.layer_stack)
     if args.stack_shape is not None:
