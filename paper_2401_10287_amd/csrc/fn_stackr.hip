@@ -5,34 +5,38 @@
 // w1 = 256, in the modes whose layer weights are one BF16 part (activations
 // split into NA exact-or-rounded BF16 parts).
 //
-// Workgroup: four waves and two walkers.  Wave q owns the two electrons of
-// spin q & 1 of walker q >> 1 (electrons are stored spin-up first), all 256
-// output columns of their 32 rows.  Every product runs transposed,
+// Workgroup: eight waves and two walkers.  Wave q owns electron q & 3 of
+// walker q >> 2 (electrons stored spin-up first, so waves q and q ^ 1 hold
+// the two electrons of one spin), all 256 output columns of its 16 rows.
+// Every product runs transposed,
 //   D^T = W^T X^T,
 // so the weight fragments (rows = output columns) are the matrix
-// instruction's A operand, read from an LDS ring that the four waves share,
+// instruction's A operand, read from an LDS ring that the eight waves share,
 // and the activations are the B operand, taken from the wave's own
 // registers.  Accumulator ("D") layout: lane (t = lane % 16, og = lane / 16)
-// of block c holds output columns 16 c + 4 og + e, e = 0..3, of row t of an
-// electron.  The B operand of reduction step s (input columns 32 s + 8 kg ..
-// + 7 of row t in lane (t, kg)) is formed from blocks 2 s and 2 s + 1 of the
-// previous layer's output by one 32-lane and one 16-lane swap per element.
+// of block c holds output columns 16 c + 4 og + e, e = 0..3, of row t.  The
+// B operand of reduction step s (input columns 32 s + 8 kg .. + 7 of row t
+// in lane (t, kg)) is formed from blocks 2 s and 2 s + 1 of the previous
+// layer's output by one 32-lane and one 16-lane swap per element.
 //
 // Per layer l:
-//   A phase: P_spin = g_spin V_g^spin over the wave's own spin (g = mean of
-//            its two electrons' h), one 16-row block, then exchanged: the
-//            spin-up wave stores its partial, the spin-down wave adds its own
-//            (P = P_up + P_dn, the same in both waves).
-//   B phase: X = [h | g_i_up | g_i_dn] V_h for both electrons (the pair
-//            means g_i come through the ring as well, each wave its own rows).
-//   epilogue in registers: z = (X + P) + b, value y = tanh(z_0) (formed once
-//            per column through a per-wave LDS scratch), tangents (1 - y^2) z_c,
-//            Laplacian (1 - y^2) z_L - 2 y (1 - y^2) sum_c z_c^2 (the source sum
-//            over the 16 lanes of a row group by DPP butterflies), residual.
+//   input steps s of h (one barrier each): P_spin += g_spin V_g^spin for
+//            eight of the sixteen column blocks (g = mean of the wave's and
+//            its partner's operand, the partner's through LDS), and
+//            X += h V_h for the wave's electron;
+//   exchange: the spin-up waves store P_up plus the bias on the value row,
+//            the spin-down waves add P_dn (P + b, the same for all four
+//            electrons of the walker);
+//   pair-mean steps: X += [g_i_up | g_i_dn] V_h (the pair means come
+//            through the ring as well, each wave its own rows);
+//   epilogue in registers: z = X + (P + b), value y = tanh(z_0), tangents
+//            (1 - y^2) z_c, Laplacian (1 - y^2) z_L - 2 y (1 - y^2) sum_c
+//            z_c^2 (the sum over the tangent rows by a transpose through
+//            the wave's LDS scratch), residual.
 // Weights stream through the ring as 16 KB tiles (256 output rows x 32
-// reduction columns) by direct global-to-LDS copies, several tiles ahead;
-// each step waits only for its own tiles.  Only the features, the pair
-// means and h^L touch HBM.
+// reduction columns) by direct global-to-LDS copies a step ahead, issued
+// between the products; each step waits only for its own tiles.  Only the
+// features, the pair means and h^L touch HBM.
 #include "fn_internal.h"
 #include "fn_kernels.h"
 
