@@ -203,9 +203,9 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
         for (; issued < NT && issued < first - 3 + RT; ++issued) issue(0, CPT);
     };
     // refill position p of a step (p static): a whole tile at positions 0,
-    // 2, 4 and 5 (at most three go out in a step)
+    // 2 and 4
     auto refill_at = [&](int p) {
-        if ((p == 0 || p == 2 || p == 4 || p == 5) && issued < NT && issued < first + RT) {
+        if ((p == 0 || p == 2 || p == 4) && issued < NT && issued < first + RT) {
             issue(0, CPT);
             ++issued;
         }
@@ -247,45 +247,30 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
         lo = mask4r(*(const float4 *)p, trow);
         hi = mask4r(*(const float4 *)(p + 4), trow);
     };
-    // one input step of h: the spin-mean products of this wave's eight
-    // column blocks of P_spin (tile first + spin) and the electron's products
-    // over all sixteen blocks (tile first + 2); weight fragments two at a
-    // time, the next two requested before a pair's products
+    // one input step of h: the electron's products over all sixteen blocks
+    // (tile first + 2) and the spin-mean products of this wave's eight
+    // column blocks of P_spin (tile first + spin); weight fragments two at a
+    // time, the next two requested before a pair's products; refills at
+    // positions 0, 2 and 4 of the step's twelve product groups
     f32x4 pm[8];
     auto step_products = [&](const float4 &plo, const float4 &phi) {
-        const float4 mlo = make_float4((own_lo.x + plo.x) * 0.5f, (own_lo.y + plo.y) * 0.5f, (own_lo.z + plo.z) * 0.5f,
-                                       (own_lo.w + plo.w) * 0.5f);
-        const float4 mhi = make_float4((own_hi.x + phi.x) * 0.5f, (own_hi.y + phi.y) * 0.5f, (own_hi.z + phi.z) * 0.5f,
-                                       (own_hi.w + phi.w) * 0.5f);
         bf16x8 ha[NA], hb[NA];
-        split_fragment<NA>(mlo, mhi, ha);
+        auto mean_operand = [&]() {
+            const float4 mlo = make_float4((own_lo.x + plo.x) * 0.5f, (own_lo.y + plo.y) * 0.5f,
+                                           (own_lo.z + plo.z) * 0.5f, (own_lo.w + plo.w) * 0.5f);
+            const float4 mhi = make_float4((own_hi.x + phi.x) * 0.5f, (own_hi.y + phi.y) * 0.5f,
+                                           (own_hi.z + phi.z) * 0.5f, (own_hi.w + phi.w) * 0.5f);
+            split_fragment<NA>(mlo, mhi, ha);
+        };
+        // with several activation parts the electron's products go first and
+        // the spin-mean operand is formed and split while the first of them
+        // run; with one part (short product groups) the spin-mean products
+        // go first
+        constexpr bool own_first = NA > 1;
         split_fragment<NA>(own_lo, own_hi, hb);
+        if (!own_first) mean_operand();
         const int af = afrag_now();
-        {
-            const unsigned char *tile = ring + slot_of(sig) * TILE + af + 8 * half * 1024;
-            bf16x8 wa[2], wn[2];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) wa[j] = *(const bf16x8 *)(tile + j * 1024);
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                asm volatile("" ::: "memory");
-                if (g < 3) {
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) wn[j] = *(const bf16x8 *)(tile + (2 * g + 2 + j) * 1024);
-                }
-#pragma unroll
-                for (int p = 0; p < NA; ++p)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        pm[2 * g + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], ha[p], pm[2 * g + j], 0, 0, 0);
-                refill_at(g);
-                if (g < 3) {
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) wa[j] = wn[j];
-                }
-            }
-        }
-        {
+        auto own_products = [&](int p0) {
             const unsigned char *tile = ring + slot_of(2) * TILE + af;
             bf16x8 wa[2], wn[2];
 #pragma unroll
@@ -302,12 +287,44 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
                         acc[2 * g + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], hb[p], acc[2 * g + j], 0, 0, 0);
-                refill_at(4 + g);
+                if (own_first && g == 0) mean_operand();
+                refill_at(p0 + g);
                 if (g < 7) {
 #pragma unroll
                     for (int j = 0; j < 2; ++j) wa[j] = wn[j];
                 }
             }
+        };
+        auto mean_products = [&](int p0) {
+            const unsigned char *tile = ring + slot_of(sig) * TILE + af + 8 * half * 1024;
+            bf16x8 wa[2], wn[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) wa[j] = *(const bf16x8 *)(tile + j * 1024);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                asm volatile("" ::: "memory");
+                if (g < 3) {
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) wn[j] = *(const bf16x8 *)(tile + (2 * g + 2 + j) * 1024);
+                }
+#pragma unroll
+                for (int p = 0; p < NA; ++p)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        pm[2 * g + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], ha[p], pm[2 * g + j], 0, 0, 0);
+                refill_at(p0 + g);
+                if (g < 3) {
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) wa[j] = wn[j];
+                }
+            }
+        };
+        if (own_first) {
+            own_products(0);
+            mean_products(8);
+        } else {
+            mean_products(0);
+            own_products(4);
         }
     };
 
