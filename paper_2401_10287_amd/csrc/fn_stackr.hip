@@ -24,12 +24,12 @@
 //            eight of the sixteen column blocks (g = mean of the wave's and
 //            its partner's operand, the partner's through LDS), and
 //            X += h V_h for the wave's electron;
-//   exchange: the spin-up waves store P_up plus the bias on the value row,
-//            the spin-down waves add P_dn (P + b, the same for all four
-//            electrons of the walker);
+//   exchange: the spin-up waves store P_up, the spin-down waves add P_dn
+//            (P, the same for all four electrons of the walker);
 //   pair-mean steps: X += [g_i_up | g_i_dn] V_h (the pair means come
-//            through the ring as well, each wave its own rows);
-//   epilogue in registers: z = X + (P + b), value y = tanh(z_0), tangents
+//            through the ring as well, each wave its own rows, with the
+//            layer's bias in their padding rows);
+//   epilogue in registers: z = X + P, value y = tanh(z_0 + b), tangents
 //            (1 - y^2) z_c, Laplacian (1 - y^2) z_L - 2 y (1 - y^2) sum_c
 //            z_c^2 (the sum over the tangent rows by a transpose through
 //            the wave's LDS scratch), residual.
@@ -143,17 +143,24 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
     int il = 0, iph = 0, is = 0, ir = 0, islot = 0;
     const uint16_t *iWg = a.Wg[0], *iWx = a.Wx[0];
     int iHW = a.HW[0], iGW = a.GW[0];
-    const float *igi = a.GI + row0 * a.ldgi;
+    const float *igi = a.GI + row0 * a.ldgi, *ibias = a.bias[0];
     // copies j0 .. j1 - 1 of the next tile; the position moves on after its last
     auto issue = [&](int j0, int j1) {
         unsigned char *slot = ring + islot * TILE;
         if (iph == 1 && ir == 1) {
             // pair means, step is: rows 8 j + lane / 8 of this wave's 16,
-            // 16-byte chunk c of the row stored at slot c ^ (row & 7)
+            // 16-byte chunk c of the row stored at slot c ^ (row & 7).  Rows
+            // 14 and 15 are padding: their lanes bring 64 bias values of the
+            // layer instead (columns 64 (wave & 3) .. + 63, in order), which
+            // the epilogue reads while the slot stays untouched
             const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(igi + 32 * is, (uint32_t)(16 * a.ldgi * 4));
 #pragma unroll
-            for (int j = j0; j < j1; ++j)
-                copy16_buf(rs, glane, (uint32_t)(8 * j * a.ldgi * 4), slot + wave * 2048 + j * 1024);
+            for (int j = j0; j < j1; ++j) {
+                if (j == 0 || lane < 48) copy16_buf(rs, glane, (uint32_t)(8 * j * a.ldgi * 4), slot + wave * 2048 + j * 1024);
+                if (j == 1 && lane >= 48)
+                    copy16_buf(buffer_rsrc(ibias, 256 * 4), (uint32_t)(16 * (lane - 48)), (uint32_t)(256 * (wave & 3)),
+                               slot + wave * 2048 + 1024);
+            }
         } else {
             const uint16_t *W;
             int ld;
@@ -189,6 +196,7 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
             iHW = a.HW[il];
             iGW = a.GW[il];
             igi += a.gi_stride;
+            ibias = a.bias[il];
         }
     };
     int issued = 0, first = 0;
@@ -332,11 +340,6 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
         const int nH = a.HW[l] >> 5, nG = a.GW[l] >> 5;
 #pragma unroll
         for (int j = 0; j < 8; ++j) pm[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-        // the bias of this wave's eight column blocks, block t in lane (t, og)
-        // (t < 8): the spin-up waves add it to the value row of P_up at the
-        // exchange, so that P + b comes out of it
-        f32x4 bias8 = f32x4{0.f, 0.f, 0.f, 0.f};
-        if (sig == 0 && t < 8) bias8 = *(const f32x4 *)(a.bias[l] + 16 * (8 * half + t) + 4 * og);
 #pragma unroll
         for (int c = 0; c < 16; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
 
@@ -362,16 +365,15 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
                 step_sync(first + 3);
                 const f32x4 *const ps = lane_slot(&slc[s & 1][wave ^ 1][0][0]);
                 const float4 plo = *(const float4 *)ps, phi = *(const float4 *)(ps + 64);
-                float4 nlo = own_lo, nhi = own_hi;
-                if (s + 1 < nH) {
-                    d_to_b(hp[2 * s + 2], hp[2 * s + 3], nlo, nhi);
-                    f32x4 *const ns = lane_slot(&slc[(s + 1) & 1][wave][0][0]);
-                    *(float4 *)ns = nlo;
-                    *(float4 *)(ns + 64) = nhi;
-                }
                 step_products(plo, phi);
-                own_lo = nlo;
-                own_hi = nhi;
+                // the next step's operand, and its slice for the partner
+                // (formed after the products: not live through them)
+                if (s + 1 < nH) {
+                    d_to_b(hp[2 * s + 2], hp[2 * s + 3], own_lo, own_hi);
+                    f32x4 *const ns = lane_slot(&slc[(s + 1) & 1][wave][0][0]);
+                    *(float4 *)ns = own_lo;
+                    *(float4 *)(ns + 64) = own_hi;
+                }
                 advance(3);
             }
         }
@@ -379,21 +381,8 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
         // waves add theirs after the barrier (complete before the barrier of
         // the first pair-mean step)
         if (sig == 0) {
-            int ln = __lane_id();
-            asm volatile("" : "+v"(ln));
-            const bool vrow = (ln & 15) == 0;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                // lane (0, og) takes block j's bias from lane (j, og)
-                const int src = 4 * (j + (ln & 48));
-                f32x4 b;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) b[e] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(bias8[e])));
-                f32x4 v = pm[j];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] = vrow ? v[e] + b[e] : v[e];
-                lane_slot(&pex[wl][8 * half][0])[64 * j] = v;
-            }
+            for (int j = 0; j < 8; ++j) lane_slot(&pex[wl][8 * half][0])[64 * j] = pm[j];
         }
         ring_barrier();
         if (sig == 1) {
@@ -405,10 +394,12 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
         }
 
         // ---- pair-mean steps: the V_h tile, then this wave's pair-mean rows
+        int gi_slot = 0;
 #pragma unroll 1
         for (int g = 0; g < nG; ++g) {
             step_sync(first + 2);
-            const unsigned char *gt = ring + slot_of(1) * TILE + wave * 2048 + t * 128;
+            gi_slot = slot_of(1);
+            const unsigned char *gt = ring + gi_slot * TILE + wave * 2048 + t * 128;
             const float4 lo = mask4r(*(const float4 *)(gt + 16 * ((2 * og) ^ (t & 7))), trow);
             const float4 hi = mask4r(*(const float4 *)(gt + 16 * ((2 * og + 1) ^ (t & 7))), trow);
             bf16x8 hb[NA];
@@ -490,9 +481,11 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
             }
         }
         float *const y0T = sA, *const ddT = sA + 256, *const srcT = sB, *const zeroT = sB + 256;
+        // the bias, from the padding rows of the last pair-mean tile
+        const float *const bsl = reinterpret_cast<const float *>(ring + gi_slot * TILE + 1792);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const float y = tanhf(z0[q]);
+            const float y = tanhf(z0[q] + bsl[512 * q + ln]);
             const float d = 1.f - y * y;
             y0T[64 * q + ln] = y;
             ddT[64 * q + ln] = d;
