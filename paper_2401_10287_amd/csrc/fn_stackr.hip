@@ -334,6 +334,9 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
             mean_products(0);
             own_products(4);
         }
+        // the electron's sums live in the accumulator registers between steps
+#pragma unroll
+        for (int c = 0; c < 16; ++c) asm volatile("" : "+a"(acc[c]));
     };
 
     for (int l = 0; l < a.L; ++l) {
@@ -399,9 +402,13 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
         for (int g = 0; g < nG; ++g) {
             step_sync(first + 2);
             gi_slot = slot_of(1);
-            const unsigned char *gt = ring + gi_slot * TILE + wave * 2048 + t * 128;
-            const float4 lo = mask4r(*(const float4 *)(gt + 16 * ((2 * og) ^ (t & 7))), trow);
-            const float4 hi = mask4r(*(const float4 *)(gt + 16 * ((2 * og + 1) ^ (t & 7))), trow);
+            // (lane offsets formed here from the lane id, not kept across the loop)
+            int ln = __lane_id();
+            asm volatile("" : "+v"(ln));
+            const int lt = ln & 15, lg = ln >> 4;
+            const unsigned char *gt = ring + gi_slot * TILE + wave * 2048 + lt * 128;
+            const float4 lo = mask4r(*(const float4 *)(gt + 16 * ((2 * lg) ^ (lt & 7))), trow);
+            const float4 hi = mask4r(*(const float4 *)(gt + 16 * ((2 * lg + 1) ^ (lt & 7))), trow);
             bf16x8 hb[NA];
             split_fragment<NA>(lo, hi, hb);
             const unsigned char *tile = ring + fslot * TILE + afrag_now();
