@@ -73,16 +73,15 @@ typedef int32_t fn_status;
    products whose part indices sum to at most 2, accumulated in FP32 (FP32
    operand precision on the BF16 matrix cores); the orbital head uses the
    same split.
-   FN_BF16W_MIXED: BF16 stream weights with FP32 activations.  The weight
-   matrices V of the one-electron layers are taken as their BF16 values
-   (each FP32 parameter rounded to nearest even); the activations, tangent
-   and Laplacian rows stay FP32 and enter the products split exactly into
-   three BF16 parts, so each layer product is three BF16 matrix products
-   whose terms are exact, accumulated in FP32.  Every call in this mode
-   (values, local energies, Metropolis moves, gradients) is the network whose
-   V are so rounded; gradients are with respect to those rounded entries.
-   The orbital head keeps FP32 weights (six-product split), the pair layers
-   FP32.
+   FN_BF16W_MIXED: BF16 weights with FP32 activations.  The weight matrices
+   V of the one-electron layers and the orbital head weights w are taken as
+   their BF16 values (each FP32 parameter rounded to nearest even); the
+   activations, tangent and Laplacian rows stay FP32 and enter the products
+   split exactly into three BF16 parts, so each product is three BF16 matrix
+   products whose terms are exact, accumulated in FP32.  Every call in this
+   mode (values, local energies, Metropolis moves, gradients) is the network
+   whose V and w are so rounded; gradients are with respect to those rounded
+   entries.  Biases, the pair layers and the envelope keep FP32 parameters.
    FN_BF16W2_MIXED: as FN_BF16W_MIXED with the activations split into two
    BF16 parts (16 significant bits), two products per layer product.
    In every mode the envelope, the determinants and their derivative traces

@@ -112,7 +112,7 @@ struct Ctx {
     int smode;       // per-electron stream-layer products
     int wmode;       // per-walker mean-field products
     int hmode;       // orbital head product
-    bool round_v;    // the layer weights V are their BF16 roundings (FN_BF16W*_MIXED)
+    bool round_v;    // the layer weights V and head weights w are their BF16 roundings (FN_BF16W*_MIXED)
     double vnn;
 };
 
@@ -165,11 +165,12 @@ fn_status make_ctx(const fn_config *cfg, Ctx &c)
     default: c.smode = GEMM_BF16X6; break;
     }
     // orbital head: FP32 operands; the six-product BF16 split carries them to
-    // FP32 accuracy on the matrix cores, so the modes with FP32-exact
-    // activation splits use it here as well (with FP32 weights)
+    // FP32 accuracy on the matrix cores, so the six-product mode uses it here
+    // as well; in the BF16-weight modes the head weights are BF16 roundings
+    // too, with the activations split as in the layers
     c.hmode = c.f64 ? GEMM_F64
-                    : (c.smode == GEMM_BF16X6 || c.smode == GEMM_BF16W3 || c.smode == GEMM_BF16W2 ? GEMM_BF16X6
-                                                                                                 : GEMM_F32);
+                    : (c.smode == GEMM_BF16X6 ? GEMM_BF16X6
+                                              : (c.smode == GEMM_BF16W3 || c.smode == GEMM_BF16W2 ? c.smode : GEMM_F32));
     c.wmode = c.smode;
     c.round_v = bf16_weight_mode(c.smode);
     // diagnostic: selected product classes on the FP32 matrix cores in the
@@ -383,7 +384,7 @@ void pack_weights(const Ctx &c, const Plan &p, const T *theta, char *ws, hipStre
         const int n = sp == 0 ? s.nu : s.nd;
         if (n == 0) continue;
         PackSeg g{};
-        g.kind = 1; g.mode = c.hmode; g.off = c.P.w[sp];
+        g.kind = 1; g.mode = c.hmode; g.off = c.P.w[sp]; g.round = c.round_v;
         g.w1 = s.w1; g.W1p = c.W.W1p; g.kn = s.K * n;
         g.count = (int64_t)g.kn * g.W1p;
         g.d0 = ws + p.wh[sp];
@@ -404,7 +405,7 @@ void pack_weights(const Ctx &c, const Plan &p, const T *theta, char *ws, hipStre
     for (int sp = 0; sp < 2; ++sp) {
         const int n = sp == 0 ? s.nu : s.nd;
         if (n > 0 && p.save)
-            launch_pack_head_bwd<T>(theta, c.P.w[sp], s.w1, s.K * n, c.W.KNp[sp], (T *)(ws + p.wb[sp]), st);
+            launch_pack_head_bwd<T>(theta, c.P.w[sp], s.w1, s.K * n, c.W.KNp[sp], c.round_v, (T *)(ws + p.wb[sp]), st);
     }
 }
 

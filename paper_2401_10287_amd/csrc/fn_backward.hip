@@ -874,14 +874,17 @@ __global__ void k_grad_out(const double *acc, int64_t n, T *grad)
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) grad[q] = (T)acc[q];
 }
 
-// Wb[u][col] = w[u][col] for col < kn, 0 up to KNp (adjoint of the head)
+// Wb[u][col] = w[u][col] for col < kn, 0 up to KNp (adjoint of the head);
+// rounded to BF16 when the forward's head weights are (BF16-weight modes)
 template <typename T>
-__global__ void k_pack_head_bwd(const T *theta, int64_t woff, int w1, int kn, int KNp, T *Wb)
+__global__ void k_pack_head_bwd(const T *theta, int64_t woff, int w1, int kn, int KNp, bool round, T *Wb)
 {
     const int64_t n = (int64_t)w1 * KNp;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
         const int u = (int)(q / KNp), col = (int)(q % KNp);
-        Wb[q] = col < kn ? theta[woff + (int64_t)u * kn + col] : T(0);
+        T v = col < kn ? theta[woff + (int64_t)u * kn + col] : T(0);
+        if (round) v = (T)bf16_round((float)v);
+        Wb[q] = v;
     }
 }
 
@@ -1089,9 +1092,10 @@ void launch_grad_out(const double *acc, int64_t n, T *grad, hipStream_t st)
 }
 
 template <typename T>
-void launch_pack_head_bwd(const T *theta, int64_t woff, int w1, int kn, int KNp, T *Wb, hipStream_t st)
+void launch_pack_head_bwd(const T *theta, int64_t woff, int w1, int kn, int KNp, bool round, T *Wb, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pack_head_bwd<T>, dim3(gridn((int64_t)w1 * KNp)), dim3(256), 0, st, theta, woff, w1, kn, KNp, Wb);
+    hipLaunchKernelGGL(k_pack_head_bwd<T>, dim3(gridn((int64_t)w1 * KNp)), dim3(256), 0, st, theta, woff, w1, kn, KNp,
+                       round, Wb);
 }
 
 #define FN_BWD_INST(T)                                                                                               \
@@ -1107,7 +1111,7 @@ void launch_pack_head_bwd(const T *theta, int64_t woff, int w1, int kn, int KNp,
     template void launch_colsum<T>(const T *, int64_t, int, int64_t, T *, double *, int64_t, int, int64_t,           \
                                    hipStream_t);                                                                      \
     template void launch_grad_out<T>(const double *, int64_t, T *, hipStream_t);                                      \
-    template void launch_pack_head_bwd<T>(const T *, int64_t, int, int, int, T *, hipStream_t);
+    template void launch_pack_head_bwd<T>(const T *, int64_t, int, int, int, bool, T *, hipStream_t);
 
 FN_BWD_INST(float)
 FN_BWD_INST(double)

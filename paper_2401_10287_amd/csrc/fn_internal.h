@@ -134,6 +134,15 @@ __device__ inline void split_bf16_pair(float a, float b, uint32_t (&h)[NP])
     }
 }
 
+// v rounded to the nearest BF16 value, ties to even (NaN stays NaN): the
+// weights of the BF16-weight modes
+__device__ inline float bf16_round(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return v;
+    return __uint_as_float(((u + 0x7fffu + ((u >> 16) & 1u)) >> 16) << 16);
+}
+
 // Direct global-to-LDS staging of operand tiles (split-BF16 products).
 // copy16_to_lds: each lane copies 16 bytes from its own global address g to
 // lds + 16 * lane (lds: the wave's 1 KB block, the same for all lanes).

@@ -137,7 +137,7 @@ void launch_zero_f64(double *p, int64_t n, hipStream_t st);
 template <typename T>
 void launch_grad_out(const double *acc, int64_t n, T *grad, hipStream_t st);
 template <typename T>
-void launch_pack_head_bwd(const T *theta, int64_t woff, int w1, int kn, int KNp, T *Wb, hipStream_t st);
+void launch_pack_head_bwd(const T *theta, int64_t woff, int w1, int kn, int KNp, bool round, T *Wb, hipStream_t st);
 
 // Monte Carlo
 void launch_propose(const double *x, int64_t B, int n3, double sigma, uint64_t seed, uint64_t step, uint32_t stream_id,

@@ -35,14 +35,6 @@ __device__ inline void put_w(int mode, void *base, int64_t part, int64_t idx, T 
     }
 }
 
-// v rounded to the nearest BF16 value, ties to even (NaN stays NaN)
-__device__ inline float bf16_round(float v)
-{
-    const uint32_t u = __float_as_uint(v);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return v;
-    return __uint_as_float(((u + 0x7fffu + ((u >> 16) & 1u)) >> 16) << 16);
-}
-
 // Element t of a layer block.  Wx [w1][HWl + GWl]: per-electron inputs
 // [h_i | g_i_up | g_i_dn]; Wg [w1][2 HWl]: per-walker inputs [g_up | g_dn].
 template <typename T>
@@ -76,7 +68,8 @@ __device__ inline void pack_head_elem(const T *theta, const PackSeg &g, int64_t 
 {
     const int64_t n = (int64_t)g.kn * g.W1p;
     const int col = (int)(t / g.W1p), k = (int)(t % g.W1p);
-    const T v = k < g.w1 ? theta[g.off + (int64_t)k * g.kn + col] : T(0);
+    T v = k < g.w1 ? theta[g.off + (int64_t)k * g.kn + col] : T(0);
+    if (g.round) v = (T)bf16_round((float)v);
     put_w<T>(g.mode, g.d0, n, t, v);
 }
 

@@ -44,13 +44,14 @@ def equilibrated(name, walkers):
 
 def bf16_weights(s, th):
     """The parameters of the BF16-weight modes: th with every entry of the
-    one-electron layer weight matrices V_l rounded to the nearest BF16 value
-    (ties to even); all other entries unchanged.  The oracle evaluates this
-    vector when it checks those modes."""
+    one-electron layer weight matrices V_l and of the orbital head weights
+    w_up, w_dn rounded to the nearest BF16 value (ties to even); all other
+    entries unchanged.  The oracle evaluates this vector when it checks those
+    modes."""
     from paper_2401_10287_amd import inputs as I
     out = np.array(th, dtype=np.float64, copy=True)
     for name, (o, shape) in I.param_offsets(s).items():
-        if name.startswith("V"):
+        if name.startswith("V") or name in ("w_up", "w_dn"):
             n = int(np.prod(shape))
             u = out[o:o + n].astype(np.float32).view(np.uint32).astype(np.uint64)
             u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
