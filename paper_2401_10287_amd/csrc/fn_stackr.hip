@@ -50,7 +50,9 @@ constexpr int CPT = 2;                // 16-byte copies per lane per tile (eight
 constexpr int N3 = 12;                // tangent rows: three coordinates of four electrons
 
 // until at most CPT * n vector-memory operations of this wave are
-// outstanding (n tiles still in flight; waiting for fewer is always safe)
+// outstanding (n tiles still in flight).  Loads complete in order, so this
+// lands every older tile; a pair-mean tile takes one copy more than CPT (its
+// padding rows bring the bias), which only makes the wait stricter
 __device__ inline void wait_tiles(int n)
 {
 #define FN_WVM(k) \
@@ -123,7 +125,6 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
     const bool trow = t <= N3 + 1;                    // rows past the Laplacian row are padding
     const int64_t row0 = (wc * 4 + el) * 16;         // this wave's electron
     const int64_t row = row0 + t;
-    const int64_t rowp0 = (wc * 4 + 2 * sig) * 16;   // the spin's first electron
 
     // ---- ring tiles, in consumption order, per layer: for each input step
     //      of h the V_g tiles of both spins and the V_h tile; for each
@@ -144,8 +145,8 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
     const uint16_t *iWg = a.Wg[0], *iWx = a.Wx[0];
     int iHW = a.HW[0], iGW = a.GW[0];
     const float *igi = a.GI + row0 * a.ldgi, *ibias = a.bias[0];
-    // copies j0 .. j1 - 1 of the next tile; the position moves on after its last
-    auto issue = [&](int j0, int j1) {
+    // the copies of the next tile, then the position moves on
+    auto issue = [&]() {
         unsigned char *slot = ring + islot * TILE;
         if (iph == 1 && ir == 1) {
             // pair means, step is: rows 8 j + lane / 8 of this wave's 16,
@@ -154,13 +155,12 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
             // layer instead (columns 64 (wave & 3) .. + 63, in order), which
             // the epilogue reads while the slot stays untouched
             const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(igi + 32 * is, (uint32_t)(16 * a.ldgi * 4));
-#pragma unroll
-            for (int j = j0; j < j1; ++j) {
-                if (j == 0 || lane < 48) copy16_buf(rs, glane, (uint32_t)(8 * j * a.ldgi * 4), slot + wave * 2048 + j * 1024);
-                if (j == 1 && lane >= 48)
-                    copy16_buf(buffer_rsrc(ibias, 256 * 4), (uint32_t)(16 * (lane - 48)), (uint32_t)(256 * (wave & 3)),
-                               slot + wave * 2048 + 1024);
-            }
+            copy16_buf(rs, glane, 0u, slot + wave * 2048);
+            if (lane < 48)
+                copy16_buf(rs, glane, (uint32_t)(8 * a.ldgi * 4), slot + wave * 2048 + 1024);
+            else
+                copy16_buf(buffer_rsrc(ibias, 256 * 4), (uint32_t)(16 * (lane - 48)), (uint32_t)(256 * (wave & 3)),
+                           slot + wave * 2048 + 1024);
         } else {
             const uint16_t *W;
             int ld;
@@ -174,12 +174,11 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
             const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(W, (uint32_t)(256 * ld * 2));
             const uint32_t voff = wrow2 * (uint32_t)ld + wchunk;
 #pragma unroll
-            for (int j = j0; j < j1; ++j) {
+            for (int j = 0; j < CPT; ++j) {
                 const int b = CPT * wave + j;
                 copy16_buf(rs, voff, (uint32_t)(16 * b * ld * 2), slot + b * 1024);
             }
         }
-        if (j1 < CPT) return;
         if (++islot == RT) islot = 0;
         if (++ir < 3 - iph) return;
         ir = 0;
@@ -208,17 +207,17 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
     auto step_sync = [&](int need) {
         wait_tiles(issued - need);
         ring_barrier();
-        for (; issued < NT && issued < first - 3 + RT; ++issued) issue(0, CPT);
+        for (; issued < NT && issued < first - 3 + RT; ++issued) issue();
     };
     // refill position p of a step (p static): a whole tile at positions 0,
     // 2 and 4
     auto refill_at = [&](int p) {
         if ((p == 0 || p == 2 || p == 4) && issued < NT && issued < first + RT) {
-            issue(0, CPT);
+            issue();
             ++issued;
         }
     };
-    for (; issued < NT && issued < RT; ++issued) issue(0, CPT);
+    for (; issued < NT && issued < RT; ++issued) issue();
     // ring slot of tile first + k (k < RT)
     int fslot = 0;
     auto slot_of = [&](int k) { return fslot + k < RT ? fslot + k : fslot + k - RT; };
