@@ -210,9 +210,11 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
         for (; issued < NT && issued < first - 3 + RT; ++issued) issue();
     };
     // refill position p of a step (p static): a whole tile at positions 0,
-    // 2 and 4
+    // 4 and 8 (each burst of copies drains before the next one queues up;
+    // closer positions, or the two walkers' waves at alternating positions,
+    // measured slower)
     auto refill_at = [&](int p) {
-        if ((p == 0 || p == 2 || p == 4) && issued < NT && issued < first + RT) {
+        if ((p == 0 || p == 4 || p == 8) && issued < NT && issued < first + RT) {
             issue();
             ++issued;
         }
@@ -257,8 +259,8 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
     // one input step of h: the electron's products over all sixteen blocks
     // (tile first + 2) and the spin-mean products of this wave's eight
     // column blocks of P_spin (tile first + spin); weight fragments two at a
-    // time, the next two requested before a pair's products; refills at
-    // positions 0, 2 and 4 of the step's twelve product groups
+    // time, the next two requested before a pair's products; refills after
+    // product groups 0, 4 and 8 of the step's twelve
     f32x4 pm[8];
     auto step_products = [&](const float4 &plo, const float4 &phi) {
         bf16x8 ha[NA], hb[NA];
