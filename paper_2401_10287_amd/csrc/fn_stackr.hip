@@ -115,6 +115,7 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
     // two slices of a wave are also its epilogue scratch
     __shared__ __attribute__((aligned(16))) float4 slc[2][8][2][64];
 
+    __builtin_amdgcn_s_setprio(1);                    // (0 while issuing copies)
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int t = lane & 15, og = lane >> 4;
     const int wl = wave >> 2, el = wave & 3;          // walker of the workgroup, electron of the walker
@@ -212,10 +213,13 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
     // refill position p of a step (p static): a whole tile at positions 0,
     // 4 and 8 (each burst of copies drains before the next one queues up;
     // closer positions, or the two walkers' waves at alternating positions,
-    // measured slower)
+    // measured slower).  The wave drops to the lower priority while it
+    // issues its copies, so that a wave with products to issue goes first
     auto refill_at = [&](int p) {
         if ((p == 0 || p == 4 || p == 8) && issued < NT && issued < first + RT) {
+            __builtin_amdgcn_s_setprio(0);
             issue();
+            __builtin_amdgcn_s_setprio(1);
             ++issued;
         }
     };
