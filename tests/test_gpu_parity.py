@@ -668,7 +668,8 @@ def test_bf16_weight_rounding_agrees(name, walkers):
           f"(batch mean {abs(e32.mean() - e1.cpu().numpy().mean()):.2e} Ha)")
 
 
-@pytest.mark.parametrize("name,walkers", [("LiH", 63), ((4, 0), 9), ((5, 1), 5), ((3, -1), 4)])
+@pytest.mark.parametrize("name,walkers", [("LiH", 63), ((4, 0), 9), ((5, 1), 5), ((3, -1), 4),
+                                          ((4, 0, 2, 32), 7), ((4, 0, 3, 16), 6), ((4, 0, 2, 64), 3)])
 def test_stack_regs_kernel(name, walkers):
     """Every one-electron layer in one kernel with the activations held in
     registers (four electrons, two of each spin, one BF16 weight part),
@@ -676,8 +677,12 @@ def test_stack_regs_kernel(name, walkers):
     oracle on the rounded parameters: in bf16w the local energy and log|psi|
     within the FP32-level bounds; bf16w2 and the one-pass mode are reported
     and must agree with the layer path to the size of their own errors.
-    Odd batches leave the last workgroup one walker short."""
-    s = SYSTEMS[name]() if isinstance(name, str) else I.atom_ion(*name, walkers=walkers)
+    Odd batches leave the last workgroup one walker short.  Atoms are given
+    as (Z, charge[, layers, pair width]): two and three layers and pair
+    widths 16, 32 and 64 (one, two and four pair-mean steps per layer) give
+    other tile sequences through the ring."""
+    s = SYSTEMS[name]() if isinstance(name, str) else I.atom_ion(
+        *name[:2], walkers=walkers, **dict(zip(("n_layers", "w2"), name[2:])))
     x = T.equilibrated("LiH", walkers) if name == "LiH" else (
         T.equilibrated(f"Z{name[0]}q{name[1]:+d}", 6).repeat(-(-walkers // 6), axis=0)[:walkers])
     o = O.Oracle(s)
