@@ -427,8 +427,18 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
     T *X = (T *)(ws + p.X);
     double *DR = (double *)(ws + p.DR);
     const int64_t ldh = c.W.HWmax, ldg = c.W.GWmax;
+    // every one-electron layer in one kernel with the activations in
+    // registers: it forms the spin-mean products from the features itself
+    bool regs = false;
+    if constexpr (std::is_same<T, float>::value)
+        regs = fl && !p.save && c.wmode == c.smode &&
+               stack_regs_supported(c.smode, s.N, s.nu, TR, s.w1, s.L, c.W.HWl, c.W.GWl);
     // the features and, in the same launch, the first layer's spin means
-    { Timed t_(K_FEATURES, st); launch_features<T>(s, xw, b, TR, c.W.HWl[0], ldh, Hbuf(0), G, st); }
+    // (not needed by the register kernel)
+    {
+        Timed t_(K_FEATURES, st);
+        launch_features<T>(s, xw, b, TR, c.W.HWl[0], ldh, Hbuf(0), regs ? nullptr : G, st);
+    }
     {
         Timed t_(K_PAIR, st);
         launch_pair_stream<T>(s, xw, theta, c.P, b, TR, fl, ldg, p.gi_layer_stride, c.W.GWl[0],
@@ -438,9 +448,8 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
     bool g_ready = true;             // spin means of h^l already written (features, previous layer)
     bool stacked = false;
     if constexpr (std::is_same<T, float>::value) {
-        // every one-electron layer in one kernel (activations stay in LDS)
-        const bool regs = fl && !p.save && c.wmode == c.smode &&
-                          stack_regs_supported(c.smode, s.N, s.nu, TR, s.w1, s.L, c.W.HWl, c.W.GWl);
+        // every one-electron layer in one kernel (activations in registers,
+        // or in LDS)
         if (regs || (fl && !p.save && c.wmode == c.smode && stack_supported(c.smode, s.N, TR, s.w1, s.L))) {
             StackArgs sa{};
             sa.H0 = Hbuf(0); sa.ldh = ldh;
