@@ -433,6 +433,8 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
     if constexpr (std::is_same<T, float>::value)
         regs = fl && !p.save && c.wmode == c.smode &&
                stack_regs_supported(c.smode, s.N, s.nu, TR, s.w1, s.L, c.W.HWl, c.W.GWl);
+    // ... and the orbital head with it
+    const bool head_fused = regs && stack_regs_head(c.smode, c.hmode, s.K, s.nu, s.nd, c.W.W1p);
     // the features and, in the same launch, the first layer's spin means
     // (not needed by the register kernel)
     {
@@ -466,6 +468,13 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
             }
             sa.Hout = Hbuf(s.L);
             sa.B = b; sa.L = s.L; sa.nu = s.nu; sa.n3 = n3;
+            if (regs && head_fused)
+                for (int sp = 0; sp < 2; ++sp) {
+                    sa.WH[sp] = (const uint16_t *)(ws + p.wh[sp]);
+                    sa.O[sp] = (float *)(ws + p.O[sp]);
+                    sa.ldo[sp] = c.W.KNp[sp];
+                    sa.ldwh = c.W.W1p;
+                }
             Timed t_(K_STREAM_GEMM, st);
             if (regs) launch_stack_regs(c.smode, sa, st);
             else launch_stack(c.smode, sa, s.N, st);
@@ -559,7 +568,7 @@ void forward_chunk(const Ctx &c, const Plan &p, const T *theta, const double *xw
             gh.rows = b * n * TR; gh.rows_per_group = (int64_t)n * TR;
         }
     }
-    {
+    if (!head_fused) {
         Timed t_(K_HEAD_GEMM, st);
         (void)launch_gemm2(c.hmode, ghs[0], ghs[1], st);
     }

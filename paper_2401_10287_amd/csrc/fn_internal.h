@@ -483,6 +483,10 @@ struct StackArgs {
     const float *bias[FN_MAX_LAYERS];
     float *Hout;                               // h^L, live rows, leading dimension ldh
     int64_t B; int L; int nu; int n3;
+    // the orbital head in the register kernel (WH[0] non-null): BF16 head
+    // weights per spin, [32 = K n][ldwh], and the outputs O[spin] (rows
+    // (walker n + j) 16 + t, leading dimension ldo[spin]); Hout unused then
+    const uint16_t *WH[2]; int ldwh; float *O[2]; int64_t ldo[2];
 };
 extern int g_use_stack;                        // tuning switch "layer_stack": 0 never, 1 one-pass BF16, 2 every split mode
 extern int g_stack_shape;                      // tuning switch "stack_shape": workgroup shape 0, 1, 2
@@ -496,6 +500,11 @@ void launch_stack(int mode, const StackArgs &a, int N, hipStream_t st);
 // (tuning switch "stack_regs", on by default)
 extern bool g_stack_regs;
 bool stack_regs_supported(int mode, int N, int nu, int TR, int w1, int L, const int *HW, const int *GW);
+// the orbital head fused into it: one BF16 weight part, K n = 32 per spin, w1 = 256
+inline bool stack_regs_head(int mode, int hmode, int K, int nu, int nd, int W1p)
+{
+    return hmode == mode && (mode == GEMM_BF16W3 || mode == GEMM_BF16W2) && K * nu == 32 && K * nd == 32 && W1p == 256;
+}
 void launch_stack_regs(int mode, const StackArgs &a, hipStream_t st);
 // 128-row tiles of the fused layer hold whole walkers
 inline bool stream_layer_whole_walkers(int N, int TR) { return N * TR <= 128 && 128 % (N * TR) == 0; }

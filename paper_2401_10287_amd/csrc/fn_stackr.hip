@@ -131,6 +131,7 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
     //      of h the V_g tiles of both spins and the V_h tile; for each
     //      pair-mean step the V_h tile and then the pair means of every
     //      wave's rows (2 KB per wave, rows chunk-swizzled)
+    const bool head = a.WH[0] != nullptr;
     int NT = 0;
     for (int l = 0; l < a.L; ++l) NT += 3 * (a.HW[l] >> 5) + 2 * (a.GW[l] >> 5);
     // lane parts of the copy offsets (the same for every tile): weight tiles
@@ -454,6 +455,22 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
         //      Pass 3: every row as A z + C with (A, C) by row role: value
         //      (0, y_0), tangent and padding (d, 0), Laplacian (d, source);
         //      then the residual.
+        if (head && l + 1 == a.L) {
+            // the head weights of both spins into the next two ring slots
+            // (their tiles were read before the pair-mean step: free now);
+            // they land while the epilogue runs.  Spin sp's tile: 1 KB block
+            // b = 2 s + c holds output rows 16 c .. + 15, reduction columns
+            // 32 s .. + 31 (s = wave)
+#pragma unroll
+            for (int sp = 0; sp < 2; ++sp) {
+                const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(a.WH[sp], (uint32_t)(32 * a.ldwh * 2));
+                const uint32_t voff = wrow2 * (uint32_t)a.ldwh + wchunk;
+                unsigned char *slot = ring + slot_of(sp) * TILE;
+#pragma unroll
+                for (int j = 0; j < CPT; ++j)
+                    copy16_buf(rs, voff, (uint32_t)((16 * j * a.ldwh + 32 * wave) * 2), slot + (CPT * wave + j) * 1024);
+            }
+        }
         float *const sA = &slc[0][wave][0][0].x, *const sB = &slc[1][wave][0][0].x;
         // (lane-dependent offsets formed here from the lane id, not kept
         // across the layer loop)
@@ -540,10 +557,41 @@ __global__ __launch_bounds__(512, 1) void k_stack_regs(StackArgs a)
         }
     }
 
-    // h^L of the live rows for the orbital head
-    if (live && trow) {
+    if (!head) {
+        // h^L of the live rows for the orbital head
+        if (live && trow) {
 #pragma unroll
-        for (int c = 0; c < 16; ++c) *(f32x4 *)(a.Hout + row * a.ldh + 16 * c + 4 * og) = hp[c];
+            for (int c = 0; c < 16; ++c) *(f32x4 *)(a.Hout + row * a.ldh + 16 * c + 4 * og) = hp[c];
+        }
+        return;
+    }
+    // the orbital head (FermiNet Model section): O = h^L w for the wave's
+    // electron, K n = 32 outputs of its spin, from h^L in registers and the
+    // spin's head weights (tile first + spin), in the layers' product form
+    wait_tiles(0);
+    ring_barrier();
+    f32x4 ho[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+    {
+        const unsigned char *tile = ring + slot_of(sig) * TILE + afrag_now();
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            float4 lo, hi;
+            d_to_b(hp[2 * s], hp[2 * s + 1], lo, hi);
+            bf16x8 hb[NA];
+            split_fragment<NA>(lo, hi, hb);
+            const bf16x8 w0 = *(const bf16x8 *)(tile + (2 * s) * 1024);
+            const bf16x8 w1 = *(const bf16x8 *)(tile + (2 * s + 1) * 1024);
+#pragma unroll
+            for (int p = 0; p < NA; ++p) {
+                ho[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, hb[p], ho[0], 0, 0, 0);
+                ho[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, hb[p], ho[1], 0, 0, 0);
+            }
+        }
+    }
+    if (live && trow) {
+        float *o = a.O[sig] + ((wc * 2 + half) * 16 + t) * a.ldo[sig] + 4 * og;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) *(f32x4 *)(o + 16 * c) = ho[c];
     }
 }
 
