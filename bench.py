@@ -67,6 +67,13 @@ def mean_field_flops(s, walkers):
     return sum(2 * walkers * T * 2 * I.layer_dims(s, l)[0] * s.w1 for l in range(s.n_layers))
 
 
+def head_flops(s, walkers):
+    """Algorithmic FLOPs of the orbital head of one local-energy pass:
+    2 B N T w1 (K n_spin) over the T = 3N + 2 rows of every electron."""
+    T = 3 * s.n_elec + 2
+    return sum(2 * walkers * n * T * s.w1 * s.n_det * n for n in (s.n_up, s.n_dn))
+
+
 def time_steps(fn, steps, torch):
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
@@ -343,6 +350,10 @@ def main():
     if stacked:
         flops_per_launch = flops + mean_field_flops(s, args.walkers)
         kernel_name = "k_stack_regs (every one-electron layer, per-electron and mean-field products)"
+        if kern.get("head_gemm", (0.0, 0))[1] == 0:
+            # the orbital head runs in the same launch
+            flops_per_launch += head_flops(s, args.walkers)
+            kernel_name = "k_stack_regs (every one-electron layer and the orbital head)"
         traffic = measured_traffic(STACK_TRAFFIC_FILE, STACK_SOURCE) if args.walkers == 4096 else None
     else:
         flops_per_launch = flops / s.n_layers
