@@ -1222,6 +1222,23 @@ __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *
 // (Eq. 4) and, with FL, its electron-j gradient and Laplacian, the orbital
 // value a (head output plus bias) and A = a e; all FP64.
 template <typename T, int NS, bool FL>
+__device__ __forceinline__ void small_entry(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof,
+                                            int64_t sigof, const T *O, int64_t ldo, int TR, int j0, int64_t w, int k,
+                                            int io, int jj, double &ev, double (&ge)[3], double &le, double &a0,
+                                            double &A)
+{
+    const int col = k * NS + io, j = j0 + jj;
+    const double *xj = x + (w * s.N + j) * 3;
+    double env = 0.0, g3[3] = {0.0, 0.0, 0.0}, lp = 0.0;
+    for (int m = 0; m < s.M; ++m) env_add<T, FL>(s, theta, piof, sigof, col, m, xj, env, g3, lp);
+    ev = env;
+    ge[0] = g3[0]; ge[1] = g3[1]; ge[2] = g3[2];
+    le = lp;
+    a0 = (double)O[((w * NS + jj) * TR) * ldo + col] + (double)theta[gof + col];
+    A = a0 * env;
+}
+
+template <typename T, int NS, bool FL>
 __device__ __forceinline__ void small_entries(const Sys &s, const double *x, const T *theta, int64_t gof, int64_t piof,
                                               int64_t sigof, const T *O, int64_t ldo, int TR, int j0, int64_t w, int k,
                                               double (&ev)[NS][NS], double (&ge)[NS][NS][3], double (&le)[NS][NS],
@@ -1230,17 +1247,9 @@ __device__ __forceinline__ void small_entries(const Sys &s, const double *x, con
 #pragma unroll
     for (int io = 0; io < NS; ++io)
 #pragma unroll
-        for (int jj = 0; jj < NS; ++jj) {
-            const int col = k * NS + io, j = j0 + jj;
-            const double *xj = x + (w * s.N + j) * 3;
-            double env = 0.0, g3[3] = {0.0, 0.0, 0.0}, lp = 0.0;
-            for (int m = 0; m < s.M; ++m) env_add<T, FL>(s, theta, piof, sigof, col, m, xj, env, g3, lp);
-            ev[io][jj] = env;
-            ge[io][jj][0] = g3[0]; ge[io][jj][1] = g3[1]; ge[io][jj][2] = g3[2];
-            le[io][jj] = lp;
-            a0[io][jj] = (double)O[((w * NS + jj) * TR) * ldo + col] + (double)theta[gof + col];
-            A[io][jj] = a0[io][jj] * env;
-        }
+        for (int jj = 0; jj < NS; ++jj)
+            small_entry<T, NS, FL>(s, x, theta, gof, piof, sigof, O, ldo, TR, j0, w, k, io, jj, ev[io][jj], ge[io][jj],
+                                   le[io][jj], a0[io][jj], A[io][jj]);
 }
 
 // LU with partial pivoting of A in place (rows = orbitals): row permutation,
@@ -1288,21 +1297,52 @@ __device__ __forceinline__ void small_lu(double (&A)[NS][NS], int (&perm)[NS], i
 // matrices in registers (two adjacent threads in the forward-Laplacian form,
 // each taking half of the directions; four measured slower).  Same quantities as k_orbdet; here
 // the directions use the explicit inverse from the pivoted LU,
-// M_c = A^-1 d_c A.
-template <typename T, int NS, bool FL>
+// M_c = A^-1 d_c A.  The spin's envelope parameters and orbital offsets are
+// copied into LDS once per workgroup (when they fit: SMALL_STAGE_MAX
+// elements), and the orbital rows a thread reads are requested before the
+// envelope arithmetic, SMALL_DIRS directions at a time, so that a thread
+// waits for global memory about twice instead of once per direction.
+constexpr int SMALL_DIRS = 8;
+constexpr int SMALL_STAGE_MAX = 8192;
+
+// elements of the staged parameter block of one spin: pi [K n][M], Sigma
+// [K n][M][1 or 9], orbital offsets g [K n]
+inline __host__ __device__ int64_t small_stage_elems(const Sys &s, int n)
+{
+    const int64_t kn = (int64_t)s.K * n;
+    return kn * s.M * (s.iso ? 2 : 10) + kn;
+}
+
+template <typename T, int NS, bool FL, bool ST>
 __global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, const T *theta, OrbSpins<T> S, int sp0,
                                                       int64_t B, int TR, double *DR, int rec)
 {
+    extern __shared__ __attribute__((aligned(16))) unsigned char small_smem[];
     // spins sp0 .. of NS electrons each, ceil(H B K / 256) workgroups per spin
     constexpr int H = FL ? 2 : 1;                         // threads per determinant
     const int64_t per = B * s.K * H, gsp = (per + 255) / 256;
     const int sp = sp0 + (int)(blockIdx.x / gsp);
-    const int64_t gof = sp ? S.gof1 : S.gof0, piof = sp ? S.piof1 : S.piof0, sigof = sp ? S.sigof1 : S.sigof0;
+    int64_t gof = sp ? S.gof1 : S.gof0, piof = sp ? S.piof1 : S.piof0, sigof = sp ? S.sigof1 : S.sigof0;
     const int64_t ldo = sp ? S.ldo1 : S.ldo0;
     const T *O = sp ? S.O1 : S.O0;
     const int j0 = sp == 0 ? 0 : s.nu;
     const int n3 = 3 * s.N;
     const int64_t tid = (blockIdx.x % gsp) * (int64_t)blockDim.x + threadIdx.x;
+    // the spin's parameters into LDS (ST: they fit; every thread of the
+    // workgroup takes part before any of them leaves)
+    const T *tp = theta;
+    if constexpr (ST) {
+        const int64_t nst = small_stage_elems(s, NS);
+        T *sm = reinterpret_cast<T *>(small_smem);
+        const int64_t kn = (int64_t)s.K * NS, npi = kn * s.M, nsg = npi * (s.iso ? 1 : 9);
+        for (int64_t q = threadIdx.x; q < nst; q += blockDim.x)
+            sm[q] = q < npi ? theta[piof + q] : (q < npi + nsg ? theta[sigof + (q - npi)] : theta[gof + (q - npi - nsg)]);
+        __syncthreads();
+        tp = sm;
+        piof = 0;
+        sigof = npi;
+        gof = npi + nsg;
+    }
     // the H threads of a determinant are adjacent lanes (per is a multiple of
     // H, so either all of them return here or none)
     if (tid >= per) return;
@@ -1310,8 +1350,62 @@ __global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, co
     const int64_t id = tid / H;
     const int64_t w = id / s.K;
     const int k = (int)(id % s.K);
+    // directions mt0 .. mt1 - 1 of the 3N tangents and the Laplacian (mt = 3N);
+    // direction mt reads orbital row 1 + mt (the Laplacian row is 3N + 1), the
+    // Laplacian also electron j's own tangent rows
+    const int mt0 = hh * ((n3 + 1) / H), mt1 = hh + 1 == H ? n3 + 1 : (hh + 1) * ((n3 + 1) / H);
+    const T *Ob = O + (w * NS * TR) * ldo + k * NS;      // row (jj, t) at (jj TR + t) ldo
+    T ov[SMALL_DIRS][NS][NS], lj[NS][NS][3];
+    auto load_dirs = [&](int mb) {
+#pragma unroll
+        for (int u = 0; u < SMALL_DIRS; ++u)
+#pragma unroll
+            for (int io = 0; io < NS; ++io)
+#pragma unroll
+                for (int jj = 0; jj < NS; ++jj)
+                    ov[u][io][jj] = mb + u < mt1 ? Ob[((int64_t)jj * TR + 1 + mb + u) * ldo + io] : T(0);
+    };
+    if constexpr (FL) {
+        load_dirs(mt0);
+#pragma unroll
+        for (int io = 0; io < NS; ++io)
+#pragma unroll
+            for (int jj = 0; jj < NS; ++jj)
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    lj[io][jj][a] = mt1 == n3 + 1 ? Ob[((int64_t)jj * TR + 1 + 3 * (j0 + jj) + a) * ldo + io] : T(0);
+    }
     double ev[NS][NS], ge[NS][NS][3], le[NS][NS], a0[NS][NS], A[NS][NS];
-    small_entries<T, NS, FL>(s, x, theta, gof, piof, sigof, O, ldo, TR, j0, w, k, ev, ge, le, a0, A);
+    if constexpr (H == 2 && NS == 2) {
+        // each of the two threads forms one orbital row (io = hh), then the
+        // pair swaps them (adjacent lanes)
+        double rv[NS][7];
+#pragma unroll
+        for (int jj = 0; jj < NS; ++jj) {
+            double g3[3];
+            small_entry<T, NS, FL>(s, x, tp, gof, piof, sigof, O, ldo, TR, j0, w, k, hh, jj, rv[jj][0], g3, rv[jj][4],
+                                   rv[jj][5], rv[jj][6]);
+            rv[jj][1] = g3[0]; rv[jj][2] = g3[1]; rv[jj][3] = g3[2];
+        }
+#pragma unroll
+        for (int jj = 0; jj < NS; ++jj) {
+            double ov7[7];
+#pragma unroll
+            for (int q = 0; q < 7; ++q) ov7[q] = __shfl_xor(rv[jj][q], 1);
+#pragma unroll
+            for (int io = 0; io < NS; ++io) {
+                ev[io][jj] = io == hh ? rv[jj][0] : ov7[0];
+                ge[io][jj][0] = io == hh ? rv[jj][1] : ov7[1];
+                ge[io][jj][1] = io == hh ? rv[jj][2] : ov7[2];
+                ge[io][jj][2] = io == hh ? rv[jj][3] : ov7[3];
+                le[io][jj] = io == hh ? rv[jj][4] : ov7[4];
+                a0[io][jj] = io == hh ? rv[jj][5] : ov7[5];
+                A[io][jj] = io == hh ? rv[jj][6] : ov7[6];
+            }
+        }
+    } else {
+        small_entries<T, NS, FL>(s, x, tp, gof, piof, sigof, O, ldo, TR, j0, w, k, ev, ge, le, a0, A);
+    }
     // LU with partial pivoting (rows = orbitals), then the inverse
     int perm[NS], sgn;
     double lg;
@@ -1352,49 +1446,51 @@ __global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, co
         for (int r = 0; r < NS; ++r) Ai[r][e] = v[r];
     }
     // directions: D = d_c A (tangents) or lap A; M = A^-1 D
-    const T *Ob = O + (w * NS * TR) * ldo + k * NS;      // row (jj, t) at (jj TR + t) ldo
-    // directions mt0 .. mt1 - 1 of the 3N tangents and the Laplacian (mt = 3N)
-    const int mt0 = hh * ((n3 + 1) / H), mt1 = hh + 1 == H ? n3 + 1 : (hh + 1) * ((n3 + 1) / H);
     double sq = 0.0, trl = 0.0;
-    for (int mt = mt0; mt < mt1; ++mt) {
-        double D[NS][NS];
+    for (int mb = mt0; mb < mt1; mb += SMALL_DIRS) {
+        if (mb != mt0) load_dirs(mb);
 #pragma unroll
-        for (int io = 0; io < NS; ++io)
+        for (int u = 0; u < SMALL_DIRS; ++u) {
+            const int mt = mb + u;
+            if (mt >= mt1) break;
+            double D[NS][NS];
 #pragma unroll
-            for (int jj = 0; jj < NS; ++jj) {
-                const int j = j0 + jj;
-                const T *Oj = Ob + (int64_t)jj * TR * ldo + io;
-                double dv;
-                if (mt < n3) {
-                    dv = ev[io][jj] * (double)Oj[(1 + mt) * ldo];
-                    if (mt / 3 == j) dv += a0[io][jj] * ge[io][jj][mt % 3];
-                } else {
-                    dv = ev[io][jj] * (double)Oj[(n3 + 1) * ldo] + a0[io][jj] * le[io][jj];
-                    for (int a = 0; a < 3; ++a) dv += 2.0 * (double)Oj[(1 + 3 * j + a) * ldo] * ge[io][jj][a];
+            for (int io = 0; io < NS; ++io)
+#pragma unroll
+                for (int jj = 0; jj < NS; ++jj) {
+                    const int j = j0 + jj;
+                    double dv;
+                    if (mt < n3) {
+                        dv = ev[io][jj] * (double)ov[u][io][jj];
+                        if (mt / 3 == j) dv += a0[io][jj] * ge[io][jj][mt % 3];
+                    } else {
+                        dv = ev[io][jj] * (double)ov[u][io][jj] + a0[io][jj] * le[io][jj];
+                        for (int a = 0; a < 3; ++a) dv += 2.0 * (double)lj[io][jj][a] * ge[io][jj][a];
+                    }
+                    D[io][jj] = dv;
                 }
-                D[io][jj] = dv;
-            }
-        double M[NS][NS];
-#pragma unroll
-        for (int i = 0; i < NS; ++i)
-#pragma unroll
-            for (int c = 0; c < NS; ++c) {
-                double acc = 0.0;
-#pragma unroll
-                for (int r = 0; r < NS; ++r) acc += Ai[i][r] * D[r][c];
-                M[i][c] = acc;
-            }
-        double tr = 0.0;
-#pragma unroll
-        for (int i = 0; i < NS; ++i) tr += M[i][i];
-        if (mt < n3) {
-            out[2 + mt] = tr;
+            double M[NS][NS];
 #pragma unroll
             for (int i = 0; i < NS; ++i)
 #pragma unroll
-                for (int c = 0; c < NS; ++c) sq += M[i][c] * M[c][i];
-        } else {
-            trl = tr;
+                for (int c = 0; c < NS; ++c) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int r = 0; r < NS; ++r) acc += Ai[i][r] * D[r][c];
+                    M[i][c] = acc;
+                }
+            double tr = 0.0;
+#pragma unroll
+            for (int i = 0; i < NS; ++i) tr += M[i][i];
+            if (mt < n3) {
+                out[2 + mt] = tr;
+#pragma unroll
+                for (int i = 0; i < NS; ++i)
+#pragma unroll
+                    for (int c = 0; c < NS; ++c) sq += M[i][c] * M[c][i];
+            } else {
+                trl = tr;
+            }
         }
     }
     // the H threads' sums of tr(M_c^2) added in thread order; the Laplacian
@@ -1772,7 +1868,12 @@ static void launch_small(const Sys &s, const double *x, const T *theta, const Or
 {
     const int H = FL ? 2 : 1;                             // threads per determinant (as in the kernel)
     const dim3 gs((unsigned)(nsp * ((H * B * s.K + 255) / 256)));
-    hipLaunchKernelGGL((k_orbdet_small<T, NS, FL>), gs, dim3(256), 0, st, s, x, theta, S, sp0, B, TR, DR, rec);
+    const int64_t nst = small_stage_elems(s, NS);
+    if (nst <= SMALL_STAGE_MAX)
+        hipLaunchKernelGGL((k_orbdet_small<T, NS, FL, true>), gs, dim3(256), (size_t)nst * sizeof(T), st, s, x, theta, S,
+                           sp0, B, TR, DR, rec);
+    else
+        hipLaunchKernelGGL((k_orbdet_small<T, NS, FL, false>), gs, dim3(256), 0, st, s, x, theta, S, sp0, B, TR, DR, rec);
 }
 
 // spins sp0 .. sp0 + nsp - 1 (of n electrons each) in one launch: one thread
