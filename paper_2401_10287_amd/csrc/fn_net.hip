@@ -1560,14 +1560,14 @@ __global__ __launch_bounds__(64) void k_combine(Sys s, const double *x, const do
     }
     if (lane < K) s_w[lane] = node ? 0.0 : ek / S;
     __syncthreads();
-    // sum_k w_k |grad l_k|^2 over coordinates, and sum_k w_k lap l_k
+    // sum_k w_k |grad l_k|^2 over coordinates, and sum_k w_k lap l_k (one
+    // item per (determinant, coordinate): a lane's loads are independent)
     double q = 0.0;
-    for (int c = lane; c < n3; c += 64) {
-        for (int k = 0; k < K; ++k) {
-            double gu = s.nu > 0 ? ru[k * rec + 2 + c] : 0.0, gd = s.nd > 0 ? rd[k * rec + 2 + c] : 0.0;
-            double g = gu + gd;
-            q += s_w[k] * g * g;
-        }
+    for (int it = lane; it < K * n3; it += 64) {
+        const int k = it / n3, c = it - k * n3;
+        const double gu = s.nu > 0 ? ru[k * rec + 2 + c] : 0.0, gd = s.nd > 0 ? rd[k * rec + 2 + c] : 0.0;
+        const double g = gu + gd;
+        q += s_w[k] * g * g;
     }
     double lsum = 0.0;
     if (lane < K) {
