@@ -222,8 +222,10 @@ def h20_local_energy(prec, steps=5, warmup=1, envelope=0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    # the clocks take some tens of milliseconds of load to settle: the
+    # warm-up covers about 0.2 s of local-energy passes
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", default="bf16w", choices=["bf16", "bf16x3", "bf16x6", "bf16w", "bf16w2", "fp32"])
     ap.add_argument("--walkers", type=int, default=4096)
     ap.add_argument("--sample", type=int, default=4096,
