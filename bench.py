@@ -75,18 +75,27 @@ def head_flops(s, walkers):
 
 
 def time_steps(fn, steps, torch):
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    """Wall time of `steps` back-to-back calls (no per-step events inside the
+    timed region)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def step_latencies(fn, steps, torch):
+    """GPU time of each of `steps` more calls, every call bracketed by events
+    (a separate pass after the timed one)."""
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     for k in range(steps):
         starts[k].record()
         fn()
         ends[k].record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
-    return wall, lat
+    return np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
 
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2401_10287_amd", "csrc", "fn_layer.hip")
@@ -196,7 +205,7 @@ def h20_local_energy(prec, steps=5, warmup=1, envelope=0):
     fnvmc.fn_timing_reset()
     fnvmc.fn_timing_select("stream_gemm")
     fnvmc.fn_timing_enable(True)
-    wall, lat = time_steps(lambda: fnvmc.fn_local_energy(cfg, tt, xt, ws=ws, want_parts=False), steps, torch)
+    wall = time_steps(lambda: fnvmc.fn_local_energy(cfg, tt, xt, ws=ws, want_parts=False), steps, torch)
     ms_g, n_g = fnvmc.fn_timing_read("stream_gemm")
     fnvmc.fn_timing_reset()
     fnvmc.fn_timing_select("det")
@@ -279,10 +288,12 @@ def main():
             fnvmc.fn_timing_reset()
             fnvmc.fn_timing_select("stream_gemm")
             fnvmc.fn_timing_enable(True)
-        wall, lat = time_steps(step, args.steps, torch)
+        wall = time_steps(step, args.steps, torch)
         if timing:
             fnvmc.fn_timing_enable(False)
             results["stream_gemm"] = fnvmc.fn_timing_read("stream_gemm")
+        lat = step_latencies(step, args.steps, torch)
+        if timing:
             # per-kernel breakdown from a separate pass with every class bracketed
             fnvmc.fn_timing_reset()
             fnvmc.fn_timing_select(None)
