@@ -1009,19 +1009,26 @@ size_t orbdet_lds(int n, bool fl)
     const size_t nn = (size_t)n * n;
     return ((fl ? 7 * nn + (size_t)orbdet_cd(n) * nn : nn)) * sizeof(double) + (size_t)n * sizeof(int) + 16;
 }
+// byte offset of the staged envelope parameters (after the orbdet_lds bytes, 16-byte aligned)
+__host__ __device__ inline size_t orbdet_stage_off(int n, bool fl)
+{
+    const size_t nn = (size_t)n * n;
+    return ((fl ? 7 * nn + (size_t)orbdet_cd(n) * nn : nn) * sizeof(double) + (size_t)n * sizeof(int) + 16 + 15) &
+           ~(size_t)15;
+}
 
 // FL = false: value only (envelope, LU, sign and log|det|), LDS holds the matrix only.
 // REG: triangular solves of the directions in registers (spins of 7 ..
 // ORB_PF electrons, where LDS, not registers, bounds the resident waves)
 // Spins sp0 .. sp0 + nsp - 1 of equal size, B * K workgroups each.
-template <typename T, bool FL, bool REG>
+template <typename T, bool FL, bool REG, bool ST>
 __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *theta, OrbSpins<T> S, int sp0,
                                                int64_t B, int TR, double *DR, int rec)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int64_t per = B * s.K;
     const int sp = sp0 + (int)(blockIdx.x / per);
-    const int64_t gof = sp ? S.gof1 : S.gof0, piof = sp ? S.piof1 : S.piof0, sigof = sp ? S.sigof1 : S.sigof0;
+    int64_t gof = sp ? S.gof1 : S.gof0, piof = sp ? S.piof1 : S.piof0, sigof = sp ? S.sigof1 : S.sigof0;
     const int64_t ldo = sp ? S.ldo1 : S.ldo0;
     const T *O = sp ? S.O1 : S.O0;
     const int n = sp == 0 ? s.nu : s.nd, j0 = sp == 0 ? 0 : s.nu;
@@ -1041,14 +1048,31 @@ __global__ __launch_bounds__(64) void k_orbdet(Sys s, const double *x, const T *
     const int k = (int)(wk % s.K);
     if (w >= B) return;
 
+    // ST: this determinant's pi [n][M], Sigma [n][M][1 or 9] and orbital
+    // offsets [n] into LDS first (after the matrices and the permutation),
+    // requested together instead of once per nucleus
+    const T *tp = theta;
+    if constexpr (ST) {
+        T *prm = reinterpret_cast<T *>(smem_raw + orbdet_stage_off(n, FL));
+        const int64_t c0 = (int64_t)k * n, npi = (int64_t)n * s.M, sz = s.iso ? 1 : 9, nsg = npi * sz;
+        for (int q = lane; q < npi + nsg + n; q += 64)
+            prm[q] = q < npi ? theta[piof + c0 * s.M + q]
+                             : (q < npi + nsg ? theta[sigof + c0 * s.M * sz + (q - npi)] : theta[gof + c0 + (q - npi - nsg)]);
+        __syncthreads();
+        // offsets such that column k n + io lands on staged row io
+        tp = prm;
+        piof = -c0 * s.M;
+        sigof = npi - c0 * s.M * sz;
+        gof = npi + nsg - c0;
+    }
     // envelope and orbital value of every (orbital io, electron jj)
     for (int q = lane; q < nn; q += 64) {
         const int io = q / n, jj = q - io * n;
         const int col = k * n + io, j = j0 + jj;
         const double *xj = x + (w * s.N + j) * 3;
         double env = 0.0, ge[3] = {0.0, 0.0, 0.0}, le = 0.0;
-        for (int m = 0; m < s.M; ++m) env_add<T, FL>(s, theta, piof, sigof, col, m, xj, env, ge, le);
-        const double a0 = (double)O[((w * n + jj) * TR) * ldo + col] + (double)theta[gof + col];
+        for (int m = 0; m < s.M; ++m) env_add<T, FL>(s, tp, piof, sigof, col, m, xj, env, ge, le);
+        const double a0 = (double)O[((w * n + jj) * TR) * ldo + col] + (double)tp[gof + col];
         if constexpr (FL) {
             EV[q] = env;
             GE[3 * q] = ge[0]; GE[3 * q + 1] = ge[1]; GE[3 * q + 2] = ge[2];
@@ -1903,15 +1927,30 @@ static void launch_orbdet_spins(const Sys &s, const double *x, const T *theta, c
     }
 #undef FN_SMALL
     const dim3 g((unsigned)(nsp * B * s.K));
+    // the determinant's envelope parameters staged in LDS when that adds at
+    // most a quarter to the workgroup's LDS (more lowers the resident
+    // workgroups by more than the staging saves: H20, 20 nuclei, 46%
+    // slower; LiF, 2 nuclei, 8% faster)
+    const size_t base = orbdet_lds(n, FL);
+    const size_t staged = orbdet_stage_off(n, FL) + ((size_t)n * s.M * (s.iso ? 2 : 10) + n) * sizeof(T);
+    const bool st_ok = 4 * (staged - base) <= base && staged <= 64 * 1024;
     if constexpr (FL) {
         if (n >= 7 && n <= ORB_PF) {
-            hipLaunchKernelGGL((k_orbdet<T, true, true>), g, dim3(64), orbdet_lds(n, FL), st, s, x, theta, S, sp0, B, TR,
-                               DR, rec);
+            if (st_ok)
+                hipLaunchKernelGGL((k_orbdet<T, true, true, true>), g, dim3(64), staged, st, s, x, theta, S, sp0,
+                                   B, TR, DR, rec);
+            else
+                hipLaunchKernelGGL((k_orbdet<T, true, true, false>), g, dim3(64), base, st, s, x, theta, S, sp0, B, TR,
+                                   DR, rec);
             return;
         }
     }
-    hipLaunchKernelGGL((k_orbdet<T, FL, false>), g, dim3(64), orbdet_lds(n, FL), st, s, x, theta, S, sp0, B, TR, DR,
-                       rec);
+    if (st_ok)
+        hipLaunchKernelGGL((k_orbdet<T, FL, false, true>), g, dim3(64), staged, st, s, x, theta, S, sp0, B, TR,
+                           DR, rec);
+    else
+        hipLaunchKernelGGL((k_orbdet<T, FL, false, false>), g, dim3(64), base, st, s, x, theta, S, sp0, B, TR, DR,
+                           rec);
 }
 
 template <typename T>
