@@ -417,7 +417,11 @@ fn_status fn_timing_read(const char *name, double *total_ms, int64_t *launches);
    (0: chosen by N and w2).  "pair_items" 0..4096: (pair, column group)
    items per workgroup of the vector kernel, pair rows per workgroup of the
    matrix-core kernel (0: default); the workgroup's LDS use caps it.
-   Neither of the last two changes the arithmetic. */
+   Neither of the last two changes the arithmetic.
+   "det_stage" 0/1: the determinant kernels copy a determinant's envelope
+   parameters and orbital offsets into LDS before the envelope arithmetic
+   where they fit (default 1) or read them from global memory; the values
+   and the arithmetic are the same, so are the results, bit for bit. */
 fn_status fn_tuning_set(const char *name, int64_t value);
 
 #ifdef __cplusplus

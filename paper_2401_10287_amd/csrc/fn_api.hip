@@ -1190,6 +1190,11 @@ fn_status fn_tuning_set(const char *name, int64_t value)
         g_fp32_products = (int)value;
         return FN_OK;
     }
+    if (strcmp(name, "det_stage") == 0) {
+        if (value < 0 || value > 1) return fail(FN_EINVAL, "det_stage: 0 or 1");
+        fn::g_det_stage = (int)value;
+        return FN_OK;
+    }
     if (strcmp(name, "pair_items") == 0) {
         if (value < 0 || value > 4096) return fail(FN_EINVAL, "pair_items: 0..4096");
         fn::g_pair_items = (int)value;

@@ -467,6 +467,7 @@ extern thread_local bool g_splitk_suppressed;
 // pair-stream launch shape: output columns per thread (0: by size) and
 // (pair, column group) items per workgroup (0: by form)
 extern int g_pair_oc, g_pair_items;
+extern int g_det_stage;     // determinant kernels: envelope parameters staged in LDS where they fit
 // FP32 pair layers on the matrix cores (false: vector kernel)
 extern bool g_pair_mfma;
 void launch_stream_layer(int mode, const LayerArgs &a, int TR, hipStream_t st);

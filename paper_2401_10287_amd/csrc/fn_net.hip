@@ -1735,6 +1735,7 @@ size_t pair_stream_lds(const Sys &s, bool fl, size_t elem) { return pair_stream_
 // forward-Laplacian form takes fewer columns per thread for small N * w2
 // (more threads share the LDS rows of a pair); the value form takes 4.
 int g_pair_oc = 0, g_pair_items = 0;
+int g_det_stage = 1;
 
 static int pair_stream_oc(const Sys &s, bool fl)
 {
@@ -1893,7 +1894,7 @@ static void launch_small(const Sys &s, const double *x, const T *theta, const Or
     const int H = FL ? 2 : 1;                             // threads per determinant (as in the kernel)
     const dim3 gs((unsigned)(nsp * ((H * B * s.K + 255) / 256)));
     const int64_t nst = small_stage_elems(s, NS);
-    if (nst <= SMALL_STAGE_MAX)
+    if (g_det_stage && nst <= SMALL_STAGE_MAX)
         hipLaunchKernelGGL((k_orbdet_small<T, NS, FL, true>), gs, dim3(256), (size_t)nst * sizeof(T), st, s, x, theta, S,
                            sp0, B, TR, DR, rec);
     else
@@ -1933,7 +1934,7 @@ static void launch_orbdet_spins(const Sys &s, const double *x, const T *theta, c
     // slower; LiF, 2 nuclei, 8% faster)
     const size_t base = orbdet_lds(n, FL);
     const size_t staged = orbdet_stage_off(n, FL) + ((size_t)n * s.M * (s.iso ? 2 : 10) + n) * sizeof(T);
-    const bool st_ok = 4 * (staged - base) <= base && staged <= 64 * 1024;
+    const bool st_ok = g_det_stage && 4 * (staged - base) <= base && staged <= 64 * 1024;
     if constexpr (FL) {
         if (n >= 7 && n <= ORB_PF) {
             if (st_ok)

@@ -385,6 +385,37 @@ def test_pair_kernels_and_launch_shapes(name, walkers):
         fnvmc.fn_tuning_set("pair_items", 0)
 
 
+@pytest.mark.parametrize("name,prec,walkers", [("He", "fp64", 33), ("LiH", "bf16w", 61), ("LiH", "fp64", 9),
+                                               ("LiF", "bf16w", 13), ("LiF", "fp32", 7)])
+def test_det_parameter_staging_bitwise(name, prec, walkers):
+    """The determinant kernels with a determinant's envelope parameters
+    (Eq. 4: pi, Sigma) and orbital offsets copied into LDS first (switch
+    "det_stage" 1, the default) and read from global memory (0): the same
+    values go through the same arithmetic, so the local energy (forward
+    Laplacian: the one-thread-per-determinant kernel for one or two
+    electrons per spin, the one-wave kernel above) and log|psi| (value form)
+    are bitwise equal, and within the oracle bounds."""
+    s = SYSTEMS[name]()
+    x = _walkers(name, s, walkers)
+    torch, fnvmc, cfg, tt, xt, th, x = _setup(s, prec, walkers, x=x)
+    got = {}
+    try:
+        for st in (1, 0):
+            fnvmc.fn_tuning_set("det_stage", st)
+            e, lp, _ = fnvmc.fn_local_energy(cfg, tt, xt)
+            lv, sg = fnvmc.fn_log_psi(cfg, tt, xt)
+            torch.cuda.synchronize()
+            got[st] = (e.cpu().numpy(), lp.cpu().numpy(), lv.cpu().numpy(), sg.cpu().numpy())
+    finally:
+        fnvmc.fn_tuning_set("det_stage", 1)
+    for a, b, what in zip(got[1], got[0], ("E_L", "log|psi| (forward-Laplacian pass)", "log|psi|", "sign")):
+        np.testing.assert_array_equal(a, b, err_msg=f"{name} {prec}: {what}")
+    o = O.Oracle(s)
+    ref = o.log_psi(th, x)
+    kap, C = T.kappa_and_c(o, s, th, x)
+    T.check_logpsi(got[1][2], ref, 1e-5 if prec != "fp64" else 1e-10, f"{name} {prec} staged", C, prec == "fp64")
+
+
 @pytest.mark.parametrize("name,walkers", [("LiH", 256), ("LiF", 37), ("LiH", 1024), ("LiH", 37), ((8, 0), 13),
                                           ((16, 0), 5)])
 def test_small_grid_products_both_kernels(name, walkers):
