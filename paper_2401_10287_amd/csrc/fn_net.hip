@@ -299,11 +299,32 @@ __device__ void write_pair_means_wg(const Sys &s, const float *S, int per, int w
     // (every product over these rows reads its live rows only)
     const int n3 = 3 * s.N, rows = FL ? TR : 1, live_rows = FL ? n3 + 2 : 1, cqn = GWl / 4;
     const int items = nwi * live_rows * cqn;
+    // item it = (bb live_rows + t) cqn + col / 4.  When cqn divides the
+    // workgroup size a thread keeps its column and its (row, t) advances by
+    // a fixed step, so the index arithmetic is done once
+    const bool fixed_col = (int)blockDim.x % cqn == 0;
+    const int rstep = (int)blockDim.x / cqn;
+    const int i0 = (int)(wi0 % s.N);
+    int t = 0, bb = 0, ccol = 0;
+    if (fixed_col) {
+        const int rt0 = (int)threadIdx.x / cqn;
+        ccol = 4 * ((int)threadIdx.x - rt0 * cqn);
+        t = rt0 % live_rows;
+        bb = rt0 / live_rows;
+    }
     for (int it = threadIdx.x; it < items; it += blockDim.x) {
-        const int col = 4 * (it % cqn), rt = it / cqn;
-        const int t = rt % live_rows, bb = rt / live_rows;
+        int col;
+        if (fixed_col) {
+            col = ccol;
+        } else {
+            const int rt = it / cqn;
+            col = 4 * (it - rt * cqn);
+            t = rt % live_rows;
+            bb = rt / live_rows;
+        }
         const int64_t wi = wi0 + bb;
-        const int i = (int)(wi % s.N);
+        int i = i0 + bb;                               // (wi0 + bb) mod N, bb < nwi
+        while (i >= s.N) i -= s.N;
         const float *Sb = S + (int64_t)bb * per;
         const bool live = col < 2 * dp;
         const int sp = live ? col / dp : 0, o = live ? col - sp * dp : 0;
@@ -332,6 +353,13 @@ __device__ void write_pair_means_wg(const Sys &s, const float *S, int per, int w
             }
         }
         *(float4 *)(gi0 + (wi * rows + t) * ldg + col) = v;
+        if (fixed_col) {
+            t += rstep;
+            while (t >= live_rows) {
+                t -= live_rows;
+                ++bb;
+            }
+        }
     }
 }
 
