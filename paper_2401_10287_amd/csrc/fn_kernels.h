@@ -20,6 +20,7 @@ struct PackSeg {
     int64_t begin, count, off, off2;
     int kind, mode, mode2, dh, dp, w1, HWl, GWl, kn, W1p, w2, wc, ks;   // mode2: Wg of a layer block
     int round;
+    int bbegin;     // first workgroup of the segment (set by launch_pack)
     void *d0, *d1;
 };
 struct PackList {

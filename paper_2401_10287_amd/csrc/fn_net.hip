@@ -40,10 +40,10 @@ __device__ inline void put_w(int mode, void *base, int64_t part, int64_t idx, T 
 template <typename T>
 __device__ inline void pack_layer_elem(const T *theta, const PackSeg &g, int64_t t)
 {
-    const int64_t kx = g.HWl + g.GWl, kg = 2 * g.HWl;
+    const int kx = g.HWl + g.GWl, kg = 2 * g.HWl;
     const int64_t nx = (int64_t)g.w1 * kx, ng = (int64_t)g.w1 * kg;
     if (t < nx) {
-        const int o = (int)(t / kx), k = (int)(t % kx);
+        const int ti = (int)t, o = ti / kx, k = ti - o * kx;
         int row = -1;
         if (k < g.dh) row = k;
         else if (k >= g.HWl && k < g.HWl + 2 * g.dp) row = 3 * g.dh + (k - g.HWl);
@@ -52,7 +52,7 @@ __device__ inline void pack_layer_elem(const T *theta, const PackSeg &g, int64_t
         put_w<T>(g.mode, g.d0, nx, t, v);
     } else {
         const int64_t u = t - nx;
-        const int o = (int)(u / kg), k = (int)(u % kg);
+        const int ui = (int)u, o = ui / kg, k = ui - o * kg;
         int row = -1;
         if (k < g.dh) row = g.dh + k;
         else if (k >= g.HWl && k < g.HWl + g.dh) row = 2 * g.dh + (k - g.HWl);
@@ -67,7 +67,7 @@ template <typename T>
 __device__ inline void pack_head_elem(const T *theta, const PackSeg &g, int64_t t)
 {
     const int64_t n = (int64_t)g.kn * g.W1p;
-    const int col = (int)(t / g.W1p), k = (int)(t % g.W1p);
+    const int ti = (int)t, col = ti / g.W1p, k = ti - col * g.W1p;
     T v = k < g.w1 ? theta[g.off + (int64_t)k * g.kn + col] : T(0);
     if (g.round) v = (T)bf16_round((float)v);
     put_w<T>(g.mode, g.d0, n, t, v);
@@ -79,7 +79,7 @@ __device__ inline void pack_pair_elem(const T *theta, const PackSeg &g, int64_t 
 {
     T v = T(0);
     if (t < (int64_t)g.wc * g.ks) {
-        const int o = (int)(t / g.ks), k = (int)(t % g.ks);
+        const int ti = (int)t, o = ti / g.ks, k = ti - o * g.ks;
         if (o < g.w2 && k < g.dp) v = theta[g.off + (int64_t)k * g.w2 + o];
     } else {
         const int o = (int)(t - (int64_t)g.wc * g.ks);
@@ -88,20 +88,21 @@ __device__ inline void pack_pair_elem(const T *theta, const PackSeg &g, int64_t 
     ((float *)g.d0)[t] = (float)v;
 }
 
-// every forward operand block in one launch; segment q covers the element
-// range [begin_q, begin_q + count_q) of one index space
+// every forward operand block in one launch; segment q takes the
+// workgroups [bbegin_q, bbegin_(q+1)), one element of its count_q per thread
+// (the segment is the same for the whole workgroup)
 template <typename T>
-__global__ void k_pack(const T *theta, PackList pl, int64_t total)
+__global__ __launch_bounds__(256) void k_pack(const T *theta, PackList pl)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        int q = 0;
-        while (q + 1 < pl.n && i >= pl.seg[q + 1].begin) ++q;
-        const PackSeg &g = pl.seg[q];
-        if (g.kind == 0) pack_layer_elem<T>(theta, g, i - g.begin);
-        else if (g.kind == 1) pack_head_elem<T>(theta, g, i - g.begin);
-        else if (g.kind == 2) pack_pair_elem<T>(theta, g, i - g.begin);
-        else ((T *)g.d0)[i - g.begin] = (T)bf16_round((float)theta[g.off + (i - g.begin)]);
-    }
+    int q = 0;
+    while (q + 1 < pl.n && (int)blockIdx.x >= pl.seg[q + 1].bbegin) ++q;
+    const PackSeg &g = pl.seg[q];
+    const int64_t t = (int64_t)((int)blockIdx.x - g.bbegin) * blockDim.x + threadIdx.x;
+    if (t >= g.count) return;
+    if (g.kind == 0) pack_layer_elem<T>(theta, g, t);
+    else if (g.kind == 1) pack_head_elem<T>(theta, g, t);
+    else if (g.kind == 2) pack_pair_elem<T>(theta, g, t);
+    else ((T *)g.d0)[t] = (T)bf16_round((float)theta[g.off + t]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1735,8 +1736,14 @@ template <typename T>
 void launch_pack(const T *theta, const PackList &pl, hipStream_t st)
 {
     if (pl.n <= 0) return;
-    const int64_t total = pl.seg[pl.n - 1].begin + pl.seg[pl.n - 1].count;
-    hipLaunchKernelGGL(k_pack<T>, dim3(grid_for(total)), dim3(256), 0, st, theta, pl, total);
+    PackList q = pl;
+    int64_t nb = 0;
+    for (int k = 0; k < q.n; ++k) {
+        q.seg[k].bbegin = (int)nb;
+        nb += (q.seg[k].count + 255) / 256;
+    }
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_pack<T>, dim3((unsigned)nb), dim3(256), 0, st, theta, q);
 }
 
 template <typename T>
