@@ -1432,7 +1432,7 @@ __global__ __launch_bounds__(256) void k_orbdet_small(Sys s, const double *x, co
     if constexpr (H == 2 && NS == 2) {
         // each of the two threads forms one orbital row (io = hh), then the
         // pair swaps them (adjacent lanes)
-        double rv[NS][7];
+        double rv[NS][7];                                 // per electron: e, grad e (3), lap e, a, A
 #pragma unroll
         for (int jj = 0; jj < NS; ++jj) {
             double g3[3];
